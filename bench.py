@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark: one J/K build per step on one MI355X.
+
+Workload: a 30-atom synthetic molecule with 3s2p1d shells per atom (1-6
+primitives per shell, exponents log-uniform [0.05, 5e3] bohr^-2, spherical d;
+N = 420 functions, 180 shells), Schwarz threshold 1e-12, FP64 throughout.
+A step is one hgp_jk call (J and K together) on a plan built once before the
+timed region, as in the density updates of an SCF run.  The plan build (pair
+data, Schwarz factors, screened class lists) is reported as setup_s.
+
+Prints ONE JSON line.  `value` is contracted ERIs per second: the number of
+unique contracted spherical integrals the kept quartets hold, per second of
+J/K build.  `roofline` refers to the class kernel with the largest share of
+the step, timed with HIP events recorded on the stream it runs on;
+`cpu_baseline` times the CPU oracle (integrals only, all host threads) on a
+random sample of the same screened unique quartets.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "J/K build time & contracted ERIs/s at stated err vs FP64; served p50/p99"
+FP64_VALU_PEAK_TFLOPS = 78.6    # 256 CU x 128 FP64 FLOP/clk x 2.4 GHz
+TAU = 1e-12
+
+
+def nsph(l):
+    return 2 * l + 1
+
+
+def overhead_flops(L):
+    """Per primitive quartet, outside the VRR graph: pair combination (25),
+    Boys Taylor step (21) and downward recurrence (2 per order)."""
+    return 46 + 2 * L
+
+
+def algorithmic_flops(c):
+    la, lb, lc, ld = c["ls"]
+    nint = nsph(la) * nsph(lb) * nsph(lc) * nsph(ld)
+    per_prim = c["vrr_flops"] + overhead_flops(la + lb + lc + ld)
+    per_quartet = c["phase2_flops"] + 12 * nint
+    return c["prim_quartets"] * per_prim + c["quartets"] * per_quartet
+
+
+def cpu_baseline(bw, target_s, seed=7):
+    """Oracle ERIs/s on random screened unique quartets of the same workload."""
+    import oracle
+
+    rng = np.random.default_rng(seed)
+    Q = oracle.schwarz(bw)
+    ns = bw.nshell
+    iu = np.tril_indices(ns)
+    npair = len(iu[0])
+
+    def draw(n):
+        out = []
+        while len(out) < n:
+            p = rng.integers(0, npair, 4 * n)
+            r = rng.integers(0, npair, 4 * n)
+            p, r = np.maximum(p, r), np.minimum(p, r)
+            keep = Q[iu[0][p], iu[1][p]] * Q[iu[0][r], iu[1][r]] >= TAU
+            for a, c in zip(p[keep], r[keep]):
+                out.append((iu[0][a], iu[1][a], iu[0][c], iu[1][c]))
+        return np.array(out[:n], np.int32)
+
+    probe = draw(200)
+    t = time.perf_counter()
+    oracle.eri_quartet_list(bw, probe)
+    dt = time.perf_counter() - t
+    n = int(max(200, min(2_000_000, 200 * target_s / max(dt, 1e-3))))
+    sample = draw(n)
+    t = time.perf_counter()
+    cnt, _ = oracle.eri_quartet_list(bw, sample)
+    dt = time.perf_counter() - t
+    return {"value": cnt / dt, "unit": "contracted ERIs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n} uniformly drawn screened unique shell quartets of the same workload, "
+                      f"integrals only (no J/K digestion), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2605_10312_amd as hgp
+    import workloads
+
+    bw, D = workloads.molecule_3s2p1d()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    basis = hgp.Basis.from_workload(bw)
+    plan = hgp.Plan(basis, tau=TAU)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    classes = plan.classes()
+    stats = plan.stats()
+    eris = sum(c["quartets"] * np.prod([nsph(x) for x in c["ls"]]) for c in classes)
+
+    Dt = torch.tensor(D, dtype=torch.float64, device="cuda")
+    J = torch.empty_like(Dt)
+    K = torch.empty_like(Dt)
+    for _ in range(args.warmup):
+        plan.jk(Dt, J, K)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        plan.jk(Dt, J, K)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    timing = plan.class_timing()
+    plan.set_timing(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    per_class = []
+    for c, (ls, n, ms) in zip(classes, timing):
+        fl = algorithmic_flops(c)
+        avg = ms / max(n, 1)
+        per_class.append({"class": "".join(str(x) for x in ls), "quartets": c["quartets"],
+                          "prim_quartets": c["prim_quartets"], "avg_ms": round(avg, 4),
+                          "gflop_per_launch": round(fl / 1e9, 3),
+                          "tflops": round(fl / (avg * 1e-3) / 1e12, 3) if avg > 0 else None})
+    per_class.sort(key=lambda x: -x["avg_ms"])
+    dom = per_class[0]
+    achieved = dom["tflops"]
+    roofline = {"bound": "alu", "kernel": f"jk_{dom['class']}", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": dom["avg_ms"]}
+    total_kernel_ms = sum(x["avg_ms"] for x in per_class)
+    total_flops = sum(algorithmic_flops(c) for c in classes)
+
+    err = None
+    if not args.no_check:
+        import oracle
+        off = bw.shell_offsets()
+        ss = np.where(bw.l == 0)[0]
+        pr = (int(ss[7]), int(ss[30]))
+        Js, Ks = oracle.jk_blocks(bw, D, [pr], tau=TAU)
+        Jg, Kg = J.cpu().numpy(), K.cpu().numpy()
+        sl = (slice(off[pr[0]], off[pr[0] + 1]), slice(off[pr[1]], off[pr[1] + 1]))
+        err = {"jk_block_max_abs": float(max(np.abs(Jg[sl] - Js[0]).max(), np.abs(Kg[sl] - Ks[0]).max())),
+               "block": list(pr)}
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(bw, args.cpu_seconds)
+
+    line = {
+        "metric": METRIC,
+        "value": eris / (ms_per_step * 1e-3),
+        "unit": "contracted ERIs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "mol30_3s2p1d: 30-atom synthetic molecule, 3s2p1d per atom (1-6 primitives), "
+                               "N=420, Schwarz tau=1e-12, J+K in FP64",
+                   "nbf": int(bw.nbf), "shells": int(bw.nshell), "tau": TAU,
+                   "quartets_kept": stats["quartets_kept"], "quartets_total": stats["quartets_total"],
+                   "eris_per_step": int(eris)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "jk_build_ms": round(ms_per_step, 4),
+        "setup_s": round(setup_s, 3),
+        "step_tflops": round(total_flops / (ms_per_step * 1e-3) / 1e12, 3),
+        "kernel_ms_sum": round(total_kernel_ms, 4),
+        "err": err,
+        "classes": per_class,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,162 @@
+/*
+ * hgp.h -- C ABI of the MI355X (gfx950) Head-Gordon-Pople ERI / J-K library.
+ *
+ * What it computes (the paper's statement of the problem, Sec. II-A and
+ * Alg. 2's input/output): contracted two-electron repulsion integrals
+ *     (mn|ls) = int int phi_m(r1) phi_n(r1) phi_l(r2) phi_s(r2) / |r1 - r2|
+ * (Eq. eri-def) over shells of contracted Cartesian Gaussians, transformed to
+ * pure spherical functions (Sec. III-B, Eq. cart2sph), and their digestion
+ * into the Coulomb and exchange matrices
+ *     J_mn = sum_ls (mn|ls) D_ls,     K_mn = sum_ls (ml|ns) D_ls
+ * for a symmetric density D.  Evaluation follows the HGP scheme: Boys
+ * function, vertical recurrence (Eq. vrr) per primitive quartet with the
+ * contraction accumulated before the horizontal recurrence (Eq. hrr), which
+ * is fused with the spherical transform index by index (Eq. stepwise-sph).
+ *
+ * Conventions
+ *   - Units: bohr for coordinates, bohr^-2 for exponents, hartree for integrals.
+ *   - Shells: l = 0..4.  Contraction coefficients are raw: the library scales
+ *     them so that x^l exp(-a r^2) components are normalised (each primitive
+ *     carries N(a,l) = (2a/pi)^(3/4) (4a)^(l/2) / sqrt((2l-1)!!)) and the
+ *     contracted x^l component has unit norm.
+ *   - Spherical functions per shell: s: 1; p: x, y, z (untransformed);
+ *     l >= 2: 2l+1 real solid harmonics, m = -l .. l, unit norm, leading
+ *     monomial coefficient positive (no Condon-Shortley phase).
+ *   - Basis function order: shell by shell, in the order given.
+ *   - Matrices: N x N, row-major, FP64, N = number of spherical functions.
+ *
+ * Memory and streams
+ *   - Host pointers are read during the call and copied; device pointers
+ *     (marked "device") are borrowed for the call and must stay valid until
+ *     the work enqueued on the stream has completed.
+ *   - hip_stream is a hipStream_t passed as void* (0: the null stream).
+ *     Calls that enqueue work return after enqueueing; the caller
+ *     synchronises the stream before reading results.
+ *   - Handles own their device allocations; *_destroy frees them.  A handle
+ *     must not be used from two host threads at once; distinct plans may run
+ *     on distinct streams concurrently.
+ *
+ * Errors
+ *   - Every call returns an hgp_status.  Argument errors are detected before
+ *     any work is enqueued.  hgp_last_error() returns a thread-local message
+ *     describing the last non-OK status.
+ *   - A device or launch failure returns HGP_E_DEVICE and marks the plan
+ *     unusable (later calls on it return HGP_E_STATE).
+ */
+#ifndef HGP_H
+#define HGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HGP_OK = 0,
+    HGP_E_INVALID = -1,        /* bad argument (null pointer, bad size, non-finite or non-positive exponent) */
+    HGP_E_UNSUPPORTED_L = -2,  /* a shell with l > 4, or a class not built into this library */
+    HGP_E_OOM = -3,            /* device allocation failed or the plan exceeds hbm_budget_bytes */
+    HGP_E_DEVICE = -4,         /* HIP runtime or launch failure */
+    HGP_E_STATE = -5           /* handle unusable after an earlier device failure */
+} hgp_status;
+
+typedef struct hgp_basis hgp_basis;  /* validated shells, normalised coefficients, device copies */
+typedef struct hgp_plan hgp_plan;    /* pair data, Schwarz factors and screened class quartet lists */
+
+#define HGP_FP64 0
+
+/* Library version and the highest l built into this library's class kernels. */
+int32_t hgp_version(void);
+int32_t hgp_max_l(void);
+
+/*
+ * hgp_basis_create -- ingest nshell shells (Alg. 2's input: shells with
+ * primitives {(alpha_i, c_i)}) onto the current HIP device.
+ *   l[nshell]         angular momentum per shell, 0..4              (host)
+ *   nprim[nshell]     primitives per shell, 1..64                   (host)
+ *   centers[3*nshell] x, y, z per shell, bohr                       (host)
+ *   exps[sum nprim]   exponents, shell by shell, > 0                (host)
+ *   coefs[sum nprim]  raw contraction coefficients                  (host)
+ * Normalisation runs in a device kernel.  nshell = 0 is allowed (N = 0).
+ */
+hgp_status hgp_basis_create(int32_t nshell, const int32_t *l, const int32_t *nprim, const double *centers,
+                            const double *exps, const double *coefs, hgp_basis **out);
+/* Number of spherical functions; shell_offsets[nshell+1] (host, may be NULL) gets each shell's first function. */
+hgp_status hgp_basis_nbf(const hgp_basis *b, int32_t *nbf, int32_t *shell_offsets);
+hgp_status hgp_basis_destroy(hgp_basis *b);
+
+/*
+ * hgp_plan_create -- everything a J/K build reuses across density updates:
+ * shell-pair and primitive-pair data (the Gaussian-product quantities of
+ * Alg. 2's GaussianPairs), Schwarz factors Q_ab = sqrt(max |(mn|mn)|), and per
+ * canonical class (la lb|lc ld) the list of unique quartets with
+ * Q_ab Q_cd >= schwarz_tau (0: keep all).  All of it is computed by device
+ * kernels on hip_stream; the call waits for the stream before returning.
+ *   precision         HGP_FP64
+ *   hbm_budget_bytes  0 = unlimited; otherwise HGP_E_OOM if the plan needs more
+ */
+hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t precision, size_t hbm_budget_bytes,
+                           void *hip_stream, hgp_plan **out);
+hgp_status hgp_plan_destroy(hgp_plan *p);
+/* Plan statistics: unique quartets kept after screening, candidate quartets, device bytes held. */
+hgp_status hgp_plan_stats(const hgp_plan *p, int64_t *quartets_kept, int64_t *quartets_total, int64_t *device_bytes);
+/* Per class c (0 .. n-1, n = hgp_plan_num_classes): angular momenta ls[4], quartets kept, and the
+ * generator's FLOP counts per primitive quartet (VRR + accumulate) and per contracted quartet (Phase 2). */
+int32_t hgp_plan_num_classes(const hgp_plan *p);
+hgp_status hgp_plan_class_info(const hgp_plan *p, int32_t c, int32_t *ls, int64_t *nquartets, int64_t *nprim_quartets,
+                               double *vrr_flops, double *phase2_flops);
+
+/* The plan's Schwarz factors by shell: Q[i*nshell + j] = Q[j*nshell + i] =
+ * sqrt(max |(mn|mn)|) over m in shell i, n in shell j (host array, nshell^2). */
+hgp_status hgp_plan_schwarz(const hgp_plan *p, double *Q);
+
+/*
+ * Kernel timing for profiling: with timing enabled, hgp_jk records a pair of
+ * HIP events on its stream around each class kernel (the work enqueued is
+ * unchanged).  hgp_plan_set_timing(p, 1) also resets the counters.
+ * hgp_plan_class_timing waits for the recorded events and returns, for class
+ * c, the number of timed launches and their summed duration in milliseconds.
+ */
+hgp_status hgp_plan_set_timing(hgp_plan *p, int32_t enable);
+hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int64_t *launches, double *total_ms);
+
+/*
+ * hgp_jk -- J and K for density D (Alg. 2's Scatter step, 8-fold symmetry).
+ *   D   N x N symmetric density (device; symmetry is assumed, not checked)
+ *   J   N x N output (device, overwritten) or NULL to skip J
+ *   K   N x N output (device, overwritten) or NULL to skip K
+ * Enqueues: zeroing of the plan's accumulators, one kernel per class, and
+ * the symmetrisation J = J' + J'^T, K = K' + K'^T into the outputs.
+ */
+hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_stream);
+
+/*
+ * hgp_eri_shell_quartets -- integrals out, any shell order.
+ *   quartets[4*nq]  shell indices (i, j, k, l) per quartet          (host)
+ *   offsets[nq]     element offset of each block in out             (host)
+ *   out             blocks [n_i][n_j][n_k][n_l] row-major at out + offsets[q] (device)
+ * Waits for the stream before returning (temporary device buffers are freed).
+ */
+hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartets, const int64_t *offsets,
+                                  double *out, void *hip_stream);
+
+/*
+ * hgp_eri_prim_quartets -- n independent primitive quartets of class
+ * (la lb|lc ld), each primitive normalised (coefficient N(a,l)).
+ *   centers[12*n]  A, B, C, D per quartet, bohr                      (device)
+ *   exps[4*n]      a, b, c, d per quartet                            (device)
+ *   out[n * nsph(la) nsph(lb) nsph(lc) nsph(ld)]  spherical blocks   (device)
+ * Stream-ordered; returns after enqueueing.
+ */
+hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64_t n, const double *centers,
+                                 const double *exps, double *out, int32_t precision, void *hip_stream);
+
+/* Thread-local description of the last non-OK status (never NULL). */
+const char *hgp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HGP_H */

@@ -185,3 +185,19 @@ def eri_tensor(basis, precision: str = "double") -> np.ndarray:
     out = np.zeros((N, N, N, N))
     _check(_fn("eri_tensor", precision)(*args, _p(out)), "eri_tensor")
     return out
+
+
+def eri_quartet_list(basis, quartets, precision: str = "double"):
+    """Evaluate the listed shell quartets; returns (integrals evaluated, checksum)."""
+    keep, args = _basis_args(basis)
+    q = np.ascontiguousarray(np.asarray(quartets, dtype=np.int32).reshape(-1, 4))
+    cnt = ctypes.c_int64()
+    chk = ctypes.c_double()
+    rc = _fn("eri_quartet_list", precision)(*args, ctypes.c_int64(q.shape[0]), _p(q), ctypes.byref(cnt),
+                                             ctypes.byref(chk))
+    _check(rc, "eri_quartet_list")
+    return cnt.value, chk.value
+
+
+def num_threads(precision: str = "double") -> int:
+    return int(_fn("num_threads", precision)())

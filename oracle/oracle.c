@@ -802,3 +802,53 @@ int PFX(eri_tensor)(int nshell, const int *l, const int *nprim, const double *ce
     basis_free(&b);
     return err;
 }
+
+/* Spherical blocks of the nq listed shell quartets (4 shell indices each),
+ * evaluated in parallel; *count gets the number of integrals evaluated and
+ * *checksum the sum of all their values (the blocks are not kept). */
+int PFX(eri_quartet_list)(int nshell, const int *l, const int *nprim, const double *centers, const double *exps,
+                          const double *coefs, int64_t nq, const int *quartets, int64_t *count, double *checksum)
+{
+    basis_t b;
+    int rc = basis_make(&b, nshell, l, nprim, centers, exps, coefs);
+    for (int64_t q = 0; !rc && q < 4 * nq; ++q)
+        if (quartets[q] < 0 || quartets[q] >= nshell) rc = -1;
+    if (rc) { basis_free(&b); return rc; }
+    int64_t cnt = 0;
+    real sum = 0;
+    int err = 0;
+#pragma omp parallel reduction(+ : cnt, sum)
+    {
+        work_t w; memset(&w, 0, sizeof(w));
+        real *blk = malloc(sizeof(real) * 9 * 9 * 9 * 9);
+        int lrc = blk ? 0 : -3;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t q = 0; q < nq; ++q) {
+            if (lrc) continue;
+            const int *s = quartets + 4 * q;
+            lrc = quartet_sph(&w, &b, s[0], s[1], s[2], s[3], blk);
+            int64_t n = (int64_t)nsph(l[s[0]]) * nsph(l[s[1]]) * nsph(l[s[2]]) * nsph(l[s[3]]);
+            for (int64_t i = 0; i < n && !lrc; ++i) sum += blk[i];
+            cnt += n;
+        }
+        if (lrc) {
+#pragma omp atomic write
+            err = lrc;
+        }
+        free(blk); work_free(&w);
+    }
+    if (count) *count = cnt;
+    if (checksum) *checksum = (double)sum;
+    basis_free(&b);
+    return err;
+}
+
+/* threads an OpenMP parallel region of the oracle uses */
+int PFX(num_threads)(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

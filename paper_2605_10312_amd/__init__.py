@@ -1,0 +1,213 @@
+"""Python binding of libhgp.so (include/hgp.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels on the GPU.  Device
+buffers are torch tensors (``data_ptr()``) and streams are torch streams
+(``cuda_stream``); torch provides memory and streams, nothing else.  When the
+library is missing this module raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgp.so")
+
+STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_UNSUPPORTED_L", -3: "HGP_E_OOM", -4: "HGP_E_DEVICE",
+          -5: "HGP_E_STATE"}
+HGP_FP64 = 0
+
+# exported symbol -> (restype, argtypes)
+_vp, _i32, _i64, _d, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+SIGNATURES = {
+    "hgp_version": (_i32, []),
+    "hgp_max_l": (_i32, []),
+    "hgp_basis_create": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "hgp_basis_nbf": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), _vp]),
+    "hgp_basis_destroy": (ctypes.c_int, [_vp]),
+    "hgp_plan_create": (ctypes.c_int, [_vp, _d, _i32, _sz, _vp, ctypes.POINTER(_vp)]),
+    "hgp_plan_destroy": (ctypes.c_int, [_vp]),
+    "hgp_plan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "hgp_plan_num_classes": (_i32, [_vp]),
+    "hgp_plan_class_info": (ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                           ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+    "hgp_plan_schwarz": (ctypes.c_int, [_vp, _vp]),
+    "hgp_plan_set_timing": (ctypes.c_int, [_vp, _i32]),
+    "hgp_plan_class_timing": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
+    "hgp_jk": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "hgp_eri_shell_quartets": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
+    "hgp_eri_prim_quartets": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i64, _vp, _vp, _vp, _i32, _vp]),
+    "hgp_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class HGPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libhgp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_10312_amd.build`")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise HGPError(rc, lib().hgp_last_error().decode())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _dptr(t, dtype=None):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Basis:
+    """hgp_basis: shells l[n], nprim[n], centres [n,3] (bohr), exponents and raw
+    coefficients (flat, shell by shell)."""
+
+    def __init__(self, l, nprim, centers, exps, coefs):
+        self._keep = [_host(l, np.int32), _host(nprim, np.int32), _host(centers, np.float64),
+                      _host(exps, np.float64), _host(coefs, np.float64)]
+        ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in self._keep]
+        h = ctypes.c_void_p()
+        _check(lib().hgp_basis_create(int(self._keep[0].shape[0]), *ptrs, ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_int32()
+        self.shell_offsets = np.zeros(self._keep[0].shape[0] + 1, np.int32)
+        _check(lib().hgp_basis_nbf(h, ctypes.byref(n), self.shell_offsets.ctypes.data_as(ctypes.c_void_p)))
+        self.nbf = int(n.value)
+        self.l = self._keep[0]
+
+    @classmethod
+    def from_workload(cls, b):
+        return cls(b.l, b.nprim, b.centers, b.exps, b.coefs)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hgp_basis_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """hgp_plan: pairs, Schwarz factors and screened class quartet lists."""
+
+    def __init__(self, basis: Basis, tau: float = 1e-12, hbm_budget: int = 0, stream=None):
+        self.basis = basis
+        h = ctypes.c_void_p()
+        _check(lib().hgp_plan_create(basis.handle, float(tau), HGP_FP64, int(hbm_budget),
+                                     ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)))
+        self.handle = h
+
+    def stats(self):
+        k, t, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().hgp_plan_stats(self.handle, ctypes.byref(k), ctypes.byref(t), ctypes.byref(b)))
+        return {"quartets_kept": k.value, "quartets_total": t.value, "device_bytes": b.value}
+
+    def classes(self):
+        out = []
+        for c in range(lib().hgp_plan_num_classes(self.handle)):
+            ls = np.zeros(4, np.int32)
+            nq, npq, vf, pf = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+            _check(lib().hgp_plan_class_info(self.handle, c, ls.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nq),
+                                             ctypes.byref(npq), ctypes.byref(vf), ctypes.byref(pf)))
+            out.append({"ls": tuple(int(x) for x in ls), "quartets": nq.value, "prim_quartets": npq.value,
+                        "vrr_flops": vf.value, "phase2_flops": pf.value})
+        return out
+
+    def schwarz(self):
+        """Schwarz factors by shell pair, [nshell, nshell]."""
+        n = int(self.basis.l.shape[0])
+        q = np.zeros((n, n))
+        _check(lib().hgp_plan_schwarz(self.handle, q.ctypes.data_as(ctypes.c_void_p)))
+        return q
+
+    def set_timing(self, enable: bool):
+        _check(lib().hgp_plan_set_timing(self.handle, 1 if enable else 0))
+
+    def class_timing(self):
+        """[(ls, launches, total_ms)] per class, waiting for recorded events."""
+        out = []
+        for c, info in enumerate(self.classes()):
+            n, ms = ctypes.c_int64(), ctypes.c_double()
+            _check(lib().hgp_plan_class_timing(self.handle, c, ctypes.byref(n), ctypes.byref(ms)))
+            out.append((info["ls"], n.value, ms.value))
+        return out
+
+    def jk(self, D, J=None, K=None, stream=None):
+        """Enqueue J/K for device density D into device J and/or K (overwritten)."""
+        import torch
+        _check(lib().hgp_jk(self.handle, _dptr(D, torch.float64), _dptr(J, torch.float64), _dptr(K, torch.float64),
+                            ctypes.c_void_p(_stream_ptr(stream))))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hgp_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eri_shell_quartets(basis: Basis, quartets, offsets, out, stream=None):
+    """Spherical blocks of the listed shell quartets into device tensor `out`."""
+    import torch
+    q = _host(quartets, np.int32).reshape(-1, 4)
+    off = _host(offsets, np.int64).reshape(-1)
+    _check(lib().hgp_eri_shell_quartets(basis.handle, int(q.shape[0]), q.ctypes.data_as(ctypes.c_void_p),
+                                        off.ctypes.data_as(ctypes.c_void_p), _dptr(out, torch.float64),
+                                        ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def eri_prim_quartets(ls, centers, exps, out, stream=None):
+    """n normalised primitive quartets of class ls: device centres [n,4,3],
+    exponents [n,4] and output [n, nsph...]."""
+    import torch
+    n = int(centers.shape[0])
+    _check(lib().hgp_eri_prim_quartets(*[int(x) for x in ls], n, _dptr(centers, torch.float64),
+                                       _dptr(exps, torch.float64), _dptr(out, torch.float64), HGP_FP64,
+                                       ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def max_l() -> int:
+    return int(lib().hgp_max_l())

@@ -1,0 +1,27 @@
+// Launchers of the hand-written auxiliary kernels (hgp_kernels_aux.hip).
+#pragma once
+#include "hgp_types.h"
+
+namespace hgp {
+
+void launch_boys_table(double *tab, hipStream_t s);
+void launch_normalize(int nshell, const int *l, const int *nprim, const int *poff, const double *exps,
+                      const double *coefs, double *out, hipStream_t s);
+void launch_pairs(int npair, const PairInfo *pairs, const double *cen, const int *poff, const double *exps,
+                  const double *ncoef, PairGeo *geo, PrimPair *prims, hipStream_t s);
+void launch_prim_quartet_pairs(int64_t n, const double *centers, const double *exps, const int ls[4],
+                               const int perm[4], const int strides[4], int64_t block, PairInfo *pairs,
+                               PairGeo *geo, PrimPair *prims, EriTask *tasks, hipStream_t s);
+void launch_screen_count(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau, int64_t *counts,
+                         hipStream_t s);
+void launch_scan(int64_t *v, int n, int64_t *total, hipStream_t s);
+void launch_screen_write(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau, const int64_t *offsets,
+                         int2 *out, hipStream_t s);
+void launch_store_q(int npair, const double *qv, PairGeo *geo, double *Q, hipStream_t s);
+void launch_fill_zero(double *x, int64_t n, hipStream_t s);
+void launch_symmetrize(const double *acc, double *out, int n, hipStream_t s);
+
+extern const ClassKernels g_class_table[];
+extern const int g_num_classes;
+
+}  // namespace hgp

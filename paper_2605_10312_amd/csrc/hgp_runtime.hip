@@ -1,0 +1,712 @@
+// Host runtime behind the C ABI in include/hgp.h: validation, basis ingest,
+// plan construction (pairs, Schwarz factors, screened class lists) and the
+// per-class dispatch of the generated kernels.  All arithmetic of the method
+// runs in device kernels; the host only does index bookkeeping.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hgp.h"
+#include "hgp_aux.h"
+
+using namespace hgp;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+hgp_status fail(hgp_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HGP_HIP(call)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (call);                                                                         \
+        if (e_ != hipSuccess) return fail(HGP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int nsph(int l) { return 2 * l + 1; }
+int pair_class_of(int la, int lb) { return la * (la + 1) / 2 + lb; }   // la >= lb
+
+std::mutex g_mu;
+double *g_boys[64] = {};
+
+hgp_status boys_table(int dev, const double **out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (dev < 0 || dev >= 64) return fail(HGP_E_DEVICE, "device index out of range");
+    if (!g_boys[dev]) {
+        double *t = nullptr;
+        HGP_HIP(hipMalloc(&t, sizeof(double) * BOYS_NPTS * BOYS_NORD));
+        launch_boys_table(t, 0);
+        HGP_HIP(hipGetLastError());
+        HGP_HIP(hipStreamSynchronize(0));
+        g_boys[dev] = t;
+    }
+    *out = g_boys[dev];
+    return HGP_OK;
+}
+
+int class_index(int la, int lb, int lc, int ld)
+{
+    for (int c = 0; c < g_num_classes; ++c) {
+        const ClassKernels &k = g_class_table[c];
+        if (k.la == la && k.lb == lb && k.lc == lc && k.ld == ld) return c;
+    }
+    return -1;
+}
+
+// doubles of scratch per lane the staged classes with every l <= lmax need
+int64_t staged_slots(int lmax)
+{
+    int64_t m = 0;
+    for (int c = 0; c < g_num_classes; ++c) {
+        const ClassKernels &k = g_class_table[c];
+        if (k.tier == 1 && k.la <= lmax) m = std::max<int64_t>(m, k.scratch_slots);
+    }
+    return m;
+}
+
+int built_max_l()
+{
+    int m = -1;
+    for (int c = 0; c < g_num_classes; ++c) m = std::max(m, g_class_table[c].la);
+    return m;
+}
+
+template <class T>
+hgp_status dalloc(T **p, size_t n, int64_t *bytes = nullptr)
+{
+    *p = nullptr;
+    if (n == 0) return HGP_OK;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(HGP_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    if (bytes) *bytes += (int64_t)(n * sizeof(T));
+    return HGP_OK;
+}
+
+template <class T>
+hgp_status upload(T **p, const std::vector<T> &v, int64_t *bytes = nullptr)
+{
+    hgp_status s = dalloc(p, v.size(), bytes);
+    if (s != HGP_OK) return s;
+    if (!v.empty()) HGP_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return HGP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct hgp_basis {
+    int device = 0;
+    int nshell = 0, nbf = 0, lmax = 0;
+    std::vector<int32_t> l, nprim, poff, foff;
+    std::vector<double> cen, exps, coefs;
+    int *d_l = nullptr, *d_nprim = nullptr, *d_poff = nullptr;
+    double *d_cen = nullptr, *d_exps = nullptr, *d_coefs = nullptr, *d_ncoef = nullptr;
+};
+
+struct ClassList {
+    int cls;          // index into g_class_table
+    int64_t nq = 0;   // unique quartets kept
+    int64_t nprimq = 0;
+    int2 *d_q = nullptr;
+    int64_t launches = 0;   // timed launches
+    double ms = 0.0;        // their summed duration
+};
+
+struct PendingTiming {
+    int list;
+    hipEvent_t start, stop;
+};
+
+struct hgp_plan {
+    const hgp_basis *b = nullptr;
+    int device = 0;
+    bool broken = false;
+    int npair = 0;
+    std::vector<int> pc_begin, pc_count;
+    std::vector<PairInfo> pairs;           // host copy, same order as d_pairs
+    PairInfo *d_pairs = nullptr;
+    PairGeo *d_geo = nullptr;
+    PrimPair *d_prims = nullptr;
+    double *d_Q = nullptr;
+    double *d_Jacc = nullptr, *d_Kacc = nullptr;
+    double *d_scratch = nullptr;           // staged classes, SCRATCH_LANES x slots
+    std::vector<ClassList> lists;
+    int64_t kept = 0, total = 0, bytes = 0;
+    bool timing = false;
+    std::vector<PendingTiming> pending;
+    std::vector<hipEvent_t> event_pool;
+};
+
+static hipEvent_t take_event(hgp_plan *p)
+{
+    if (!p->event_pool.empty()) {
+        hipEvent_t e = p->event_pool.back();
+        p->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static hgp_status collect_timing(hgp_plan *p)
+{
+    for (const PendingTiming &t : p->pending) {
+        float ms = 0.f;
+        HGP_HIP(hipEventSynchronize(t.stop));
+        HGP_HIP(hipEventElapsedTime(&ms, t.start, t.stop));
+        p->lists[t.list].ms += ms;
+        p->lists[t.list].launches += 1;
+        p->event_pool.push_back(t.start);
+        p->event_pool.push_back(t.stop);
+    }
+    p->pending.clear();
+    return HGP_OK;
+}
+
+extern "C" {
+
+int32_t hgp_version(void) { return 1; }
+int32_t hgp_max_l(void) { return built_max_l(); }
+const char *hgp_last_error(void) { return g_err.c_str(); }
+
+hgp_status hgp_basis_destroy(hgp_basis *b)
+{
+    if (!b) return HGP_OK;
+    hipFree(b->d_l); hipFree(b->d_nprim); hipFree(b->d_poff);
+    hipFree(b->d_cen); hipFree(b->d_exps); hipFree(b->d_coefs); hipFree(b->d_ncoef);
+    delete b;
+    return HGP_OK;
+}
+
+hgp_status hgp_basis_create(int32_t nshell, const int32_t *l, const int32_t *nprim, const double *centers,
+                            const double *exps, const double *coefs, hgp_basis **out)
+{
+    if (!out) return fail(HGP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (nshell < 0) return fail(HGP_E_INVALID, "nshell < 0");
+    if (nshell > 0 && (!l || !nprim || !centers || !exps || !coefs)) return fail(HGP_E_INVALID, "NULL shell array");
+    auto *b = new hgp_basis();
+    b->nshell = nshell;
+    b->poff.assign(1, 0);
+    b->foff.assign(1, 0);
+    for (int s = 0; s < nshell; ++s) {
+        if (l[s] < 0) { hgp_basis_destroy(b); return fail(HGP_E_INVALID, "negative l"); }
+        if (l[s] > 4) { hgp_basis_destroy(b); return fail(HGP_E_UNSUPPORTED_L, "shell with l > 4"); }
+        if (nprim[s] < 1 || nprim[s] > 64) { hgp_basis_destroy(b); return fail(HGP_E_INVALID, "nprim outside 1..64"); }
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(centers[3 * s + k])) { hgp_basis_destroy(b); return fail(HGP_E_INVALID, "non-finite centre"); }
+        b->l.push_back(l[s]);
+        b->nprim.push_back(nprim[s]);
+        b->poff.push_back(b->poff.back() + nprim[s]);
+        b->foff.push_back(b->foff.back() + nsph(l[s]));
+        b->lmax = std::max(b->lmax, (int)l[s]);
+    }
+    b->nbf = b->foff.back();
+    const int np = b->poff.back();
+    for (int k = 0; k < np; ++k) {
+        if (!(exps[k] > 0.0) || !std::isfinite(exps[k]) || !std::isfinite(coefs[k])) {
+            hgp_basis_destroy(b);
+            return fail(HGP_E_INVALID, "exponents must be finite and > 0, coefficients finite");
+        }
+    }
+    b->cen.assign(centers, centers + 3 * nshell);
+    b->exps.assign(exps, exps + np);
+    b->coefs.assign(coefs, coefs + np);
+    if (hipGetDevice(&b->device) != hipSuccess) { hgp_basis_destroy(b); return fail(HGP_E_DEVICE, "hipGetDevice failed"); }
+    hgp_status st;
+    if ((st = upload(&b->d_l, b->l)) || (st = upload(&b->d_nprim, b->nprim)) || (st = upload(&b->d_poff, b->poff)) ||
+        (st = upload(&b->d_cen, b->cen)) || (st = upload(&b->d_exps, b->exps)) || (st = upload(&b->d_coefs, b->coefs)) ||
+        (st = dalloc(&b->d_ncoef, (size_t)std::max(np, 1)))) {
+        hgp_basis_destroy(b);
+        return st;
+    }
+    launch_normalize(nshell, b->d_l, b->d_nprim, b->d_poff, b->d_exps, b->d_coefs, b->d_ncoef, 0);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(0) != hipSuccess) {
+        hgp_basis_destroy(b);
+        return fail(HGP_E_DEVICE, "normalisation kernel failed");
+    }
+    *out = b;
+    return HGP_OK;
+}
+
+hgp_status hgp_basis_nbf(const hgp_basis *b, int32_t *nbf, int32_t *shell_offsets)
+{
+    if (!b || !nbf) return fail(HGP_E_INVALID, "NULL argument");
+    *nbf = b->nbf;
+    if (shell_offsets) std::memcpy(shell_offsets, b->foff.data(), sizeof(int32_t) * b->foff.size());
+    return HGP_OK;
+}
+
+hgp_status hgp_plan_destroy(hgp_plan *p)
+{
+    if (!p) return HGP_OK;
+    for (const PendingTiming &t : p->pending) {
+        hipEventSynchronize(t.stop);
+        p->event_pool.push_back(t.start);
+        p->event_pool.push_back(t.stop);
+    }
+    for (hipEvent_t e : p->event_pool) hipEventDestroy(e);
+    hipFree(p->d_pairs); hipFree(p->d_geo); hipFree(p->d_prims); hipFree(p->d_Q);
+    hipFree(p->d_Jacc); hipFree(p->d_Kacc); hipFree(p->d_scratch);
+    for (auto &c : p->lists) hipFree(c.d_q);
+    delete p;
+    return HGP_OK;
+}
+
+static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t s)
+{
+    const hgp_basis *b = p->b;
+    const int lmax = b->lmax;
+    const int npc = pair_class_of(lmax, lmax) + 1;
+    // ---- pair lists per pair class, sorted by primitive-pair count (descending)
+    std::vector<std::vector<PairInfo>> per(npc);
+    for (int i = 0; i < b->nshell; ++i)
+        for (int j = 0; j < b->nshell; ++j) {
+            const int li = b->l[i], lj = b->l[j];
+            if (li < lj || (li == lj && j > i)) continue;
+            PairInfo pi{};
+            pi.sh_a = i; pi.sh_b = j;
+            pi.nprim = b->nprim[i] * b->nprim[j];
+            pi.fa = b->foff[i]; pi.fb = b->foff[j];
+            pi.same = (i == j);
+            pi.cls = pair_class_of(li, lj);
+            per[pi.cls].push_back(pi);
+        }
+    std::vector<PairInfo> pairs;
+    p->pc_begin.assign(npc, 0);
+    p->pc_count.assign(npc, 0);
+    int prim_off = 0;
+    for (int c = 0; c < npc; ++c) {
+        std::stable_sort(per[c].begin(), per[c].end(), [](const PairInfo &x, const PairInfo &y) { return x.nprim > y.nprim; });
+        p->pc_begin[c] = (int)pairs.size();
+        p->pc_count[c] = (int)per[c].size();
+        for (auto &pi : per[c]) {
+            pi.prim_off = prim_off;
+            prim_off += pi.nprim;
+            pairs.push_back(pi);
+        }
+    }
+    p->npair = (int)pairs.size();
+    p->pairs = pairs;
+    const int64_t nbf = b->nbf;
+    const int64_t need = (int64_t)pairs.size() * (sizeof(PairInfo) + sizeof(PairGeo) + 2 * sizeof(double)) +
+                         (int64_t)prim_off * sizeof(PrimPair) + 2 * nbf * nbf * (int64_t)sizeof(double);
+    if (budget && (size_t)need > budget) return fail(HGP_E_OOM, "plan exceeds the HBM budget (pair data and accumulators)");
+    hgp_status st;
+    if ((st = upload(&p->d_pairs, pairs, &p->bytes)) || (st = dalloc(&p->d_geo, pairs.size(), &p->bytes)) ||
+        (st = dalloc(&p->d_prims, (size_t)prim_off, &p->bytes)) || (st = dalloc(&p->d_Q, pairs.size(), &p->bytes)) ||
+        (st = dalloc(&p->d_Jacc, (size_t)(nbf * nbf), &p->bytes)) || (st = dalloc(&p->d_Kacc, (size_t)(nbf * nbf), &p->bytes)))
+        return st;
+    const int64_t slots = staged_slots(lmax);
+    if (budget && (size_t)(p->bytes + slots * SCRATCH_LANES * (int64_t)sizeof(double)) > budget)
+        return fail(HGP_E_OOM, "plan exceeds the HBM budget (staged-tier scratch)");
+    if ((st = dalloc(&p->d_scratch, (size_t)(slots * SCRATCH_LANES), &p->bytes))) return st;
+    launch_pairs(p->npair, p->d_pairs, b->d_cen, b->d_poff, b->d_exps, b->d_ncoef, p->d_geo, p->d_prims, s);
+    HGP_HIP(hipGetLastError());
+    const double *boys = nullptr;
+    if ((st = boys_table(p->device, &boys))) return st;
+
+    // ---- Schwarz factors: diagonal quartets (p|p) of every pair class
+    if (p->npair > 0) {
+        double *qv = nullptr;
+        EriTask *tasks = nullptr;
+        if ((st = dalloc(&qv, pairs.size())) || (st = dalloc(&tasks, pairs.size()))) { hipFree(qv); return st; }
+        std::vector<EriTask> th(pairs.size());
+        for (int i = 0; i < p->npair; ++i) th[i] = EriTask{i, i, 0, 0, 0, 0, 0};
+        HGP_HIP(hipMemcpyAsync(tasks, th.data(), th.size() * sizeof(EriTask), hipMemcpyHostToDevice, s));
+        for (int c = 0; c < npc; ++c) {
+            if (!p->pc_count[c]) continue;
+            int la = 0;
+            while (pair_class_of(la + 1, 0) <= c) ++la;
+            const int lb = c - pair_class_of(la, 0);
+            const int ci = class_index(la, lb, la, lb);
+            if (ci < 0) { hipFree(qv); hipFree(tasks); return fail(HGP_E_UNSUPPORTED_L, "class kernel not built"); }
+            EriArgs a{};
+            a.tasks = tasks + p->pc_begin[c];
+            a.ntask = p->pc_count[c];
+            a.pairs = p->d_pairs; a.geo = p->d_geo; a.prims = p->d_prims; a.boys = boys;
+            a.out = qv + p->pc_begin[c];
+            a.mode = 1;
+            a.scratch = p->d_scratch;
+            a.scratch_lanes = SCRATCH_LANES;
+            g_class_table[ci].eri(a, s);
+        }
+        launch_store_q(p->npair, qv, p->d_geo, p->d_Q, s);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        hipFree(qv);
+        hipFree(tasks);
+        if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("Schwarz kernels: ") + hipGetErrorString(e));
+    }
+
+    // ---- screened unique-quartet lists per canonical class
+    int64_t *d_counts = nullptr, *d_total = nullptr;
+    int maxrows = 1;
+    for (int c = 0; c < npc; ++c) maxrows = std::max(maxrows, p->pc_count[c]);
+    if ((st = dalloc(&d_counts, (size_t)maxrows + 1)) || (st = dalloc(&d_total, 2))) { hipFree(d_counts); return st; }
+    std::vector<int64_t> rowprim(maxrows);
+    for (int bc = 0; bc < npc; ++bc) {
+        for (int kc = 0; kc <= bc; ++kc) {
+            const int nb = p->pc_count[bc], nk = p->pc_count[kc];
+            if (!nb || !nk) continue;
+            int la = 0, lc = 0;
+            while (pair_class_of(la + 1, 0) <= bc) ++la;
+            while (pair_class_of(lc + 1, 0) <= kc) ++lc;
+            const int lb = bc - pair_class_of(la, 0), ld = kc - pair_class_of(lc, 0);
+            const int ci = class_index(la, lb, lc, ld);
+            if (ci < 0) { hipFree(d_counts); hipFree(d_total); return fail(HGP_E_UNSUPPORTED_L, "class kernel not built"); }
+            const int sym = (bc == kc);
+            const int b0 = p->pc_begin[bc], k0 = p->pc_begin[kc];
+            p->total += sym ? (int64_t)nb * (nb + 1) / 2 : (int64_t)nb * nk;
+            const double t = tau > 0 ? tau : -1.0;
+            launch_screen_count(b0, nb, k0, nk, sym, p->d_Q, t, d_counts, s);
+            // primitive quartets per row for the FLOP accounting
+            std::vector<int64_t> cnt(nb);
+            HGP_HIP(hipMemcpyAsync(cnt.data(), d_counts, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s));
+            launch_scan(d_counts, nb, d_total, s);
+            int64_t total = 0;
+            HGP_HIP(hipMemcpyAsync(&total, d_total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            HGP_HIP(hipStreamSynchronize(s));
+            ClassList cl;
+            cl.cls = ci;
+            cl.nq = total;
+            if (budget && (size_t)(p->bytes + total * (int64_t)sizeof(int2)) > budget) {
+                hipFree(d_counts); hipFree(d_total);
+                return fail(HGP_E_OOM, "plan exceeds the HBM budget (quartet lists)");
+            }
+            if ((st = dalloc(&cl.d_q, (size_t)total, &p->bytes))) { hipFree(d_counts); hipFree(d_total); return st; }
+            if (total > 0) launch_screen_write(b0, nb, k0, nk, sym, p->d_Q, t, d_counts, cl.d_q, s);
+            HGP_HIP(hipGetLastError());
+            // primitive-quartet count: sum over kept quartets of nprim(bra) * nprim(ket)
+            if (total > 0) {
+                std::vector<int2> q((size_t)total);
+                HGP_HIP(hipMemcpyAsync(q.data(), cl.d_q, sizeof(int2) * total, hipMemcpyDeviceToHost, s));
+                HGP_HIP(hipStreamSynchronize(s));
+                int64_t np = 0;
+                for (const int2 &x : q) np += (int64_t)pairs[x.x].nprim * pairs[x.y].nprim;
+                cl.nprimq = np;
+            }
+            p->kept += total;
+            p->lists.push_back(cl);
+        }
+    }
+    hipFree(d_counts);
+    hipFree(d_total);
+    // heaviest classes first
+    std::stable_sort(p->lists.begin(), p->lists.end(), [](const ClassList &x, const ClassList &y) {
+        const double cx = x.nprimq * g_class_table[x.cls].vrr_flops + x.nq * g_class_table[x.cls].p2_flops;
+        const double cy = y.nprimq * g_class_table[y.cls].vrr_flops + y.nq * g_class_table[y.cls].p2_flops;
+        return cx > cy;
+    });
+    HGP_HIP(hipStreamSynchronize(s));
+    return HGP_OK;
+}
+
+hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t precision, size_t hbm_budget_bytes,
+                           void *hip_stream, hgp_plan **out)
+{
+    if (!out) return fail(HGP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!b) return fail(HGP_E_INVALID, "basis is NULL");
+    if (!(schwarz_tau >= 0.0) || !std::isfinite(schwarz_tau)) return fail(HGP_E_INVALID, "schwarz_tau must be >= 0");
+    if (precision != HGP_FP64) return fail(HGP_E_INVALID, "only HGP_FP64 is supported");
+    if (b->lmax > built_max_l()) return fail(HGP_E_UNSUPPORTED_L, "basis has l above the classes built into this library");
+    auto *p = new hgp_plan();
+    p->b = b;
+    p->device = b->device;
+    hgp_status st = plan_build(p, schwarz_tau, hbm_budget_bytes, (hipStream_t)hip_stream);
+    if (st != HGP_OK) {
+        hgp_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return HGP_OK;
+}
+
+hgp_status hgp_plan_stats(const hgp_plan *p, int64_t *kept, int64_t *total, int64_t *bytes)
+{
+    if (!p) return fail(HGP_E_INVALID, "plan is NULL");
+    if (kept) *kept = p->kept;
+    if (total) *total = p->total;
+    if (bytes) *bytes = p->bytes;
+    return HGP_OK;
+}
+
+int32_t hgp_plan_num_classes(const hgp_plan *p) { return p ? (int32_t)p->lists.size() : 0; }
+
+hgp_status hgp_plan_class_info(const hgp_plan *p, int32_t c, int32_t *ls, int64_t *nq, int64_t *npq, double *vf,
+                               double *pf)
+{
+    if (!p || c < 0 || c >= (int32_t)p->lists.size()) return fail(HGP_E_INVALID, "bad plan or class index");
+    const ClassList &cl = p->lists[c];
+    const ClassKernels &k = g_class_table[cl.cls];
+    if (ls) { ls[0] = k.la; ls[1] = k.lb; ls[2] = k.lc; ls[3] = k.ld; }
+    if (nq) *nq = cl.nq;
+    if (npq) *npq = cl.nprimq;
+    if (vf) *vf = k.vrr_flops;
+    if (pf) *pf = k.p2_flops;
+    return HGP_OK;
+}
+
+hgp_status hgp_plan_schwarz(const hgp_plan *p, double *Q)
+{
+    if (!p || !Q) return fail(HGP_E_INVALID, "NULL argument");
+    const int ns = p->b->nshell;
+    std::vector<double> q((size_t)p->npair);
+    if (p->npair) HGP_HIP(hipMemcpy(q.data(), p->d_Q, sizeof(double) * q.size(), hipMemcpyDeviceToHost));
+    std::fill(Q, Q + (size_t)ns * ns, 0.0);
+    for (int i = 0; i < p->npair; ++i) {
+        const PairInfo &pi = p->pairs[i];
+        Q[(size_t)pi.sh_a * ns + pi.sh_b] = Q[(size_t)pi.sh_b * ns + pi.sh_a] = q[i];
+    }
+    return HGP_OK;
+}
+
+hgp_status hgp_plan_set_timing(hgp_plan *p, int32_t enable)
+{
+    if (!p) return fail(HGP_E_INVALID, "plan is NULL");
+    hgp_status st = collect_timing(p);
+    if (st) return st;
+    for (ClassList &cl : p->lists) { cl.ms = 0.0; cl.launches = 0; }
+    p->timing = enable != 0;
+    return HGP_OK;
+}
+
+hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int64_t *launches, double *total_ms)
+{
+    if (!p || c < 0 || c >= (int32_t)p->lists.size()) return fail(HGP_E_INVALID, "bad plan or class index");
+    hgp_status st = collect_timing(p);
+    if (st) return st;
+    if (launches) *launches = p->lists[c].launches;
+    if (total_ms) *total_ms = p->lists[c].ms;
+    return HGP_OK;
+}
+
+hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_stream)
+{
+    if (!p) return fail(HGP_E_INVALID, "plan is NULL");
+    if (p->broken) return fail(HGP_E_STATE, "plan unusable after an earlier device failure");
+    const int n = p->b->nbf;
+    if (n == 0) return HGP_OK;                       // empty basis: J and K are 0 x 0
+    if (!D) return fail(HGP_E_INVALID, "D is NULL");
+    if (!J && !K) return fail(HGP_E_INVALID, "both J and K are NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t nn = (int64_t)n * n;
+    const double *boys = nullptr;
+    hgp_status st = boys_table(p->device, &boys);
+    if (st) return st;
+    if (J) launch_fill_zero(p->d_Jacc, nn, s);
+    if (K) launch_fill_zero(p->d_Kacc, nn, s);
+    for (size_t li = 0; li < p->lists.size(); ++li) {
+        const ClassList &cl = p->lists[li];
+        if (cl.nq == 0) continue;
+        const ClassKernels &k = g_class_table[cl.cls];
+        PendingTiming tm{(int)li, nullptr, nullptr};
+        if (p->timing) {
+            tm.start = take_event(p);
+            tm.stop = take_event(p);
+            if (!tm.start || !tm.stop) return fail(HGP_E_DEVICE, "hipEventCreate failed");
+            HGP_HIP(hipEventRecord(tm.start, s));
+        }
+        JKArgs a{};
+        a.pairs = p->d_pairs; a.geo = p->d_geo; a.prims = p->d_prims; a.boys = boys;
+        a.D = D; a.J = p->d_Jacc; a.K = p->d_Kacc; a.nbf = n;
+        a.want_j = J != nullptr; a.want_k = K != nullptr;
+        a.scratch = p->d_scratch;
+        a.scratch_lanes = SCRATCH_LANES;
+        const int64_t chunk = (int64_t)k.block * 1048576;
+        for (int64_t q0 = 0; q0 < cl.nq; q0 += chunk) {
+            a.quartets = cl.d_q + q0;
+            a.nq = std::min(chunk, cl.nq - q0);
+            k.jk(a, s);
+        }
+        if (p->timing) {
+            HGP_HIP(hipEventRecord(tm.stop, s));
+            p->pending.push_back(tm);
+        }
+    }
+    if (J) launch_symmetrize(p->d_Jacc, J, n, s);
+    if (K) launch_symmetrize(p->d_Kacc, K, n, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        p->broken = true;
+        return fail(HGP_E_DEVICE, std::string("J/K launch failed: ") + hipGetErrorString(e));
+    }
+    return HGP_OK;
+}
+
+hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartets, const int64_t *offsets,
+                                  double *out, void *hip_stream)
+{
+    if (!b) return fail(HGP_E_INVALID, "basis is NULL");
+    if (nq < 0) return fail(HGP_E_INVALID, "nq < 0");
+    if (nq == 0) return HGP_OK;
+    if (!quartets || !offsets || !out) return fail(HGP_E_INVALID, "NULL argument");
+    if (nq > (int64_t)1 << 28) return fail(HGP_E_INVALID, "too many quartets in one call");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const double *boys = nullptr;
+    hgp_status st = boys_table(b->device, &boys);
+    if (st) return st;
+    std::vector<PairInfo> pairs((size_t)(2 * nq));
+    std::vector<std::vector<EriTask>> per(g_num_classes);
+    int prim_off = 0;
+    for (int64_t q = 0; q < nq; ++q) {
+        int sh[4];
+        for (int r = 0; r < 4; ++r) {
+            sh[r] = quartets[4 * q + r];
+            if (sh[r] < 0 || sh[r] >= b->nshell) return fail(HGP_E_INVALID, "shell index out of range");
+        }
+        if (offsets[q] < 0) return fail(HGP_E_INVALID, "negative offset");
+        int n[4], stride[4];
+        for (int r = 0; r < 4; ++r) n[r] = nsph(b->l[sh[r]]);
+        stride[3] = 1; stride[2] = n[3]; stride[1] = n[2] * n[3]; stride[0] = n[1] * n[2] * n[3];
+        int pos[4] = {0, 1, 2, 3};   // canonical role -> requested position
+        if (b->l[sh[0]] < b->l[sh[1]]) std::swap(pos[0], pos[1]);
+        if (b->l[sh[2]] < b->l[sh[3]]) std::swap(pos[2], pos[3]);
+        const int cb = pair_class_of(b->l[sh[pos[0]]], b->l[sh[pos[1]]]);
+        const int ck = pair_class_of(b->l[sh[pos[2]]], b->l[sh[pos[3]]]);
+        if (cb < ck) { std::swap(pos[0], pos[2]); std::swap(pos[1], pos[3]); }
+        int ls[4];
+        for (int r = 0; r < 4; ++r) ls[r] = b->l[sh[pos[r]]];
+        const int ci = class_index(ls[0], ls[1], ls[2], ls[3]);
+        if (ci < 0) return fail(HGP_E_UNSUPPORTED_L, "class kernel not built");
+        for (int side = 0; side < 2; ++side) {
+            PairInfo &pi = pairs[(size_t)(2 * q + side)];
+            pi.sh_a = sh[pos[2 * side]];
+            pi.sh_b = sh[pos[2 * side + 1]];
+            pi.prim_off = prim_off;
+            pi.nprim = b->nprim[pi.sh_a] * b->nprim[pi.sh_b];
+            pi.fa = b->foff[pi.sh_a]; pi.fb = b->foff[pi.sh_b];
+            pi.same = pi.sh_a == pi.sh_b;
+            pi.cls = pair_class_of(ls[2 * side], ls[2 * side + 1]);
+            prim_off += pi.nprim;
+        }
+        per[ci].push_back(EriTask{(int32_t)(2 * q), (int32_t)(2 * q + 1), offsets[q], stride[pos[0]], stride[pos[1]],
+                                  stride[pos[2]], stride[pos[3]]});
+    }
+    PairInfo *d_pairs = nullptr;
+    PairGeo *d_geo = nullptr;
+    PrimPair *d_prims = nullptr;
+    EriTask *d_tasks = nullptr;
+    double *d_scr = nullptr;
+    int64_t slots = 0;
+    for (int c = 0; c < g_num_classes; ++c)
+        if (!per[c].empty() && g_class_table[c].tier == 1) slots = std::max<int64_t>(slots, g_class_table[c].scratch_slots);
+    std::vector<EriTask> all;
+    std::vector<std::pair<int, int64_t>> ranges;
+    for (int c = 0; c < g_num_classes; ++c)
+        if (!per[c].empty()) {
+            ranges.push_back({c, (int64_t)all.size()});
+            all.insert(all.end(), per[c].begin(), per[c].end());
+        }
+    auto cleanup = [&]() { hipFree(d_pairs); hipFree(d_geo); hipFree(d_prims); hipFree(d_tasks); hipFree(d_scr); };
+    if ((st = upload(&d_pairs, pairs)) || (st = dalloc(&d_geo, pairs.size())) || (st = dalloc(&d_prims, (size_t)prim_off)) ||
+        (st = upload(&d_tasks, all)) || (st = dalloc(&d_scr, (size_t)(slots * SCRATCH_LANES)))) {
+        cleanup();
+        return st;
+    }
+    launch_pairs((int)pairs.size(), d_pairs, b->d_cen, b->d_poff, b->d_exps, b->d_ncoef, d_geo, d_prims, s);
+    for (size_t r = 0; r < ranges.size(); ++r) {
+        const int c = ranges[r].first;
+        const int64_t begin = ranges[r].second;
+        const int64_t end = (r + 1 < ranges.size()) ? ranges[r + 1].second : (int64_t)all.size();
+        EriArgs a{};
+        a.tasks = d_tasks + begin;
+        a.ntask = end - begin;
+        a.pairs = d_pairs; a.geo = d_geo; a.prims = d_prims; a.boys = boys;
+        a.out = out;
+        a.mode = 0;
+        a.scratch = d_scr;
+        a.scratch_lanes = SCRATCH_LANES;
+        g_class_table[c].eri(a, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cleanup();
+    if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("integral kernels: ") + hipGetErrorString(e));
+    return HGP_OK;
+}
+
+hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64_t n, const double *centers,
+                                 const double *exps, double *out, int32_t precision, void *hip_stream)
+{
+    const int lin[4] = {la, lb, lc, ld};
+    for (int r = 0; r < 4; ++r) {
+        if (lin[r] < 0) return fail(HGP_E_INVALID, "negative l");
+        if (lin[r] > 4) return fail(HGP_E_UNSUPPORTED_L, "l > 4");
+    }
+    if (precision != HGP_FP64) return fail(HGP_E_INVALID, "only HGP_FP64 is supported");
+    if (n < 0) return fail(HGP_E_INVALID, "n < 0");
+    if (n == 0) return HGP_OK;
+    if (!centers || !exps || !out) return fail(HGP_E_INVALID, "NULL argument");
+    if (n > (int64_t)1 << 30) return fail(HGP_E_INVALID, "n too large for one call");
+    int pos[4] = {0, 1, 2, 3};
+    if (lin[0] < lin[1]) std::swap(pos[0], pos[1]);
+    if (lin[2] < lin[3]) std::swap(pos[2], pos[3]);
+    if (pair_class_of(lin[pos[0]], lin[pos[1]]) < pair_class_of(lin[pos[2]], lin[pos[3]])) {
+        std::swap(pos[0], pos[2]);
+        std::swap(pos[1], pos[3]);
+    }
+    int ls[4], nn[4], stride[4], cs[4];
+    for (int r = 0; r < 4; ++r) { ls[r] = lin[pos[r]]; nn[r] = nsph(lin[r]); }
+    const int ci = class_index(ls[0], ls[1], ls[2], ls[3]);
+    if (ci < 0) return fail(HGP_E_UNSUPPORTED_L, "class kernel not built into this library");
+    stride[3] = 1; stride[2] = nn[3]; stride[1] = nn[2] * nn[3]; stride[0] = nn[1] * nn[2] * nn[3];
+    for (int r = 0; r < 4; ++r) cs[r] = stride[pos[r]];
+    const int64_t blk = (int64_t)nn[0] * nn[1] * nn[2] * nn[3];
+    hipStream_t s = (hipStream_t)hip_stream;
+    int dev = 0;
+    HGP_HIP(hipGetDevice(&dev));
+    const double *boys = nullptr;
+    hgp_status st = boys_table(dev, &boys);
+    if (st) return st;
+    PairInfo *d_pairs = nullptr;
+    PairGeo *d_geo = nullptr;
+    PrimPair *d_prims = nullptr;
+    EriTask *d_tasks = nullptr;
+    double *d_scr = nullptr;
+    const int64_t slots = g_class_table[ci].tier == 1 ? g_class_table[ci].scratch_slots : 0;
+    hipError_t e = hipMallocAsync((void **)&d_pairs, sizeof(PairInfo) * 2 * n, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&d_geo, sizeof(PairGeo) * 2 * n, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&d_prims, sizeof(PrimPair) * 2 * n, s);
+    if (e == hipSuccess) e = hipMallocAsync((void **)&d_tasks, sizeof(EriTask) * n, s);
+    if (e == hipSuccess && slots) e = hipMallocAsync((void **)&d_scr, sizeof(double) * slots * SCRATCH_LANES, s);
+    if (e != hipSuccess) {
+        if (d_pairs) hipFreeAsync(d_pairs, s);
+        if (d_geo) hipFreeAsync(d_geo, s);
+        if (d_prims) hipFreeAsync(d_prims, s);
+        if (d_tasks) hipFreeAsync(d_tasks, s);
+        return fail(HGP_E_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    }
+    launch_prim_quartet_pairs(n, centers, exps, ls, pos, cs, blk, d_pairs, d_geo, d_prims, d_tasks, s);
+    EriArgs a{};
+    a.tasks = d_tasks; a.ntask = n; a.pairs = d_pairs; a.geo = d_geo; a.prims = d_prims; a.boys = boys;
+    a.out = out; a.mode = 0;
+    a.scratch = d_scr;
+    a.scratch_lanes = SCRATCH_LANES;
+    g_class_table[ci].eri(a, s);
+    e = hipGetLastError();
+    if (d_scr) hipFreeAsync(d_scr, s);
+    hipFreeAsync(d_pairs, s);
+    hipFreeAsync(d_geo, s);
+    hipFreeAsync(d_prims, s);
+    hipFreeAsync(d_tasks, s);
+    if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("microbench launch: ") + hipGetErrorString(e));
+    return HGP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Data layout shared by the host runtime and the generated class kernels.
+// Everything lives in HBM; sizes are per plan.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hgp {
+
+// One shell pair (a, b) with l_a >= l_b, in the role of a bra or a ket.
+// 32 bytes.  prim_off/nprim index the primitive-pair records.
+struct PairInfo {
+    int32_t sh_a, sh_b;     // shell indices
+    int32_t prim_off;       // first primitive-pair record
+    int32_t nprim;          // number of primitive pairs (n_a * n_b)
+    int32_t fa, fb;         // first spherical function of shell a and b
+    int32_t same;           // 1 if sh_a == sh_b
+    int32_t cls;            // pair class index
+};
+
+// Per-pair geometry, 64 bytes: centre A, A - B, Schwarz factor Q.
+struct PairGeo {
+    double ax, ay, az;
+    double abx, aby, abz;
+    double q;
+    double pad;
+};
+
+// Per primitive pair, 64 bytes (one half cache line):
+// zeta = a + b, 1/(2 zeta), P = (a A + b B)/zeta and
+// K = c_a c_b exp(-a b |AB|^2 / zeta) * sqrt(2) pi^(5/4) / zeta, so that the
+// base integral of a primitive quartet is K_ab K_cd / sqrt(zeta + eta) * F_m(T).
+struct PrimPair {
+    double zeta, o2z;
+    double px, py, pz;
+    double k;
+    double pad0, pad1;
+};
+
+// Integrals-out work item: canonical (bra, ket) pair indices and where each
+// canonical element (m, n, l, s) lands: out[off + m*s0 + n*s1 + l*s2 + s*s3].
+struct EriTask {
+    int32_t bra, ket;
+    int64_t off;
+    int32_t s0, s1, s2, s3;
+};
+
+struct JKArgs {
+    const int2 *quartets;   // (bra pair, ket pair) per unique quartet of the class
+    int64_t nq;
+    const PairInfo *pairs;
+    const PairGeo *geo;
+    const PrimPair *prims;
+    const double *boys;     // Boys table
+    const double *D;        // N x N, symmetric
+    double *J;              // unsymmetrised accumulators, N x N
+    double *K;
+    int32_t nbf;
+    int32_t want_j, want_k;
+    double *scratch;        // staged classes: slot k of lane t at scratch[k * lanes + t]
+    int64_t scratch_lanes;  // lanes the scratch buffer holds (bounds the staged grid)
+};
+
+struct EriArgs {
+    const EriTask *tasks;
+    int64_t ntask;
+    const PairInfo *pairs;
+    const PairGeo *geo;
+    const PrimPair *prims;
+    const double *boys;
+    double *out;
+    int32_t mode;           // 0: write blocks, 1: Schwarz factor of a diagonal quartet into out[task]
+    double *scratch;
+    int64_t scratch_lanes;
+};
+
+// Boys table: F_m(T_k) for T_k = k * BOYS_STEP, k = 0 .. BOYS_NPTS-1, m = 0 .. BOYS_NORD-1,
+// stored [k][m] so that the orders one evaluation reads are contiguous.
+constexpr double BOYS_STEP = 0.05;
+constexpr double BOYS_INV_STEP = 20.0;
+constexpr double BOYS_TMAX = 36.0;
+constexpr int BOYS_NPTS = 722;
+constexpr int BOYS_NORD = 24;      // orders needed: L + 7 <= 23 for L <= 16
+
+// Lanes of the staged tier's scratch buffer: 256 CUs x 4 SIMDs x 2 waves x 64
+// lanes, enough for every wave the staged kernels can keep resident.
+constexpr int64_t SCRATCH_LANES = 131072;
+
+// Launchers take the number of work items and pick their own grid: register
+// classes one lane per item, staged classes a grid-stride loop over at most
+// scratch_lanes lanes.
+typedef void (*launch_jk_fn)(const JKArgs &, hipStream_t);
+typedef void (*launch_eri_fn)(const EriArgs &, hipStream_t);
+
+struct ClassKernels {
+    int la, lb, lc, ld;
+    int tier;               // 0 register, 1 staged (HBM scratch)
+    launch_jk_fn jk;
+    launch_eri_fn eri;
+    int block;              // threads per block
+    double vrr_flops;       // per primitive quartet (generator count)
+    double p2_flops;        // per contracted quartet: HRR + transform
+    int n_hrr;
+    int peak_live;
+    int scratch_slots;      // doubles of scratch per lane (0 for the register tier)
+    int chunks;             // Phase-1 target chunks
+};
+
+}  // namespace hgp

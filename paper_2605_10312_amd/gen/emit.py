@@ -1,0 +1,324 @@
+"""HIP source emission for one canonical quartet class (la lb|lc ld).
+
+Each class becomes one translation unit holding
+  - an inlined quartet evaluator: the primitive loops with the Boys function
+    and the straight-line VRR in the chosen order, the contraction into the
+    accumulator bank H, then the Phase-2 HRR + stepwise spherical transform
+    (Alg. 2's structure, Sec. III-C.1);
+  - a J/K kernel, one lane per unique shell quartet, with the digestion into
+    the unsymmetrised J', K' fused after Phase 2 (FP64 global atomics);
+  - an integrals-out kernel (blocks written with caller strides, or the
+    Schwarz factor of a diagonal quartet);
+  - host launchers with C linkage for the runtime's class table.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+from . import phase2 as p2mod
+from . import vrr as vrrmod
+from .cart import comps, levels
+from .sph import tmatrix
+
+XYZ = "xyz"
+
+
+@dataclasses.dataclass
+class ClassMeta:
+    ls: tuple
+    tag: str
+    tier: int
+    block: int
+    vrr_nodes: int
+    vrr_flops: int
+    n_hrr: int
+    peak_live: int
+    scheduler: str
+    p2_flops: int
+    n_out: int
+    rule: str
+    scratch_slots: int = 0
+    chunks: int = 1
+    recompute: float = 1.0
+    cap: int = 0
+    waves: int = 0
+
+
+def tag_of(ls):
+    return "".join(str(x) for x in ls)
+
+
+def _fmt(c: float) -> str:
+    r = repr(float(c))
+    return r if ("." in r or "e" in r) else r + ".0"
+
+
+def _vrr_lines(g, order, hnames, indent):
+    """Straight-line VRR in `order`; targets are added to their accumulators."""
+    lines = []
+    tpos = {tid: k for k, tid in enumerate(g.target_ids)}
+    used = set()
+    for v in order:
+        nd = g.nodes[v]
+        name = f"v{v}"
+        if nd.kind == "base":
+            expr = f"base * F[{nd.key[2]}]"
+        else:
+            p1, p2, p3, p4, p5 = nd.parents
+            ax = XYZ[nd.axis]
+            if nd.kind == "bra":
+                c1, c2, o2, rr = f"PA{ax}", f"WP{ax}", "o2z", "rz"
+            else:
+                c1, c2, o2, rr = f"QC{ax}", f"WQ{ax}", "o2e", "re"
+            used.update([c1, c2])
+            expr = f"fma({c1}, v{p1}, {c2} * v{p2})"
+            if nd.k_same:
+                k = "" if nd.k_same == 1 else f"{nd.k_same}.0 * "
+                expr = f"fma({k}{o2}, fma(-{rr}, v{p4}, v{p3}), {expr})"
+                used.update([o2, rr])
+            if nd.k_cross:
+                k = "" if nd.k_cross == 1 else f"{nd.k_cross}.0 * "
+                expr = f"fma({k}o2ze, v{p5}, {expr})"
+                used.add("o2ze")
+        lines.append(f"{indent}const double {name} = {expr};")
+        if v in tpos:
+            lines.append(f"{indent}{hnames[tpos[v]]} += {name};")
+    return lines, used
+
+
+def _p2_lines(p2, indent):
+    lines = []
+    for op in p2.ops:
+        if op[1] == "hrr":
+            d, _, hi, lo, coef = op
+            lines.append(f"{indent}const double {d} = fma({coef}, {lo}, {hi});")
+        else:
+            d, _, terms = op
+            expr = f"{_fmt(terms[0][0])} * {terms[0][1]}"
+            for c, s in terms[1:]:
+                expr = f"fma({_fmt(c)}, {s}, {expr})"
+            lines.append(f"{indent}const double {d} = {expr};")
+    return lines
+
+
+def loop_prelude(L, ind):
+    """Primitive loops up to the VRR: pair combination, Boys F_0..F_L and the
+    VRR coefficients (Alg. 2's GaussianPairs and Boys steps)."""
+    i2 = ind + "    "
+    i3 = ind + "        "
+    return [
+        f"{ind}const double Ax = gb.ax, Ay = gb.ay, Az = gb.az;",
+        f"{ind}const double Cx = gk.ax, Cy = gk.ay, Cz = gk.az;",
+        f"{ind}const PrimPair *__restrict__ pbp = prims + pb.prim_off;",
+        f"{ind}const PrimPair *__restrict__ pkp = prims + pk.prim_off;",
+        f"{ind}const int nbp = pb.nprim, nkp = pk.nprim;",
+        f"{ind}for (int ip = 0; ip < nbp; ++ip) {{",
+        f"{i2}const PrimPair bp = pbp[ip];",
+        f"{i2}const double zeta = bp.zeta, o2z = bp.o2z, Px = bp.px, Py = bp.py, Pz = bp.pz, Kb = bp.k;",
+        f"{i2}const double PAx = Px - Ax, PAy = Py - Ay, PAz = Pz - Az;",
+        f"{i2}for (int jp = 0; jp < nkp; ++jp) {{",
+        f"{i3}const PrimPair kp = pkp[jp];",
+        f"{i3}const double eta = kp.zeta, o2e = kp.o2z, Qx = kp.px, Qy = kp.py, Qz = kp.pz;",
+        f"{i3}const double QCx = Qx - Cx, QCy = Qy - Cy, QCz = Qz - Cz;",
+        f"{i3}const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;",
+        f"{i3}const double ize = 1.0 / (zeta + eta);",
+        f"{i3}const double rz = eta * ize, re = zeta * ize, o2ze = 0.5 * ize;",
+        f"{i3}const double T = zeta * rz * (PQx * PQx + PQy * PQy + PQz * PQz);",
+        f"{i3}double F[{L + 1}];",
+        f"{i3}boys_fm<{L}>(T, boys, F);",
+        f"{i3}const double base = Kb * kp.k * sqrt(ize);",
+        f"{i3}const double WPx = -rz * PQx, WPy = -rz * PQy, WPz = -rz * PQz;",
+        f"{i3}const double WQx = re * PQx, WQy = re * PQy, WQz = re * PQz;",
+        f"{i3}(void)o2z; (void)o2e; (void)o2ze; (void)PAx; (void)PAy; (void)PAz; (void)QCx; (void)QCy; (void)QCz;",
+        f"{i3}(void)WPx; (void)WPy; (void)WPz; (void)WQx; (void)WQy; (void)WQz; (void)re;",
+    ]
+
+
+def loop_close(ind):
+    return [f"{ind}    }}", f"{ind}}}"]
+
+
+def waves_attr(waves):
+    return f" __attribute__((amdgpu_waves_per_eu({waves}, {waves})))" if waves else ""
+
+
+def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves=0):
+    ls = (la, lb, lc, ld)
+    tag = tag_of(ls)
+    L = sum(ls)
+    g = vrrmod.VRRGraph(la, lb, lc, ld, rule=rule)
+    sched, pl, order = vrrmod.best_order(g) if schedulers is None else vrrmod.best_order(g, schedulers)
+    hnames = [f"h{k}" for k in range(len(g.targets))]
+    hmap = {t: hnames[k] for k, t in enumerate(g.targets)}
+    p2 = p2mod.Phase2(la, lb, lc, ld, hname=lambda e, f: hmap[(e, f)])
+    na, nb, nc, nd = (len(tmatrix(l)) for l in ls)
+    nout = na * nb * nc * nd
+    I = {k: v for k, v in p2.out.items()}
+
+    vlines, used = _vrr_lines(g, order, hnames, "            ")
+    out = []
+    w = out.append
+    w(f"// Generated: class ({la}{lb}|{lc}{ld}), axis rule {rule}, VRR order '{sched}' (PeakLive {pl}),")
+    w(f"// {len(g.nodes)} VRR nodes, {g.flops()} VRR FLOP per primitive quartet, N_hrr {len(g.targets)},")
+    w(f"// Phase-2 {p2.flops} FLOP per contracted quartet, {nout} spherical integrals.")
+    w('#include "hgp_device.h"')
+    w("")
+    w("namespace hgp {")
+    w("namespace {")
+    w("")
+    w(f"__device__ __forceinline__ void quartet_{tag}(const PairInfo &pb, const PairGeo &gb, const PairInfo &pk,")
+    w(f"                                              const PairGeo &gk, const PrimPair *__restrict__ prims,")
+    w(f"                                              const double *__restrict__ boys, double *__restrict__ I)")
+    w("{")
+    for k in range(0, len(hnames), 8):
+        w("    double " + ", ".join(f"{h} = 0.0" for h in hnames[k:k + 8]) + ";")
+    out.extend(loop_prelude(L, "    "))
+    out.extend(vlines)
+    out.extend(loop_close("    "))
+    w("    const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz;")
+    w("    const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
+    w("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz;")
+    out.extend(_p2_lines(p2, "    "))
+    for mu in range(na):
+        for nu in range(nb):
+            for lam in range(nc):
+                for sig in range(nd):
+                    k = ((mu * nb + nu) * nc + lam) * nd + sig
+                    w(f"    I[{k}] = {I[(mu, nu, lam, sig)]};")
+    w("}")
+    w("")
+    # ---------------------------------------------------------------- J/K kernel
+    def idx(mu, nu, lam, sig):
+        return ((mu * nb + nu) * nc + lam) * nd + sig
+
+    w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void jk_{tag}(JKArgs a)")
+    w("{")
+    w(f"    const int64_t q = (int64_t)blockIdx.x * {block} + threadIdx.x;")
+    w("    if (q >= a.nq) return;")
+    w("    const int2 pq = a.quartets[q];")
+    w("    const PairInfo pb = a.pairs[pq.x], pk = a.pairs[pq.y];")
+    w("    const PairGeo gb = a.geo[pq.x], gk = a.geo[pq.y];")
+    w(f"    double I[{nout}];")
+    w(f"    quartet_{tag}(pb, gb, pk, gk, a.prims, a.boys, I);")
+    w("    const double *__restrict__ D = a.D;")
+    w("    const int N = a.nbf;")
+    w("    const int fa = pb.fa, fb = pb.fb, fc = pk.fa, fd = pk.fb;")
+    w("    const double s = (pb.same ? 0.5 : 1.0) * (pk.same ? 0.5 : 1.0) * (pq.x == pq.y ? 0.5 : 1.0);")
+    w("    if (a.want_j) {")
+    w("        const double s2 = 2.0 * s;")
+    for lam in range(nc):
+        for sig in range(nd):
+            w(f"        const double dcd_{lam}_{sig} = D[(fc + {lam}) * N + fd + {sig}];")
+    for mu in range(na):
+        for nu in range(nb):
+            terms = [(f"I[{idx(mu, nu, lam, sig)}]", f"dcd_{lam}_{sig}") for lam in range(nc) for sig in range(nd)]
+            expr = f"{terms[0][0]} * {terms[0][1]}"
+            for x, y in terms[1:]:
+                expr = f"fma({x}, {y}, {expr})"
+            w(f"        atomicAdd(a.J + (fa + {mu}) * N + fb + {nu}, s2 * ({expr}));")
+    for mu in range(na):
+        for nu in range(nb):
+            w(f"        const double dab_{mu}_{nu} = D[(fa + {mu}) * N + fb + {nu}];")
+    for lam in range(nc):
+        for sig in range(nd):
+            terms = [(f"I[{idx(mu, nu, lam, sig)}]", f"dab_{mu}_{nu}") for mu in range(na) for nu in range(nb)]
+            expr = f"{terms[0][0]} * {terms[0][1]}"
+            for x, y in terms[1:]:
+                expr = f"fma({x}, {y}, {expr})"
+            w(f"        atomicAdd(a.J + (fc + {lam}) * N + fd + {sig}, s2 * ({expr}));")
+    w("    }")
+    w("    if (a.want_k) {")
+    # K'[a,c] += s sum_{n,s} I D[b,d]; K'[b,c] += s sum_{m,s} I D[a,d]
+    # K'[a,d] += s sum_{n,l} I D[b,c]; K'[b,d] += s sum_{m,l} I D[a,c]
+    blocks = [("bd", "fb", "fd", nb, nd), ("ad", "fa", "fd", na, nd), ("bc", "fb", "fc", nb, nc), ("ac", "fa", "fc", na, nc)]
+    for nm, r0, c0, nr, ncol in blocks:
+        for i in range(nr):
+            for j in range(ncol):
+                w(f"        const double d{nm}_{i}_{j} = D[({r0} + {i}) * N + {c0} + {j}];")
+
+    def ksum(outer, inner_terms, target):
+        for o in outer:
+            terms = inner_terms(*o)
+            expr = f"{terms[0][0]} * {terms[0][1]}"
+            for x, y in terms[1:]:
+                expr = f"fma({x}, {y}, {expr})"
+            w(f"        atomicAdd(a.K + {target(*o)}, s * ({expr}));")
+
+    ksum([(mu, lam) for mu in range(na) for lam in range(nc)],
+         lambda mu, lam: [(f"I[{idx(mu, nu, lam, sig)}]", f"dbd_{nu}_{sig}") for nu in range(nb) for sig in range(nd)],
+         lambda mu, lam: f"(fa + {mu}) * N + fc + {lam}")
+    ksum([(nu, lam) for nu in range(nb) for lam in range(nc)],
+         lambda nu, lam: [(f"I[{idx(mu, nu, lam, sig)}]", f"dad_{mu}_{sig}") for mu in range(na) for sig in range(nd)],
+         lambda nu, lam: f"(fb + {nu}) * N + fc + {lam}")
+    ksum([(mu, sig) for mu in range(na) for sig in range(nd)],
+         lambda mu, sig: [(f"I[{idx(mu, nu, lam, sig)}]", f"dbc_{nu}_{lam}") for nu in range(nb) for lam in range(nc)],
+         lambda mu, sig: f"(fa + {mu}) * N + fd + {sig}")
+    ksum([(nu, sig) for nu in range(nb) for sig in range(nd)],
+         lambda nu, sig: [(f"I[{idx(mu, nu, lam, sig)}]", f"dac_{mu}_{lam}") for mu in range(na) for lam in range(nc)],
+         lambda nu, sig: f"(fb + {nu}) * N + fd + {sig}")
+    w("    }")
+    w("}")
+    w("")
+    # ---------------------------------------------------------------- integrals-out kernel
+    diag_class = (la, lb) == (lc, ld)
+    w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void eri_{tag}(EriArgs a)")
+    w("{")
+    w(f"    const int64_t q = (int64_t)blockIdx.x * {block} + threadIdx.x;")
+    w("    if (q >= a.ntask) return;")
+    w("    const EriTask t = a.tasks[q];")
+    w("    const PairInfo pb = a.pairs[t.bra], pk = a.pairs[t.ket];")
+    w("    const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];")
+    w(f"    double I[{nout}];")
+    w(f"    quartet_{tag}(pb, gb, pk, gk, a.prims, a.boys, I);")
+    if diag_class:
+        w("    if (a.mode == 1) {")
+        w("        double m = 0.0;")
+        for mu in range(na):
+            for nu in range(nb):
+                w(f"        m = fmax(m, fabs(I[{idx(mu, nu, mu, nu)}]));")
+        w("        a.out[q] = sqrt(m);")
+        w("        return;")
+        w("    }")
+    w("    double *__restrict__ o = a.out + t.off;")
+    for mu in range(na):
+        for nu in range(nb):
+            for lam in range(nc):
+                for sig in range(nd):
+                    w(f"    o[{mu} * t.s0 + {nu} * t.s1 + {lam} * t.s2 + {sig} * t.s3] = I[{idx(mu, nu, lam, sig)}];")
+    w("}")
+    w("")
+    w("}  // namespace")
+    w("")
+    w(f"void launch_jk_{tag}(const JKArgs &a, hipStream_t s)")
+    w("{")
+    w(f"    hipLaunchKernelGGL(jk_{tag}, dim3((unsigned)((a.nq + {block - 1}) / {block})), dim3({block}), 0, s, a);")
+    w("}")
+    w(f"void launch_eri_{tag}(const EriArgs &a, hipStream_t s)")
+    w("{")
+    w(f"    hipLaunchKernelGGL(eri_{tag}, dim3((unsigned)((a.ntask + {block - 1}) / {block})), dim3({block}), 0, s, a);")
+    w("}")
+    w("")
+    w("}  // namespace hgp")
+    meta = ClassMeta(ls, tag, 0, block, len(g.nodes), g.flops(), len(g.targets), pl, sched, p2.flops, nout, rule,
+                     waves=waves)
+    return "\n".join(out) + "\n", meta
+
+
+def emit_table(metas):
+    out = ['// Generated: the class table the runtime dispatches on (host code only).', '#include "hgp_types.h"', "",
+           "#if !defined(__HIP_DEVICE_COMPILE__)", "namespace hgp {"]
+    for m in metas:
+        out.append(f"void launch_jk_{m.tag}(const JKArgs &, hipStream_t);")
+        out.append(f"void launch_eri_{m.tag}(const EriArgs &, hipStream_t);")
+    out.append("")
+    out.append("extern const ClassKernels g_class_table[] = {")
+    for m in metas:
+        la, lb, lc, ld = m.ls
+        out.append(f"    {{{la}, {lb}, {lc}, {ld}, {m.tier}, launch_jk_{m.tag}, launch_eri_{m.tag}, {m.block}, "
+                   f"{m.vrr_flops}.0, {m.p2_flops}.0, {m.n_hrr}, {m.peak_live}, {m.scratch_slots}, {m.chunks}}},")
+    out.append("};")
+    out.append(f"extern const int g_num_classes = {len(metas)};")
+    out.append("")
+    out.append("}  // namespace hgp")
+    out.append("#endif")
+    return "\n".join(out) + "\n"

@@ -1,0 +1,329 @@
+"""HIP emission of the staged (HBM-scratch) tier for classes whose accumulator
+bank and VRR frontier do not fit the register file together (Sec. III-C's
+Regime II; the paper's buffered Tier 2, Sec. III-C.2, redesigned for gfx950).
+
+Structure of one lane's work on one shell quartet (grid-stride loop, one
+wavefront per block, a lane-interleaved scratch buffer in HBM: slot k of lane
+t lives at scratch[k * lanes + t], so every access is coalesced):
+
+  Phase 1, chunk by chunk: the targets [e0|f0] are split by bra component e
+    into chunks of at most `cap` accumulators; each chunk runs the primitive
+    loops over only its own VRR subgraph (the sub-DAG reaching its targets),
+    keeps its accumulators in registers and stores them once to scratch.
+  Phase 2, bra stage, one ket component f at a time: load H[:, f], bra HRR,
+    T(la) then T(lb), store the spherical (m n|f) values over H[:, f]'s slots.
+  Phase 2, ket stage, one (m, n) at a time: load (m n|f) for all f, ket HRR,
+    T(lc) then T(ld), store the final integrals to their own slots.
+  Digestion (J/K kernel): the six contractions of the 8-fold symmetric
+    Scatter, each streaming the integrals back from scratch, FP64 atomics.
+
+Compared with a single register-resident evaluation, chunking recomputes the
+VRR nodes shared between chunks (the generator reports the factor); in
+exchange every stage runs without compiler spills.
+"""
+from __future__ import annotations
+
+from . import phase2 as p2mod
+from . import vrr as vrrmod
+from .cart import levels
+from .emit import ClassMeta, XYZ, _fmt, loop_close, loop_prelude, tag_of, waves_attr
+
+
+def chunk_targets(g, cap):
+    """Group the targets by bra component e (in level order), packing whole
+    e rows (all f) into chunks of at most cap accumulators."""
+    la, lb, lc, ld = g.ls
+    nf = len(levels(lc, lc + ld))
+    per_row = max(1, cap // nf)
+    es = list(levels(la, la + lb))
+    rows = [es[i:i + per_row] for i in range(0, len(es), per_row)]
+    out = []
+    for r in rows:
+        rs = set(r)
+        out.append([t for t in g.target_ids if g.nodes[t].key[0] in rs])
+    return out
+
+
+def subgraph(g, tids):
+    seen = set()
+    st = list(tids)
+    while st:
+        v = st.pop()
+        if v in seen:
+            continue
+        seen.add(v)
+        for p in g.nodes[v].parents:
+            if p is not None:
+                st.append(p)
+    return seen
+
+
+def node_flops(g, nodes, ntarg):
+    n = 0
+    for v in nodes:
+        nd = g.nodes[v]
+        if nd.kind == "base":
+            n += 1
+            continue
+        n += 3 + (4 if nd.k_same else 0) + (2 if nd.k_cross else 0)
+    return n + ntarg
+
+
+def _vrr_chunk_lines(g, order, tnames, ind):
+    lines = []
+    for v in order:
+        nd = g.nodes[v]
+        if nd.kind == "base":
+            expr = f"base * F[{nd.key[2]}]"
+        else:
+            p1, p2, p3, p4, p5 = nd.parents
+            ax = XYZ[nd.axis]
+            if nd.kind == "bra":
+                c1, c2, o2, rr = f"PA{ax}", f"WP{ax}", "o2z", "rz"
+            else:
+                c1, c2, o2, rr = f"QC{ax}", f"WQ{ax}", "o2e", "re"
+            expr = f"fma({c1}, v{p1}, {c2} * v{p2})"
+            if nd.k_same:
+                k = "" if nd.k_same == 1 else f"{nd.k_same}.0 * "
+                expr = f"fma({k}{o2}, fma(-{rr}, v{p4}, v{p3}), {expr})"
+            if nd.k_cross:
+                k = "" if nd.k_cross == 1 else f"{nd.k_cross}.0 * "
+                expr = f"fma({k}o2ze, v{p5}, {expr})"
+        lines.append(f"{ind}const double v{v} = {expr};")
+        if v in tnames:
+            lines.append(f"{ind}{tnames[v]} += v{v};")
+    return lines
+
+
+def _op_line(op, ren):
+    r = lambda n: ren.get(n, n)
+    if op[1] == "hrr":
+        d, _, hi, lo, coef = op
+        return f"const double {d} = fma({coef}, {r(lo)}, {r(hi)});"
+    d, _, terms = op
+    expr = f"{_fmt(terms[0][0])} * {r(terms[0][1])}"
+    for c, s in terms[1:]:
+        expr = f"fma({_fmt(c)}, {r(s)}, {expr})"
+    return f"const double {d} = {expr};"
+
+
+def _names_in(op):
+    if op[1] == "hrr":
+        return [op[2], op[3]]
+    return [s for _, s in op[2]]
+
+
+def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedulers=None, waves=0):
+    ls = (la, lb, lc, ld)
+    tag = tag_of(ls)
+    g = vrrmod.VRRGraph(la, lb, lc, ld, rule=rule)
+    sched, pl, order = vrrmod.best_order(g) if schedulers is None else vrrmod.best_order(g, schedulers)
+    tslot = {tid: k for k, tid in enumerate(g.target_ids)}          # H slot of each target node
+    hname_of = {t: f"h{k}" for k, t in enumerate(g.targets)}
+    p2 = p2mod.Phase2(la, lb, lc, ld, hname=lambda e, f: hname_of[(e, f)])
+    na, nb, nc, nd = p2.na, p2.nb, p2.nc, p2.nd
+    nout = na * nb * nc * nd
+    E = list(levels(la, la + lb))
+    assert na * nb <= len(E)
+    hslot = {f"h{k}": k for k in range(len(g.targets))}
+    tindex = {t: k for k, t in enumerate(g.targets)}
+    n_h = len(g.targets)
+    islot = lambda mu, nu, lam, sig: n_h + ((mu * nb + nu) * nc + lam) * nd + sig
+    nslots = n_h + nout
+    chunks = chunk_targets(g, cap)
+    full = g.flops()
+    recompute = sum(node_flops(g, subgraph(g, c), len(c)) for c in chunks) / full
+
+    out = []
+    w = out.append
+    w(f"// Generated: class ({la}{lb}|{lc}{ld}), staged tier: {len(chunks)} Phase-1 chunks of <= {cap} accumulators")
+    w(f"// (VRR recomputation x{recompute:.2f}), axis rule {rule}, VRR order '{sched}'; {len(g.nodes)} VRR nodes,")
+    w(f"// {full} VRR FLOP per primitive quartet unchunked, N_hrr {n_h}, Phase-2 {p2.flops} FLOP, {nslots} scratch")
+    w(f"// slots per lane.")
+    w('#include "hgp_device.h"')
+    w("")
+    w("namespace hgp {")
+    w("namespace {")
+    w("")
+    w(f"// Evaluates one shell quartet into scratch: integral (m n|l s) at slot {n_h} + ((m*{nb} + n)*{nc} + l)*{nd} + s.")
+    w(f"__device__ __forceinline__ void staged_{tag}(const PairInfo &pb, const PairGeo &gb, const PairInfo &pk,")
+    w(f"                                             const PairGeo &gk, const PrimPair *__restrict__ prims,")
+    w(f"                                             const double *__restrict__ boys, double *scr, const int64_t S)")
+    w("{")
+    w("    HGP_STAGE(scr);")
+    pos = {v: i for i, v in enumerate(order)}
+    for ci, ch in enumerate(chunks):
+        sub = subgraph(g, ch)
+        corder = sorted(sub, key=lambda v: pos[v])
+        Lc = max(g.nodes[v].key[2] for v in sub if g.nodes[v].kind == "base")
+        tnames = {t: f"h{tslot[t]}" for t in ch}
+        w(f"    {{   // Phase 1, chunk {ci}: {len(ch)} accumulators, {len(sub)} VRR nodes")
+        names = [tnames[t] for t in ch]
+        for k in range(0, len(names), 8):
+            w("        double " + ", ".join(f"{h} = 0.0" for h in names[k:k + 8]) + ";")
+        out.extend(loop_prelude(Lc, "        "))
+        out.extend(_vrr_chunk_lines(g, corder, tnames, "                    "))
+        out.extend(loop_close("        "))
+        for t in ch:
+            w(f"        scr[{tslot[t]} * S] = h{tslot[t]};")
+        w("    }")
+        w("    HGP_STAGE(scr);")
+    w("    const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz;")
+    w("    const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
+    w("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz;")
+    # ---- bra stage
+    s2slot = {}
+    for (f, a0, a1) in p2.bra_stages:
+        ops = p2.ops[a0:a1]
+        used = set()
+        for op in ops:
+            used.update(n for n in _names_in(op) if n in hslot)
+        outs = [(mu, nu) for mu in range(na) for nu in range(nb)]
+        for (mu, nu) in outs:
+            nm = p2.s2[(mu, nu, f)]
+            if nm in hslot:
+                used.add(nm)
+        w(f"    {{   // bra HRR + T(la) T(lb) for ket component {f}")
+        for h in sorted(used, key=lambda x: hslot[x]):
+            w(f"        const double {h} = scr[{hslot[h]} * S];")
+        for op in ops:
+            w("        " + _op_line(op, {}))
+        for (mu, nu) in outs:
+            slot = hslot[hname_of[(E[mu * nb + nu], f)]]
+            s2slot[(mu, nu, f)] = slot
+            w(f"        scr[{slot} * S] = {p2.s2[(mu, nu, f)]};")
+        w("    }")
+        w("    HGP_STAGE(scr);")
+    # ---- ket stage
+    F = list(levels(lc, lc + ld))
+    for (mu, nu, a0, a1) in p2.ket_stages:
+        ops = p2.ops[a0:a1]
+        w(f"    {{   // ket HRR + T(lc) T(ld) for bra functions ({mu}, {nu})")
+        ren = {}
+        for k, f in enumerate(F):
+            nm = p2.s2[(mu, nu, f)]
+            ren[nm] = f"y{k}"
+            w(f"        const double y{k} = scr[{s2slot[(mu, nu, f)]} * S];")
+        for op in ops:
+            w("        " + _op_line(op, ren))
+        for lam in range(nc):
+            for sig in range(nd):
+                nm = p2.out[(mu, nu, lam, sig)]
+                w(f"        scr[{islot(mu, nu, lam, sig)} * S] = {ren.get(nm, nm)};")
+        w("    }")
+        w("    HGP_STAGE(scr);")
+    w("}")
+    w("")
+
+    def I(mu, nu, lam, sig):
+        return f"scr[{islot(mu, nu, lam, sig)} * S]"
+
+    # ---- J/K kernel
+    w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void jk_{tag}(JKArgs a)")
+    w("{")
+    w(f"    const int64_t lane = (int64_t)blockIdx.x * {block} + threadIdx.x;")
+    w(f"    const int64_t S = (int64_t)gridDim.x * {block};")
+    w("    double *scr = a.scratch + lane;")
+    w("    const double *__restrict__ D = a.D;")
+    w("    const int N = a.nbf;")
+    w("    for (int64_t q = lane; q < a.nq; q += S) {")
+    w("        const int2 pq = a.quartets[q];")
+    w("        const PairInfo pb = a.pairs[pq.x], pk = a.pairs[pq.y];")
+    w("        const PairGeo gb = a.geo[pq.x], gk = a.geo[pq.y];")
+    w(f"        staged_{tag}(pb, gb, pk, gk, a.prims, a.boys, scr, S);")
+    w("        HGP_STAGE(scr);")
+    w("        const int fa = pb.fa, fb = pb.fb, fc = pk.fa, fd = pk.fb;")
+    w("        const double s = (pb.same ? 0.5 : 1.0) * (pk.same ? 0.5 : 1.0) * (pq.x == pq.y ? 0.5 : 1.0);")
+
+    def contraction(outer, inner, dexpr, target, scale):
+        for o in outer:
+            terms = inner(*o)
+            expr = f"{terms[0][0]} * {terms[0][1]}"
+            for x, y in terms[1:]:
+                expr = f"fma({x}, {y}, {expr})"
+            w(f"                atomicAdd({target(*o)}, {scale} * ({expr}));")
+        w("                HGP_STAGE(scr);")
+
+    w("        if (a.want_j) {")
+    w("            const double s2 = 2.0 * s;")
+    w("            {")
+    contraction([(mu, nu) for mu in range(na) for nu in range(nb)],
+                lambda mu, nu: [(I(mu, nu, lam, sig), f"D[(fc + {lam}) * N + fd + {sig}]")
+                                for lam in range(nc) for sig in range(nd)],
+                None, lambda mu, nu: f"a.J + (fa + {mu}) * N + fb + {nu}", "s2")
+    contraction([(lam, sig) for lam in range(nc) for sig in range(nd)],
+                lambda lam, sig: [(I(mu, nu, lam, sig), f"D[(fa + {mu}) * N + fb + {nu}]")
+                                  for mu in range(na) for nu in range(nb)],
+                None, lambda lam, sig: f"a.J + (fc + {lam}) * N + fd + {sig}", "s2")
+    w("            }")
+    w("        }")
+    w("        if (a.want_k) {")
+    w("            {")
+    contraction([(mu, lam) for mu in range(na) for lam in range(nc)],
+                lambda mu, lam: [(I(mu, nu, lam, sig), f"D[(fb + {nu}) * N + fd + {sig}]")
+                                 for nu in range(nb) for sig in range(nd)],
+                None, lambda mu, lam: f"a.K + (fa + {mu}) * N + fc + {lam}", "s")
+    contraction([(nu, lam) for nu in range(nb) for lam in range(nc)],
+                lambda nu, lam: [(I(mu, nu, lam, sig), f"D[(fa + {mu}) * N + fd + {sig}]")
+                                 for mu in range(na) for sig in range(nd)],
+                None, lambda nu, lam: f"a.K + (fb + {nu}) * N + fc + {lam}", "s")
+    contraction([(mu, sig) for mu in range(na) for sig in range(nd)],
+                lambda mu, sig: [(I(mu, nu, lam, sig), f"D[(fb + {nu}) * N + fc + {lam}]")
+                                 for nu in range(nb) for lam in range(nc)],
+                None, lambda mu, sig: f"a.K + (fa + {mu}) * N + fd + {sig}", "s")
+    contraction([(nu, sig) for nu in range(nb) for sig in range(nd)],
+                lambda nu, sig: [(I(mu, nu, lam, sig), f"D[(fa + {mu}) * N + fc + {lam}]")
+                                 for mu in range(na) for lam in range(nc)],
+                None, lambda nu, sig: f"a.K + (fb + {nu}) * N + fd + {sig}", "s")
+    w("            }")
+    w("        }")
+    w("    }")
+    w("}")
+    w("")
+    # ---- integrals-out kernel
+    diag_class = (la, lb) == (lc, ld)
+    w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void eri_{tag}(EriArgs a)")
+    w("{")
+    w(f"    const int64_t lane = (int64_t)blockIdx.x * {block} + threadIdx.x;")
+    w(f"    const int64_t S = (int64_t)gridDim.x * {block};")
+    w("    double *scr = a.scratch + lane;")
+    w("    for (int64_t q = lane; q < a.ntask; q += S) {")
+    w("        const EriTask t = a.tasks[q];")
+    w("        const PairInfo pb = a.pairs[t.bra], pk = a.pairs[t.ket];")
+    w("        const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];")
+    w(f"        staged_{tag}(pb, gb, pk, gk, a.prims, a.boys, scr, S);")
+    w("        HGP_STAGE(scr);")
+    if diag_class:
+        w("        if (a.mode == 1) {")
+        w("            double m = 0.0;")
+        for mu in range(na):
+            for nu in range(nb):
+                w(f"            m = fmax(m, fabs({I(mu, nu, mu, nu)}));")
+        w("            a.out[q] = sqrt(m);")
+        w("            continue;")
+        w("        }")
+    w("        double *__restrict__ o = a.out + t.off;")
+    for mu in range(na):
+        for nu in range(nb):
+            for lam in range(nc):
+                for sig in range(nd):
+                    w(f"        o[{mu} * t.s0 + {nu} * t.s1 + {lam} * t.s2 + {sig} * t.s3] = {I(mu, nu, lam, sig)};")
+    w("    }")
+    w("}")
+    w("")
+    w("}  // namespace")
+    w("")
+    for kind, cnt in (("jk", "nq"), ("eri", "ntask")):
+        args = "JKArgs" if kind == "jk" else "EriArgs"
+        w(f"void launch_{kind}_{tag}(const {args} &a, hipStream_t s)")
+        w("{")
+        w(f"    int64_t grid = (a.{cnt} + {block - 1}) / {block};")
+        w(f"    const int64_t cap = a.scratch_lanes / {block};")
+        w("    if (grid > cap) grid = cap;")
+        w(f"    if (grid > 0) hipLaunchKernelGGL({kind}_{tag}, dim3((unsigned)grid), dim3({block}), 0, s, a);")
+        w("}")
+    w("")
+    w("}  // namespace hgp")
+    meta = ClassMeta(ls, tag, 1, block, len(g.nodes), full, n_h, pl, sched, p2.flops, nout, rule,
+                     scratch_slots=nslots, chunks=len(chunks), recompute=recompute, cap=cap, waves=waves)
+    return "\n".join(out) + "\n", meta

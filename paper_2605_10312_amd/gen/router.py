@@ -1,0 +1,55 @@
+"""Tier routing per quartet class (Sec. III-C, Eq. rtotal, redone for gfx950).
+
+The paper routes by the register demand R_total ~ 2 (PeakLive_VRR + N_acc)
+against a 255-register limit.  On gfx950 a lane can hold at most 512 32-bit
+registers (256 ArchVGPR + 256 AccVGPR, at one wave per SIMD), i.e. 256
+doubles, and the accumulator bank is the contracted [e0|f0] set, so the
+model here is
+
+    demand = N_hrr + PeakLive + 40      (40: pair/Boys/VRR coefficients)
+
+    register tier (one kernel, everything in VGPR/AGPR)   if demand <= 240
+    staged tier (Phase-1 chunks + HBM-staged Phase 2)     otherwise
+
+The 240-double line was set from the compiler's resource reports: every
+class at or under it compiles without scratch, every class above it spilled.
+A tuning table measured on the GPU (tuning/gfx950.json) overrides the model
+per class: tier, chunk cap and waves per SIMD.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+from . import vrr as vrrmod
+
+REGISTER_DOUBLES = 240
+DEFAULT_CAP = 96
+TABLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tuning", "gfx950.json")
+
+
+def model_demand(ls):
+    g = vrrmod.VRRGraph(*ls)
+    _, pl, _ = vrrmod.best_order(g)
+    return g.n_hrr() + pl + 40
+
+
+def load_table(path=TABLE):
+    if path and os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh).get("classes", {})
+    return {}
+
+
+def route(ls, table=None):
+    """-> dict(tier=0|1, cap=int, waves=int, source='model'|'table')"""
+    tag = "".join(str(x) for x in ls)
+    table = load_table() if table is None else table
+    if tag in table:
+        t = dict(table[tag])
+        t.setdefault("cap", DEFAULT_CAP)
+        t.setdefault("waves", 0)
+        t["source"] = "table"
+        return t
+    tier = 0 if model_demand(ls) <= REGISTER_DOUBLES else 1
+    return {"tier": tier, "cap": DEFAULT_CAP, "waves": 0, "source": "model"}

@@ -1,0 +1,81 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every entry point
+that include/hgp.h declares, and rejects invalid input before any device
+work (these paths make no HIP call, so they run without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "hgp.h")).read()
+    return sorted(set(re.findall(r"\b(hgp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("hgp_basis_create", "hgp_plan_create", "hgp_jk", "hgp_eri_shell_quartets",
+                 "hgp_eri_prim_quartets", "hgp_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2605_10312_amd as hgp
+    h = hgp.lib()
+    for name in _declared():
+        assert hasattr(h, name), name
+    assert set(_declared()) == set(hgp.SIGNATURES)
+
+
+def test_version_and_built_l():
+    import paper_2605_10312_amd as hgp
+    assert hgp.lib().hgp_version() >= 1
+    assert 2 <= hgp.max_l() <= 4
+
+
+def _create(l, nprim, cen, exps, coefs):
+    import paper_2605_10312_amd as hgp
+    h = ctypes.c_void_p()
+    arrs = [np.ascontiguousarray(l, np.int32), np.ascontiguousarray(nprim, np.int32),
+            np.ascontiguousarray(cen, np.float64), np.ascontiguousarray(exps, np.float64),
+            np.ascontiguousarray(coefs, np.float64)]
+    rc = hgp.lib().hgp_basis_create(len(arrs[0]), *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs], ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("case,status", [
+    ("l5", -2), ("lneg", -1), ("nprim0", -1), ("nan_exp", -1), ("neg_exp", -1), ("inf_centre", -1)])
+def test_basis_validation(case, status):
+    import paper_2605_10312_amd as hgp
+    l, nprim, cen, exps, coefs = [0, 1], [1, 2], np.zeros((2, 3)), [1.0, 2.0, 3.0], [1.0, 1.0, 1.0]
+    if case == "l5":
+        l = [5, 1]
+    elif case == "lneg":
+        l = [-1, 1]
+    elif case == "nprim0":
+        nprim, exps, coefs = [0, 2], [2.0, 3.0], [1.0, 1.0]
+    elif case == "nan_exp":
+        exps = [1.0, float("nan"), 3.0]
+    elif case == "neg_exp":
+        exps = [1.0, -2.0, 3.0]
+    elif case == "inf_centre":
+        cen = np.array([[0, 0, 0], [0, np.inf, 0]], float)
+    rc, h = _create(l, nprim, cen, exps, coefs)
+    assert rc == status
+    assert h.value is None
+    assert len(hgp.lib().hgp_last_error()) > 0
+
+
+def test_null_arguments_rejected():
+    import paper_2605_10312_amd as hgp
+    L = hgp.lib()
+    assert L.hgp_basis_create(1, None, None, None, None, None, ctypes.byref(ctypes.c_void_p())) == -1
+    assert L.hgp_plan_create(None, 1e-12, 0, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
+    assert L.hgp_jk(None, None, None, None, None) == -1
+    assert L.hgp_eri_prim_quartets(5, 0, 0, 0, 1, None, None, None, 0, None) == -2
+    assert L.hgp_eri_prim_quartets(0, 0, 0, 0, -1, None, None, None, 0, None) == -1
+    assert L.hgp_eri_prim_quartets(0, 0, 0, 0, 0, None, None, None, 0, None) == 0

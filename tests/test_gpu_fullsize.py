@@ -1,0 +1,105 @@
+"""Parity at the benchmark's full size, in the launch configuration bench.py
+times: 30-atom 3s2p1d molecule (N = 420, 180 shells, 16 290 shell pairs),
+Schwarz tau = 1e-12, J and K built together.
+
+The oracle cannot digest all ~1.3e8 quartets in seconds, so it computes
+sampled J/K blocks directly from their definitions (every ordered shell pair
+(R,S) of the sum, same screening rule) and the screened quartet count by
+brute force over its own Schwarz factors; the rest is checked through
+properties that hold at any size (symmetry, positivity of tr(DJ), tr(DK))."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+TAU = 1e-12
+JK_TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def built():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_10312_amd as hgp
+    bw, D = workloads.molecule_3s2p1d()
+    b = hgp.Basis.from_workload(bw)
+    plan = hgp.Plan(b, tau=TAU)
+    Dt = torch.tensor(D, device="cuda")
+    J = torch.empty_like(Dt)
+    K = torch.empty_like(Dt)
+    plan.jk(Dt, J, K)
+    torch.cuda.synchronize()
+    out = dict(bw=bw, D=D, J=J.cpu().numpy(), K=K.cpu().numpy(), stats=plan.stats(), classes=plan.classes(),
+               Q=plan.schwarz())
+    plan.close()
+    b.close()
+    return out
+
+
+def test_sizes(built):
+    bw = built["bw"]
+    assert bw.nshell == 180 and bw.nbf == 420
+    st = built["stats"]
+    assert st["quartets_total"] == 16290 * 16291 // 2
+    assert len(built["classes"]) == 21
+
+
+def _count_kept(Q, nshell):
+    """Unique quartets {P, R} of shell pairs with Q_P Q_R >= tau, brute force."""
+    iu = np.tril_indices(nshell)
+    q = np.sort(Q[iu])
+    # ordered pairs (P,R) with q_P q_R >= tau, then unordered with the diagonal once
+    ordered = sum(len(q) - np.searchsorted(q, TAU / x, side="left") for x in q if x > 0)
+    diag = int(np.sum(q * q >= TAU))
+    return (ordered + diag) // 2
+
+
+def test_screen_compaction_is_exact(built):
+    # the class lists hold exactly the quartets the plan's own factors keep
+    kept = built["stats"]["quartets_kept"]
+    assert kept == _count_kept(built["Q"], built["bw"].nshell)
+
+
+def test_schwarz_factors_vs_oracle(built):
+    """Q^2 is a diagonal integral (ab|ab).  Some of them lose digits to the
+    horizontal recurrence in FP64 (the FP64 oracle itself is off by up to
+    ~1e-4 relative on a few pairs), so the GPU is compared with the
+    long-double oracle, allowing a few times the FP64 oracle's own error."""
+    bw = built["bw"]
+    Qo = oracle.schwarz(bw)
+    Ql = oracle.schwarz(bw, precision="long double")
+    Qg = built["Q"]
+    e_gpu = np.abs(Qg ** 2 - Ql ** 2)
+    e_orc = np.abs(Qo ** 2 - Ql ** 2)
+    # Q^2 is an integral: the per-integral bar (1e-12 absolute) plus the FP64 oracle's own error
+    allow = 1e-12 + 8.0 * e_orc
+    bad = e_gpu > allow
+    print(f"max |Qg^2 - Qld^2| {e_gpu.max():.3e}, max |Qo^2 - Qld^2| {e_orc.max():.3e}, pairs over bar {bad.sum()}")
+    assert not bad.any()
+
+
+def test_jk_properties(built):
+    J, K, D = built["J"], built["K"], built["D"]
+    assert np.all(np.isfinite(J)) and np.all(np.isfinite(K))
+    assert np.abs(J - J.T).max() <= 1e-12 * np.abs(J).max()
+    assert np.abs(K - K.T).max() <= 1e-12 * np.abs(K).max()
+    assert np.trace(D @ J) > 0 and np.trace(D @ K) > 0
+
+
+def test_sampled_blocks_vs_oracle(built):
+    bw, D, J, K = built["bw"], built["D"], built["J"], built["K"]
+    off = bw.shell_offsets()
+    ds = np.where(bw.l == 2)[0]
+    ps = np.where(bw.l == 1)[0]
+    ss = np.where(bw.l == 0)[0]
+    pairs = [(int(ds[3]), int(ds[17])), (int(ps[5]), int(ss[40])), (int(ss[7]), int(ss[7]))]
+    Js, Ks = oracle.jk_blocks(bw, D, pairs, tau=TAU)
+    for (p, r), jb, kb in zip(pairs, Js, Ks):
+        gj = J[off[p]:off[p + 1], off[r]:off[r + 1]]
+        gk = K[off[p]:off[p + 1], off[r]:off[r + 1]]
+        ej, ek = np.abs(gj - jb).max(), np.abs(gk - kb).max()
+        print(f"block ({p},{r}) l=({bw.l[p]},{bw.l[r]}): |dJ| {ej:.2e} |dK| {ek:.2e} (|J| {np.abs(jb).max():.2e})")
+        assert ej <= JK_TOL and ek <= JK_TOL
