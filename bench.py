@@ -40,12 +40,19 @@ def overhead_flops(L):
     return 46 + 2 * L
 
 
-def algorithmic_flops(c):
+def phase_flops(c):
+    """(Phase-1 FLOPs, Phase-2 + digestion FLOPs) of one class per J/K build:
+    per primitive quartet the unchunked VRR graph plus the pair/Boys overhead,
+    per contracted quartet the HRR + transforms plus 12 per integral."""
     la, lb, lc, ld = c["ls"]
     nint = nsph(la) * nsph(lb) * nsph(lc) * nsph(ld)
     per_prim = c["vrr_flops"] + overhead_flops(la + lb + lc + ld)
     per_quartet = c["phase2_flops"] + 12 * nint
-    return c["prim_quartets"] * per_prim + c["quartets"] * per_quartet
+    return c["prim_quartets"] * per_prim, c["quartets"] * per_quartet
+
+
+def algorithmic_flops(c):
+    return sum(phase_flops(c))
 
 
 def cpu_baseline(bw, target_s, seed=7):
@@ -127,21 +134,31 @@ def main():
     plan.set_timing(False)
     ms_per_step = 1e3 * elapsed / args.steps
 
-    per_class = []
-    for c, (ls, n, ms) in zip(classes, timing):
-        fl = algorithmic_flops(c)
-        avg = ms / max(n, 1)
-        per_class.append({"class": "".join(str(x) for x in ls), "quartets": c["quartets"],
-                          "prim_quartets": c["prim_quartets"], "avg_ms": round(avg, 4),
-                          "gflop_per_launch": round(fl / 1e9, 3),
-                          "tflops": round(fl / (avg * 1e-3) / 1e12, 3) if avg > 0 else None})
-    per_class.sort(key=lambda x: -x["avg_ms"])
-    dom = per_class[0]
+    # one entry per kernel: register tier jk_<class>; staged tier p1_<class> (Phase 1)
+    # and jk_<class> (Phase 2 + digestion); average duration per launch from HIP events
+    per_kernel = []
+    for c, t in zip(classes, timing):
+        tag = "".join(str(x) for x in c["ls"])
+        f1, f2 = phase_flops(c)
+        if t["tier"] == 0:
+            parts = [(f"jk_{tag}", f1 + f2, t["kernels"][0])]
+        else:
+            parts = [(f"p1_{tag}", f1, t["kernels"][0]), (f"jk_{tag}", f2, t["kernels"][1])]
+        for name, fl, (n, ms) in parts:
+            launches_per_step = max(n, 1) / args.steps
+            avg = ms / max(n, 1)
+            per_kernel.append({"kernel": name, "tier": t["tier"], "quartets": c["quartets"],
+                               "prim_quartets": c["prim_quartets"], "avg_ms": round(avg, 4),
+                               "ms_per_step": round(ms / args.steps, 4),
+                               "gflop_per_launch": round(fl / launches_per_step / 1e9, 3),
+                               "tflops": round(fl / launches_per_step / (avg * 1e-3) / 1e12, 3) if avg > 0 else None})
+    per_kernel.sort(key=lambda x: -x["ms_per_step"])
+    dom = per_kernel[0]
     achieved = dom["tflops"]
-    roofline = {"bound": "alu", "kernel": f"jk_{dom['class']}", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+    roofline = {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
-                "avg_launch_ms": dom["avg_ms"]}
-    total_kernel_ms = sum(x["avg_ms"] for x in per_class)
+                "avg_launch_ms": dom["avg_ms"], "gflop_per_launch": dom["gflop_per_launch"]}
+    total_kernel_ms = sum(x["ms_per_step"] for x in per_kernel)
     total_flops = sum(algorithmic_flops(c) for c in classes)
 
     err = None
@@ -183,7 +200,7 @@ def main():
         "step_tflops": round(total_flops / (ms_per_step * 1e-3) / 1e12, 3),
         "kernel_ms_sum": round(total_kernel_ms, 4),
         "err": err,
-        "classes": per_class,
+        "kernels": per_kernel,
     }
     print(json.dumps(line), flush=True)
 

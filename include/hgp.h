@@ -102,11 +102,12 @@ hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t preci
 hgp_status hgp_plan_destroy(hgp_plan *p);
 /* Plan statistics: unique quartets kept after screening, candidate quartets, device bytes held. */
 hgp_status hgp_plan_stats(const hgp_plan *p, int64_t *quartets_kept, int64_t *quartets_total, int64_t *device_bytes);
-/* Per class c (0 .. n-1, n = hgp_plan_num_classes): angular momenta ls[4], quartets kept, and the
- * generator's FLOP counts per primitive quartet (VRR + accumulate) and per contracted quartet (Phase 2). */
+/* Per class c (0 .. n-1, n = hgp_plan_num_classes, in launch order): angular momenta ls[4], quartets
+ * kept, primitive quartets they hold, the generator's FLOP counts per primitive quartet (VRR +
+ * accumulate, unchunked) and per contracted quartet (Phase 2), and the tier (0 register, 1 staged). */
 int32_t hgp_plan_num_classes(const hgp_plan *p);
 hgp_status hgp_plan_class_info(const hgp_plan *p, int32_t c, int32_t *ls, int64_t *nquartets, int64_t *nprim_quartets,
-                               double *vrr_flops, double *phase2_flops);
+                               double *vrr_flops, double *phase2_flops, int32_t *tier);
 
 /* The plan's Schwarz factors by shell: Q[i*nshell + j] = Q[j*nshell + i] =
  * sqrt(max |(mn|mn)|) over m in shell i, n in shell j (host array, nshell^2). */
@@ -117,10 +118,12 @@ hgp_status hgp_plan_schwarz(const hgp_plan *p, double *Q);
  * HIP events on its stream around each class kernel (the work enqueued is
  * unchanged).  hgp_plan_set_timing(p, 1) also resets the counters.
  * hgp_plan_class_timing waits for the recorded events and returns, for class
- * c, the number of timed launches and their summed duration in milliseconds.
+ * c and kernel k, the number of timed launches and their summed duration in
+ * milliseconds.  k = 0: the register tier's kernel or a staged class's Phase-1
+ * kernel; k = 1: a staged class's Phase-2 + digestion kernel.
  */
 hgp_status hgp_plan_set_timing(hgp_plan *p, int32_t enable);
-hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int64_t *launches, double *total_ms);
+hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int32_t kernel, int64_t *launches, double *total_ms);
 
 /*
  * hgp_jk -- J and K for density D (Alg. 2's Scatter step, 8-fold symmetry).

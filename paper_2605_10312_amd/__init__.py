@@ -32,10 +32,10 @@ SIGNATURES = {
     "hgp_plan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "hgp_plan_num_classes": (_i32, [_vp]),
     "hgp_plan_class_info": (ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
-                                           ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+                                           ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i32)]),
     "hgp_plan_schwarz": (ctypes.c_int, [_vp, _vp]),
     "hgp_plan_set_timing": (ctypes.c_int, [_vp, _i32]),
-    "hgp_plan_class_timing": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
+    "hgp_plan_class_timing": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
     "hgp_jk": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "hgp_eri_shell_quartets": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
     "hgp_eri_prim_quartets": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i64, _vp, _vp, _vp, _i32, _vp]),
@@ -146,10 +146,11 @@ class Plan:
         for c in range(lib().hgp_plan_num_classes(self.handle)):
             ls = np.zeros(4, np.int32)
             nq, npq, vf, pf = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+            tier = ctypes.c_int32()
             _check(lib().hgp_plan_class_info(self.handle, c, ls.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nq),
-                                             ctypes.byref(npq), ctypes.byref(vf), ctypes.byref(pf)))
+                                             ctypes.byref(npq), ctypes.byref(vf), ctypes.byref(pf), ctypes.byref(tier)))
             out.append({"ls": tuple(int(x) for x in ls), "quartets": nq.value, "prim_quartets": npq.value,
-                        "vrr_flops": vf.value, "phase2_flops": pf.value})
+                        "vrr_flops": vf.value, "phase2_flops": pf.value, "tier": tier.value})
         return out
 
     def schwarz(self):
@@ -163,12 +164,18 @@ class Plan:
         _check(lib().hgp_plan_set_timing(self.handle, 1 if enable else 0))
 
     def class_timing(self):
-        """[(ls, launches, total_ms)] per class, waiting for recorded events."""
+        """Per class: {ls, tier, kernels: [(launches, total_ms) for kernel 0, 1]},
+        waiting for the recorded events.  Kernel 0 is the register tier's
+        kernel or a staged class's Phase-1 kernel, kernel 1 a staged class's
+        Phase-2 + digestion kernel."""
         out = []
         for c, info in enumerate(self.classes()):
-            n, ms = ctypes.c_int64(), ctypes.c_double()
-            _check(lib().hgp_plan_class_timing(self.handle, c, ctypes.byref(n), ctypes.byref(ms)))
-            out.append((info["ls"], n.value, ms.value))
+            ks = []
+            for k in (0, 1):
+                n, ms = ctypes.c_int64(), ctypes.c_double()
+                _check(lib().hgp_plan_class_timing(self.handle, c, k, ctypes.byref(n), ctypes.byref(ms)))
+                ks.append((n.value, ms.value))
+            out.append({"ls": info["ls"], "tier": info["tier"], "kernels": ks})
         return out
 
     def jk(self, D, J=None, K=None, stream=None):

@@ -61,22 +61,59 @@ int class_index(int la, int lb, int lc, int ld)
     return -1;
 }
 
-// doubles of scratch per lane the staged classes with every l <= lmax need
-int64_t staged_slots(int lmax)
-{
-    int64_t m = 0;
-    for (int c = 0; c < g_num_classes; ++c) {
-        const ClassKernels &k = g_class_table[c];
-        if (k.tier == 1 && k.la <= lmax) m = std::max<int64_t>(m, k.scratch_slots);
-    }
-    return m;
-}
-
 int built_max_l()
 {
     int m = -1;
     for (int c = 0; c < g_num_classes; ++c) m = std::max(m, g_class_table[c].la);
     return m;
+}
+
+// Batch size of a staged class over a buffer of `doubles`: a multiple of 64.
+int64_t staged_batch(const ClassKernels &k, int64_t doubles)
+{
+    int64_t b = doubles / (k.scratch_slots > 0 ? k.scratch_slots : 1);
+    b = (b / 64) * 64;
+    return b < 64 ? 64 : b;
+}
+
+// Buffer a staged class needs to run all n items in one batch (capped).
+int64_t staged_need(const ClassKernels &k, int64_t n)
+{
+    if (k.tier != 1 || n <= 0) return 0;
+    const int64_t want = (int64_t)k.scratch_slots * (((n + 63) / 64) * 64);
+    const int64_t floor64 = (int64_t)k.scratch_slots * 64;
+    return std::max(floor64, std::min(want, SCRATCH_MAX_DOUBLES));
+}
+
+// Integrals-out work of one class: register tier in launches of at most 2^20
+// blocks; staged tier in batches (Phase 1 then Phase 2).
+void run_eri_class(const ClassKernels &k, EriArgs a, int64_t scratch_doubles, hipStream_t s)
+{
+    const int64_t ntask = a.ntask;
+    if (k.tier == 0) {
+        const int64_t chunk = (int64_t)k.block << 20;
+        for (int64_t q0 = 0; q0 < ntask; q0 += chunk) {
+            EriArgs b = a;
+            b.tasks = a.tasks + q0;
+            b.ntask = std::min(chunk, ntask - q0);
+            if (a.mode == 1) b.out = a.out + q0;
+            k.eri(b, s);
+        }
+        return;
+    }
+    const int64_t B = staged_batch(k, scratch_doubles);
+    for (int64_t q0 = 0; q0 < ntask; q0 += B) {
+        const int64_t nb = std::min(B, ntask - q0);
+        P1Args pa{(const int32_t *)(a.tasks + q0), (int64_t)(sizeof(EriTask) / sizeof(int32_t)), nb, a.pairs, a.geo,
+                  a.prims, a.boys, a.scratch, B};
+        k.p1(pa, s);
+        EriArgs b = a;
+        b.tasks = a.tasks + q0;
+        b.ntask = nb;
+        if (a.mode == 1) b.out = a.out + q0;
+        b.stride = B;
+        k.eri(b, s);
+    }
 }
 
 template <class T>
@@ -121,12 +158,12 @@ struct ClassList {
     int64_t nq = 0;   // unique quartets kept
     int64_t nprimq = 0;
     int2 *d_q = nullptr;
-    int64_t launches = 0;   // timed launches
-    double ms = 0.0;        // their summed duration
+    int64_t launches[2] = {0, 0};   // timed launches: [0] whole / Phase-1 kernel, [1] Phase-2 kernel
+    double ms[2] = {0.0, 0.0};      // their summed durations
 };
 
 struct PendingTiming {
-    int list;
+    int list, kernel;
     hipEvent_t start, stop;
 };
 
@@ -142,7 +179,8 @@ struct hgp_plan {
     PrimPair *d_prims = nullptr;
     double *d_Q = nullptr;
     double *d_Jacc = nullptr, *d_Kacc = nullptr;
-    double *d_scratch = nullptr;           // staged classes, SCRATCH_LANES x slots
+    double *d_scratch = nullptr;           // staged classes: slot-major batch buffer
+    int64_t scratch_doubles = 0;
     std::vector<ClassList> lists;
     int64_t kept = 0, total = 0, bytes = 0;
     bool timing = false;
@@ -168,8 +206,8 @@ static hgp_status collect_timing(hgp_plan *p)
         float ms = 0.f;
         HGP_HIP(hipEventSynchronize(t.stop));
         HGP_HIP(hipEventElapsedTime(&ms, t.start, t.stop));
-        p->lists[t.list].ms += ms;
-        p->lists[t.list].launches += 1;
+        p->lists[t.list].ms[t.kernel] += ms;
+        p->lists[t.list].launches[t.kernel] += 1;
         p->event_pool.push_back(t.start);
         p->event_pool.push_back(t.stop);
     }
@@ -311,10 +349,6 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
         (st = dalloc(&p->d_prims, (size_t)prim_off, &p->bytes)) || (st = dalloc(&p->d_Q, pairs.size(), &p->bytes)) ||
         (st = dalloc(&p->d_Jacc, (size_t)(nbf * nbf), &p->bytes)) || (st = dalloc(&p->d_Kacc, (size_t)(nbf * nbf), &p->bytes)))
         return st;
-    const int64_t slots = staged_slots(lmax);
-    if (budget && (size_t)(p->bytes + slots * SCRATCH_LANES * (int64_t)sizeof(double)) > budget)
-        return fail(HGP_E_OOM, "plan exceeds the HBM budget (staged-tier scratch)");
-    if ((st = dalloc(&p->d_scratch, (size_t)(slots * SCRATCH_LANES), &p->bytes))) return st;
     launch_pairs(p->npair, p->d_pairs, b->d_cen, b->d_poff, b->d_exps, b->d_ncoef, p->d_geo, p->d_prims, s);
     HGP_HIP(hipGetLastError());
     const double *boys = nullptr;
@@ -324,7 +358,17 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
     if (p->npair > 0) {
         double *qv = nullptr;
         EriTask *tasks = nullptr;
-        if ((st = dalloc(&qv, pairs.size())) || (st = dalloc(&tasks, pairs.size()))) { hipFree(qv); return st; }
+        double *sscr = nullptr;
+        int64_t sneed = 0;
+        for (int c = 0; c < npc; ++c) {
+            if (!p->pc_count[c]) continue;
+            int la = 0;
+            while (pair_class_of(la + 1, 0) <= c) ++la;
+            const int ci = class_index(la, c - pair_class_of(la, 0), la, c - pair_class_of(la, 0));
+            if (ci >= 0) sneed = std::max(sneed, staged_need(g_class_table[ci], p->pc_count[c]));
+        }
+        if ((st = dalloc(&qv, pairs.size())) || (st = dalloc(&tasks, pairs.size())) ||
+            (st = dalloc(&sscr, (size_t)sneed))) { hipFree(qv); hipFree(tasks); return st; }
         std::vector<EriTask> th(pairs.size());
         for (int i = 0; i < p->npair; ++i) th[i] = EriTask{i, i, 0, 0, 0, 0, 0};
         HGP_HIP(hipMemcpyAsync(tasks, th.data(), th.size() * sizeof(EriTask), hipMemcpyHostToDevice, s));
@@ -341,15 +385,15 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
             a.pairs = p->d_pairs; a.geo = p->d_geo; a.prims = p->d_prims; a.boys = boys;
             a.out = qv + p->pc_begin[c];
             a.mode = 1;
-            a.scratch = p->d_scratch;
-            a.scratch_lanes = SCRATCH_LANES;
-            g_class_table[ci].eri(a, s);
+            a.scratch = sscr;
+            run_eri_class(g_class_table[ci], a, sneed, s);
         }
         launch_store_q(p->npair, qv, p->d_geo, p->d_Q, s);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         hipFree(qv);
         hipFree(tasks);
+        hipFree(sscr);
         if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("Schwarz kernels: ") + hipGetErrorString(e));
     }
 
@@ -406,6 +450,13 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
     }
     hipFree(d_counts);
     hipFree(d_total);
+    // staged-tier buffer: one batch per class where it fits under the cap
+    int64_t sbuf = 0;
+    for (const ClassList &cl : p->lists) sbuf = std::max(sbuf, staged_need(g_class_table[cl.cls], cl.nq));
+    if (budget && (size_t)(p->bytes + sbuf * (int64_t)sizeof(double)) > budget)
+        return fail(HGP_E_OOM, "plan exceeds the HBM budget (staged-tier buffer)");
+    if ((st = dalloc(&p->d_scratch, (size_t)sbuf, &p->bytes))) return st;
+    p->scratch_doubles = sbuf;
     // heaviest classes first
     std::stable_sort(p->lists.begin(), p->lists.end(), [](const ClassList &x, const ClassList &y) {
         const double cx = x.nprimq * g_class_table[x.cls].vrr_flops + x.nq * g_class_table[x.cls].p2_flops;
@@ -449,7 +500,7 @@ hgp_status hgp_plan_stats(const hgp_plan *p, int64_t *kept, int64_t *total, int6
 int32_t hgp_plan_num_classes(const hgp_plan *p) { return p ? (int32_t)p->lists.size() : 0; }
 
 hgp_status hgp_plan_class_info(const hgp_plan *p, int32_t c, int32_t *ls, int64_t *nq, int64_t *npq, double *vf,
-                               double *pf)
+                               double *pf, int32_t *tier)
 {
     if (!p || c < 0 || c >= (int32_t)p->lists.size()) return fail(HGP_E_INVALID, "bad plan or class index");
     const ClassList &cl = p->lists[c];
@@ -459,6 +510,7 @@ hgp_status hgp_plan_class_info(const hgp_plan *p, int32_t c, int32_t *ls, int64_
     if (npq) *npq = cl.nprimq;
     if (vf) *vf = k.vrr_flops;
     if (pf) *pf = k.p2_flops;
+    if (tier) *tier = k.tier;
     return HGP_OK;
 }
 
@@ -481,18 +533,22 @@ hgp_status hgp_plan_set_timing(hgp_plan *p, int32_t enable)
     if (!p) return fail(HGP_E_INVALID, "plan is NULL");
     hgp_status st = collect_timing(p);
     if (st) return st;
-    for (ClassList &cl : p->lists) { cl.ms = 0.0; cl.launches = 0; }
+    for (ClassList &cl : p->lists) {
+        cl.ms[0] = cl.ms[1] = 0.0;
+        cl.launches[0] = cl.launches[1] = 0;
+    }
     p->timing = enable != 0;
     return HGP_OK;
 }
 
-hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int64_t *launches, double *total_ms)
+hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int32_t kernel, int64_t *launches, double *total_ms)
 {
-    if (!p || c < 0 || c >= (int32_t)p->lists.size()) return fail(HGP_E_INVALID, "bad plan or class index");
+    if (!p || c < 0 || c >= (int32_t)p->lists.size() || kernel < 0 || kernel > 1)
+        return fail(HGP_E_INVALID, "bad plan, class or kernel index");
     hgp_status st = collect_timing(p);
     if (st) return st;
-    if (launches) *launches = p->lists[c].launches;
-    if (total_ms) *total_ms = p->lists[c].ms;
+    if (launches) *launches = p->lists[c].launches[kernel];
+    if (total_ms) *total_ms = p->lists[c].ms[kernel];
     return HGP_OK;
 }
 
@@ -511,32 +567,54 @@ hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_
     if (st) return st;
     if (J) launch_fill_zero(p->d_Jacc, nn, s);
     if (K) launch_fill_zero(p->d_Kacc, nn, s);
+    auto mark = [&](hipEvent_t *e) -> hgp_status {
+        *e = nullptr;
+        if (!p->timing) return HGP_OK;
+        *e = take_event(p);
+        if (!*e) return fail(HGP_E_DEVICE, "hipEventCreate failed");
+        HGP_HIP(hipEventRecord(*e, s));
+        return HGP_OK;
+    };
+    auto done = [&](int li, int kernel, hipEvent_t a, hipEvent_t b) {
+        if (p->timing) p->pending.push_back(PendingTiming{li, kernel, a, b});
+    };
     for (size_t li = 0; li < p->lists.size(); ++li) {
         const ClassList &cl = p->lists[li];
         if (cl.nq == 0) continue;
         const ClassKernels &k = g_class_table[cl.cls];
-        PendingTiming tm{(int)li, nullptr, nullptr};
-        if (p->timing) {
-            tm.start = take_event(p);
-            tm.stop = take_event(p);
-            if (!tm.start || !tm.stop) return fail(HGP_E_DEVICE, "hipEventCreate failed");
-            HGP_HIP(hipEventRecord(tm.start, s));
-        }
         JKArgs a{};
         a.pairs = p->d_pairs; a.geo = p->d_geo; a.prims = p->d_prims; a.boys = boys;
         a.D = D; a.J = p->d_Jacc; a.K = p->d_Kacc; a.nbf = n;
         a.want_j = J != nullptr; a.want_k = K != nullptr;
-        a.scratch = p->d_scratch;
-        a.scratch_lanes = SCRATCH_LANES;
-        const int64_t chunk = (int64_t)k.block * 1048576;
-        for (int64_t q0 = 0; q0 < cl.nq; q0 += chunk) {
-            a.quartets = cl.d_q + q0;
-            a.nq = std::min(chunk, cl.nq - q0);
-            k.jk(a, s);
-        }
-        if (p->timing) {
-            HGP_HIP(hipEventRecord(tm.stop, s));
-            p->pending.push_back(tm);
+        hipEvent_t e0, e1, e2, e3;
+        if (k.tier == 0) {
+            if ((st = mark(&e0))) return st;
+            const int64_t chunk = (int64_t)k.block << 20;
+            for (int64_t q0 = 0; q0 < cl.nq; q0 += chunk) {
+                a.quartets = cl.d_q + q0;
+                a.nq = std::min(chunk, cl.nq - q0);
+                k.jk(a, s);
+            }
+            if ((st = mark(&e1))) return st;
+            done((int)li, 0, e0, e1);
+        } else {
+            const int64_t B = staged_batch(k, p->scratch_doubles);
+            for (int64_t q0 = 0; q0 < cl.nq; q0 += B) {
+                const int64_t nb = std::min(B, cl.nq - q0);
+                P1Args pa{(const int32_t *)(cl.d_q + q0), 2, nb, p->d_pairs, p->d_geo, p->d_prims, boys,
+                          p->d_scratch, B};
+                if ((st = mark(&e0))) return st;
+                k.p1(pa, s);
+                if ((st = mark(&e1)) || (st = mark(&e2))) return st;
+                a.quartets = cl.d_q + q0;
+                a.nq = nb;
+                a.scratch = p->d_scratch;
+                a.stride = B;
+                k.jk(a, s);
+                if ((st = mark(&e3))) return st;
+                done((int)li, 0, e0, e1);
+                done((int)li, 1, e2, e3);
+            }
         }
     }
     if (J) launch_symmetrize(p->d_Jacc, J, n, s);
@@ -603,9 +681,8 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
     PrimPair *d_prims = nullptr;
     EriTask *d_tasks = nullptr;
     double *d_scr = nullptr;
-    int64_t slots = 0;
-    for (int c = 0; c < g_num_classes; ++c)
-        if (!per[c].empty() && g_class_table[c].tier == 1) slots = std::max<int64_t>(slots, g_class_table[c].scratch_slots);
+    int64_t sneed = 0;
+    for (int c = 0; c < g_num_classes; ++c) sneed = std::max(sneed, staged_need(g_class_table[c], (int64_t)per[c].size()));
     std::vector<EriTask> all;
     std::vector<std::pair<int, int64_t>> ranges;
     for (int c = 0; c < g_num_classes; ++c)
@@ -615,7 +692,7 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
         }
     auto cleanup = [&]() { hipFree(d_pairs); hipFree(d_geo); hipFree(d_prims); hipFree(d_tasks); hipFree(d_scr); };
     if ((st = upload(&d_pairs, pairs)) || (st = dalloc(&d_geo, pairs.size())) || (st = dalloc(&d_prims, (size_t)prim_off)) ||
-        (st = upload(&d_tasks, all)) || (st = dalloc(&d_scr, (size_t)(slots * SCRATCH_LANES)))) {
+        (st = upload(&d_tasks, all)) || (st = dalloc(&d_scr, (size_t)sneed))) {
         cleanup();
         return st;
     }
@@ -631,8 +708,7 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
         a.out = out;
         a.mode = 0;
         a.scratch = d_scr;
-        a.scratch_lanes = SCRATCH_LANES;
-        g_class_table[c].eri(a, s);
+        run_eri_class(g_class_table[c], a, sneed, s);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -679,12 +755,12 @@ hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld,
     PrimPair *d_prims = nullptr;
     EriTask *d_tasks = nullptr;
     double *d_scr = nullptr;
-    const int64_t slots = g_class_table[ci].tier == 1 ? g_class_table[ci].scratch_slots : 0;
+    const int64_t sneed = staged_need(g_class_table[ci], n);
     hipError_t e = hipMallocAsync((void **)&d_pairs, sizeof(PairInfo) * 2 * n, s);
     if (e == hipSuccess) e = hipMallocAsync((void **)&d_geo, sizeof(PairGeo) * 2 * n, s);
     if (e == hipSuccess) e = hipMallocAsync((void **)&d_prims, sizeof(PrimPair) * 2 * n, s);
     if (e == hipSuccess) e = hipMallocAsync((void **)&d_tasks, sizeof(EriTask) * n, s);
-    if (e == hipSuccess && slots) e = hipMallocAsync((void **)&d_scr, sizeof(double) * slots * SCRATCH_LANES, s);
+    if (e == hipSuccess && sneed) e = hipMallocAsync((void **)&d_scr, sizeof(double) * sneed, s);
     if (e != hipSuccess) {
         if (d_pairs) hipFreeAsync(d_pairs, s);
         if (d_geo) hipFreeAsync(d_geo, s);
@@ -697,8 +773,7 @@ hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld,
     a.tasks = d_tasks; a.ntask = n; a.pairs = d_pairs; a.geo = d_geo; a.prims = d_prims; a.boys = boys;
     a.out = out; a.mode = 0;
     a.scratch = d_scr;
-    a.scratch_lanes = SCRATCH_LANES;
-    g_class_table[ci].eri(a, s);
+    run_eri_class(g_class_table[ci], a, sneed, s);
     e = hipGetLastError();
     if (d_scr) hipFreeAsync(d_scr, s);
     hipFreeAsync(d_pairs, s);

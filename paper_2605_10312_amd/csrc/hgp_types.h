@@ -56,8 +56,8 @@ struct JKArgs {
     double *K;
     int32_t nbf;
     int32_t want_j, want_k;
-    double *scratch;        // staged classes: slot k of lane t at scratch[k * lanes + t]
-    int64_t scratch_lanes;  // lanes the scratch buffer holds (bounds the staged grid)
+    double *scratch;        // staged classes: slot k of batch quartet i at scratch[k * stride + i]
+    int64_t stride;         // slot stride of the staged buffer (>= quartets in the batch)
 };
 
 struct EriArgs {
@@ -70,7 +70,21 @@ struct EriArgs {
     double *out;
     int32_t mode;           // 0: write blocks, 1: Schwarz factor of a diagonal quartet into out[task]
     double *scratch;
-    int64_t scratch_lanes;
+    int64_t stride;
+};
+
+// Phase-1 kernel of a staged class: items i < n, pair indices at idx[i*istride]
+// (bra) and idx[i*istride + 1] (ket); accumulators to scratch[slot*stride + i].
+struct P1Args {
+    const int32_t *idx;
+    int64_t istride;
+    int64_t n;
+    const PairInfo *pairs;
+    const PairGeo *geo;
+    const PrimPair *prims;
+    const double *boys;
+    double *scratch;
+    int64_t stride;
 };
 
 // Boys table: F_m(T_k) for T_k = k * BOYS_STEP, k = 0 .. BOYS_NPTS-1, m = 0 .. BOYS_NORD-1,
@@ -81,21 +95,23 @@ constexpr double BOYS_TMAX = 36.0;
 constexpr int BOYS_NPTS = 722;
 constexpr int BOYS_NORD = 24;      // orders needed: L + 7 <= 23 for L <= 16
 
-// Lanes of the staged tier's scratch buffer: 256 CUs x 4 SIMDs x 2 waves x 64
-// lanes, enough for every wave the staged kernels can keep resident.
-constexpr int64_t SCRATCH_LANES = 131072;
+// Largest staged-tier buffer a plan allocates (doubles): 4 GiB.  Classes whose
+// quartets do not fit in one batch are processed in several.
+constexpr int64_t SCRATCH_MAX_DOUBLES = (int64_t)1 << 29;
 
-// Launchers take the number of work items and pick their own grid: register
-// classes one lane per item, staged classes a grid-stride loop over at most
-// scratch_lanes lanes.
+// Launchers run one lane per work item (nq or ntask): the register tier's
+// whole evaluation, or a staged class's Phase 2 + digestion; p1 launchers run
+// a staged class's Phase 1 over (item, chunk).
 typedef void (*launch_jk_fn)(const JKArgs &, hipStream_t);
 typedef void (*launch_eri_fn)(const EriArgs &, hipStream_t);
+typedef void (*launch_p1_fn)(const P1Args &, hipStream_t);
 
 struct ClassKernels {
     int la, lb, lc, ld;
     int tier;               // 0 register, 1 staged (HBM scratch)
     launch_jk_fn jk;
     launch_eri_fn eri;
+    launch_p1_fn p1;        // staged tier only (nullptr otherwise)
     int block;              // threads per block
     double vrr_flops;       // per primitive quartet (generator count)
     double p2_flops;        // per contracted quartet: HRR + transform

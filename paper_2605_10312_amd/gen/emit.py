@@ -102,40 +102,47 @@ def _p2_lines(p2, indent):
 
 
 def loop_prelude(L, ind):
-    """Primitive loops up to the VRR: pair combination, Boys F_0..F_L and the
-    VRR coefficients (Alg. 2's GaussianPairs and Boys steps)."""
+    """The primitive-quartet loop up to the VRR (Alg. 2's GaussianPairs and
+    Boys steps), flattened over bra x ket primitive pairs; the next
+    iteration's pair records are loaded while the current one computes."""
     i2 = ind + "    "
-    i3 = ind + "        "
     return [
         f"{ind}const double Ax = gb.ax, Ay = gb.ay, Az = gb.az;",
         f"{ind}const double Cx = gk.ax, Cy = gk.ay, Cz = gk.az;",
         f"{ind}const PrimPair *__restrict__ pbp = prims + pb.prim_off;",
         f"{ind}const PrimPair *__restrict__ pkp = prims + pk.prim_off;",
-        f"{ind}const int nbp = pb.nprim, nkp = pk.nprim;",
-        f"{ind}for (int ip = 0; ip < nbp; ++ip) {{",
-        f"{i2}const PrimPair bp = pbp[ip];",
-        f"{i2}const double zeta = bp.zeta, o2z = bp.o2z, Px = bp.px, Py = bp.py, Pz = bp.pz, Kb = bp.k;",
+        f"{ind}const int nkp = pk.nprim, ntot = pb.nprim * pk.nprim;",
+        f"{ind}double nzeta = pbp[0].zeta, no2z = pbp[0].o2z, nPx = pbp[0].px, nPy = pbp[0].py, nPz = pbp[0].pz, nKb = pbp[0].k;",
+        f"{ind}double neta = pkp[0].zeta, no2e = pkp[0].o2z, nQx = pkp[0].px, nQy = pkp[0].py, nQz = pkp[0].pz, nKk = pkp[0].k;",
+        f"{ind}int ip = 0, jp = 0;",
+        f"{ind}for (int t = 0; t < ntot; ++t) {{",
+        f"{i2}const double zeta = nzeta, o2z = no2z, Px = nPx, Py = nPy, Pz = nPz, Kb = nKb;",
+        f"{i2}const double eta = neta, o2e = no2e, Qx = nQx, Qy = nQy, Qz = nQz, Kk = nKk;",
+        f"{i2}if (++jp == nkp) {{ jp = 0; ++ip; }}",
+        f"{i2}if (t + 1 < ntot) {{",
+        f"{i2}    const PrimPair *b = pbp + ip, *k = pkp + jp;",
+        f"{i2}    nzeta = b->zeta; no2z = b->o2z; nPx = b->px; nPy = b->py; nPz = b->pz; nKb = b->k;",
+        f"{i2}    neta = k->zeta; no2e = k->o2z; nQx = k->px; nQy = k->py; nQz = k->pz; nKk = k->k;",
+        f"{i2}}}",
         f"{i2}const double PAx = Px - Ax, PAy = Py - Ay, PAz = Pz - Az;",
-        f"{i2}for (int jp = 0; jp < nkp; ++jp) {{",
-        f"{i3}const PrimPair kp = pkp[jp];",
-        f"{i3}const double eta = kp.zeta, o2e = kp.o2z, Qx = kp.px, Qy = kp.py, Qz = kp.pz;",
-        f"{i3}const double QCx = Qx - Cx, QCy = Qy - Cy, QCz = Qz - Cz;",
-        f"{i3}const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;",
-        f"{i3}const double ize = 1.0 / (zeta + eta);",
-        f"{i3}const double rz = eta * ize, re = zeta * ize, o2ze = 0.5 * ize;",
-        f"{i3}const double T = zeta * rz * (PQx * PQx + PQy * PQy + PQz * PQz);",
-        f"{i3}double F[{L + 1}];",
-        f"{i3}boys_fm<{L}>(T, boys, F);",
-        f"{i3}const double base = Kb * kp.k * sqrt(ize);",
-        f"{i3}const double WPx = -rz * PQx, WPy = -rz * PQy, WPz = -rz * PQz;",
-        f"{i3}const double WQx = re * PQx, WQy = re * PQy, WQz = re * PQz;",
-        f"{i3}(void)o2z; (void)o2e; (void)o2ze; (void)PAx; (void)PAy; (void)PAz; (void)QCx; (void)QCy; (void)QCz;",
-        f"{i3}(void)WPx; (void)WPy; (void)WPz; (void)WQx; (void)WQy; (void)WQz; (void)re;",
+        f"{i2}const double QCx = Qx - Cx, QCy = Qy - Cy, QCz = Qz - Cz;",
+        f"{i2}const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;",
+        f"{i2}const double ze = zeta + eta;",
+        f"{i2}const double ize = hgp_rcp(ze);",
+        f"{i2}const double rz = eta * ize, re = zeta * ize, o2ze = 0.5 * ize;",
+        f"{i2}const double T = zeta * rz * (PQx * PQx + PQy * PQy + PQz * PQz);",
+        f"{i2}double F[{L + 1}];",
+        f"{i2}boys_fm<{L}>(T, boys, F);",
+        f"{i2}const double base = Kb * Kk * hgp_rsqrt(ze);",
+        f"{i2}const double WPx = -rz * PQx, WPy = -rz * PQy, WPz = -rz * PQz;",
+        f"{i2}const double WQx = re * PQx, WQy = re * PQy, WQz = re * PQz;",
+        f"{i2}(void)o2z; (void)o2e; (void)o2ze; (void)PAx; (void)PAy; (void)PAz; (void)QCx; (void)QCy; (void)QCz;",
+        f"{i2}(void)WPx; (void)WPy; (void)WPz; (void)WQx; (void)WQy; (void)WQz; (void)re;",
     ]
 
 
 def loop_close(ind):
-    return [f"{ind}    }}", f"{ind}}}"]
+    return [f"{ind}}}"]
 
 
 def waves_attr(waves):
@@ -155,7 +162,7 @@ def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves
     nout = na * nb * nc * nd
     I = {k: v for k, v in p2.out.items()}
 
-    vlines, used = _vrr_lines(g, order, hnames, "            ")
+    vlines, used = _vrr_lines(g, order, hnames, "        ")
     out = []
     w = out.append
     w(f"// Generated: class ({la}{lb}|{lc}{ld}), axis rule {rule}, VRR order '{sched}' (PeakLive {pl}),")
@@ -310,11 +317,14 @@ def emit_table(metas):
     for m in metas:
         out.append(f"void launch_jk_{m.tag}(const JKArgs &, hipStream_t);")
         out.append(f"void launch_eri_{m.tag}(const EriArgs &, hipStream_t);")
+        if m.tier == 1:
+            out.append(f"void launch_p1_{m.tag}(const P1Args &, hipStream_t);")
     out.append("")
     out.append("extern const ClassKernels g_class_table[] = {")
     for m in metas:
         la, lb, lc, ld = m.ls
-        out.append(f"    {{{la}, {lb}, {lc}, {ld}, {m.tier}, launch_jk_{m.tag}, launch_eri_{m.tag}, {m.block}, "
+        p1 = f"launch_p1_{m.tag}" if m.tier == 1 else "nullptr"
+        out.append(f"    {{{la}, {lb}, {lc}, {ld}, {m.tier}, launch_jk_{m.tag}, launch_eri_{m.tag}, {p1}, {m.block}, "
                    f"{m.vrr_flops}.0, {m.p2_flops}.0, {m.n_hrr}, {m.peak_live}, {m.scratch_slots}, {m.chunks}}},")
     out.append("};")
     out.append(f"extern const int g_num_classes = {len(metas)};")

@@ -2,20 +2,25 @@
 bank and VRR frontier do not fit the register file together (Sec. III-C's
 Regime II; the paper's buffered Tier 2, Sec. III-C.2, redesigned for gfx950).
 
-Structure of one lane's work on one shell quartet (grid-stride loop, one
-wavefront per block, a lane-interleaved scratch buffer in HBM: slot k of lane
-t lives at scratch[k * lanes + t], so every access is coalesced):
+The class list is processed in batches of B quartets (B = the scratch
+buffer's lane count).  A slot-major buffer in HBM holds, for quartet i of the
+batch, slot k at scratch[k * B + i], so consecutive lanes touch consecutive
+addresses.  Per batch, two kernels:
 
-  Phase 1, chunk by chunk: the targets [e0|f0] are split by bra component e
-    into chunks of at most `cap` accumulators; each chunk runs the primitive
-    loops over only its own VRR subgraph (the sub-DAG reaching its targets),
-    keeps its accumulators in registers and stores them once to scratch.
-  Phase 2, bra stage, one ket component f at a time: load H[:, f], bra HRR,
-    T(la) then T(lb), store the spherical (m n|f) values over H[:, f]'s slots.
-  Phase 2, ket stage, one (m, n) at a time: load (m n|f) for all f, ket HRR,
-    T(lc) then T(ld), store the final integrals to their own slots.
-  Digestion (J/K kernel): the six contractions of the 8-fold symmetric
-    Scatter, each streaming the integrals back from scratch, FP64 atomics.
+  Kernel 1 (Phase 1): one lane per (quartet, chunk).  The targets [e0|f0] are
+    split by bra component e into chunks of at most `cap` accumulators; a
+    lane runs the primitive loops over only its chunk's VRR subgraph (the
+    sub-DAG reaching its targets), keeps the accumulators in registers and
+    stores them once.  Blocks alternate over chunks, so each wavefront runs
+    one chunk's code and small classes still fill the GPU.
+  Kernel 2 (Phase 2 + digestion), one lane per quartet:
+    bra stage, one ket component f at a time: load H[:, f], bra HRR, T(la)
+      then T(lb), store the spherical (m n|f) values over H[:, f]'s slots;
+    ket stage, one (m, n) at a time: load (m n|f) for all f, ket HRR, T(lc)
+      then T(ld), store the final integrals to their own slots;
+    digestion (J/K): the six contractions of the 8-fold symmetric Scatter,
+      each streaming the integrals back, FP64 atomics.  The integrals-out
+      variant copies them to the caller's layout instead.
 
 Compared with a single register-resident evaluation, chunking recomputes the
 VRR nodes shared between chunks (the generator reports the factor); in
@@ -136,42 +141,61 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
 
     out = []
     w = out.append
-    w(f"// Generated: class ({la}{lb}|{lc}{ld}), staged tier: {len(chunks)} Phase-1 chunks of <= {cap} accumulators")
+    nch = len(chunks)
+    w(f"// Generated: class ({la}{lb}|{lc}{ld}), staged tier: {nch} Phase-1 chunks of <= {cap} accumulators")
     w(f"// (VRR recomputation x{recompute:.2f}), axis rule {rule}, VRR order '{sched}'; {len(g.nodes)} VRR nodes,")
-    w(f"// {full} VRR FLOP per primitive quartet unchunked, N_hrr {n_h}, Phase-2 {p2.flops} FLOP, {nslots} scratch")
-    w(f"// slots per lane.")
+    w(f"// {full} VRR FLOP per primitive quartet unchunked, N_hrr {n_h}, Phase-2 {p2.flops} FLOP, {nslots} buffer")
+    w(f"// slots per quartet.")
     w('#include "hgp_device.h"')
     w("")
     w("namespace hgp {")
     w("namespace {")
     w("")
-    w(f"// Evaluates one shell quartet into scratch: integral (m n|l s) at slot {n_h} + ((m*{nb} + n)*{nc} + l)*{nd} + s.")
-    w(f"__device__ __forceinline__ void staged_{tag}(const PairInfo &pb, const PairGeo &gb, const PairInfo &pk,")
-    w(f"                                             const PairGeo &gk, const PrimPair *__restrict__ prims,")
-    w(f"                                             const double *__restrict__ boys, double *scr, const int64_t S)")
+    # ---------------------------------------------------------------- Phase 1 kernel
+    w(f"// Phase 1: item (block / {nch}) * {block} + thread, chunk = block % {nch}.")
+    w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void p1_{tag}(P1Args a)")
     w("{")
-    w("    HGP_STAGE(scr);")
+    w(f"    const int chunk = (int)(blockIdx.x % {nch});")
+    w(f"    const int64_t i = (int64_t)(blockIdx.x / {nch}) * {block} + threadIdx.x;")
+    w("    if (i >= a.n) return;")
+    w("    const int bra = a.idx[i * a.istride], ket = a.idx[i * a.istride + 1];")
+    w("    const PairInfo pb = a.pairs[bra], pk = a.pairs[ket];")
+    w("    const PairGeo gb = a.geo[bra], gk = a.geo[ket];")
+    w("    const PrimPair *__restrict__ prims = a.prims;")
+    w("    const double *__restrict__ boys = a.boys;")
+    w("    double *const sb = a.scratch;")
+    w("    const uint32_t S32 = (uint32_t)a.stride;")
+    w("    uint32_t li = (uint32_t)i;")
+    w("    switch (chunk) {")
     pos = {v: i for i, v in enumerate(order)}
     for ci, ch in enumerate(chunks):
         sub = subgraph(g, ch)
         corder = sorted(sub, key=lambda v: pos[v])
         Lc = max(g.nodes[v].key[2] for v in sub if g.nodes[v].kind == "base")
         tnames = {t: f"h{tslot[t]}" for t in ch}
-        w(f"    {{   // Phase 1, chunk {ci}: {len(ch)} accumulators, {len(sub)} VRR nodes")
+        w(f"    case {ci}: {{   // {len(ch)} accumulators, {len(sub)} VRR nodes")
         names = [tnames[t] for t in ch]
         for k in range(0, len(names), 8):
             w("        double " + ", ".join(f"{h} = 0.0" for h in names[k:k + 8]) + ";")
         out.extend(loop_prelude(Lc, "        "))
-        out.extend(_vrr_chunk_lines(g, corder, tnames, "                    "))
+        out.extend(_vrr_chunk_lines(g, corder, tnames, "            "))
         out.extend(loop_close("        "))
         for t in ch:
-            w(f"        scr[{tslot[t]} * S] = h{tslot[t]};")
+            w(f"        sb[{tslot[t]}u * S32 + li] = h{tslot[t]};")
+        w("        break;")
         w("    }")
-        w("    HGP_STAGE(scr);")
+    w("    default:")
+    w("        break;")
+    w("    }")
+    w("}")
+    w("")
+    # ---------------------------------------------------------------- Phase 2 (device function)
+    w(f"// Phase 2, bra stage, for one quartet whose accumulators sit in slots 0..{n_h - 1}: per ket")
+    w(f"// component f, the spherical (m n|f) values replace H[:, f] in place.")
+    w(f"__device__ __forceinline__ void bra_stage_{tag}(const PairGeo &gb, double *const sb, uint32_t li, const uint32_t S32)")
+    w("{")
     w("    const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz;")
-    w("    const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
-    w("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz;")
-    # ---- bra stage
+    w("    (void)ABx; (void)ABy; (void)ABz;")
     s2slot = {}
     for (f, a0, a1) in p2.bra_stages:
         ops = p2.ops[a0:a1]
@@ -185,142 +209,155 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
                 used.add(nm)
         w(f"    {{   // bra HRR + T(la) T(lb) for ket component {f}")
         for h in sorted(used, key=lambda x: hslot[x]):
-            w(f"        const double {h} = scr[{hslot[h]} * S];")
+            w(f"        const double {h} = sb[{hslot[h]}u * S32 + li];")
         for op in ops:
             w("        " + _op_line(op, {}))
         for (mu, nu) in outs:
             slot = hslot[hname_of[(E[mu * nb + nu], f)]]
             s2slot[(mu, nu, f)] = slot
-            w(f"        scr[{slot} * S] = {p2.s2[(mu, nu, f)]};")
+            w(f"        sb[{slot}u * S32 + li] = {p2.s2[(mu, nu, f)]};")
         w("    }")
-        w("    HGP_STAGE(scr);")
-    # ---- ket stage
+        w("    HGP_STAGE(li);")
+    w("}")
+    w("")
     F = list(levels(lc, lc + ld))
-    for (mu, nu, a0, a1) in p2.ket_stages:
+
+    def ket_stage(mu, nu, a0, a1, sink, ind="    "):
+        """Ket HRR + T(lc) T(ld) for bra functions (mu, nu); sink(lam, sig, name)
+        emits the use of each integral while it is still in a register."""
         ops = p2.ops[a0:a1]
-        w(f"    {{   // ket HRR + T(lc) T(ld) for bra functions ({mu}, {nu})")
+        w(f"{ind}{{   // ket HRR + T(lc) T(ld) for bra functions ({mu}, {nu})")
         ren = {}
         for k, f in enumerate(F):
             nm = p2.s2[(mu, nu, f)]
             ren[nm] = f"y{k}"
-            w(f"        const double y{k} = scr[{s2slot[(mu, nu, f)]} * S];")
+            w(f"{ind}    const double y{k} = sb[{s2slot[(mu, nu, f)]}u * S32 + li];")
         for op in ops:
-            w("        " + _op_line(op, ren))
+            w(f"{ind}    " + _op_line(op, ren))
         for lam in range(nc):
             for sig in range(nd):
                 nm = p2.out[(mu, nu, lam, sig)]
-                w(f"        scr[{islot(mu, nu, lam, sig)} * S] = {ren.get(nm, nm)};")
-        w("    }")
-        w("    HGP_STAGE(scr);")
-    w("}")
-    w("")
+                sink(mu, nu, lam, sig, ren.get(nm, nm), ind + "    ")
+        w(f"{ind}}}")
+        w(f"{ind}HGP_STAGE(li);")
 
-    def I(mu, nu, lam, sig):
-        return f"scr[{islot(mu, nu, lam, sig)} * S]"
-
-    # ---- J/K kernel
-    w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void jk_{tag}(JKArgs a)")
+    # ---------------------------------------------------------------- Phase 2 + digestion kernel
+    # Digestion of (m n|l s) with the 8-fold symmetric Scatter: the ket stages
+    # store the integrals, then six contractions stream them back
+    #   J'[ab] += 2s sum_ls I D[cd],  J'[cd] += 2s sum_mn I D[ab],
+    #   K'[ac] += s sum_ns I D[bd],   K'[bc] += s sum_ms I D[ad],
+    #   K'[ad] += s sum_nl I D[bc],   K'[bd] += s sum_ml I D[ac].
+    w(f"__global__ __launch_bounds__({block}) void jk_{tag}(JKArgs a)")
     w("{")
-    w(f"    const int64_t lane = (int64_t)blockIdx.x * {block} + threadIdx.x;")
-    w(f"    const int64_t S = (int64_t)gridDim.x * {block};")
-    w("    double *scr = a.scratch + lane;")
+    w(f"    const int64_t i = (int64_t)blockIdx.x * {block} + threadIdx.x;")
+    w("    if (i >= a.nq) return;")
+    w("    double *const sb = a.scratch;")
+    w("    const uint32_t S32 = (uint32_t)a.stride;")
+    w("    uint32_t li = (uint32_t)i;")
     w("    const double *__restrict__ D = a.D;")
     w("    const int N = a.nbf;")
-    w("    for (int64_t q = lane; q < a.nq; q += S) {")
-    w("        const int2 pq = a.quartets[q];")
-    w("        const PairInfo pb = a.pairs[pq.x], pk = a.pairs[pq.y];")
-    w("        const PairGeo gb = a.geo[pq.x], gk = a.geo[pq.y];")
-    w(f"        staged_{tag}(pb, gb, pk, gk, a.prims, a.boys, scr, S);")
-    w("        HGP_STAGE(scr);")
-    w("        const int fa = pb.fa, fb = pb.fb, fc = pk.fa, fd = pk.fb;")
-    w("        const double s = (pb.same ? 0.5 : 1.0) * (pk.same ? 0.5 : 1.0) * (pq.x == pq.y ? 0.5 : 1.0);")
+    w("    const int2 pq = a.quartets[i];")
+    w("    const PairInfo pb = a.pairs[pq.x], pk = a.pairs[pq.y];")
+    w("    const PairGeo gb = a.geo[pq.x], gk = a.geo[pq.y];")
+    w(f"    bra_stage_{tag}(gb, sb, li, S32);")
+    w("    const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
+    w("    (void)CDx; (void)CDy; (void)CDz;")
+    w("    const int fa = pb.fa, fb = pb.fb, fc = pk.fa, fd = pk.fb;")
+    w("    const double s = (pb.same ? 0.5 : 1.0) * (pk.same ? 0.5 : 1.0) * (pq.x == pq.y ? 0.5 : 1.0);")
+    w("    const double sj = a.want_j ? 2.0 * s : 0.0, sk = a.want_k ? s : 0.0;")
 
-    def contraction(outer, inner, dexpr, target, scale):
+    def store_sink(mu, nu, lam, sig, name, ind):
+        w(f"{ind}sb[{islot(mu, nu, lam, sig)}u * S32 + li] = {name};")
+
+    for (mu, nu, a0, a1) in p2.ket_stages:
+        ket_stage(mu, nu, a0, a1, store_sink)
+
+    def I(mu, nu, lam, sig):
+        return f"sb[{islot(mu, nu, lam, sig)}u * S32 + li]"
+
+    def contraction(outer, inner, target, scale):
+        """One output element at a time: a dot product of integrals streamed
+        from the buffer with D entries, then one atomic."""
         for o in outer:
             terms = inner(*o)
             expr = f"{terms[0][0]} * {terms[0][1]}"
             for x, y in terms[1:]:
                 expr = f"fma({x}, {y}, {expr})"
-            w(f"                atomicAdd({target(*o)}, {scale} * ({expr}));")
-        w("                HGP_STAGE(scr);")
+            w(f"        atomicAdd({target(*o)}, {scale} * ({expr}));")
+            w("        HGP_STAGE(li);")
 
-    w("        if (a.want_j) {")
-    w("            const double s2 = 2.0 * s;")
-    w("            {")
+    w("    if (a.want_j) {")
     contraction([(mu, nu) for mu in range(na) for nu in range(nb)],
-                lambda mu, nu: [(I(mu, nu, lam, sig), f"D[(fc + {lam}) * N + fd + {sig}]")
+                lambda mu, nu: [(I(mu, nu, lam, sig), f"D[(int64_t)(fc + {lam}) * N + fd + {sig}]")
                                 for lam in range(nc) for sig in range(nd)],
-                None, lambda mu, nu: f"a.J + (fa + {mu}) * N + fb + {nu}", "s2")
+                lambda mu, nu: f"a.J + (int64_t)(fa + {mu}) * N + fb + {nu}", "sj")
     contraction([(lam, sig) for lam in range(nc) for sig in range(nd)],
-                lambda lam, sig: [(I(mu, nu, lam, sig), f"D[(fa + {mu}) * N + fb + {nu}]")
+                lambda lam, sig: [(I(mu, nu, lam, sig), f"D[(int64_t)(fa + {mu}) * N + fb + {nu}]")
                                   for mu in range(na) for nu in range(nb)],
-                None, lambda lam, sig: f"a.J + (fc + {lam}) * N + fd + {sig}", "s2")
-    w("            }")
-    w("        }")
-    w("        if (a.want_k) {")
-    w("            {")
+                lambda lam, sig: f"a.J + (int64_t)(fc + {lam}) * N + fd + {sig}", "sj")
+    w("    }")
+    w("    if (a.want_k) {")
     contraction([(mu, lam) for mu in range(na) for lam in range(nc)],
-                lambda mu, lam: [(I(mu, nu, lam, sig), f"D[(fb + {nu}) * N + fd + {sig}]")
+                lambda mu, lam: [(I(mu, nu, lam, sig), f"D[(int64_t)(fb + {nu}) * N + fd + {sig}]")
                                  for nu in range(nb) for sig in range(nd)],
-                None, lambda mu, lam: f"a.K + (fa + {mu}) * N + fc + {lam}", "s")
+                lambda mu, lam: f"a.K + (int64_t)(fa + {mu}) * N + fc + {lam}", "sk")
     contraction([(nu, lam) for nu in range(nb) for lam in range(nc)],
-                lambda nu, lam: [(I(mu, nu, lam, sig), f"D[(fa + {mu}) * N + fd + {sig}]")
+                lambda nu, lam: [(I(mu, nu, lam, sig), f"D[(int64_t)(fa + {mu}) * N + fd + {sig}]")
                                  for mu in range(na) for sig in range(nd)],
-                None, lambda nu, lam: f"a.K + (fb + {nu}) * N + fc + {lam}", "s")
+                lambda nu, lam: f"a.K + (int64_t)(fb + {nu}) * N + fc + {lam}", "sk")
     contraction([(mu, sig) for mu in range(na) for sig in range(nd)],
-                lambda mu, sig: [(I(mu, nu, lam, sig), f"D[(fb + {nu}) * N + fc + {lam}]")
+                lambda mu, sig: [(I(mu, nu, lam, sig), f"D[(int64_t)(fb + {nu}) * N + fc + {lam}]")
                                  for nu in range(nb) for lam in range(nc)],
-                None, lambda mu, sig: f"a.K + (fa + {mu}) * N + fd + {sig}", "s")
+                lambda mu, sig: f"a.K + (int64_t)(fa + {mu}) * N + fd + {sig}", "sk")
     contraction([(nu, sig) for nu in range(nb) for sig in range(nd)],
-                lambda nu, sig: [(I(mu, nu, lam, sig), f"D[(fa + {mu}) * N + fc + {lam}]")
+                lambda nu, sig: [(I(mu, nu, lam, sig), f"D[(int64_t)(fa + {mu}) * N + fc + {lam}]")
                                  for mu in range(na) for lam in range(nc)],
-                None, lambda nu, sig: f"a.K + (fb + {nu}) * N + fd + {sig}", "s")
-    w("            }")
-    w("        }")
+                lambda nu, sig: f"a.K + (int64_t)(fb + {nu}) * N + fd + {sig}", "sk")
     w("    }")
     w("}")
     w("")
-    # ---- integrals-out kernel
+    # ---------------------------------------------------------------- Phase 2 + integrals-out kernel
     diag_class = (la, lb) == (lc, ld)
-    w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void eri_{tag}(EriArgs a)")
+    w(f"__global__ __launch_bounds__({block}) void eri_{tag}(EriArgs a)")
     w("{")
-    w(f"    const int64_t lane = (int64_t)blockIdx.x * {block} + threadIdx.x;")
-    w(f"    const int64_t S = (int64_t)gridDim.x * {block};")
-    w("    double *scr = a.scratch + lane;")
-    w("    for (int64_t q = lane; q < a.ntask; q += S) {")
-    w("        const EriTask t = a.tasks[q];")
-    w("        const PairInfo pb = a.pairs[t.bra], pk = a.pairs[t.ket];")
-    w("        const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];")
-    w(f"        staged_{tag}(pb, gb, pk, gk, a.prims, a.boys, scr, S);")
-    w("        HGP_STAGE(scr);")
+    w(f"    const int64_t i = (int64_t)blockIdx.x * {block} + threadIdx.x;")
+    w("    if (i >= a.ntask) return;")
+    w("    double *const sb = a.scratch;")
+    w("    const uint32_t S32 = (uint32_t)a.stride;")
+    w("    uint32_t li = (uint32_t)i;")
+    w("    const EriTask t = a.tasks[i];")
+    w("    const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];")
+    w(f"    bra_stage_{tag}(gb, sb, li, S32);")
+    w("    const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
+    w("    (void)CDx; (void)CDy; (void)CDz;")
+    w("    double *__restrict__ o = a.out + t.off;")
     if diag_class:
-        w("        if (a.mode == 1) {")
-        w("            double m = 0.0;")
-        for mu in range(na):
-            for nu in range(nb):
-                w(f"            m = fmax(m, fabs({I(mu, nu, mu, nu)}));")
-        w("            a.out[q] = sqrt(m);")
-        w("            continue;")
-        w("        }")
-    w("        double *__restrict__ o = a.out + t.off;")
-    for mu in range(na):
-        for nu in range(nb):
-            for lam in range(nc):
-                for sig in range(nd):
-                    w(f"        o[{mu} * t.s0 + {nu} * t.s1 + {lam} * t.s2 + {sig} * t.s3] = {I(mu, nu, lam, sig)};")
-    w("    }")
+        w("    double dmax = 0.0;")
+
+    def eri_sink(mu, nu, lam, sig, name, ind):
+        if diag_class and (mu, nu) == (lam, sig):
+            w(f"{ind}dmax = fmax(dmax, fabs({name}));")
+        w(f"{ind}if (a.mode == 0) o[{mu} * t.s0 + {nu} * t.s1 + {lam} * t.s2 + {sig} * t.s3] = {name};")
+
+    for (mu, nu, a0, a1) in p2.ket_stages:
+        ket_stage(mu, nu, a0, a1, eri_sink)
+    if diag_class:
+        w("    if (a.mode == 1) a.out[i] = sqrt(dmax);")
     w("}")
     w("")
     w("}  // namespace")
     w("")
+    w(f"void launch_p1_{tag}(const P1Args &a, hipStream_t s)")
+    w("{")
+    w(f"    const int64_t blocks = (a.n + {block - 1}) / {block};")
+    w(f"    if (blocks > 0) hipLaunchKernelGGL(p1_{tag}, dim3((unsigned)(blocks * {nch})), dim3({block}), 0, s, a);")
+    w("}")
     for kind, cnt in (("jk", "nq"), ("eri", "ntask")):
         args = "JKArgs" if kind == "jk" else "EriArgs"
         w(f"void launch_{kind}_{tag}(const {args} &a, hipStream_t s)")
         w("{")
-        w(f"    int64_t grid = (a.{cnt} + {block - 1}) / {block};")
-        w(f"    const int64_t cap = a.scratch_lanes / {block};")
-        w("    if (grid > cap) grid = cap;")
-        w(f"    if (grid > 0) hipLaunchKernelGGL({kind}_{tag}, dim3((unsigned)grid), dim3({block}), 0, s, a);")
+        w(f"    const int64_t blocks = (a.{cnt} + {block - 1}) / {block};")
+        w(f"    if (blocks > 0) hipLaunchKernelGGL({kind}_{tag}, dim3((unsigned)blocks), dim3({block}), 0, s, a);")
         w("}")
     w("")
     w("}  // namespace hgp")

@@ -41,6 +41,42 @@ def load_table(path=TABLE):
     return {}
 
 
+CAPS = (128, 96, 64, 48, 32, 24, 16)
+
+
+def chunk_demand(g, order, chunk):
+    """Accumulators + PeakLive of one chunk's subgraph in the given order, + 40."""
+    from .emit_staged import subgraph
+    sub = subgraph(g, chunk)
+    pos = [v for v in order if v in sub]
+    idx = {v: i for i, v in enumerate(pos)}
+    last = {}
+    for v in pos:
+        for c in g.children[v]:
+            if c in idx:
+                last[v] = max(last.get(v, -1), idx[c])
+    live = peak = 0
+    dies = {}
+    for i, v in enumerate(pos):
+        if last.get(v, -1) > i:
+            live += 1
+            dies.setdefault(last[v], []).append(v)
+        peak = max(peak, live)
+        live -= len(dies.pop(i, ()))
+    return len(chunk) + peak + 40
+
+
+def model_cap(ls):
+    """Largest chunk cap whose every chunk fits the register line."""
+    from .emit_staged import chunk_targets
+    g = vrrmod.VRRGraph(*ls)
+    _, _, order = vrrmod.best_order(g)
+    for cap in CAPS:
+        if all(chunk_demand(g, order, c) <= REGISTER_DOUBLES for c in chunk_targets(g, cap)):
+            return cap
+    return CAPS[-1]
+
+
 def route(ls, table=None):
     """-> dict(tier=0|1, cap=int, waves=int, source='model'|'table')"""
     tag = "".join(str(x) for x in ls)
@@ -52,4 +88,5 @@ def route(ls, table=None):
         t["source"] = "table"
         return t
     tier = 0 if model_demand(ls) <= REGISTER_DOUBLES else 1
-    return {"tier": tier, "cap": DEFAULT_CAP, "waves": 0, "source": "model"}
+    cap = model_cap(ls) if tier == 1 else DEFAULT_CAP
+    return {"tier": tier, "cap": cap, "waves": 0, "source": "model"}
