@@ -192,6 +192,7 @@ def main():
                                "N=420, Schwarz tau=1e-12, J+K in FP64",
                    "nbf": int(bw.nbf), "shells": int(bw.nshell), "tau": TAU,
                    "quartets_kept": stats["quartets_kept"], "quartets_total": stats["quartets_total"],
+                   "prim_pairs_kept": stats["prim_pairs_kept"], "prim_pairs_total": stats["prim_pairs_total"],
                    "eris_per_step": int(eris)},
         "roofline": roofline,
         "cpu_baseline": cpu,

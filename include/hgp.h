@@ -94,6 +94,12 @@ hgp_status hgp_basis_destroy(hgp_basis *b);
  * canonical class (la lb|lc ld) the list of unique quartets with
  * Q_ab Q_cd >= schwarz_tau (0: keep all).  All of it is computed by device
  * kernels on hip_stream; the call waits for the stream before returning.
+ * With schwarz_tau > 0 the plan also drops primitive pairs: with q_r the
+ * Schwarz factor of primitive pair r (contraction coefficients included),
+ * Qmax the largest q over the basis and P the largest primitive-pair count of
+ * a shell pair, pair r is left out when q_r Qmax < 0.1 schwarz_tau / P^2, so
+ * the part dropped from any one integral is below 0.1 schwarz_tau.  With
+ * schwarz_tau = 0 nothing is dropped and every integral is the exact sum.
  *   precision         HGP_FP64
  *   hbm_budget_bytes  0 = unlimited; otherwise HGP_E_OOM if the plan needs more
  */
@@ -102,6 +108,8 @@ hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t preci
 hgp_status hgp_plan_destroy(hgp_plan *p);
 /* Plan statistics: unique quartets kept after screening, candidate quartets, device bytes held. */
 hgp_status hgp_plan_stats(const hgp_plan *p, int64_t *quartets_kept, int64_t *quartets_total, int64_t *device_bytes);
+/* Primitive pairs held by the plan's shell pairs after and before primitive-pair screening. */
+hgp_status hgp_plan_prim_stats(const hgp_plan *p, int64_t *prim_pairs_kept, int64_t *prim_pairs_total);
 /* Per class c (0 .. n-1, n = hgp_plan_num_classes, in launch order): angular momenta ls[4], quartets
  * kept, primitive quartets they hold, the generator's FLOP counts per primitive quartet (VRR +
  * accumulate, unchunked) and per contracted quartet (Phase 2), and the tier (0 register, 1 staged). */
@@ -110,7 +118,8 @@ hgp_status hgp_plan_class_info(const hgp_plan *p, int32_t c, int32_t *ls, int64_
                                double *vrr_flops, double *phase2_flops, int32_t *tier);
 
 /* The plan's Schwarz factors by shell: Q[i*nshell + j] = Q[j*nshell + i] =
- * sqrt(max |(mn|mn)|) over m in shell i, n in shell j (host array, nshell^2). */
+ * sqrt(max |(mn|mn)|) over m in shell i, n in shell j (host array, nshell^2),
+ * from the primitive pairs the plan kept; 0 for a shell pair with none kept. */
 hgp_status hgp_plan_schwarz(const hgp_plan *p, double *Q);
 
 /*

@@ -30,6 +30,7 @@ SIGNATURES = {
     "hgp_plan_create": (ctypes.c_int, [_vp, _d, _i32, _sz, _vp, ctypes.POINTER(_vp)]),
     "hgp_plan_destroy": (ctypes.c_int, [_vp]),
     "hgp_plan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "hgp_plan_prim_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "hgp_plan_num_classes": (_i32, [_vp]),
     "hgp_plan_class_info": (ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                            ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i32)]),
@@ -139,7 +140,10 @@ class Plan:
     def stats(self):
         k, t, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().hgp_plan_stats(self.handle, ctypes.byref(k), ctypes.byref(t), ctypes.byref(b)))
-        return {"quartets_kept": k.value, "quartets_total": t.value, "device_bytes": b.value}
+        pk, pt = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().hgp_plan_prim_stats(self.handle, ctypes.byref(pk), ctypes.byref(pt)))
+        return {"quartets_kept": k.value, "quartets_total": t.value, "device_bytes": b.value,
+                "prim_pairs_kept": pk.value, "prim_pairs_total": pt.value}
 
     def classes(self):
         out = []

@@ -183,6 +183,7 @@ struct hgp_plan {
     int64_t scratch_doubles = 0;
     std::vector<ClassList> lists;
     int64_t kept = 0, total = 0, bytes = 0;
+    int64_t prim_total = 0, prim_kept = 0;   // primitive pairs before / after primitive screening
     bool timing = false;
     std::vector<PendingTiming> pending;
     std::vector<hipEvent_t> event_pool;
@@ -305,6 +306,62 @@ hgp_status hgp_plan_destroy(hgp_plan *p)
     return HGP_OK;
 }
 
+// Schwarz factors sqrt(max |(mn|mn)|) of npair pairs grouped by pair class
+// (class c occupies [begin[c], begin[c] + count[c])), from the diagonal quartets
+// (p|p) run through the class kernels' integrals-out mode.  q: device, npair.
+static hgp_status schwarz_factors(const PairInfo *d_pairs, const PairGeo *d_geo, const PrimPair *d_prims,
+                                  const std::vector<int> &begin, const std::vector<int> &count, int npair,
+                                  const double *boys, double *q, hipStream_t s)
+{
+    if (npair <= 0) return HGP_OK;
+    const int npc = (int)begin.size();
+    EriTask *tasks = nullptr;
+    double *sscr = nullptr;
+    int64_t sneed = 0;
+    std::vector<int> cls(npc, -1);
+    for (int c = 0; c < npc; ++c) {
+        if (!count[c]) continue;
+        int la = 0;
+        while (pair_class_of(la + 1, 0) <= c) ++la;
+        const int lb = c - pair_class_of(la, 0);
+        cls[c] = class_index(la, lb, la, lb);
+        if (cls[c] < 0) return fail(HGP_E_UNSUPPORTED_L, "class kernel not built");
+        sneed = std::max(sneed, staged_need(g_class_table[cls[c]], count[c]));
+    }
+    hgp_status st;
+    if ((st = dalloc(&tasks, (size_t)npair)) || (st = dalloc(&sscr, (size_t)sneed))) { hipFree(tasks); return st; }
+    std::vector<EriTask> th((size_t)npair);
+    for (int i = 0; i < npair; ++i) th[i] = EriTask{i, i, 0, 0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(tasks, th.data(), th.size() * sizeof(EriTask), hipMemcpyHostToDevice, s);
+    for (int c = 0; c < npc && e == hipSuccess; ++c) {
+        if (!count[c]) continue;
+        EriArgs a{};
+        a.tasks = tasks + begin[c];
+        a.ntask = count[c];
+        a.pairs = d_pairs; a.geo = d_geo; a.prims = d_prims; a.boys = boys;
+        a.out = q + begin[c];
+        a.mode = 1;
+        a.scratch = sscr;
+        run_eri_class(g_class_table[cls[c]], a, sneed, s);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(tasks);
+    hipFree(sscr);
+    if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("Schwarz kernels: ") + hipGetErrorString(e));
+    return HGP_OK;
+}
+
+// Primitive-pair screening.  The contribution of one primitive quartet (r|s)
+// to any integral of its contracted quartet is bounded by q_r q_s <= q_r Qmax,
+// with q_r the Schwarz factor of primitive pair r (contraction coefficients
+// included) and Qmax the largest over the basis.  A primitive pair is dropped
+// when q_r Qmax < PRIM_SCREEN_FRACTION * tau / P^2, where P is the largest
+// primitive-pair count of any shell pair, so P^2 bounds the primitive quartets
+// of a contracted quartet: what is dropped from one integral stays below a
+// tenth of the Schwarz threshold tau.
+constexpr double PRIM_SCREEN_FRACTION = 0.1;
+
 static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t s)
 {
     const hgp_basis *b = p->b;
@@ -324,77 +381,167 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
             pi.cls = pair_class_of(li, lj);
             per[pi.cls].push_back(pi);
         }
-    std::vector<PairInfo> pairs;
-    p->pc_begin.assign(npc, 0);
-    p->pc_count.assign(npc, 0);
-    int prim_off = 0;
-    for (int c = 0; c < npc; ++c) {
-        std::stable_sort(per[c].begin(), per[c].end(), [](const PairInfo &x, const PairInfo &y) { return x.nprim > y.nprim; });
-        p->pc_begin[c] = (int)pairs.size();
-        p->pc_count[c] = (int)per[c].size();
-        for (auto &pi : per[c]) {
-            pi.prim_off = prim_off;
-            prim_off += pi.nprim;
-            pairs.push_back(pi);
+    auto layout = [&](std::vector<std::vector<PairInfo>> &groups, std::vector<PairInfo> &flat) {
+        flat.clear();
+        p->pc_begin.assign(npc, 0);
+        p->pc_count.assign(npc, 0);
+        int off = 0;
+        for (int c = 0; c < npc; ++c) {
+            std::stable_sort(groups[c].begin(), groups[c].end(),
+                             [](const PairInfo &x, const PairInfo &y) { return x.nprim > y.nprim; });
+            p->pc_begin[c] = (int)flat.size();
+            p->pc_count[c] = (int)groups[c].size();
+            for (auto &pi : groups[c]) {
+                pi.prim_off = off;
+                off += pi.nprim;
+                flat.push_back(pi);
+            }
         }
-    }
-    p->npair = (int)pairs.size();
-    p->pairs = pairs;
+        return off;
+    };
+    std::vector<PairInfo> pairs;
+    int prim_off = layout(per, pairs);
+    // candidate unique quartets over all shell pairs, before any screening
+    p->total = 0;
+    for (int bc = 0; bc < npc; ++bc)
+        for (int kc = 0; kc <= bc; ++kc) {
+            const int64_t nb = p->pc_count[bc], nk = p->pc_count[kc];
+            p->total += (bc == kc) ? nb * (nb + 1) / 2 : nb * nk;
+        }
     const int64_t nbf = b->nbf;
     const int64_t need = (int64_t)pairs.size() * (sizeof(PairInfo) + sizeof(PairGeo) + 2 * sizeof(double)) +
                          (int64_t)prim_off * sizeof(PrimPair) + 2 * nbf * nbf * (int64_t)sizeof(double);
     if (budget && (size_t)need > budget) return fail(HGP_E_OOM, "plan exceeds the HBM budget (pair data and accumulators)");
     hgp_status st;
-    if ((st = upload(&p->d_pairs, pairs, &p->bytes)) || (st = dalloc(&p->d_geo, pairs.size(), &p->bytes)) ||
-        (st = dalloc(&p->d_prims, (size_t)prim_off, &p->bytes)) || (st = dalloc(&p->d_Q, pairs.size(), &p->bytes)) ||
-        (st = dalloc(&p->d_Jacc, (size_t)(nbf * nbf), &p->bytes)) || (st = dalloc(&p->d_Kacc, (size_t)(nbf * nbf), &p->bytes)))
+    PairInfo *d_pairs = nullptr;
+    PairGeo *d_geo = nullptr;
+    PrimPair *d_prims = nullptr;
+    auto free_tmp = [&]() { hipFree(d_pairs); hipFree(d_geo); hipFree(d_prims); d_pairs = nullptr; d_geo = nullptr; d_prims = nullptr; };
+    if ((st = upload(&d_pairs, pairs)) || (st = dalloc(&d_geo, pairs.size())) || (st = dalloc(&d_prims, (size_t)prim_off))) {
+        free_tmp();
         return st;
-    launch_pairs(p->npair, p->d_pairs, b->d_cen, b->d_poff, b->d_exps, b->d_ncoef, p->d_geo, p->d_prims, s);
+    }
+    launch_pairs((int)pairs.size(), d_pairs, b->d_cen, b->d_poff, b->d_exps, b->d_ncoef, d_geo, d_prims, s);
     HGP_HIP(hipGetLastError());
     const double *boys = nullptr;
-    if ((st = boys_table(p->device, &boys))) return st;
+    if ((st = boys_table(p->device, &boys))) { free_tmp(); return st; }
 
-    // ---- Schwarz factors: diagonal quartets (p|p) of every pair class
+    // ---- primitive-pair screening (skipped when tau = 0: the path stays exact)
+    if (tau > 0 && prim_off > 0) {
+        std::vector<PairGeo> geo(pairs.size());
+        std::vector<PrimPair> recs((size_t)prim_off);
+        HGP_HIP(hipMemcpyAsync(geo.data(), d_geo, geo.size() * sizeof(PairGeo), hipMemcpyDeviceToHost, s));
+        HGP_HIP(hipMemcpyAsync(recs.data(), d_prims, recs.size() * sizeof(PrimPair), hipMemcpyDeviceToHost, s));
+        HGP_HIP(hipStreamSynchronize(s));
+        // one single-primitive pair per record; records of a class are contiguous
+        std::vector<PairInfo> pp((size_t)prim_off);
+        std::vector<PairGeo> pg((size_t)prim_off);
+        std::vector<int> pbeg(npc, 0), pcnt(npc, 0);
+        for (int c = 0; c < npc; ++c) {
+            for (int k = 0; k < p->pc_count[c]; ++k) {
+                const int pi = p->pc_begin[c] + k;
+                if (k == 0) pbeg[c] = pairs[pi].prim_off;
+                pcnt[c] += pairs[pi].nprim;
+                for (int r = 0; r < pairs[pi].nprim; ++r) {
+                    PairInfo x = pairs[pi];
+                    x.prim_off = pairs[pi].prim_off + r;
+                    x.nprim = 1;
+                    pp[(size_t)x.prim_off] = x;
+                    pg[(size_t)x.prim_off] = geo[pi];
+                }
+            }
+        }
+        PairInfo *d_pp = nullptr;
+        PairGeo *d_pg = nullptr;
+        double *d_qp = nullptr;
+        if ((st = upload(&d_pp, pp)) || (st = upload(&d_pg, pg)) || (st = dalloc(&d_qp, (size_t)prim_off)) ||
+            (st = schwarz_factors(d_pp, d_pg, d_prims, pbeg, pcnt, prim_off, boys, d_qp, s))) {
+            hipFree(d_pp); hipFree(d_pg); hipFree(d_qp); free_tmp();
+            return st;
+        }
+        std::vector<double> qp((size_t)prim_off);
+        hipError_t e = hipMemcpy(qp.data(), d_qp, qp.size() * sizeof(double), hipMemcpyDeviceToHost);
+        hipFree(d_pp); hipFree(d_pg); hipFree(d_qp);
+        if (e != hipSuccess) { free_tmp(); return fail(HGP_E_DEVICE, "copying primitive Schwarz factors"); }
+        double qmax = 0.0;
+        for (double x : qp) qmax = std::max(qmax, x);
+        int pmax = 1;
+        for (const PairInfo &x : pairs) pmax = std::max(pmax, x.nprim);
+        const double cut = PRIM_SCREEN_FRACTION * tau / ((double)pmax * (double)pmax);
+        // rebuild the pairs with only the primitive pairs that matter
+        std::vector<std::vector<PairInfo>> kept(npc);
+        std::vector<std::vector<int>> keep_recs(pairs.size());
+        std::vector<PairGeo> kgeo_by_pair(pairs.size());
+        for (size_t pi = 0; pi < pairs.size(); ++pi) {
+            for (int r = 0; r < pairs[pi].nprim; ++r) {
+                const int rr = pairs[pi].prim_off + r;
+                if (qp[(size_t)rr] * qmax >= cut) keep_recs[pi].push_back(rr);
+            }
+            if (keep_recs[pi].empty()) continue;   // no primitive quartet of this pair matters
+            PairInfo x = pairs[pi];
+            x.nprim = (int)keep_recs[pi].size();
+            x.prim_off = (int)pi;                   // temporarily: index of the original pair
+            kept[x.cls].push_back(x);
+        }
+        std::vector<PairInfo> np;
+        int noff = 0;
+        {
+            // keep the original pair index to gather records and geometry
+            std::vector<std::vector<PairInfo>> groups = kept;
+            std::vector<int> orig;
+            p->pc_begin.assign(npc, 0);
+            p->pc_count.assign(npc, 0);
+            for (int c = 0; c < npc; ++c) {
+                std::stable_sort(groups[c].begin(), groups[c].end(),
+                                 [](const PairInfo &x, const PairInfo &y) { return x.nprim > y.nprim; });
+                p->pc_begin[c] = (int)np.size();
+                p->pc_count[c] = (int)groups[c].size();
+                for (auto &x : groups[c]) {
+                    orig.push_back(x.prim_off);
+                    x.prim_off = noff;
+                    noff += x.nprim;
+                    np.push_back(x);
+                }
+            }
+            std::vector<PrimPair> nrec((size_t)noff);
+            std::vector<PairGeo> ngeo(np.size());
+            for (size_t k = 0; k < np.size(); ++k) {
+                ngeo[k] = geo[(size_t)orig[k]];
+                const auto &rs = keep_recs[(size_t)orig[k]];
+                for (size_t t = 0; t < rs.size(); ++t) nrec[(size_t)np[k].prim_off + t] = recs[(size_t)rs[t]];
+            }
+            free_tmp();
+            if ((st = upload(&d_pairs, np)) || (st = upload(&d_geo, ngeo)) || (st = upload(&d_prims, nrec))) {
+                free_tmp();
+                return st;
+            }
+        }
+        p->prim_total = prim_off;
+        pairs = np;
+        prim_off = noff;
+    } else {
+        p->prim_total = prim_off;
+    }
+    p->prim_kept = prim_off;
+    p->npair = (int)pairs.size();
+    p->pairs = pairs;
+    p->d_pairs = d_pairs; p->d_geo = d_geo; p->d_prims = d_prims;
+    p->bytes += (int64_t)pairs.size() * (sizeof(PairInfo) + sizeof(PairGeo)) + (int64_t)prim_off * sizeof(PrimPair);
+    if ((st = dalloc(&p->d_Q, pairs.size(), &p->bytes)) || (st = dalloc(&p->d_Jacc, (size_t)(nbf * nbf), &p->bytes)) ||
+        (st = dalloc(&p->d_Kacc, (size_t)(nbf * nbf), &p->bytes)))
+        return st;
+
+    // ---- Schwarz factors of the contracted pairs
     if (p->npair > 0) {
         double *qv = nullptr;
-        EriTask *tasks = nullptr;
-        double *sscr = nullptr;
-        int64_t sneed = 0;
-        for (int c = 0; c < npc; ++c) {
-            if (!p->pc_count[c]) continue;
-            int la = 0;
-            while (pair_class_of(la + 1, 0) <= c) ++la;
-            const int ci = class_index(la, c - pair_class_of(la, 0), la, c - pair_class_of(la, 0));
-            if (ci >= 0) sneed = std::max(sneed, staged_need(g_class_table[ci], p->pc_count[c]));
-        }
-        if ((st = dalloc(&qv, pairs.size())) || (st = dalloc(&tasks, pairs.size())) ||
-            (st = dalloc(&sscr, (size_t)sneed))) { hipFree(qv); hipFree(tasks); return st; }
-        std::vector<EriTask> th(pairs.size());
-        for (int i = 0; i < p->npair; ++i) th[i] = EriTask{i, i, 0, 0, 0, 0, 0};
-        HGP_HIP(hipMemcpyAsync(tasks, th.data(), th.size() * sizeof(EriTask), hipMemcpyHostToDevice, s));
-        for (int c = 0; c < npc; ++c) {
-            if (!p->pc_count[c]) continue;
-            int la = 0;
-            while (pair_class_of(la + 1, 0) <= c) ++la;
-            const int lb = c - pair_class_of(la, 0);
-            const int ci = class_index(la, lb, la, lb);
-            if (ci < 0) { hipFree(qv); hipFree(tasks); return fail(HGP_E_UNSUPPORTED_L, "class kernel not built"); }
-            EriArgs a{};
-            a.tasks = tasks + p->pc_begin[c];
-            a.ntask = p->pc_count[c];
-            a.pairs = p->d_pairs; a.geo = p->d_geo; a.prims = p->d_prims; a.boys = boys;
-            a.out = qv + p->pc_begin[c];
-            a.mode = 1;
-            a.scratch = sscr;
-            run_eri_class(g_class_table[ci], a, sneed, s);
-        }
+        if ((st = dalloc(&qv, pairs.size()))) return st;
+        st = schwarz_factors(p->d_pairs, p->d_geo, p->d_prims, p->pc_begin, p->pc_count, p->npair, boys, qv, s);
+        if (st) { hipFree(qv); return st; }
         launch_store_q(p->npair, qv, p->d_geo, p->d_Q, s);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         hipFree(qv);
-        hipFree(tasks);
-        hipFree(sscr);
-        if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("Schwarz kernels: ") + hipGetErrorString(e));
+        if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("storing Schwarz factors: ") + hipGetErrorString(e));
     }
 
     // ---- screened unique-quartet lists per canonical class
@@ -415,7 +562,6 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
             if (ci < 0) { hipFree(d_counts); hipFree(d_total); return fail(HGP_E_UNSUPPORTED_L, "class kernel not built"); }
             const int sym = (bc == kc);
             const int b0 = p->pc_begin[bc], k0 = p->pc_begin[kc];
-            p->total += sym ? (int64_t)nb * (nb + 1) / 2 : (int64_t)nb * nk;
             const double t = tau > 0 ? tau : -1.0;
             launch_screen_count(b0, nb, k0, nk, sym, p->d_Q, t, d_counts, s);
             // primitive quartets per row for the FLOP accounting
@@ -494,6 +640,14 @@ hgp_status hgp_plan_stats(const hgp_plan *p, int64_t *kept, int64_t *total, int6
     if (kept) *kept = p->kept;
     if (total) *total = p->total;
     if (bytes) *bytes = p->bytes;
+    return HGP_OK;
+}
+
+hgp_status hgp_plan_prim_stats(const hgp_plan *p, int64_t *prim_pairs_kept, int64_t *prim_pairs_total)
+{
+    if (!p) return fail(HGP_E_INVALID, "plan is NULL");
+    if (prim_pairs_kept) *prim_pairs_kept = p->prim_kept;
+    if (prim_pairs_total) *prim_pairs_total = p->prim_total;
     return HGP_OK;
 }
 

@@ -44,6 +44,12 @@ def test_sizes(built):
     assert bw.nshell == 180 and bw.nbf == 420
     st = built["stats"]
     assert st["quartets_total"] == 16290 * 16291 // 2
+    # primitive pairs: sum over shell pairs a >= b of n_a n_b, some dropped by primitive screening
+    nprim = built["bw"].nprim
+    iu = np.tril_indices(len(nprim))
+    assert st["prim_pairs_total"] == int(np.sum(nprim[iu[0]] * nprim[iu[1]]))
+    assert 0 < st["prim_pairs_kept"] < st["prim_pairs_total"]
+    print(f"primitive pairs kept {st['prim_pairs_kept']} of {st['prim_pairs_total']}")
     assert len(built["classes"]) == 21
 
 

@@ -106,6 +106,8 @@ def test_tiny_system_jk(hgp, torch_cuda):
     Jr, Kr = oracle.jk(bw, D, tau=0.0)
     J, K, st = _jk_gpu(hgp, torch_cuda, bw, D, 0.0)
     assert st["quartets_kept"] == st["quartets_total"] == 3081
+    # tau = 0: no primitive pair is dropped
+    assert st["prim_pairs_kept"] == st["prim_pairs_total"] > 0
     ej, ek = np.abs(J - Jr).max(), np.abs(K - Kr).max()
     print(f"tiny J/K: max |dJ| {ej:.3e}, max |dK| {ek:.3e}")
     assert ej <= JK_TOL and ek <= JK_TOL
