@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy kernel (y = 1.0 * x, MIB MiB of FP64 each way), "
+                         "a known-size reference for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -106,6 +109,13 @@ def main():
     import torch
     import paper_2605_10312_amd as hgp
     import workloads
+
+    if args.copy_calibration > 0:
+        x = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        del x, y
 
     bw, D = workloads.molecule_3s2p1d()
     torch.cuda.synchronize()

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhgp.so")
+# HGP_LIB names another build of the library (the autotuner times variant builds this way)
+LIB_PATH = os.environ.get("HGP_LIB") or os.path.join(_HERE, "libhgp.so")
 
 STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_UNSUPPORTED_L", -3: "HGP_E_OOM", -4: "HGP_E_DEVICE",
           -5: "HGP_E_STATE"}

@@ -30,26 +30,37 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-ato
 DEFAULT_LMAX = 2
 
 
-def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overrides=None):
-    """Write one .hip per canonical class plus the class table into _gen/.
-    Each class is routed to the register or staged tier (gen/router.py);
-    overrides maps a class tag to {tier, cap, waves} and wins over both the
-    tuning table and the model."""
+REGISTER_OPTS = ("waves", "digest", "reduce")
+STAGED_OPTS = ("cap", "waves", "reduce")
+
+
+def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overrides=None, gen_dir: str = GEN,
+             defaults=None):
+    """Write one .hip per canonical class plus the class table into gen_dir.
+    Each class is routed to the register or staged tier (gen/router.py).
+    defaults (generator options for every class) are applied first, then
+    the router's choice (tuning table, else the register model), then
+    overrides, a map from class tag to options that wins over both.
+    Register-tier options: waves, digest, reduce; staged: cap, waves, reduce."""
     from .gen import emit, emit_staged, router
     from .gen.cart import canonical_classes
 
+    GEN = gen_dir
     os.makedirs(GEN, exist_ok=True)
     metas = []
     files = []
     for ls in canonical_classes(lmax):
         tag = "".join(str(x) for x in ls)
         r = router.route(ls, table)
+        for k, v in (defaults or {}).items():
+            if r["source"] == "model" or k not in r:    # a tuning-table entry wins over defaults
+                r[k] = v
         if overrides and tag in overrides:
             r.update(overrides[tag])
         if r["tier"] == 1:
-            src, meta = emit_staged.emit_class_staged(*ls, cap=r["cap"], waves=r["waves"])
+            src, meta = emit_staged.emit_class_staged(*ls, **{k: r[k] for k in STAGED_OPTS if k in r})
         else:
-            src, meta = emit.emit_class(*ls, waves=r["waves"])
+            src, meta = emit.emit_class(*ls, **{k: r[k] for k in REGISTER_OPTS if k in r})
         path = os.path.join(GEN, f"class_{meta.tag}.hip")
         _write_if_changed(path, src)
         files.append(path)
@@ -78,7 +89,7 @@ def _write_if_changed(path, text):
 
 
 def _compile(src: str, force: bool):
-    if os.path.dirname(src) == GEN:       # class kernels see only the device headers
+    if not src.startswith(CSRC + os.sep):  # generated class kernels see only the device headers
         deps = [src, os.path.join(CSRC, "hgp_device.h"), os.path.join(CSRC, "hgp_types.h")]
     else:
         deps = [src] + [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".h")] + \
@@ -99,10 +110,13 @@ def _compile(src: str, force: bool):
 
 
 def build(lmax: int = DEFAULT_LMAX, jobs: int | None = None, force: bool = False, verbose: bool = True,
-          overrides=None, out: str | None = None) -> str:
+          overrides=None, out: str | None = None, gen_dir: str = GEN, defaults=None, table=None) -> str:
+    """Generate, compile and link; out (default: the package's libhgp.so)
+    and gen_dir let a tuning run build variant libraries side by side."""
     t0 = time.time()
     os.makedirs(OBJ, exist_ok=True)
-    gen_files, metas = generate(lmax, verbose=False, overrides=overrides)
+    gen_files, metas = generate(lmax, verbose=False, overrides=overrides, gen_dir=gen_dir, defaults=defaults,
+                                table=table)
     srcs = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")] + gen_files
     jobs = jobs or min(8, os.cpu_count() or 4)
     objs = []

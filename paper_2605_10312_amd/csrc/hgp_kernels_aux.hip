@@ -25,11 +25,12 @@ __global__ void boys_table_kernel(double *tab)
     }
     const double e = exp(-T);
     double f = e * sum;
-    tab[k * BOYS_NORD + top] = f;
+    tab[k * BOYS_STRIDE + top] = f;
     for (int m = top - 1; m >= 0; --m) {
         f = (2.0 * T * f + e) / (double)(2 * m + 1);
-        tab[k * BOYS_NORD + m] = f;
+        tab[k * BOYS_STRIDE + m] = f;
     }
+    tab[k * BOYS_STRIDE + BOYS_NORD] = e;
 }
 
 // ---------------------------------------------------------------------------

@@ -42,7 +42,7 @@ hgp_status boys_table(int dev, const double **out)
     if (dev < 0 || dev >= 64) return fail(HGP_E_DEVICE, "device index out of range");
     if (!g_boys[dev]) {
         double *t = nullptr;
-        HGP_HIP(hipMalloc(&t, sizeof(double) * BOYS_NPTS * BOYS_NORD));
+        HGP_HIP(hipMalloc(&t, sizeof(double) * BOYS_NPTS * BOYS_STRIDE));
         launch_boys_table(t, 0);
         HGP_HIP(hipGetLastError());
         HGP_HIP(hipStreamSynchronize(0));

@@ -88,12 +88,14 @@ struct P1Args {
 };
 
 // Boys table: F_m(T_k) for T_k = k * BOYS_STEP, k = 0 .. BOYS_NPTS-1, m = 0 .. BOYS_NORD-1,
-// stored [k][m] so that the orders one evaluation reads are contiguous.
+// stored [k][m] (row stride BOYS_STRIDE) so that the orders one evaluation reads
+// are contiguous; column BOYS_NORD of row k holds exp(-T_k).
 constexpr double BOYS_STEP = 0.05;
 constexpr double BOYS_INV_STEP = 20.0;
 constexpr double BOYS_TMAX = 36.0;
 constexpr int BOYS_NPTS = 722;
 constexpr int BOYS_NORD = 24;      // orders needed: L + 7 <= 23 for L <= 16
+constexpr int BOYS_STRIDE = 25;    // per point: F_0 .. F_23, then exp(-T_k)
 
 // Largest staged-tier buffer a plan allocates (doubles): 4 GiB.  Classes whose
 // quartets do not fit in one batch are processed in several.

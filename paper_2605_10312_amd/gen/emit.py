@@ -42,6 +42,8 @@ class ClassMeta:
     recompute: float = 1.0
     cap: int = 0
     waves: int = 0
+    digest: str = "loads_first"
+    reduce: str = "segmented"
 
 
 def tag_of(ls):
@@ -149,7 +151,140 @@ def waves_attr(waves):
     return f" __attribute__((amdgpu_waves_per_eu({waves}, {waves})))" if waves else ""
 
 
-def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves=0):
+def _dot(terms):
+    expr = f"{terms[0][0]} * {terms[0][1]}"
+    for x, y in terms[1:]:
+        expr = f"fma({x}, {y}, {expr})"
+    return expr
+
+
+def digest_lines(na, nb, nc, nd, I, J, K, digest="loads_first", reduce="segmented", ind="    "):
+    """J/K digestion of one unique quartet's spherical block I(mu, nu, lam, sig)
+    (a C expression per integral) into the unsymmetrised J', K' with the
+    degeneracy factor s already in scope (pq, pk, fa, fb, fc, fd, N, D too):
+      J'[ab] += 2s sum_cd I D_cd,  J'[cd] += 2s sum_ab I D_ab,
+      K'[ac] += s sum_bd I D_bd,   K'[bc] += s sum_ad I D_ad,
+      K'[ad] += s sum_bc I D_bc,   K'[bd] += s sum_ac I D_ac.
+    digest = 'loads_first' reads every D element the quartet needs before the
+    first atomic: a GFX9 wave waits on one in-order counter for loads and
+    atomics alike, so a D load issued after an atomic would also wait for that
+    atomic's round trip to memory.  'interleaved' loads each D block just
+    before its contraction.
+    reduce: 'segmented' adds the J'[ab] terms along runs of lanes with the
+    same bra pair and the K'[ac], K'[bc] terms along runs with the same bra
+    pair and ket shell c (each lane's term carries its own degeneracy
+    factor); the run's last lane issues the atomic.  'uniform' does this for
+    J'[ab] only and only when the whole wave holds one bra pair.  'none':
+    one atomic per lane and element."""
+    out = []
+    w = out.append
+    dblocks = {"cd": ("fc", "fd", nc, nd), "ab": ("fa", "fb", na, nb), "bd": ("fb", "fd", nb, nd),
+               "ad": ("fa", "fd", na, nd), "bc": ("fb", "fc", nb, nc), "ac": ("fa", "fc", na, nc)}
+
+    def loads(nm, i2=ind + "    "):
+        r0, c0, nr, ncol = dblocks[nm]
+        for i in range(nr):
+            for j in range(ncol):
+                w(f"{i2}const double d{nm}_{i}_{j} = D[({r0} + {i}) * N + {c0} + {j}];")
+
+    def jab_terms(mu, nu):
+        return _dot([(I(mu, nu, lam, sig), f"dcd_{lam}_{sig}") for lam in range(nc) for sig in range(nd)])
+
+    def jab_atomics(i2):
+        for mu in range(na):
+            for nu in range(nb):
+                w(f"{i2}atomicAdd({J} + (fa + {mu}) * N + fb + {nu}, s2 * ({jab_terms(mu, nu)}));")
+
+    def jcd_atomics(i2):
+        for lam in range(nc):
+            for sig in range(nd):
+                e = _dot([(I(mu, nu, lam, sig), f"dab_{mu}_{nu}") for mu in range(na) for nu in range(nb)])
+                w(f"{i2}atomicAdd({J} + (fc + {lam}) * N + fd + {sig}, s2 * ({e}));")
+
+    def seg_block(i2, outer, terms, target, scale, start, tail, nm):
+        """Values summed along runs (start lane in `start`), each added by the run's
+        last lane right away, so that no more than one sum is live at a time."""
+        for k, o in enumerate(outer):
+            w(f"{i2}{{ const double {nm} = hgp_seg_sum({scale} * ({_dot(terms(*o))}), {start}); "
+              f"if ({tail}) atomicAdd({target(*o)}, {nm}); }}")
+
+    def plain_block(i2, outer, terms, target, scale):
+        for o in outer:
+            w(f"{i2}atomicAdd({target(*o)}, {scale} * ({_dot(terms(*o))}));")
+
+    kac = ([(mu, lam) for mu in range(na) for lam in range(nc)],
+           lambda mu, lam: [(I(mu, nu, lam, sig), f"dbd_{nu}_{sig}") for nu in range(nb) for sig in range(nd)],
+           lambda mu, lam: f"{K} + (fa + {mu}) * N + fc + {lam}")
+    kbc = ([(nu, lam) for nu in range(nb) for lam in range(nc)],
+           lambda nu, lam: [(I(mu, nu, lam, sig), f"dad_{mu}_{sig}") for mu in range(na) for sig in range(nd)],
+           lambda nu, lam: f"{K} + (fb + {nu}) * N + fc + {lam}")
+    kad = ([(mu, sig) for mu in range(na) for sig in range(nd)],
+           lambda mu, sig: [(I(mu, nu, lam, sig), f"dbc_{nu}_{lam}") for nu in range(nb) for lam in range(nc)],
+           lambda mu, sig: f"{K} + (fa + {mu}) * N + fd + {sig}")
+    kbd = ([(nu, sig) for nu in range(nb) for sig in range(nd)],
+           lambda nu, sig: [(I(mu, nu, lam, sig), f"dac_{mu}_{lam}") for mu in range(na) for lam in range(nc)],
+           lambda nu, sig: f"{K} + (fb + {nu}) * N + fd + {sig}")
+    jab = ([(mu, nu) for mu in range(na) for nu in range(nb)],
+           lambda mu, nu: [(I(mu, nu, lam, sig), f"dcd_{lam}_{sig}") for lam in range(nc) for sig in range(nd)],
+           lambda mu, nu: f"{J} + (fa + {mu}) * N + fb + {nu}")
+
+    def jab_block(i2):
+        if reduce == "segmented":
+            w(f"{i2}const int seg_ab = hgp_seg_start(pq.x);")
+            w(f"{i2}const bool tail_ab = hgp_seg_tail(pq.x);")
+            seg_block(i2, *jab, "s2", "seg_ab", "tail_ab", "jr")
+        elif reduce == "uniform":
+            # the bra pair is wave-uniform when every lane is active and holds the first lane's bra
+            w(f"{i2}if (__builtin_amdgcn_read_exec() == ~0ull && hgp_wave_all(pq.x == __builtin_amdgcn_readfirstlane(pq.x))) {{")
+            for mu in range(na):
+                for nu in range(nb):
+                    w(f"{i2}    const double jr_{mu}_{nu} = hgp_wave_sum(s2 * ({jab_terms(mu, nu)}));")
+            w(f"{i2}    if (__lane_id() == 0) {{")
+            for mu in range(na):
+                for nu in range(nb):
+                    w(f"{i2}        atomicAdd({J} + (fa + {mu}) * N + fb + {nu}, jr_{mu}_{nu});")
+            w(f"{i2}    }}")
+            w(f"{i2}}} else {{")
+            jab_atomics(i2 + "    ")
+            w(f"{i2}}}")
+        else:
+            jab_atomics(i2)
+
+    def k_block(i2):
+        if reduce == "segmented":
+            w(f"{i2}const long long key_ac = ((long long)pq.x << 32) | (unsigned)pk.sh_a;")
+            w(f"{i2}const int seg_ac = hgp_seg_start(key_ac);")
+            w(f"{i2}const bool tail_ac = hgp_seg_tail(key_ac);")
+            seg_block(i2, *kac, "s", "seg_ac", "tail_ac", "kac")
+            seg_block(i2, *kbc, "s", "seg_ac", "tail_ac", "kbc")
+        else:
+            plain_block(i2, *kac, "s")
+            plain_block(i2, *kbc, "s")
+        plain_block(i2, *kad, "s")
+        plain_block(i2, *kbd, "s")
+
+    if digest not in ("loads_first", "interleaved"):
+        raise ValueError(f"unknown digest style {digest!r}")
+    w(f"{ind}if (a.want_j) {{")
+    w(f"{ind}    const double s2 = 2.0 * s;")
+    loads("cd")
+    if digest == "loads_first":
+        loads("ab")
+    jab_block(ind + "    ")
+    if digest == "interleaved":
+        loads("ab")
+    jcd_atomics(ind + "    ")
+    w(f"{ind}}}")
+    w(f"{ind}if (a.want_k) {{")
+    for nm in ("bd", "ad", "bc", "ac"):
+        loads(nm)
+    k_block(ind + "    ")
+    w(f"{ind}}}")
+    return out
+
+
+def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves=0, digest="loads_first",
+               reduce="segmented"):
     ls = (la, lb, lc, ld)
     tag = tag_of(ls)
     L = sum(ls)
@@ -211,59 +346,8 @@ def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves
     w("    const int N = a.nbf;")
     w("    const int fa = pb.fa, fb = pb.fb, fc = pk.fa, fd = pk.fb;")
     w("    const double s = (pb.same ? 0.5 : 1.0) * (pk.same ? 0.5 : 1.0) * (pq.x == pq.y ? 0.5 : 1.0);")
-    w("    if (a.want_j) {")
-    w("        const double s2 = 2.0 * s;")
-    for lam in range(nc):
-        for sig in range(nd):
-            w(f"        const double dcd_{lam}_{sig} = D[(fc + {lam}) * N + fd + {sig}];")
-    for mu in range(na):
-        for nu in range(nb):
-            terms = [(f"I[{idx(mu, nu, lam, sig)}]", f"dcd_{lam}_{sig}") for lam in range(nc) for sig in range(nd)]
-            expr = f"{terms[0][0]} * {terms[0][1]}"
-            for x, y in terms[1:]:
-                expr = f"fma({x}, {y}, {expr})"
-            w(f"        atomicAdd(a.J + (fa + {mu}) * N + fb + {nu}, s2 * ({expr}));")
-    for mu in range(na):
-        for nu in range(nb):
-            w(f"        const double dab_{mu}_{nu} = D[(fa + {mu}) * N + fb + {nu}];")
-    for lam in range(nc):
-        for sig in range(nd):
-            terms = [(f"I[{idx(mu, nu, lam, sig)}]", f"dab_{mu}_{nu}") for mu in range(na) for nu in range(nb)]
-            expr = f"{terms[0][0]} * {terms[0][1]}"
-            for x, y in terms[1:]:
-                expr = f"fma({x}, {y}, {expr})"
-            w(f"        atomicAdd(a.J + (fc + {lam}) * N + fd + {sig}, s2 * ({expr}));")
-    w("    }")
-    w("    if (a.want_k) {")
-    # K'[a,c] += s sum_{n,s} I D[b,d]; K'[b,c] += s sum_{m,s} I D[a,d]
-    # K'[a,d] += s sum_{n,l} I D[b,c]; K'[b,d] += s sum_{m,l} I D[a,c]
-    blocks = [("bd", "fb", "fd", nb, nd), ("ad", "fa", "fd", na, nd), ("bc", "fb", "fc", nb, nc), ("ac", "fa", "fc", na, nc)]
-    for nm, r0, c0, nr, ncol in blocks:
-        for i in range(nr):
-            for j in range(ncol):
-                w(f"        const double d{nm}_{i}_{j} = D[({r0} + {i}) * N + {c0} + {j}];")
-
-    def ksum(outer, inner_terms, target):
-        for o in outer:
-            terms = inner_terms(*o)
-            expr = f"{terms[0][0]} * {terms[0][1]}"
-            for x, y in terms[1:]:
-                expr = f"fma({x}, {y}, {expr})"
-            w(f"        atomicAdd(a.K + {target(*o)}, s * ({expr}));")
-
-    ksum([(mu, lam) for mu in range(na) for lam in range(nc)],
-         lambda mu, lam: [(f"I[{idx(mu, nu, lam, sig)}]", f"dbd_{nu}_{sig}") for nu in range(nb) for sig in range(nd)],
-         lambda mu, lam: f"(fa + {mu}) * N + fc + {lam}")
-    ksum([(nu, lam) for nu in range(nb) for lam in range(nc)],
-         lambda nu, lam: [(f"I[{idx(mu, nu, lam, sig)}]", f"dad_{mu}_{sig}") for mu in range(na) for sig in range(nd)],
-         lambda nu, lam: f"(fb + {nu}) * N + fc + {lam}")
-    ksum([(mu, sig) for mu in range(na) for sig in range(nd)],
-         lambda mu, sig: [(f"I[{idx(mu, nu, lam, sig)}]", f"dbc_{nu}_{lam}") for nu in range(nb) for lam in range(nc)],
-         lambda mu, sig: f"(fa + {mu}) * N + fd + {sig}")
-    ksum([(nu, sig) for nu in range(nb) for sig in range(nd)],
-         lambda nu, sig: [(f"I[{idx(mu, nu, lam, sig)}]", f"dac_{mu}_{lam}") for mu in range(na) for lam in range(nc)],
-         lambda nu, sig: f"(fb + {nu}) * N + fd + {sig}")
-    w("    }")
+    out.extend(digest_lines(na, nb, nc, nd, lambda mu, nu, lam, sig: f"I[{idx(mu, nu, lam, sig)}]",
+                            "a.J", "a.K", digest, reduce))
     w("}")
     w("")
     # ---------------------------------------------------------------- integrals-out kernel
@@ -307,7 +391,7 @@ def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves
     w("")
     w("}  // namespace hgp")
     meta = ClassMeta(ls, tag, 0, block, len(g.nodes), g.flops(), len(g.targets), pl, sched, p2.flops, nout, rule,
-                     waves=waves)
+                     waves=waves, digest=digest, reduce=reduce)
     return "\n".join(out) + "\n", meta
 
 

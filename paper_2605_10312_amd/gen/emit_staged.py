@@ -118,7 +118,8 @@ def _names_in(op):
     return [s for _, s in op[2]]
 
 
-def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedulers=None, waves=0):
+def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedulers=None, waves=0,
+                      reduce="segmented"):
     ls = (la, lb, lc, ld)
     tag = tag_of(ls)
     g = vrrmod.VRRGraph(la, lb, lc, ld, rule=rule)
@@ -275,36 +276,59 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
     def I(mu, nu, lam, sig):
         return f"sb[{islot(mu, nu, lam, sig)}u * S32 + li]"
 
-    def contraction(outer, inner, target, scale):
+    def contraction(outer, inner, target, scale, seg=None):
         """One output element at a time: a dot product of integrals streamed
-        from the buffer with D entries, then one atomic."""
-        for o in outer:
+        from the buffer with D entries, then one atomic.  seg = (first lane,
+        last-lane flag, name): the values are first summed along the wave's
+        runs of lanes with the same target and the run's last lane adds them."""
+        vals = []
+        for k, o in enumerate(outer):
             terms = inner(*o)
             expr = f"{terms[0][0]} * {terms[0][1]}"
             for x, y in terms[1:]:
                 expr = f"fma({x}, {y}, {expr})"
-            w(f"        atomicAdd({target(*o)}, {scale} * ({expr}));")
+            if seg is None:
+                w(f"        atomicAdd({target(*o)}, {scale} * ({expr}));")
+            else:
+                w(f"        const double {seg[2]}{k} = hgp_seg_sum({scale} * ({expr}), {seg[0]});")
+                vals.append((f"{seg[2]}{k}", target(*o)))
             w("        HGP_STAGE(li);")
+        if seg is not None:
+            w(f"        if ({seg[1]}) {{")
+            for v, t in vals:
+                w(f"            atomicAdd({t}, {v});")
+            w("        }")
 
+    segmented = reduce == "segmented"
     w("    if (a.want_j) {")
+    if segmented:
+        w("        const int seg_ab = hgp_seg_start(pq.x);")
+        w("        const bool tail_ab = hgp_seg_tail(pq.x);")
     contraction([(mu, nu) for mu in range(na) for nu in range(nb)],
                 lambda mu, nu: [(I(mu, nu, lam, sig), f"D[(int64_t)(fc + {lam}) * N + fd + {sig}]")
                                 for lam in range(nc) for sig in range(nd)],
-                lambda mu, nu: f"a.J + (int64_t)(fa + {mu}) * N + fb + {nu}", "sj")
+                lambda mu, nu: f"a.J + (int64_t)(fa + {mu}) * N + fb + {nu}", "sj",
+                ("seg_ab", "tail_ab", "jr") if segmented else None)
     contraction([(lam, sig) for lam in range(nc) for sig in range(nd)],
                 lambda lam, sig: [(I(mu, nu, lam, sig), f"D[(int64_t)(fa + {mu}) * N + fb + {nu}]")
                                   for mu in range(na) for nu in range(nb)],
                 lambda lam, sig: f"a.J + (int64_t)(fc + {lam}) * N + fd + {sig}", "sj")
     w("    }")
     w("    if (a.want_k) {")
+    if segmented:
+        w("        const long long key_ac = ((long long)pq.x << 32) | (unsigned)pk.sh_a;")
+        w("        const int seg_ac = hgp_seg_start(key_ac);")
+        w("        const bool tail_ac = hgp_seg_tail(key_ac);")
     contraction([(mu, lam) for mu in range(na) for lam in range(nc)],
                 lambda mu, lam: [(I(mu, nu, lam, sig), f"D[(int64_t)(fb + {nu}) * N + fd + {sig}]")
                                  for nu in range(nb) for sig in range(nd)],
-                lambda mu, lam: f"a.K + (int64_t)(fa + {mu}) * N + fc + {lam}", "sk")
+                lambda mu, lam: f"a.K + (int64_t)(fa + {mu}) * N + fc + {lam}", "sk",
+                ("seg_ac", "tail_ac", "kac") if segmented else None)
     contraction([(nu, lam) for nu in range(nb) for lam in range(nc)],
                 lambda nu, lam: [(I(mu, nu, lam, sig), f"D[(int64_t)(fa + {mu}) * N + fd + {sig}]")
                                  for mu in range(na) for sig in range(nd)],
-                lambda nu, lam: f"a.K + (int64_t)(fb + {nu}) * N + fc + {lam}", "sk")
+                lambda nu, lam: f"a.K + (int64_t)(fb + {nu}) * N + fc + {lam}", "sk",
+                ("seg_ac", "tail_ac", "kbc") if segmented else None)
     contraction([(mu, sig) for mu in range(na) for sig in range(nd)],
                 lambda mu, sig: [(I(mu, nu, lam, sig), f"D[(int64_t)(fb + {nu}) * N + fc + {lam}]")
                                  for nu in range(nb) for lam in range(nc)],
@@ -362,5 +386,6 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
     w("")
     w("}  // namespace hgp")
     meta = ClassMeta(ls, tag, 1, block, len(g.nodes), full, n_h, pl, sched, p2.flops, nout, rule,
-                     scratch_slots=nslots, chunks=len(chunks), recompute=recompute, cap=cap, waves=waves)
+                     scratch_slots=nslots, chunks=len(chunks), recompute=recompute, cap=cap, waves=waves,
+                     digest="", reduce=reduce)
     return "\n".join(out) + "\n", meta

@@ -81,12 +81,11 @@ def route(ls, table=None):
     """-> dict(tier=0|1, cap=int, waves=int, source='model'|'table')"""
     tag = "".join(str(x) for x in ls)
     table = load_table() if table is None else table
-    if tag in table:
-        t = dict(table[tag])
-        t.setdefault("cap", DEFAULT_CAP)
-        t.setdefault("waves", 0)
-        t["source"] = "table"
-        return t
-    tier = 0 if model_demand(ls) <= REGISTER_DOUBLES else 1
+    t = dict(table.get(tag, {}))
+    tier = t.get("tier", 0 if model_demand(ls) <= REGISTER_DOUBLES else 1)
     cap = model_cap(ls) if tier == 1 else DEFAULT_CAP
-    return {"tier": tier, "cap": cap, "waves": 0, "source": "model"}
+    r = {"tier": tier, "cap": cap, "waves": 0, "source": "model"}
+    if t:                      # measured entries win; what they leave out comes from the model
+        r.update({k: v for k, v in t.items() if k not in ("variant", "ms")})
+        r["source"] = "table"
+    return r

@@ -1,0 +1,152 @@
+"""Autotuner for the per-class kernel choices on gfx950.
+
+The router's register model picks each class's tier and staged chunk cap
+from its VRR graph.  It cannot see occupancy effects or how the compiler
+schedules the digestion, so the choices are checked on the hardware.
+
+    python -m paper_2605_10312_amd.tune build             (CPU: variant libraries)
+    python -m paper_2605_10312_amd.tune measure --out F   (GPU: time every variant)
+    python -m paper_2605_10312_amd.tune select F          (CPU: write the tuning table)
+
+`build` generates one complete library per variant into _variants/.  A
+variant is a set of generator options applied to every class (waves per
+SIMD, digestion style, staged cap).  `measure` runs each library in a child
+process on the 30-atom 3s2p1d workload.  The child times every class kernel
+with HIP events and reports milliseconds per J/K build.  `select` keeps, for
+each class, the fastest variant and writes its options to tuning/gfx950.json.
+The router reads that file in the next ordinary build.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+VARIANTS_DIR = os.path.join(HERE, "_variants")
+TABLE = os.path.join(HERE, "tuning", "gfx950.json")
+
+# generator options per variant; keys the tier does not use are ignored
+VARIANTS = {
+    "plain": {"digest": "interleaved", "reduce": "none"},
+    "uniform": {"digest": "loads_first", "reduce": "uniform"},
+    "seg": {"digest": "loads_first", "reduce": "segmented"},
+    "seg_il": {"digest": "interleaved", "reduce": "segmented"},
+    "seg_w2": {"digest": "loads_first", "reduce": "segmented", "waves": 2},
+}
+
+
+def build_variants(names, lmax):
+    from . import build as b
+    os.makedirs(VARIANTS_DIR, exist_ok=True)
+    for name in names:
+        t = time.time()
+        gen = os.path.join(b.ROOT, "_build", "gen_" + name)
+        out = os.path.join(VARIANTS_DIR, f"libhgp_{name}.so")
+        b.build(lmax, verbose=False, out=out, gen_dir=gen, defaults=VARIANTS[name], table={})
+        print(f"built variant {name} -> {out} in {time.time() - t:.1f}s", flush=True)
+
+
+def time_library(steps, warmup):
+    """Child process: per-class milliseconds per J/K build with the library named by HGP_LIB."""
+    import torch
+    import paper_2605_10312_amd as hgp
+    import workloads
+
+    bw, D = workloads.molecule_3s2p1d()
+    basis = hgp.Basis.from_workload(bw)
+    plan = hgp.Plan(basis, tau=1e-12)
+    Dt = torch.tensor(D, dtype=torch.float64, device="cuda")
+    J = torch.empty_like(Dt)
+    K = torch.empty_like(Dt)
+    for _ in range(warmup):
+        plan.jk(Dt, J, K)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    t = time.perf_counter()
+    for _ in range(steps):
+        plan.jk(Dt, J, K)
+    torch.cuda.synchronize()
+    total = (time.perf_counter() - t) * 1e3 / steps
+    res = {}
+    for c, tm in zip(plan.classes(), plan.class_timing()):
+        tag = "".join(str(x) for x in c["ls"])
+        res[tag] = {"tier": tm["tier"], "ms": sum(ms for _, ms in tm["kernels"]) / steps}
+    plan.close()
+    basis.close()
+    print(json.dumps({"ms_per_build": total, "classes": res}), flush=True)
+
+
+def measure(names, out, steps, warmup, timeout):
+    results = {}
+    for name in names:
+        lib = os.path.join(VARIANTS_DIR, f"libhgp_{name}.so")
+        if not os.path.exists(lib):
+            raise FileNotFoundError(f"{lib}: run `python -m paper_2605_10312_amd.tune build` first")
+        env = dict(os.environ, HGP_LIB=lib)
+        print(f"== variant {name}", flush=True)
+        r = subprocess.run([sys.executable, "-m", "paper_2605_10312_amd.tune", "_time", "--steps", str(steps),
+                            "--warmup", str(warmup)], env=env, capture_output=True, text=True, timeout=timeout)
+        if r.returncode != 0:
+            print(r.stderr[-3000:], flush=True)
+            raise SystemExit(f"variant {name} failed with status {r.returncode}")
+        results[name] = json.loads(r.stdout.strip().splitlines()[-1])
+        print(f"   {results[name]['ms_per_build']:.2f} ms per J/K build", flush=True)
+        with open(out, "w") as fh:
+            json.dump(results, fh, indent=1)
+
+
+def select(path, table=TABLE):
+    res = json.load(open(path))
+    classes = sorted({t for r in res.values() for t in r["classes"]})
+    chosen = {}
+    for tag in classes:
+        best = min((r["classes"][tag]["ms"], name) for name, r in res.items() if tag in r["classes"])
+        opts = {"tier": res[best[1]]["classes"][tag]["tier"]}
+        opts.update({k: v for k, v in VARIANTS[best[1]].items()})
+        if opts["tier"] == 1:
+            opts = {k: v for k, v in opts.items() if k in ("tier", "cap", "waves", "reduce")}
+        opts["variant"] = best[1]
+        opts["ms"] = round(best[0], 4)
+        chosen[tag] = opts
+        print(f"{tag}: {best[1]:8s} {best[0]:8.3f} ms  " +
+              "  ".join(f"{n}={r['classes'][tag]['ms']:.3f}" for n, r in res.items() if tag in r["classes"]))
+    os.makedirs(os.path.dirname(table), exist_ok=True)
+    with open(table, "w") as fh:
+        json.dump({"device": "gfx950", "workload": "mol30_3s2p1d, tau 1e-12", "classes": chosen}, fh, indent=1)
+    print(f"wrote {table}; estimated J/K build {sum(c['ms'] for c in chosen.values()):.2f} ms")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    pb = sub.add_parser("build")
+    pb.add_argument("--variants", nargs="*", default=list(VARIANTS))
+    pb.add_argument("--lmax", type=int, default=2)
+    pm = sub.add_parser("measure")
+    pm.add_argument("--variants", nargs="*", default=list(VARIANTS))
+    pm.add_argument("--out", required=True)
+    pm.add_argument("--steps", type=int, default=3)
+    pm.add_argument("--warmup", type=int, default=1)
+    pm.add_argument("--timeout", type=float, default=120.0)
+    ps = sub.add_parser("select")
+    ps.add_argument("results")
+    pt = sub.add_parser("_time")
+    pt.add_argument("--steps", type=int, default=3)
+    pt.add_argument("--warmup", type=int, default=1)
+    a = ap.parse_args(argv)
+    if a.cmd == "build":
+        build_variants(a.variants, a.lmax)
+    elif a.cmd == "measure":
+        measure(a.variants, a.out, a.steps, a.warmup, a.timeout)
+    elif a.cmd == "select":
+        select(a.results)
+    else:
+        time_library(a.steps, a.warmup)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
