@@ -30,8 +30,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-ato
 DEFAULT_LMAX = 2
 
 
-REGISTER_OPTS = ("waves", "digest", "reduce")
-STAGED_OPTS = ("cap", "waves", "reduce")
+REGISTER_OPTS = ("waves", "digest", "reduce", "loop")
+STAGED_OPTS = ("cap", "waves", "reduce", "loop")
 
 
 def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overrides=None, gen_dir: str = GEN,
@@ -41,7 +41,8 @@ def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overri
     defaults (generator options for every class) are applied first, then
     the router's choice (tuning table, else the register model), then
     overrides, a map from class tag to options that wins over both.
-    Register-tier options: waves, digest, reduce; staged: cap, waves, reduce."""
+    Register-tier options: waves, digest, reduce, loop; staged: cap, waves,
+    reduce, loop."""
     from .gen import emit, emit_staged, router
     from .gen.cart import canonical_classes
 

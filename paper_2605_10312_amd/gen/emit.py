@@ -44,6 +44,7 @@ class ClassMeta:
     waves: int = 0
     digest: str = "loads_first"
     reduce: str = "segmented"
+    loop: str = "late"
 
 
 def tag_of(ls):
@@ -103,29 +104,24 @@ def _p2_lines(p2, indent):
     return lines
 
 
-def loop_prelude(L, ind):
+def loop_prelude(L, ind, style="late"):
     """The primitive-quartet loop up to the VRR (Alg. 2's GaussianPairs and
-    Boys steps), flattened over bra x ket primitive pairs; the next
-    iteration's pair records are loaded while the current one computes."""
+    Boys steps), flattened over bra x ket primitive pairs.
+    style 'prefetch': the next iteration's pair records are loaded at the top
+    of the iteration into a second set of registers (copied over at the end).
+    style 'late': they are loaded into the same registers as soon as the
+    current records have been turned into the derived quantities, so no
+    second set and no copies are needed; the loads still have the Boys step
+    and the whole VRR to arrive."""
     i2 = ind + "    "
-    return [
+    head = [
         f"{ind}const double Ax = gb.ax, Ay = gb.ay, Az = gb.az;",
         f"{ind}const double Cx = gk.ax, Cy = gk.ay, Cz = gk.az;",
         f"{ind}const PrimPair *__restrict__ pbp = prims + pb.prim_off;",
         f"{ind}const PrimPair *__restrict__ pkp = prims + pk.prim_off;",
         f"{ind}const int nkp = pk.nprim, ntot = pb.nprim * pk.nprim;",
-        f"{ind}double nzeta = pbp[0].zeta, no2z = pbp[0].o2z, nPx = pbp[0].px, nPy = pbp[0].py, nPz = pbp[0].pz, nKb = pbp[0].k;",
-        f"{ind}double neta = pkp[0].zeta, no2e = pkp[0].o2z, nQx = pkp[0].px, nQy = pkp[0].py, nQz = pkp[0].pz, nKk = pkp[0].k;",
-        f"{ind}int ip = 0, jp = 0;",
-        f"{ind}for (int t = 0; t < ntot; ++t) {{",
-        f"{i2}const double zeta = nzeta, o2z = no2z, Px = nPx, Py = nPy, Pz = nPz, Kb = nKb;",
-        f"{i2}const double eta = neta, o2e = no2e, Qx = nQx, Qy = nQy, Qz = nQz, Kk = nKk;",
-        f"{i2}if (++jp == nkp) {{ jp = 0; ++ip; }}",
-        f"{i2}if (t + 1 < ntot) {{",
-        f"{i2}    const PrimPair *b = pbp + ip, *k = pkp + jp;",
-        f"{i2}    nzeta = b->zeta; no2z = b->o2z; nPx = b->px; nPy = b->py; nPz = b->pz; nKb = b->k;",
-        f"{i2}    neta = k->zeta; no2e = k->o2z; nQx = k->px; nQy = k->py; nQz = k->pz; nKk = k->k;",
-        f"{i2}}}",
+    ]
+    derived = [
         f"{i2}const double PAx = Px - Ax, PAy = Py - Ay, PAz = Pz - Az;",
         f"{i2}const double QCx = Qx - Cx, QCy = Qy - Cy, QCz = Qz - Cz;",
         f"{i2}const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;",
@@ -133,14 +129,50 @@ def loop_prelude(L, ind):
         f"{i2}const double ize = hgp_rcp(ze);",
         f"{i2}const double rz = eta * ize, re = zeta * ize, o2ze = 0.5 * ize;",
         f"{i2}const double T = zeta * rz * (PQx * PQx + PQy * PQy + PQz * PQz);",
+        f"{i2}const double base = Kb * Kk * hgp_rsqrt(ze);",
+    ]
+    tail = [
         f"{i2}double F[{L + 1}];",
         f"{i2}boys_fm<{L}>(T, boys, F);",
-        f"{i2}const double base = Kb * Kk * hgp_rsqrt(ze);",
         f"{i2}const double WPx = -rz * PQx, WPy = -rz * PQy, WPz = -rz * PQz;",
         f"{i2}const double WQx = re * PQx, WQy = re * PQy, WQz = re * PQz;",
         f"{i2}(void)o2z; (void)o2e; (void)o2ze; (void)PAx; (void)PAy; (void)PAz; (void)QCx; (void)QCy; (void)QCz;",
         f"{i2}(void)WPx; (void)WPy; (void)WPz; (void)WQx; (void)WQy; (void)WQz; (void)re;",
     ]
+    if style == "prefetch":
+        return head + [
+            f"{ind}double nzeta = pbp[0].zeta, no2z = pbp[0].o2z, nPx = pbp[0].px, nPy = pbp[0].py, nPz = pbp[0].pz, nKb = pbp[0].k;",
+            f"{ind}double neta = pkp[0].zeta, no2e = pkp[0].o2z, nQx = pkp[0].px, nQy = pkp[0].py, nQz = pkp[0].pz, nKk = pkp[0].k;",
+            f"{ind}int ip = 0, jp = 0;",
+            f"{ind}for (int t = 0; t < ntot; ++t) {{",
+            f"{i2}const double zeta = nzeta, o2z = no2z, Px = nPx, Py = nPy, Pz = nPz, Kb = nKb;",
+            f"{i2}const double eta = neta, o2e = no2e, Qx = nQx, Qy = nQy, Qz = nQz, Kk = nKk;",
+            f"{i2}if (++jp == nkp) {{ jp = 0; ++ip; }}",
+            f"{i2}if (t + 1 < ntot) {{",
+            f"{i2}    const PrimPair *b = pbp + ip, *k = pkp + jp;",
+            f"{i2}    nzeta = b->zeta; no2z = b->o2z; nPx = b->px; nPy = b->py; nPz = b->pz; nKb = b->k;",
+            f"{i2}    neta = k->zeta; no2e = k->o2z; nQx = k->px; nQy = k->py; nQz = k->pz; nKk = k->k;",
+            f"{i2}}}",
+        ] + derived + tail
+    if style != "late":
+        raise ValueError(f"unknown loop style {style!r}")
+    return head + [
+        f"{ind}const int nbm1 = pb.nprim - 1;",
+        f"{ind}double rzeta = pbp[0].zeta, ro2z = pbp[0].o2z, rPx = pbp[0].px, rPy = pbp[0].py, rPz = pbp[0].pz, rKb = pbp[0].k;",
+        f"{ind}double reta = pkp[0].zeta, ro2e = pkp[0].o2z, rQx = pkp[0].px, rQy = pkp[0].py, rQz = pkp[0].pz, rKk = pkp[0].k;",
+        f"{ind}int ip = 0, jp = 0;",
+        f"{ind}for (int t = 0; t < ntot; ++t) {{",
+        f"{i2}const double zeta = rzeta, o2z = ro2z, Px = rPx, Py = rPy, Pz = rPz, Kb = rKb;",
+        f"{i2}const double eta = reta, o2e = ro2e, Qx = rQx, Qy = rQy, Qz = rQz, Kk = rKk;",
+    ] + derived + [
+        # the records of iteration t + 1 (clamped in range on the last iteration)
+        f"{i2}if (++jp == nkp) {{ jp = 0; ++ip; }}",
+        f"{i2}{{",
+        f"{i2}    const PrimPair *b = pbp + min(ip, nbm1), *k = pkp + jp;",
+        f"{i2}    rzeta = b->zeta; ro2z = b->o2z; rPx = b->px; rPy = b->py; rPz = b->pz; rKb = b->k;",
+        f"{i2}    reta = k->zeta; ro2e = k->o2z; rQx = k->px; rQy = k->py; rQz = k->pz; rKk = k->k;",
+        f"{i2}}}",
+    ] + tail
 
 
 def loop_close(ind):
@@ -284,7 +316,7 @@ def digest_lines(na, nb, nc, nd, I, J, K, digest="loads_first", reduce="segmente
 
 
 def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves=0, digest="loads_first",
-               reduce="segmented"):
+               reduce="segmented", loop="late"):
     ls = (la, lb, lc, ld)
     tag = tag_of(ls)
     L = sum(ls)
@@ -314,7 +346,7 @@ def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves
     w("{")
     for k in range(0, len(hnames), 8):
         w("    double " + ", ".join(f"{h} = 0.0" for h in hnames[k:k + 8]) + ";")
-    out.extend(loop_prelude(L, "    "))
+    out.extend(loop_prelude(L, "    ", loop))
     out.extend(vlines)
     out.extend(loop_close("    "))
     w("    const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz;")
@@ -391,7 +423,7 @@ def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves
     w("")
     w("}  // namespace hgp")
     meta = ClassMeta(ls, tag, 0, block, len(g.nodes), g.flops(), len(g.targets), pl, sched, p2.flops, nout, rule,
-                     waves=waves, digest=digest, reduce=reduce)
+                     waves=waves, digest=digest, reduce=reduce, loop=loop)
     return "\n".join(out) + "\n", meta
 
 

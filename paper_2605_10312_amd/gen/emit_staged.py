@@ -119,7 +119,7 @@ def _names_in(op):
 
 
 def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedulers=None, waves=0,
-                      reduce="segmented"):
+                      reduce="segmented", loop="late"):
     ls = (la, lb, lc, ld)
     tag = tag_of(ls)
     g = vrrmod.VRRGraph(la, lb, lc, ld, rule=rule)
@@ -178,7 +178,7 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
         names = [tnames[t] for t in ch]
         for k in range(0, len(names), 8):
             w("        double " + ", ".join(f"{h} = 0.0" for h in names[k:k + 8]) + ";")
-        out.extend(loop_prelude(Lc, "        "))
+        out.extend(loop_prelude(Lc, "        ", loop))
         out.extend(_vrr_chunk_lines(g, corder, tnames, "            "))
         out.extend(loop_close("        "))
         for t in ch:
@@ -387,5 +387,5 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
     w("}  // namespace hgp")
     meta = ClassMeta(ls, tag, 1, block, len(g.nodes), full, n_h, pl, sched, p2.flops, nout, rule,
                      scratch_slots=nslots, chunks=len(chunks), recompute=recompute, cap=cap, waves=waves,
-                     digest="", reduce=reduce)
+                     digest="", reduce=reduce, loop=loop)
     return "\n".join(out) + "\n", meta

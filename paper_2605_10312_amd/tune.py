@@ -35,7 +35,11 @@ VARIANTS = {
     "uniform": {"digest": "loads_first", "reduce": "uniform"},
     "seg": {"digest": "loads_first", "reduce": "segmented"},
     "seg_il": {"digest": "interleaved", "reduce": "segmented"},
+    "seg_pf": {"digest": "loads_first", "reduce": "segmented", "loop": "prefetch"},
     "seg_w2": {"digest": "loads_first", "reduce": "segmented", "waves": 2},
+    "cap64": {"digest": "loads_first", "reduce": "segmented", "cap": 64},
+    "cap48": {"digest": "loads_first", "reduce": "segmented", "cap": 48},
+    "staged": {"digest": "loads_first", "reduce": "segmented", "tier": 1},
 }
 
 
@@ -108,7 +112,7 @@ def select(path, table=TABLE):
         opts = {"tier": res[best[1]]["classes"][tag]["tier"]}
         opts.update({k: v for k, v in VARIANTS[best[1]].items()})
         if opts["tier"] == 1:
-            opts = {k: v for k, v in opts.items() if k in ("tier", "cap", "waves", "reduce")}
+            opts = {k: v for k, v in opts.items() if k in ("tier", "cap", "waves", "reduce", "loop")}
         opts["variant"] = best[1]
         opts["ms"] = round(best[0], 4)
         chosen[tag] = opts
