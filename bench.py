@@ -90,6 +90,54 @@ def cpu_baseline(bw, target_s, seed=7):
                       f"integrals only (no J/K digestion), {dt:.1f} s"}
 
 
+MICRO_N = 100_000
+
+
+def microbench(args):
+    """High-l class microbench: 1e5 independent normalised primitive quartets
+    per class, (dd|dd), (ff|ff), (gg|gg), centres in a 6 A box, exponents
+    log-uniform [0.1, 100]; inputs and outputs device-resident.  One JSON line
+    per class: primitive-quartet spherical integrals per second and the
+    generator's FLOP count per quartet against the FP64 VALU peak."""
+    import torch
+    import paper_2605_10312_amd as hgp
+    import workloads
+    from paper_2605_10312_amd.gen import phase2 as p2mod, vrr as vrrmod
+
+    for l in (2, 3, 4):
+        ls = (l, l, l, l)
+        cen, ex = workloads.prim_quartets(l, MICRO_N)
+        ct = torch.tensor(cen, device="cuda")
+        et = torch.tensor(ex, device="cuda")
+        n_sph = (2 * l + 1) ** 4
+        out = torch.empty((MICRO_N, n_sph), dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            hgp.eri_prim_quartets(ls, ct, et, out)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            hgp.eri_prim_quartets(ls, ct, et, out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.steps
+        g = vrrmod.VRRGraph(*ls)
+        tg = {tt: f"h{k}" for k, tt in enumerate(g.targets)}
+        p2 = p2mod.Phase2(*ls, hname=lambda e, f: tg[(e, f)])
+        flop = g.flops() + overhead_flops(4 * l) + p2.flops
+        line = {"metric": "primitive-quartet spherical ERIs/s (high-l class microbench)", "value": MICRO_N * n_sph / dt,
+                "unit": "ERIs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f64", "data": "synthetic",
+                "config": {"workload": f"microbench_{l}{l}{l}{l}: {MICRO_N} primitive quartets ({'spdfg'[l]}{'spdfg'[l]}|"
+                                       f"{'spdfg'[l]}{'spdfg'[l]}), 6 A box, exponents log-uniform [0.1, 100], FP64",
+                           "flop_per_quartet": flop},
+                "roofline": {"bound": "alu", "achieved": round(MICRO_N * flop / dt / 1e12, 3),
+                             "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(MICRO_N * flop / dt / 1e12 / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None}}
+        print(json.dumps(line), flush=True)
+        del out, ct, et
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +146,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--workload", choices=("mol30", "microbench"), default="mol30",
+                    help="mol30: the J/K build (one JSON line); microbench: the high-l primitive-quartet classes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy kernel (y = 1.0 * x, MIB MiB of FP64 each way), "
                          "a known-size reference for hardware byte counters")
@@ -105,6 +155,10 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "microbench":
+        microbench(args)
+        return
 
     import torch
     import paper_2605_10312_amd as hgp

@@ -59,6 +59,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_10312_amd.build`")
+        # torch ships its own HIP runtime.  Loading torch first makes the
+        # library bind to that same runtime; loaded the other way round, the
+        # process ends up with two runtimes and the library's sees no device.
+        import torch  # noqa: F401
         h = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(h, name)

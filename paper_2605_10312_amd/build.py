@@ -27,10 +27,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", CSRC, "-I", INCLUDE]
-DEFAULT_LMAX = 2
+DEFAULT_LMAX = 4
 
 
-REGISTER_OPTS = ("waves", "digest", "reduce", "loop")
+REGISTER_OPTS = ("waves", "digest", "reduce", "loop", "block")
 STAGED_OPTS = ("cap", "waves", "reduce", "loop")
 
 
@@ -41,9 +41,9 @@ def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overri
     defaults (generator options for every class) are applied first, then
     the router's choice (tuning table, else the register model), then
     overrides, a map from class tag to options that wins over both.
-    Register-tier options: waves, digest, reduce, loop; staged: cap, waves,
-    reduce, loop."""
-    from .gen import emit, emit_staged, router
+    Register-tier options: waves, digest, reduce, loop, block; staged: cap,
+    waves, reduce, loop."""
+    from .gen import emit, emit_staged, emit_t3, router
     from .gen.cart import canonical_classes
 
     GEN = gen_dir
@@ -58,7 +58,9 @@ def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overri
                 r[k] = v
         if overrides and tag in overrides:
             r.update(overrides[tag])
-        if r["tier"] == 1:
+        if r["tier"] == 2:
+            src, meta = emit_t3.emit_class_t3(*ls)
+        elif r["tier"] == 1:
             src, meta = emit_staged.emit_class_staged(*ls, **{k: r[k] for k in STAGED_OPTS if k in r})
         else:
             src, meta = emit.emit_class(*ls, **{k: r[k] for k in REGISTER_OPTS if k in r})
@@ -90,8 +92,8 @@ def _write_if_changed(path, text):
 
 
 def _compile(src: str, force: bool):
-    if not src.startswith(CSRC + os.sep):  # generated class kernels see only the device headers
-        deps = [src, os.path.join(CSRC, "hgp_device.h"), os.path.join(CSRC, "hgp_types.h")]
+    if not src.startswith(CSRC + os.sep):  # generated class files see only these headers
+        deps = [src] + [os.path.join(CSRC, h) for h in ("hgp_device.h", "hgp_types.h", "hgp_t3.h")]
     else:
         deps = [src] + [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".h")] + \
                [os.path.join(INCLUDE, f) for f in sorted(os.listdir(INCLUDE))]
@@ -137,7 +139,9 @@ def build(lmax: int = DEFAULT_LMAX, jobs: int | None = None, force: bool = False
     os.replace(tmp, lib)
     if verbose:
         staged = [m.tag for m in metas if m.tier == 1]
-        print(f"built {lib} ({len(metas)} classes, l <= {lmax}, staged: {' '.join(staged) or 'none'}) "
+        t3 = [m.tag for m in metas if m.tier == 2]
+        print(f"built {lib} ({len(metas)} classes, l <= {lmax}, staged: {' '.join(staged) or 'none'}, "
+              f"HBM scratch: {' '.join(t3) or 'none'}) "
               f"in {time.time() - t0:.1f}s", flush=True)
     return lib
 

@@ -142,7 +142,10 @@ __device__ __forceinline__ void boys_fm(double T, const double *__restrict__ tab
             for (int m = L - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (double)(2 * m + 1));
         }
     } else {
-        const double e = L > 0 ? exp(-T) : 0.0;
+        // exp(-T) <= 2.4e-16 here: it only corrects F_m by that order, so the
+        // single-precision hardware exp2 (relative error ~1e-7, flushing to 0
+        // below 1e-38) is far more accurate than needed.
+        const double e = L > 0 ? (double)__builtin_amdgcn_exp2f((float)(T * -1.4426950408889634)) : 0.0;
         const double rt = hgp_rcp(T);
         F[0] = 0.88622692545275801365 * hgp_rsqrt(T);      // sqrt(pi)/2 * T^(-1/2)
         const double h = 0.5 * rt;

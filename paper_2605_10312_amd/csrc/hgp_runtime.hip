@@ -79,14 +79,25 @@ int64_t staged_batch(const ClassKernels &k, int64_t doubles)
 // Buffer a staged class needs to run all n items in one batch (capped).
 int64_t staged_need(const ClassKernels &k, int64_t n)
 {
-    if (k.tier != 1 || n <= 0) return 0;
+    if (k.tier == 0 || n <= 0) return 0;
     const int64_t want = (int64_t)k.scratch_slots * (((n + 63) / 64) * 64);
     const int64_t floor64 = (int64_t)k.scratch_slots * 64;
     return std::max(floor64, std::min(want, SCRATCH_MAX_DOUBLES));
 }
 
+// The HBM-scratch tier's tables must be on the device before its first launch.
+hgp_status prepare_class(const ClassKernels &k)
+{
+    const int e = k.prepare ? k.prepare() : 0;
+    if (e != 0)
+        return fail(HGP_E_DEVICE, std::string("uploading the op tables of an HBM-scratch class failed: ") +
+                                      hipGetErrorString((hipError_t)e));
+    return HGP_OK;
+}
+
 // Integrals-out work of one class: register tier in launches of at most 2^20
-// blocks; staged tier in batches (Phase 1 then Phase 2).
+// blocks; staged tier in batches (Phase 1 then Phase 2); HBM-scratch tier in
+// batches of one kernel each.
 void run_eri_class(const ClassKernels &k, EriArgs a, int64_t scratch_doubles, hipStream_t s)
 {
     const int64_t ntask = a.ntask;
@@ -104,9 +115,11 @@ void run_eri_class(const ClassKernels &k, EriArgs a, int64_t scratch_doubles, hi
     const int64_t B = staged_batch(k, scratch_doubles);
     for (int64_t q0 = 0; q0 < ntask; q0 += B) {
         const int64_t nb = std::min(B, ntask - q0);
-        P1Args pa{(const int32_t *)(a.tasks + q0), (int64_t)(sizeof(EriTask) / sizeof(int32_t)), nb, a.pairs, a.geo,
-                  a.prims, a.boys, a.scratch, B};
-        k.p1(pa, s);
+        if (k.tier == 1) {
+            P1Args pa{(const int32_t *)(a.tasks + q0), (int64_t)(sizeof(EriTask) / sizeof(int32_t)), nb, a.pairs,
+                      a.geo, a.prims, a.boys, a.scratch, B};
+            k.p1(pa, s);
+        }
         EriArgs b = a;
         b.tasks = a.tasks + q0;
         b.ntask = nb;
@@ -265,7 +278,11 @@ hgp_status hgp_basis_create(int32_t nshell, const int32_t *l, const int32_t *npr
     b->cen.assign(centers, centers + 3 * nshell);
     b->exps.assign(exps, exps + np);
     b->coefs.assign(coefs, coefs + np);
-    if (hipGetDevice(&b->device) != hipSuccess) { hgp_basis_destroy(b); return fail(HGP_E_DEVICE, "hipGetDevice failed"); }
+    const hipError_t de = hipGetDevice(&b->device);
+    if (de != hipSuccess) {
+        hgp_basis_destroy(b);
+        return fail(HGP_E_DEVICE, std::string("hipGetDevice failed: ") + hipGetErrorString(de));
+    }
     hgp_status st;
     if ((st = upload(&b->d_l, b->l)) || (st = upload(&b->d_nprim, b->nprim)) || (st = upload(&b->d_poff, b->poff)) ||
         (st = upload(&b->d_cen, b->cen)) || (st = upload(&b->d_exps, b->exps)) || (st = upload(&b->d_coefs, b->coefs)) ||
@@ -326,6 +343,8 @@ static hgp_status schwarz_factors(const PairInfo *d_pairs, const PairGeo *d_geo,
         const int lb = c - pair_class_of(la, 0);
         cls[c] = class_index(la, lb, la, lb);
         if (cls[c] < 0) return fail(HGP_E_UNSUPPORTED_L, "class kernel not built");
+        hgp_status ps = prepare_class(g_class_table[cls[c]]);
+        if (ps) return ps;
         sneed = std::max(sneed, staged_need(g_class_table[cls[c]], count[c]));
     }
     hgp_status st;
@@ -560,6 +579,7 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
             const int lb = bc - pair_class_of(la, 0), ld = kc - pair_class_of(lc, 0);
             const int ci = class_index(la, lb, lc, ld);
             if (ci < 0) { hipFree(d_counts); hipFree(d_total); return fail(HGP_E_UNSUPPORTED_L, "class kernel not built"); }
+            if ((st = prepare_class(g_class_table[ci]))) { hipFree(d_counts); hipFree(d_total); return st; }
             const int sym = (bc == kc);
             const int b0 = p->pc_begin[bc], k0 = p->pc_begin[kc];
             const double t = tau > 0 ? tau : -1.0;
@@ -755,15 +775,22 @@ hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_
             const int64_t B = staged_batch(k, p->scratch_doubles);
             for (int64_t q0 = 0; q0 < cl.nq; q0 += B) {
                 const int64_t nb = std::min(B, cl.nq - q0);
+                a.quartets = cl.d_q + q0;
+                a.nq = nb;
+                a.scratch = p->d_scratch;
+                a.stride = B;
+                if (k.tier == 2) {                     // HBM-scratch tier: one kernel per batch
+                    if ((st = mark(&e0))) return st;
+                    k.jk(a, s);
+                    if ((st = mark(&e1))) return st;
+                    done((int)li, 0, e0, e1);
+                    continue;
+                }
                 P1Args pa{(const int32_t *)(cl.d_q + q0), 2, nb, p->d_pairs, p->d_geo, p->d_prims, boys,
                           p->d_scratch, B};
                 if ((st = mark(&e0))) return st;
                 k.p1(pa, s);
                 if ((st = mark(&e1)) || (st = mark(&e2))) return st;
-                a.quartets = cl.d_q + q0;
-                a.nq = nb;
-                a.scratch = p->d_scratch;
-                a.stride = B;
                 k.jk(a, s);
                 if ((st = mark(&e3))) return st;
                 done((int)li, 0, e0, e1);
@@ -862,6 +889,10 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
         a.out = out;
         a.mode = 0;
         a.scratch = d_scr;
+        if ((st = prepare_class(g_class_table[c]))) {
+            cleanup();
+            return st;
+        }
         run_eri_class(g_class_table[c], a, sneed, s);
     }
     hipError_t e = hipGetLastError();
@@ -895,6 +926,7 @@ hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld,
     for (int r = 0; r < 4; ++r) { ls[r] = lin[pos[r]]; nn[r] = nsph(lin[r]); }
     const int ci = class_index(ls[0], ls[1], ls[2], ls[3]);
     if (ci < 0) return fail(HGP_E_UNSUPPORTED_L, "class kernel not built into this library");
+    if (hgp_status pst = prepare_class(g_class_table[ci])) return pst;
     stride[3] = 1; stride[2] = nn[3]; stride[1] = nn[2] * nn[3]; stride[0] = nn[1] * nn[2] * nn[3];
     for (int r = 0; r < 4; ++r) cs[r] = stride[pos[r]];
     const int64_t blk = (int64_t)nn[0] * nn[1] * nn[2] * nn[3];

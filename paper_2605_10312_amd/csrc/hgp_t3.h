@@ -1,0 +1,33 @@
+// HBM-scratch tier: one generic kernel per mode runs a class's op table (the
+// generator's VRR and Phase-2 programs with slot-packed operands) over a
+// lane-interleaved buffer.  A generated class file holds only the tables
+// (host data) and two launchers.
+#pragma once
+#include "hgp_types.h"
+
+namespace hgp {
+
+// Op codes of the tables (eight uint16 words per op; see gen/emit_t3.py).
+enum : int { T3_VRR_BRA = 1, T3_VRR_KET = 2, T3_ACC = 3, T3_HRR_BRA = 4, T3_HRR_KET = 5, T3_LIN = 6, T3_LIN_ACC = 7 };
+constexpr uint16_t T3_NONE = 0xFFFF;
+
+struct T3Class {
+    int la, lb, lc, ld, L;
+    int na, nb, nc, nd;          // spherical functions per shell
+    int nslots;                  // doubles of buffer per lane
+    int n_hrr, acc0;             // accumulators [e0|f0] in slots acc0 .. acc0 + n_hrr - 1
+    int n_vrr, n_p2;             // ops per primitive quartet, ops of Phase 2
+    const uint16_t *ops;         // host: 8 words per op, VRR part first
+    int ncoef;
+    const double *coefs;         // host: transform coefficients
+    const uint16_t *outslots;    // host: slot of integral (mu, nu, lam, sig), row-major
+    int block;                   // threads per block
+};
+
+// 0 (hipSuccess) once the class's tables are on the current device (uploaded
+// on first call), else the hipError_t of the step that failed.
+int t3_prepare(const T3Class &c);
+void t3_launch_jk(const T3Class &c, const JKArgs &a, hipStream_t s);
+void t3_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s);
+
+}  // namespace hgp

@@ -108,18 +108,21 @@ typedef void (*launch_jk_fn)(const JKArgs &, hipStream_t);
 typedef void (*launch_eri_fn)(const EriArgs &, hipStream_t);
 typedef void (*launch_p1_fn)(const P1Args &, hipStream_t);
 
+typedef int (*prepare_fn)();
+
 struct ClassKernels {
     int la, lb, lc, ld;
-    int tier;               // 0 register, 1 staged (HBM scratch)
+    int tier;               // 0 register, 1 staged (chunked Phase 1 + Phase 2), 2 HBM scratch (op tables)
     launch_jk_fn jk;
     launch_eri_fn eri;
     launch_p1_fn p1;        // staged tier only (nullptr otherwise)
+    prepare_fn prepare;     // HBM-scratch tier: uploads the class tables to the current device (0 on success)
     int block;              // threads per block
     double vrr_flops;       // per primitive quartet (generator count)
     double p2_flops;        // per contracted quartet: HRR + transform
     int n_hrr;
     int peak_live;
-    int scratch_slots;      // doubles of scratch per lane (0 for the register tier)
+    int scratch_slots;      // doubles of buffer per quartet (0 for the register tier)
     int chunks;             // Phase-1 target chunks
 };
 

@@ -435,12 +435,15 @@ def emit_table(metas):
         out.append(f"void launch_eri_{m.tag}(const EriArgs &, hipStream_t);")
         if m.tier == 1:
             out.append(f"void launch_p1_{m.tag}(const P1Args &, hipStream_t);")
+        if m.tier == 2:
+            out.append(f"int prepare_{m.tag}();")
     out.append("")
     out.append("extern const ClassKernels g_class_table[] = {")
     for m in metas:
         la, lb, lc, ld = m.ls
         p1 = f"launch_p1_{m.tag}" if m.tier == 1 else "nullptr"
-        out.append(f"    {{{la}, {lb}, {lc}, {ld}, {m.tier}, launch_jk_{m.tag}, launch_eri_{m.tag}, {p1}, {m.block}, "
+        prep = f"prepare_{m.tag}" if m.tier == 2 else "nullptr"
+        out.append(f"    {{{la}, {lb}, {lc}, {ld}, {m.tier}, launch_jk_{m.tag}, launch_eri_{m.tag}, {p1}, {prep}, {m.block}, "
                    f"{m.vrr_flops}.0, {m.p2_flops}.0, {m.n_hrr}, {m.peak_live}, {m.scratch_slots}, {m.chunks}}},")
     out.append("};")
     out.append(f"extern const int g_num_classes = {len(metas)};")

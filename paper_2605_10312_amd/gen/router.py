@@ -9,12 +9,19 @@ model here is
     demand = N_hrr + PeakLive + 40      (40: pair/Boys/VRR coefficients)
 
     register tier (one kernel, everything in VGPR/AGPR)   if demand <= 240
-    staged tier (Phase-1 chunks + HBM-staged Phase 2)     otherwise
+    staged tier (Phase-1 chunks + HBM-staged Phase 2)     if the VRR graph has
+                                                          <= 3000 nodes and
+                                                          N_hrr <= 1024
+    HBM-scratch tier (slot-packed op tables)              otherwise
 
 The 240-double line was set from the compiler's resource reports: every
 class at or under it compiles without scratch, every class above it spilled.
-A tuning table measured on the GPU (tuning/gfx950.json) overrides the model
-per class: tier, chunk cap and waves per SIMD.
+The staged tier recomputes, per chunk of accumulators, the part of the VRR
+graph the chunk needs and emits it as straight-line code; past (dd|dd)'s
+size (2330 nodes, 961 accumulators) the recomputation and the code grow
+faster than they pay, so larger classes go to the HBM-scratch tier, whose
+code does not grow with the class.  A tuning table measured on the GPU
+(tuning/gfx950.json) overrides the model per class.
 """
 from __future__ import annotations
 
@@ -28,10 +35,21 @@ DEFAULT_CAP = 96
 TABLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tuning", "gfx950.json")
 
 
+STAGED_MAX_NODES = 3000
+STAGED_MAX_HRR = 1024
+
+
 def model_demand(ls):
     g = vrrmod.VRRGraph(*ls)
     _, pl, _ = vrrmod.best_order(g)
     return g.n_hrr() + pl + 40
+
+
+def model_tier(ls):
+    g = vrrmod.VRRGraph(*ls)
+    if len(g.nodes) > STAGED_MAX_NODES or g.n_hrr() > STAGED_MAX_HRR:
+        return 0 if g.n_hrr() + 40 <= REGISTER_DOUBLES and model_demand(ls) <= REGISTER_DOUBLES else 2
+    return 0 if model_demand(ls) <= REGISTER_DOUBLES else 1
 
 
 def load_table(path=TABLE):
@@ -78,11 +96,11 @@ def model_cap(ls):
 
 
 def route(ls, table=None):
-    """-> dict(tier=0|1, cap=int, waves=int, source='model'|'table')"""
+    """-> dict(tier=0|1|2, cap=int, waves=int, source='model'|'table')"""
     tag = "".join(str(x) for x in ls)
     table = load_table() if table is None else table
     t = dict(table.get(tag, {}))
-    tier = t.get("tier", 0 if model_demand(ls) <= REGISTER_DOUBLES else 1)
+    tier = t.get("tier", model_tier(ls))
     cap = model_cap(ls) if tier == 1 else DEFAULT_CAP
     r = {"tier": tier, "cap": cap, "waves": 0, "source": "model"}
     if t:                      # measured entries win; what they leave out comes from the model

@@ -37,6 +37,9 @@ VARIANTS = {
     "seg_il": {"digest": "interleaved", "reduce": "segmented"},
     "seg_pf": {"digest": "loads_first", "reduce": "segmented", "loop": "prefetch"},
     "seg_w2": {"digest": "loads_first", "reduce": "segmented", "waves": 2},
+    "b64": {"digest": "loads_first", "reduce": "segmented", "block": 64},
+    "b128": {"digest": "loads_first", "reduce": "segmented", "block": 128},
+    "b64_w2": {"digest": "loads_first", "reduce": "segmented", "block": 64, "waves": 2},
     "cap64": {"digest": "loads_first", "reduce": "segmented", "cap": 64},
     "cap48": {"digest": "loads_first", "reduce": "segmented", "cap": 48},
     "staged": {"digest": "loads_first", "reduce": "segmented", "tier": 1},
