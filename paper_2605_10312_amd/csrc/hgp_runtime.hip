@@ -82,7 +82,7 @@ int64_t staged_need(const ClassKernels &k, int64_t n)
     if (k.tier == 0 || n <= 0) return 0;
     const int64_t want = (int64_t)k.scratch_slots * (((n + 63) / 64) * 64);
     const int64_t floor64 = (int64_t)k.scratch_slots * 64;
-    return std::max(floor64, std::min(want, SCRATCH_MAX_DOUBLES));
+    return std::max(floor64, std::min(want, k.tier == 2 ? T3_SCRATCH_MAX_DOUBLES : SCRATCH_MAX_DOUBLES));
 }
 
 // The HBM-scratch tier's tables must be on the device before its first launch.

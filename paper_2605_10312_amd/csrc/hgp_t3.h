@@ -10,6 +10,10 @@ namespace hgp {
 // Op codes of the tables (eight uint16 words per op; see gen/emit_t3.py).
 enum : int { T3_VRR_BRA = 1, T3_VRR_KET = 2, T3_ACC = 3, T3_HRR_BRA = 4, T3_HRR_KET = 5, T3_LIN = 6, T3_LIN_ACC = 7 };
 constexpr uint16_t T3_NONE = 0xFFFF;
+// Ops come in groups of T3_GROUP (padded with op code 0): no op of a group
+// reads a slot another op of the group writes, so a group issues all its
+// operand loads before it computes (the generator's bundling, gen/emit_t3.py).
+constexpr int T3_GROUP = 8;
 
 struct T3Class {
     int la, lb, lc, ld, L;

@@ -95,56 +95,113 @@ __device__ void t3_quartet(const T3Params &c, const uint4 *__restrict__ ops, con
             t3_boys(T, c.L, boys, b.k * q.k * hgp_rsqrt(ze), sb, S, li);
             const double WPx = -rz * PQx, WPy = -rz * PQy, WPz = -rz * PQz;
             const double WQx = re * PQx, WQy = re * PQy, WQz = re * PQz;
-            for (int k = 0; k < c.n_vrr; ++k) {
-                const uint4 o = ops[k];
-                const uint32_t w0 = o.x & 0xFFFFu, dst = o.x >> 16;
-                const uint32_t code = w0 & 15u, axis = (w0 >> 4) & 3u;
-                if (code == T3_ACC) {
-                    at(dst) += at(o.y & 0xFFFFu);
+            // groups of T3_GROUP independent ops: every operand load of the
+            // group is issued before the first result is computed
+            for (int g = 0; g < c.n_vrr; g += T3_GROUP) {
+                uint4 o[T3_GROUP];
+#pragma unroll
+                for (int j = 0; j < T3_GROUP; ++j) o[j] = ops[g + j];
+                if ((o[0].x & 15u) == T3_ACC) {
+                    double x[T3_GROUP], y[T3_GROUP];
+#pragma unroll
+                    for (int j = 0; j < T3_GROUP; ++j) {
+                        if ((o[j].x & 15u) == 0) continue;
+                        x[j] = at(o[j].x >> 16);
+                        y[j] = at(o[j].y & 0xFFFFu);
+                    }
+#pragma unroll
+                    for (int j = 0; j < T3_GROUP; ++j)
+                        if ((o[j].x & 15u) != 0) at(o[j].x >> 16) = x[j] + y[j];
                     continue;
                 }
-                const uint32_t ks = (w0 >> 6) & 31u, kc = (w0 >> 11) & 31u;
-                double X, Y, o2, r;
-                if (code == T3_VRR_BRA) {
-                    X = axis == 0 ? PAx : (axis == 1 ? PAy : PAz);
-                    Y = axis == 0 ? WPx : (axis == 1 ? WPy : WPz);
-                    o2 = b.o2z;
-                    r = rz;
-                } else {
-                    X = axis == 0 ? QCx : (axis == 1 ? QCy : QCz);
-                    Y = axis == 0 ? WQx : (axis == 1 ? WQy : WQz);
-                    o2 = q.o2z;
-                    r = re;
+                double v1[T3_GROUP], v2[T3_GROUP], v3[T3_GROUP], v4[T3_GROUP], v5[T3_GROUP];
+#pragma unroll
+                for (int j = 0; j < T3_GROUP; ++j) {
+                    if ((o[j].x & 15u) == 0) continue;
+                    const uint32_t w0 = o[j].x & 0xFFFFu;
+                    v1[j] = at(o[j].y & 0xFFFFu);
+                    v2[j] = at(o[j].y >> 16);
+                    if ((w0 >> 6) & 31u) {
+                        v3[j] = at(o[j].z & 0xFFFFu);
+                        v4[j] = at(o[j].z >> 16);
+                    }
+                    if ((w0 >> 11) & 31u) v5[j] = at(o[j].w & 0xFFFFu);
                 }
-                double v = fma(X, at(o.y & 0xFFFFu), Y * at(o.y >> 16));
-                if (ks) v = fma((double)ks * o2, fma(-r, at(o.z >> 16), at(o.z & 0xFFFFu)), v);
-                if (kc) v = fma((double)kc * o2ze, at(o.w & 0xFFFFu), v);
-                at(dst) = v;
+#pragma unroll
+                for (int j = 0; j < T3_GROUP; ++j) {
+                    const uint32_t w0 = o[j].x & 0xFFFFu;
+                    const uint32_t code = w0 & 15u, axis = (w0 >> 4) & 3u;
+                    if (code == 0) continue;
+                    const uint32_t ks = (w0 >> 6) & 31u, kc = (w0 >> 11) & 31u;
+                    double X, Y, o2, r;
+                    if (code == T3_VRR_BRA) {
+                        X = axis == 0 ? PAx : (axis == 1 ? PAy : PAz);
+                        Y = axis == 0 ? WPx : (axis == 1 ? WPy : WPz);
+                        o2 = b.o2z;
+                        r = rz;
+                    } else {
+                        X = axis == 0 ? QCx : (axis == 1 ? QCy : QCz);
+                        Y = axis == 0 ? WQx : (axis == 1 ? WQy : WQz);
+                        o2 = q.o2z;
+                        r = re;
+                    }
+                    double v = fma(X, v1[j], Y * v2[j]);
+                    if (ks) v = fma((double)ks * o2, fma(-r, v4[j], v3[j]), v);
+                    if (kc) v = fma((double)kc * o2ze, v5[j], v);
+                    at(o[j].x >> 16) = v;
+                }
             }
         }
     }
     // Phase 2: HRR and the stepwise transforms (Eq. hrr, Eqs. bra-sph .. stepwise-sph)
     const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz, CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;
-    for (int k = c.n_vrr; k < c.n_vrr + c.n_p2; ++k) {
-        const uint4 o = ops[k];
-        const uint32_t w0 = o.x & 0xFFFFu, dst = o.x >> 16;
-        const uint32_t code = w0 & 15u, axis = (w0 >> 4) & 3u;
-        if (code == T3_HRR_BRA || code == T3_HRR_KET) {
-            const double d = code == T3_HRR_BRA ? (axis == 0 ? ABx : (axis == 1 ? ABy : ABz))
-                                                : (axis == 0 ? CDx : (axis == 1 ? CDy : CDz));
-            at(dst) = fma(d, at(o.y >> 16), at(o.y & 0xFFFFu));
+    for (int g = c.n_vrr; g < c.n_vrr + c.n_p2; g += T3_GROUP) {
+        uint4 o[T3_GROUP];
+#pragma unroll
+        for (int j = 0; j < T3_GROUP; ++j) o[j] = ops[g + j];
+        const uint32_t gcode = o[0].x & 15u;
+        if (gcode == T3_HRR_BRA || gcode == T3_HRR_KET) {
+            double hi[T3_GROUP], lo[T3_GROUP];
+#pragma unroll
+            for (int j = 0; j < T3_GROUP; ++j) {
+                if ((o[j].x & 15u) == 0) continue;
+                hi[j] = at(o[j].y & 0xFFFFu);
+                lo[j] = at(o[j].y >> 16);
+            }
+#pragma unroll
+            for (int j = 0; j < T3_GROUP; ++j) {
+                const uint32_t code = o[j].x & 15u, axis = (o[j].x >> 4) & 3u;
+                if (code == 0) continue;
+                const double d = code == T3_HRR_BRA ? (axis == 0 ? ABx : (axis == 1 ? ABy : ABz))
+                                                    : (axis == 0 ? CDx : (axis == 1 ? CDy : CDz));
+                at(o[j].x >> 16) = fma(d, lo[j], hi[j]);
+            }
         } else {
-            const uint32_t s1 = o.y & 0xFFFFu, s2 = o.y >> 16, s3 = o.z & 0xFFFFu;
-            double v = code == T3_LIN_ACC ? at(dst) : 0.0;
-            v = fma(coefs[o.z >> 16], at(s1), v);
-            if (s2 != T3_NONE) v = fma(coefs[o.w & 0xFFFFu], at(s2), v);
-            if (s3 != T3_NONE) v = fma(coefs[o.w >> 16], at(s3), v);
-            at(dst) = v;
+            double x1[T3_GROUP], x2[T3_GROUP], x3[T3_GROUP], acc[T3_GROUP];
+#pragma unroll
+            for (int j = 0; j < T3_GROUP; ++j) {
+                const uint32_t code = o[j].x & 15u;
+                if (code == 0) continue;
+                x1[j] = at(o[j].y & 0xFFFFu);
+                if ((o[j].y >> 16) != T3_NONE) x2[j] = at(o[j].y >> 16);
+                if ((o[j].z & 0xFFFFu) != T3_NONE) x3[j] = at(o[j].z & 0xFFFFu);
+                if (code == T3_LIN_ACC) acc[j] = at(o[j].x >> 16);
+            }
+#pragma unroll
+            for (int j = 0; j < T3_GROUP; ++j) {
+                const uint32_t code = o[j].x & 15u;
+                if (code == 0) continue;
+                double v = code == T3_LIN_ACC ? acc[j] : 0.0;
+                v = fma(coefs[o[j].z >> 16], x1[j], v);
+                if ((o[j].y >> 16) != T3_NONE) v = fma(coefs[o[j].w & 0xFFFFu], x2[j], v);
+                if ((o[j].z & 0xFFFFu) != T3_NONE) v = fma(coefs[o[j].w >> 16], x3[j], v);
+                at(o[j].x >> 16) = v;
+            }
         }
     }
 }
 
-__global__ void t3_jk_kernel(T3Params c, const uint4 *__restrict__ ops, const double *__restrict__ coefs,
+__global__ __launch_bounds__(64) void t3_jk_kernel(T3Params c, const uint4 *__restrict__ ops, const double *__restrict__ coefs,
                              const uint16_t *__restrict__ outslots, JKArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -212,7 +269,7 @@ __global__ void t3_jk_kernel(T3Params c, const uint4 *__restrict__ ops, const do
     }
 }
 
-__global__ void t3_eri_kernel(T3Params c, const uint4 *__restrict__ ops, const double *__restrict__ coefs,
+__global__ __launch_bounds__(64) void t3_eri_kernel(T3Params c, const uint4 *__restrict__ ops, const double *__restrict__ coefs,
                               const uint16_t *__restrict__ outslots, EriArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -100,6 +100,10 @@ constexpr int BOYS_STRIDE = 25;    // per point: F_0 .. F_23, then exp(-T_k)
 // Largest staged-tier buffer a plan allocates (doubles): 4 GiB.  Classes whose
 // quartets do not fit in one batch are processed in several.
 constexpr int64_t SCRATCH_MAX_DOUBLES = (int64_t)1 << 29;
+// The HBM-scratch tier keeps every value of a quartet in the buffer (23 k
+// doubles per (gg|gg) quartet), so it may take up to 16 GiB to keep enough
+// quartets in flight; slot offsets stay below 2^32.
+constexpr int64_t T3_SCRATCH_MAX_DOUBLES = (int64_t)1 << 31;
 
 // Launchers run one lane per work item (nq or ntask): the register tier's
 // whole evaluation, or a staged class's Phase 2 + digestion; p1 launchers run

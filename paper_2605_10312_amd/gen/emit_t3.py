@@ -40,11 +40,14 @@ NONE = 0xFFFF
 XYZ_AXIS = {"x": 0, "y": 1, "z": 2}
 
 
+BUNDLE = 8      # ops per group; a group's operand loads are all in flight at once
+
+
 @dataclasses.dataclass
 class T3Tables:
-    ops: list            # flat uint16 words, 8 per op
-    n_vrr: int           # ops of the per-primitive part (VRR + ACC)
-    n_p2: int            # ops of Phase 2
+    ops: list            # flat uint16 words, 8 per op, groups of BUNDLE ops
+    n_vrr: int           # op slots of the per-primitive part (VRR + ACC), a multiple of BUNDLE
+    n_p2: int            # op slots of Phase 2, a multiple of BUNDLE
     coefs: list          # doubles
     outslots: list       # slot of integral (mu, nu, lam, sig), row-major
     nslots: int
@@ -55,6 +58,7 @@ class T3Tables:
     scheduler: str
     vrr_flops: int
     p2_flops: int
+    n_real_ops: int = 0  # ops before padding
 
 
 class _Slots:
@@ -75,62 +79,147 @@ class _Slots:
         self.free.append(s)
 
 
-def build_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None) -> T3Tables:
+def _group_class(kind):
+    return {"vrr": 0, "acc": 1, "hrr": 2, "lin": 3, "linacc": 3}[kind]
+
+
+def _bundle(ops, K):
+    """List-schedule abstract ops into groups of at most K ops of one class
+    (VRR, ACC, HRR, transform) such that no op reads a value produced in its
+    own group.  Ops are dicts with 'out' (new value or None), 'writes' (value
+    written, if it differs from 'out'), 'ins' (values read), 'after' (an op
+    that must run in an earlier group) and 'kind'; priority is the original
+    position, which keeps the liveness-minimising order as far as
+    independence allows."""
+    import heapq
+    producer = {}
+    for k, o in enumerate(ops):
+        w = o.get("writes", o["out"])
+        if w is not None:
+            producer[w] = k                      # the last writer (a chained transform's last part)
+    deps = []
+    users = [[] for _ in ops]
+    for k, o in enumerate(ops):
+        d = {producer[v] for v in o["ins"] if v in producer and producer[v] != k}
+        if o.get("after") is not None:
+            d.add(o["after"])
+        deps.append(len(d))
+        for j in d:
+            users[j].append(k)
+    ready = [k for k in range(len(ops)) if deps[k] == 0]
+    heapq.heapify(ready)
+    groups = []
+    while ready:
+        first = heapq.heappop(ready)
+        cls = _group_class(ops[first]["kind"])
+        grp, skipped = [first], []
+        while ready and len(grp) < K:
+            k = heapq.heappop(ready)
+            (grp if _group_class(ops[k]["kind"]) == cls else skipped).append(k)
+        for k in skipped:
+            heapq.heappush(ready, k)
+        groups.append(grp)
+        for k in grp:
+            for u in users[k]:
+                deps[u] -= 1
+                if deps[u] == 0:
+                    heapq.heappush(ready, u)
+    assert sum(len(g) for g in groups) == len(ops), "dependency cycle in the op list"
+    return groups
+
+
+def build_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None, bundle=BUNDLE) -> T3Tables:
     ls = (la, lb, lc, ld)
     L = sum(ls)
     g = vrrmod.VRRGraph(*ls, rule=rule)
     sched, pl, order = vrrmod.best_order(g) if schedulers is None else vrrmod.best_order(g, schedulers)
     n_hrr = len(g.targets)
     acc0 = L + 1
-    words = []
-
-    def op(w0, dst, a=NONE, b=NONE, c=NONE, d=NONE, e=NONE, f=NONE):
-        words.extend((w0, dst, a, b, c, d, e, f))
-
-    # ---- per-primitive part: VRR in schedule order, targets into accumulators
-    pos = {v: k for k, v in enumerate(order)}
-    last = [-1] * len(g.nodes)
-    for v in order:
-        for c in g.children[v]:
-            last[v] = max(last[v], pos[c])
     tpos = {tid: k for k, tid in enumerate(g.target_ids)}
-    slot = [None] * len(g.nodes)
-    alloc = _Slots(acc0 + n_hrr)
-    dies = {}
-    for k, v in enumerate(order):
-        nd = g.nodes[v]
-        if nd.kind == "base":
-            slot[v] = nd.key[2]                  # base * F_m sits in slot m
-        else:
-            s = alloc.get()
-            slot[v] = s
-            p = [slot[x] if x is not None else NONE for x in nd.parents]
-            code = OP_VRR_BRA if nd.kind == "bra" else OP_VRR_KET
-            op(code | (nd.axis << 4) | (nd.k_same << 6) | (nd.k_cross << 11), s, *p)
-        if v in tpos:
-            op(OP_ACC, acc0 + tpos[v], slot[v])
-        if nd.kind != "base":
-            if last[v] > k:
-                dies.setdefault(last[v], []).append(v)
-            else:
-                alloc.put(slot[v])               # a target with no consumer: dead after ACC
-        for u in dies.pop(k, ()):
-            alloc.put(slot[u])
-    n_vrr = len(words) // 8
-    vrr_top = alloc.next
 
+    # ---- abstract ops of the per-primitive part: VRR nodes in schedule
+    # order, each target followed by its accumulation
+    aops = []
+    for v in order:
+        nd = g.nodes[v]
+        if nd.kind != "base":
+            aops.append({"kind": "vrr", "out": ("n", v), "ins": [("n", x) for x in nd.parents if x is not None],
+                         "node": v})
+        if v in tpos:
+            aops.append({"kind": "acc", "out": None, "ins": [("n", v)], "acc": acc0 + tpos[v]})
     # ---- Phase 2: HRR + stepwise transforms over the accumulators
     hname = {t: f"h{k}" for k, t in enumerate(g.targets)}
     p2 = p2mod.Phase2(la, lb, lc, ld, hname=lambda e, f: hname[(e, f)])
-    name_slot = {f"h{k}": acc0 + k for k in range(n_hrr)}
-    outputs = set(p2.out.values())
-    p2pos = {}
-    for k, o in enumerate(p2.ops):
-        srcs = (o[2], o[3]) if o[1] == "hrr" else tuple(s for _, s in o[2])
-        for s in srcs:
-            p2pos[s] = k                         # last use
+    pops = []
+    for o in p2.ops:
+        if o[1] == "hrr":
+            pops.append({"kind": "hrr", "out": ("p", o[0]), "ins": [("p", o[2]), ("p", o[3])], "op": o})
+        else:
+            terms = list(o[2])
+            prev = None
+            for j in range(0, len(terms), 3):
+                chunk = terms[j:j + 3]
+                d = {"kind": "lin" if j == 0 else "linacc", "out": ("p", o[0]) if j == 0 else None,
+                     "writes": ("p", o[0]), "ins": [("p", x) for _, x in chunk], "terms": chunk,
+                     "dst": ("p", o[0]), "after": prev}
+                pops.append(d)
+                prev = len(pops) - 1
+    vgroups = _bundle(aops, bundle)
+    pgroups = _bundle(pops, bundle)
+
+    words = []
+    n_real = 0
+
+    def emit(w):
+        words.extend(w)
+
+    def pad(group_len):
+        for _ in range(bundle - group_len):
+            emit((0, 0, NONE, NONE, NONE, NONE, NONE, NONE))
+
+    # ---- slots, VRR part: base values in 0..L, accumulators fixed, node values
+    # allocated at their group and released after the group of their last reader
+    slot = {("n", v): g.nodes[v].key[2] for v in range(len(g.nodes)) if g.nodes[v].kind == "base"}
+    last = {}
+    for gi, grp in enumerate(vgroups):
+        for k in grp:
+            for x in aops[k]["ins"]:
+                last[x] = gi
+    alloc = _Slots(acc0 + n_hrr)
+    for gi, grp in enumerate(vgroups):
+        for k in grp:
+            o = aops[k]
+            if o["kind"] == "vrr":
+                nd = g.nodes[o["node"]]
+                s = alloc.get()
+                slot[o["out"]] = s
+                p = [slot[("n", x)] if x is not None else NONE for x in nd.parents]
+                code = OP_VRR_BRA if nd.kind == "bra" else OP_VRR_KET
+                emit((code | (nd.axis << 4) | (nd.k_same << 6) | (nd.k_cross << 11), s, *p, NONE))
+            else:
+                emit((OP_ACC, o["acc"], slot[o["ins"][0]], NONE, NONE, NONE, NONE, NONE))
+            n_real += 1
+        pad(len(grp))
+        for k in grp:
+            o = aops[k]
+            if o["kind"] == "vrr" and last.get(o["out"], -1) <= gi and g.nodes[o["node"]].kind != "base":
+                alloc.put(slot[o["out"]])        # never read again (a target, accumulated in this group)
+        for x in {x for k in grp for x in aops[k]["ins"]}:
+            if last.get(x) == gi and x in slot and slot[x] > L:
+                alloc.put(slot[x])
+    n_vrr = len(words) // 8
+    vrr_top = alloc.next
+
+    # ---- slots, Phase 2: inputs are the accumulators; VRR temporaries are free
+    name_slot = {("p", f"h{k}"): acc0 + k for k in range(n_hrr)}
+    outputs = {("p", v) for v in p2.out.values()}
+    last = {}
+    for gi, grp in enumerate(pgroups):
+        for k in grp:
+            for x in pops[k]["ins"]:
+                last[x] = gi
     alloc2 = _Slots(vrr_top)
-    alloc2.free = sorted(range(acc0 + n_hrr, vrr_top), reverse=True)   # VRR temporaries are dead now
+    alloc2.free = sorted(range(acc0 + n_hrr, vrr_top), reverse=True)
     coefs, cidx = [], {}
 
     def coef(c):
@@ -140,34 +229,37 @@ def build_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None) -> T3Tables:
             coefs.append(c)
         return cidx[c]
 
-    for k, o in enumerate(p2.ops):
-        d = o[0]
-        s = alloc2.get()
-        name_slot[d] = s
-        if o[1] == "hrr":
-            _, _, hi, lo, cname = o
-            axis = XYZ_AXIS[cname[-1]]
-            code = OP_HRR_BRA if cname.startswith("AB") else OP_HRR_KET
-            op(code | (axis << 4), s, name_slot[hi], name_slot[lo])
-        else:
-            terms = list(o[2])
-            for j in range(0, len(terms), 3):
-                chunk = terms[j:j + 3]
-                srcs = [name_slot[x] for _, x in chunk] + [NONE] * (3 - len(chunk))
-                cs = [coef(c) for c, _ in chunk] + [0] * (3 - len(chunk))
-                op(OP_LIN if j == 0 else OP_LIN_ACC, s, *srcs, *cs)
-        srcs = (o[2], o[3]) if o[1] == "hrr" else tuple(x for _, x in o[2])
-        for x in set(srcs):
-            if p2pos.get(x) == k and x not in outputs:
+    for gi, grp in enumerate(pgroups):
+        for k in grp:
+            o = pops[k]
+            if o["kind"] == "hrr":
+                _, _, hi, lo, cname = o["op"]
+                s = alloc2.get()
+                name_slot[o["out"]] = s
+                axis = XYZ_AXIS[cname[-1]]
+                code = OP_HRR_BRA if cname.startswith("AB") else OP_HRR_KET
+                emit((code | (axis << 4), s, name_slot[("p", hi)], name_slot[("p", lo)], NONE, NONE, NONE, NONE))
+            else:
+                if o["kind"] == "lin":
+                    name_slot[o["out"]] = alloc2.get()
+                s = name_slot[o["dst"]]
+                srcs = [name_slot[("p", x)] for _, x in o["terms"]] + [NONE] * (3 - len(o["terms"]))
+                cs = [coef(c) for c, _ in o["terms"]] + [0] * (3 - len(o["terms"]))
+                emit((OP_LIN if o["kind"] == "lin" else OP_LIN_ACC, s, *srcs, *cs))
+            n_real += 1
+        pad(len(grp))
+        for x in {x for k in grp for x in pops[k]["ins"]}:
+            if last.get(x) == gi and x not in outputs:
                 alloc2.put(name_slot[x])
     n_p2 = len(words) // 8 - n_vrr
     nslots = max(alloc2.next, vrr_top)
     if nslots > 0xFFFE or len(coefs) > 0xFFFF:
         raise ValueError(f"class {tag_of(ls)}: {nslots} slots do not fit 16-bit slot indices")
     na, nb, nc, nd = (nsph(x) for x in ls)
-    outslots = [name_slot[p2.out[(mu, nu, lam, sig)]] for mu in range(na) for nu in range(nb)
+    outslots = [name_slot[("p", p2.out[(mu, nu, lam, sig)])] for mu in range(na) for nu in range(nb)
                 for lam in range(nc) for sig in range(nd)]
-    return T3Tables(words, n_vrr, n_p2, coefs, outslots, nslots, n_hrr, acc0, L, pl, sched, g.flops(), p2.flops)
+    return T3Tables(words, n_vrr, n_p2, coefs, outslots, nslots, n_hrr, acc0, L, pl, sched, g.flops(), p2.flops,
+                    n_real)
 
 
 def _u16_lines(vals, per=24):

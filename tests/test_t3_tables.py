@@ -46,29 +46,41 @@ def run_tables(t, ls, centers, exps):
     ops = np.array(t.ops, dtype=np.int64).reshape(-1, 8)
     coefs = np.array(t.coefs)
     none = emit_t3.NONE
-    for k, w in enumerate(ops):
-        code, axis = w[0] & 15, (w[0] >> 4) & 3
-        dst = w[1]
-        if code == emit_t3.OP_ACC:
-            sb[dst] += sb[w[2]]
-        elif code in (emit_t3.OP_VRR_BRA, emit_t3.OP_VRR_KET):
-            ks, kc = (w[0] >> 6) & 31, (w[0] >> 11) & 31
-            X, Y, o2, r = (PA, WP, o2z, rz) if code == emit_t3.OP_VRR_BRA else (QC, WQ, o2e, re)
-            v = X[axis] * sb[w[2]] + Y[axis] * sb[w[3]]
-            if ks:
-                v = v + ks * o2 * (sb[w[4]] - r * sb[w[5]])
-            if kc:
-                v = v + kc * o2ze * sb[w[6]]
-            sb[dst] = v
-        elif code in (emit_t3.OP_HRR_BRA, emit_t3.OP_HRR_KET):
-            dv = AB if code == emit_t3.OP_HRR_BRA else CD
-            sb[dst] = sb[w[2]] + dv[axis] * sb[w[3]]
-        else:
-            v = sb[dst].copy() if code == emit_t3.OP_LIN_ACC else np.zeros(n)
-            for s, ci in zip(w[2:5], w[5:8]):
-                if s != none:
-                    v = v + coefs[ci] * sb[s]
-            sb[dst] = v
+    K = emit_t3.BUNDLE
+    assert len(ops) % K == 0 and t.n_vrr % K == 0
+
+    def val(s):
+        return sb[s] if s != none else sb[0] * 0.0
+
+    # a group reads all its operands before it writes anything, as on the GPU
+    for g0 in range(0, len(ops), K):
+        grp = [w for w in ops[g0:g0 + K] if w[0] != 0]
+        codes = {w[0] & 15 for w in grp}
+        assert len({0 if c in (1, 2) else c if c < 6 else 6 for c in codes} - {4, 5} | ({4} if codes & {4, 5} else set())) == 1
+        reads = [[val(s) for s in w[2:7]] + [sb[w[1]].copy()] for w in grp]
+        for w, r in zip(grp, reads):
+            code, axis = w[0] & 15, (w[0] >> 4) & 3
+            dst = w[1]
+            if code == emit_t3.OP_ACC:
+                sb[dst] = r[5] + r[0]
+            elif code in (emit_t3.OP_VRR_BRA, emit_t3.OP_VRR_KET):
+                ks, kc = (w[0] >> 6) & 31, (w[0] >> 11) & 31
+                X, Y, o2, rr = (PA, WP, o2z, rz) if code == emit_t3.OP_VRR_BRA else (QC, WQ, o2e, re)
+                v = X[axis] * r[0] + Y[axis] * r[1]
+                if ks:
+                    v = v + ks * o2 * (r[2] - rr * r[3])
+                if kc:
+                    v = v + kc * o2ze * r[4]
+                sb[dst] = v
+            elif code in (emit_t3.OP_HRR_BRA, emit_t3.OP_HRR_KET):
+                dv = AB if code == emit_t3.OP_HRR_BRA else CD
+                sb[dst] = r[0] + dv[axis] * r[1]
+            else:
+                v = r[5] if code == emit_t3.OP_LIN_ACC else np.zeros(n)
+                for s, x, ci in zip(w[2:5], r[0:3], w[5:8]):
+                    if s != none:
+                        v = v + coefs[ci] * x
+                sb[dst] = v
     out = sb[np.array(t.outslots)].T
     return out.reshape([n] + [2 * l + 1 for l in ls])
 
@@ -96,4 +108,7 @@ def test_t3_slot_packing():
     from paper_2605_10312_amd.gen import vrr
     g = vrr.VRRGraph(3, 3, 3, 3)
     assert t.nslots < t.acc0 + t.n_hrr + len(g.nodes) // 4
-    assert t.n_vrr == sum(1 for nd in g.nodes if nd.kind != "base") + t.n_hrr
+    K = emit_t3.BUNDLE
+    assert t.n_vrr % K == 0 and t.n_p2 % K == 0
+    assert t.n_vrr >= sum(1 for nd in g.nodes if nd.kind != "base") + t.n_hrr
+    assert t.n_real_ops >= 0.9 * (t.n_vrr + t.n_p2)       # groups stay nearly full
