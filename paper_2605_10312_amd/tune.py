@@ -31,18 +31,19 @@ TABLE = os.path.join(HERE, "tuning", "gfx950.json")
 
 # generator options per variant; keys the tier does not use are ignored
 VARIANTS = {
-    "plain": {"digest": "interleaved", "reduce": "none"},
-    "uniform": {"digest": "loads_first", "reduce": "uniform"},
     "seg": {"digest": "loads_first", "reduce": "segmented"},
     "seg_il": {"digest": "interleaved", "reduce": "segmented"},
     "seg_pf": {"digest": "loads_first", "reduce": "segmented", "loop": "prefetch"},
     "seg_w2": {"digest": "loads_first", "reduce": "segmented", "waves": 2},
     "b64": {"digest": "loads_first", "reduce": "segmented", "block": 64},
-    "b128": {"digest": "loads_first", "reduce": "segmented", "block": 128},
+    "b64_il": {"digest": "interleaved", "reduce": "segmented", "block": 64},
+    "b64_pf": {"digest": "loads_first", "reduce": "segmented", "block": 64, "loop": "prefetch"},
     "b64_w2": {"digest": "loads_first", "reduce": "segmented", "block": 64, "waves": 2},
+    "b128": {"digest": "loads_first", "reduce": "segmented", "block": 128},
     "cap64": {"digest": "loads_first", "reduce": "segmented", "cap": 64},
     "cap48": {"digest": "loads_first", "reduce": "segmented", "cap": 48},
     "staged": {"digest": "loads_first", "reduce": "segmented", "tier": 1},
+    "plain": {"digest": "interleaved", "reduce": "none"},
 }
 
 
