@@ -55,6 +55,32 @@ def algorithmic_flops(c):
     return sum(phase_flops(c))
 
 
+TRAFFIC_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "jk_mol30_3s2p1d_hbm_traffic.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy kernel), or
+    None when the summary has no row for it or the kernel's sources changed
+    since the counters were taken."""
+    from paper_2605_10312_amd import build as hb
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    tag = kernel.split("_", 1)[1]
+    for line in open(TRAFFIC_SUMMARY):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 5 and cells[0] == kernel:
+            try:
+                fetch, write = float(cells[2]), float(cells[3])
+            except ValueError:
+                return None
+            if cells[4] != hb.class_source_hash(tag):
+                return None
+            return int(round((fetch + write) * 2 ** 20))
+    return None
+
+
 def cpu_baseline(bw, target_s, seed=7):
     """Oracle ERIs/s on random screened unique quartets of the same workload."""
     import oracle
@@ -220,7 +246,8 @@ def main():
     dom = per_kernel[0]
     achieved = dom["tflops"]
     roofline = {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(dom["kernel"]),
                 "avg_launch_ms": dom["avg_ms"], "gflop_per_launch": dom["gflop_per_launch"]}
     total_kernel_ms = sum(x["ms_per_step"] for x in per_kernel)
     total_flops = sum(algorithmic_flops(c) for c in classes)

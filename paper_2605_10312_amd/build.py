@@ -91,6 +91,19 @@ def _write_if_changed(path, text):
     os.replace(path + ".tmp", path)
 
 
+def class_source_hash(tag: str, gen_dir: str = GEN) -> str | None:
+    """Hash of everything a generated class kernel is compiled from (its
+    source and the device headers): measurements tied to a kernel, such as
+    hardware byte counters, stay valid only while this is unchanged."""
+    src = os.path.join(gen_dir, f"class_{tag}.hip")
+    if not os.path.exists(src):
+        return None
+    h = hashlib.sha256()
+    for d in [src] + [os.path.join(CSRC, x) for x in ("hgp_device.h", "hgp_types.h", "hgp_t3.h")]:
+        h.update(open(d, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str, force: bool):
     if not src.startswith(CSRC + os.sep):  # generated class files see only these headers
         deps = [src] + [os.path.join(CSRC, h) for h in ("hgp_device.h", "hgp_types.h", "hgp_t3.h")]
