@@ -172,6 +172,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="mixed: quartets with Q_ab Q_cd < theta use FP32 VRR/HRR (register tier)")
+    ap.add_argument("--theta", type=float, default=None, help="mixed-precision threshold (default: the library's)")
     ap.add_argument("--workload", choices=("mol30", "microbench"), default="mol30",
                     help="mol30: the J/K build (one JSON line); microbench: the high-l primitive-quartet classes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -201,7 +204,10 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     basis = hgp.Basis.from_workload(bw)
-    plan = hgp.Plan(basis, tau=TAU)
+    theta = 0.0
+    if args.precision == "mixed":
+        theta = hgp.MIXED_THETA_DEFAULT if args.theta is None else args.theta
+    plan = hgp.Plan(basis, tau=TAU, theta=theta)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     classes = plan.classes()
@@ -231,7 +237,9 @@ def main():
         tag = "".join(str(x) for x in c["ls"])
         f1, f2 = phase_flops(c)
         if t["tier"] == 0:
-            parts = [(f"jk_{tag}", f1 + f2, t["kernels"][0])]
+            parts = [(f"jk{'32' if c['bits'] == 32 else ''}_{tag}", f1 + f2, t["kernels"][0])]
+        elif t["tier"] == 2:
+            parts = [(f"t3_jk_{tag}", f1 + f2, t["kernels"][0])]
         else:
             parts = [(f"p1_{tag}", f1, t["kernels"][0]), (f"jk_{tag}", f2, t["kernels"][1])]
         for name, fl, (n, ms) in parts:
@@ -251,6 +259,19 @@ def main():
                 "avg_launch_ms": dom["avg_ms"], "gflop_per_launch": dom["gflop_per_launch"]}
     total_kernel_ms = sum(x["ms_per_step"] for x in per_kernel)
     total_flops = sum(algorithmic_flops(c) for c in classes)
+
+    err_fp64 = None
+    if args.precision == "mixed":
+        # the same build in plain FP64, untimed: the mixed result's deviation from it
+        p64 = hgp.Plan(basis, tau=TAU)
+        J64 = torch.empty_like(Dt)
+        K64 = torch.empty_like(Dt)
+        p64.jk(Dt, J64, K64)
+        torch.cuda.synchronize()
+        err_fp64 = {"J_max_abs": float((J - J64).abs().max()), "K_max_abs": float((K - K64).abs().max()),
+                    "fp32_quartet_share": round(sum(c["quartets"] for c in classes if c["bits"] == 32) /
+                                                max(1, sum(c["quartets"] for c in classes)), 4), "theta": theta}
+        p64.close()
 
     err = None
     if not args.no_check:
@@ -277,10 +298,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32/f64 mixed",
         "data": "synthetic",
         "config": {"workload": "mol30_3s2p1d: 30-atom synthetic molecule, 3s2p1d per atom (1-6 primitives), "
-                               "N=420, Schwarz tau=1e-12, J+K in FP64",
+                               "N=420, Schwarz tau=1e-12, J+K " +
+                               ("in FP64" if args.precision == "fp64" else
+                                f"mixed (FP32 VRR/HRR below Schwarz bound {theta:g}, FP64 Boys and J/K)"),
                    "nbf": int(bw.nbf), "shells": int(bw.nshell), "tau": TAU,
                    "quartets_kept": stats["quartets_kept"], "quartets_total": stats["quartets_total"],
                    "prim_pairs_kept": stats["prim_pairs_kept"], "prim_pairs_total": stats["prim_pairs_total"],
@@ -292,6 +315,7 @@ def main():
         "step_tflops": round(total_flops / (ms_per_step * 1e-3) / 1e12, 3),
         "kernel_ms_sum": round(total_kernel_ms, 4),
         "err": err,
+        "err_vs_fp64": err_fp64,
         "kernels": per_kernel,
     }
     print(json.dumps(line), flush=True)

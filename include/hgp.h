@@ -66,6 +66,8 @@ typedef struct hgp_basis hgp_basis;  /* validated shells, normalised coefficient
 typedef struct hgp_plan hgp_plan;    /* pair data, Schwarz factors and screened class quartet lists */
 
 #define HGP_FP64 0
+#define HGP_MIXED 1               /* FP32 VRR/HRR for quartets with a small Schwarz bound (see hgp_plan_create_mixed) */
+#define HGP_MIXED_THETA_DEFAULT 1e-8
 
 /* Library version and the highest l built into this library's class kernels. */
 int32_t hgp_version(void);
@@ -100,22 +102,40 @@ hgp_status hgp_basis_destroy(hgp_basis *b);
  * a shell pair, pair r is left out when q_r Qmax < 0.1 schwarz_tau / P^2, so
  * the part dropped from any one integral is below 0.1 schwarz_tau.  With
  * schwarz_tau = 0 nothing is dropped and every integral is the exact sum.
- *   precision         HGP_FP64
+ *   precision         HGP_FP64, or HGP_MIXED (= hgp_plan_create_mixed with
+ *                     theta = HGP_MIXED_THETA_DEFAULT)
  *   hbm_budget_bytes  0 = unlimited; otherwise HGP_E_OOM if the plan needs more
  */
 hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t precision, size_t hbm_budget_bytes,
                            void *hip_stream, hgp_plan **out);
+/*
+ * hgp_plan_create_mixed -- a plan whose register-tier classes evaluate the
+ * quartets with schwarz_tau <= Q_ab Q_cd < theta with the VRR and the
+ * contraction over primitives in FP32.  The pair quantities, the Boys
+ * function, the horizontal recurrence and transforms (which cancel between
+ * large intermediates) and the J/K digestion stay FP64.  Larger-bound
+ * quartets and the staged and HBM-scratch classes run wholly in FP64.
+ * theta <= schwarz_tau gives an FP64 plan.  The deviation from the FP64
+ * result grows roughly in proportion to theta; the default threshold is
+ * the largest that keeps it below 1e-9 on the benchmark workload.  Other
+ * arguments as hgp_plan_create.
+ */
+hgp_status hgp_plan_create_mixed(const hgp_basis *b, double schwarz_tau, double theta, size_t hbm_budget_bytes,
+                                 void *hip_stream, hgp_plan **out);
 hgp_status hgp_plan_destroy(hgp_plan *p);
 /* Plan statistics: unique quartets kept after screening, candidate quartets, device bytes held. */
 hgp_status hgp_plan_stats(const hgp_plan *p, int64_t *quartets_kept, int64_t *quartets_total, int64_t *device_bytes);
 /* Primitive pairs held by the plan's shell pairs after and before primitive-pair screening. */
 hgp_status hgp_plan_prim_stats(const hgp_plan *p, int64_t *prim_pairs_kept, int64_t *prim_pairs_total);
-/* Per class c (0 .. n-1, n = hgp_plan_num_classes, in launch order): angular momenta ls[4], quartets
- * kept, primitive quartets they hold, the generator's FLOP counts per primitive quartet (VRR +
- * accumulate, unchunked) and per contracted quartet (Phase 2), and the tier (0 register, 1 staged). */
+/* Per class list c (0 .. n-1, n = hgp_plan_num_classes, in launch order; a mixed plan can hold two
+ * lists of one class): angular momenta ls[4], quartets kept, primitive quartets they hold, the
+ * generator's FLOP counts per primitive quartet (VRR + accumulate, unchunked) and per contracted
+ * quartet (Phase 2), and the tier (0 register, 1 staged, 2 HBM scratch). */
 int32_t hgp_plan_num_classes(const hgp_plan *p);
 hgp_status hgp_plan_class_info(const hgp_plan *p, int32_t c, int32_t *ls, int64_t *nquartets, int64_t *nprim_quartets,
                                double *vrr_flops, double *phase2_flops, int32_t *tier);
+/* Arithmetic width of class list c's VRR/HRR: 64, or 32 for the FP32 part of a mixed plan. */
+hgp_status hgp_plan_class_precision(const hgp_plan *p, int32_t c, int32_t *bits);
 
 /* The plan's Schwarz factors by shell: Q[i*nshell + j] = Q[j*nshell + i] =
  * sqrt(max |(mn|mn)|) over m in shell i, n in shell j (host array, nshell^2),

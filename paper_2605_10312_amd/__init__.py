@@ -19,6 +19,8 @@ LIB_PATH = os.environ.get("HGP_LIB") or os.path.join(_HERE, "libhgp.so")
 STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_UNSUPPORTED_L", -3: "HGP_E_OOM", -4: "HGP_E_DEVICE",
           -5: "HGP_E_STATE"}
 HGP_FP64 = 0
+HGP_MIXED = 1
+MIXED_THETA_DEFAULT = 1e-8      # HGP_MIXED_THETA_DEFAULT in include/hgp.h
 
 # exported symbol -> (restype, argtypes)
 _vp, _i32, _i64, _d, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -29,6 +31,8 @@ SIGNATURES = {
     "hgp_basis_nbf": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), _vp]),
     "hgp_basis_destroy": (ctypes.c_int, [_vp]),
     "hgp_plan_create": (ctypes.c_int, [_vp, _d, _i32, _sz, _vp, ctypes.POINTER(_vp)]),
+    "hgp_plan_create_mixed": (ctypes.c_int, [_vp, _d, _d, _sz, _vp, ctypes.POINTER(_vp)]),
+    "hgp_plan_class_precision": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32)]),
     "hgp_plan_destroy": (ctypes.c_int, [_vp]),
     "hgp_plan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "hgp_plan_prim_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
@@ -135,11 +139,13 @@ class Basis:
 class Plan:
     """hgp_plan: pairs, Schwarz factors and screened class quartet lists."""
 
-    def __init__(self, basis: Basis, tau: float = 1e-12, hbm_budget: int = 0, stream=None):
+    def __init__(self, basis: Basis, tau: float = 1e-12, hbm_budget: int = 0, stream=None, theta: float = 0.0):
+        """theta > tau: mixed precision, quartets with tau <= Q_ab Q_cd < theta
+        of register-tier classes use FP32 VRR/HRR (hgp_plan_create_mixed)."""
         self.basis = basis
         h = ctypes.c_void_p()
-        _check(lib().hgp_plan_create(basis.handle, float(tau), HGP_FP64, int(hbm_budget),
-                                     ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)))
+        _check(lib().hgp_plan_create_mixed(basis.handle, float(tau), float(theta), int(hbm_budget),
+                                           ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)))
         self.handle = h
 
     def stats(self):
@@ -158,8 +164,10 @@ class Plan:
             tier = ctypes.c_int32()
             _check(lib().hgp_plan_class_info(self.handle, c, ls.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nq),
                                              ctypes.byref(npq), ctypes.byref(vf), ctypes.byref(pf), ctypes.byref(tier)))
+            bits = ctypes.c_int32()
+            _check(lib().hgp_plan_class_precision(self.handle, c, ctypes.byref(bits)))
             out.append({"ls": tuple(int(x) for x in ls), "quartets": nq.value, "prim_quartets": npq.value,
-                        "vrr_flops": vf.value, "phase2_flops": pf.value, "tier": tier.value})
+                        "vrr_flops": vf.value, "phase2_flops": pf.value, "tier": tier.value, "bits": bits.value})
         return out
 
     def schwarz(self):

@@ -170,13 +170,16 @@ __device__ __forceinline__ int row_len(int row, int k0, int nk, int b0, int sym)
 }
 
 __global__ void screen_count_kernel(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau,
-                                    int64_t *counts)
+                                    double hi, int64_t *counts)
 {
     const int row = b0 + blockIdx.x;
     const int len = row_len(row, k0, nk, b0, sym);
     const double qb = Q[row];
     int c = 0;
-    for (int j = threadIdx.x; j < len; j += blockDim.x) c += (qb * Q[k0 + j] >= tau) ? 1 : 0;
+    for (int j = threadIdx.x; j < len; j += blockDim.x) {
+        const double qq = qb * Q[k0 + j];
+        c += (qq >= tau && qq < hi) ? 1 : 0;
+    }
     __shared__ int part[1024 / 64];
     // wave reduction
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
@@ -216,7 +219,7 @@ __global__ void scan_kernel(int64_t *v, int n, int64_t *total)
 }
 
 __global__ void screen_write_kernel(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau,
-                                    const int64_t *offsets, int2 *out)
+                                    double hi, const int64_t *offsets, int2 *out)
 {
     const int row = b0 + blockIdx.x;
     const int len = row_len(row, k0, nk, b0, sym);
@@ -228,7 +231,8 @@ __global__ void screen_write_kernel(int b0, int nb, int k0, int nk, int sym, con
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int j0 = 0; j0 < len; j0 += blockDim.x) {
         const int j = j0 + threadIdx.x;
-        const bool keep = (j < len) && (qb * Q[k0 + j] >= tau);
+        const double qq = j < len ? qb * Q[k0 + j] : 0.0;
+        const bool keep = (j < len) && qq >= tau && qq < hi;
         const unsigned long long m = __ballot(keep);
         const int before = __popcll(m & ((1ull << lane) - 1ull));
         if (lane == 0) wcount[wv] = __popcll(m);
@@ -299,20 +303,22 @@ void launch_prim_quartet_pairs(int64_t n, const double *centers, const double *e
                            make_int4(strides[0], strides[1], strides[2], strides[3]), block, pairs, geo, prims,
                            tasks);
 }
-void launch_screen_count(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau, int64_t *counts,
-                         hipStream_t s)
+void launch_screen_count(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau, double hi,
+                         int64_t *counts, hipStream_t s)
 {
-    if (nb > 0) hipLaunchKernelGGL(screen_count_kernel, dim3(nb), dim3(256), 0, s, b0, nb, k0, nk, sym, Q, tau, counts);
+    if (nb > 0)
+        hipLaunchKernelGGL(screen_count_kernel, dim3(nb), dim3(256), 0, s, b0, nb, k0, nk, sym, Q, tau, hi, counts);
 }
 void launch_scan(int64_t *v, int n, int64_t *total, hipStream_t s)
 {
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, v, n, total);
 }
-void launch_screen_write(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau, const int64_t *offsets,
-                         int2 *out, hipStream_t s)
+void launch_screen_write(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau, double hi,
+                         const int64_t *offsets, int2 *out, hipStream_t s)
 {
     if (nb > 0)
-        hipLaunchKernelGGL(screen_write_kernel, dim3(nb), dim3(256), 0, s, b0, nb, k0, nk, sym, Q, tau, offsets, out);
+        hipLaunchKernelGGL(screen_write_kernel, dim3(nb), dim3(256), 0, s, b0, nb, k0, nk, sym, Q, tau, hi, offsets,
+                           out);
 }
 void launch_store_q(int npair, const double *qv, PairGeo *geo, double *Q, hipStream_t s)
 {

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <limits>
 #include <vector>
 
 #include "hgp.h"
@@ -168,6 +169,7 @@ struct hgp_basis {
 
 struct ClassList {
     int cls;          // index into g_class_table
+    int bits = 64;    // 64: FP64 kernel; 32: VRR/HRR in FP32 (mixed plans, Q_ab Q_cd below theta)
     int64_t nq = 0;   // unique quartets kept
     int64_t nprimq = 0;
     int2 *d_q = nullptr;
@@ -197,6 +199,7 @@ struct hgp_plan {
     std::vector<ClassList> lists;
     int64_t kept = 0, total = 0, bytes = 0;
     int64_t prim_total = 0, prim_kept = 0;   // primitive pairs before / after primitive screening
+    double theta = 0.0;                      // mixed plans: quartets with Q_ab Q_cd < theta use FP32 VRR/HRR
     bool timing = false;
     std::vector<PendingTiming> pending;
     std::vector<hipEvent_t> event_pool;
@@ -583,23 +586,33 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
             const int sym = (bc == kc);
             const int b0 = p->pc_begin[bc], k0 = p->pc_begin[kc];
             const double t = tau > 0 ? tau : -1.0;
-            launch_screen_count(b0, nb, k0, nk, sym, p->d_Q, t, d_counts, s);
-            // primitive quartets per row for the FLOP accounting
-            std::vector<int64_t> cnt(nb);
-            HGP_HIP(hipMemcpyAsync(cnt.data(), d_counts, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s));
+            // bands of Q_ab Q_cd: [t, theta) in FP32 where the class has an FP32
+            // kernel and the plan is mixed, the rest in FP64
+            struct Band { double lo, hi; int bits; };
+            std::vector<Band> bands;
+            const double inf = std::numeric_limits<double>::infinity();
+            if (p->theta > t && g_class_table[ci].jk32) {
+                bands.push_back({t, p->theta, 32});
+                bands.push_back({p->theta, inf, 64});
+            } else {
+                bands.push_back({t, inf, 64});
+            }
+            for (const Band &bd : bands) {
+            launch_screen_count(b0, nb, k0, nk, sym, p->d_Q, bd.lo, bd.hi, d_counts, s);
             launch_scan(d_counts, nb, d_total, s);
             int64_t total = 0;
             HGP_HIP(hipMemcpyAsync(&total, d_total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
             HGP_HIP(hipStreamSynchronize(s));
             ClassList cl;
             cl.cls = ci;
+            cl.bits = bd.bits;
             cl.nq = total;
             if (budget && (size_t)(p->bytes + total * (int64_t)sizeof(int2)) > budget) {
                 hipFree(d_counts); hipFree(d_total);
                 return fail(HGP_E_OOM, "plan exceeds the HBM budget (quartet lists)");
             }
             if ((st = dalloc(&cl.d_q, (size_t)total, &p->bytes))) { hipFree(d_counts); hipFree(d_total); return st; }
-            if (total > 0) launch_screen_write(b0, nb, k0, nk, sym, p->d_Q, t, d_counts, cl.d_q, s);
+            if (total > 0) launch_screen_write(b0, nb, k0, nk, sym, p->d_Q, bd.lo, bd.hi, d_counts, cl.d_q, s);
             HGP_HIP(hipGetLastError());
             // primitive-quartet count: sum over kept quartets of nprim(bra) * nprim(ket)
             if (total > 0) {
@@ -612,6 +625,7 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
             }
             p->kept += total;
             p->lists.push_back(cl);
+            }
         }
     }
     hipFree(d_counts);
@@ -633,18 +647,19 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
     return HGP_OK;
 }
 
-hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t precision, size_t hbm_budget_bytes,
-                           void *hip_stream, hgp_plan **out)
+hgp_status hgp_plan_create_mixed(const hgp_basis *b, double schwarz_tau, double theta, size_t hbm_budget_bytes,
+                                 void *hip_stream, hgp_plan **out)
 {
     if (!out) return fail(HGP_E_INVALID, "out is NULL");
     *out = nullptr;
     if (!b) return fail(HGP_E_INVALID, "basis is NULL");
     if (!(schwarz_tau >= 0.0) || !std::isfinite(schwarz_tau)) return fail(HGP_E_INVALID, "schwarz_tau must be >= 0");
-    if (precision != HGP_FP64) return fail(HGP_E_INVALID, "only HGP_FP64 is supported");
+    if (!(theta >= 0.0) || !std::isfinite(theta)) return fail(HGP_E_INVALID, "theta must be >= 0 and finite");
     if (b->lmax > built_max_l()) return fail(HGP_E_UNSUPPORTED_L, "basis has l above the classes built into this library");
     auto *p = new hgp_plan();
     p->b = b;
     p->device = b->device;
+    p->theta = theta > schwarz_tau ? theta : 0.0;
     hgp_status st = plan_build(p, schwarz_tau, hbm_budget_bytes, (hipStream_t)hip_stream);
     if (st != HGP_OK) {
         hgp_plan_destroy(p);
@@ -652,6 +667,15 @@ hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t preci
     }
     *out = p;
     return HGP_OK;
+}
+
+hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t precision, size_t hbm_budget_bytes,
+                           void *hip_stream, hgp_plan **out)
+{
+    if (out) *out = nullptr;
+    if (precision != HGP_FP64 && precision != HGP_MIXED) return fail(HGP_E_INVALID, "precision must be HGP_FP64 or HGP_MIXED");
+    return hgp_plan_create_mixed(b, schwarz_tau, precision == HGP_MIXED ? HGP_MIXED_THETA_DEFAULT : 0.0,
+                                 hbm_budget_bytes, hip_stream, out);
 }
 
 hgp_status hgp_plan_stats(const hgp_plan *p, int64_t *kept, int64_t *total, int64_t *bytes)
@@ -672,6 +696,13 @@ hgp_status hgp_plan_prim_stats(const hgp_plan *p, int64_t *prim_pairs_kept, int6
 }
 
 int32_t hgp_plan_num_classes(const hgp_plan *p) { return p ? (int32_t)p->lists.size() : 0; }
+
+hgp_status hgp_plan_class_precision(const hgp_plan *p, int32_t c, int32_t *bits)
+{
+    if (!p || c < 0 || c >= (int32_t)p->lists.size() || !bits) return fail(HGP_E_INVALID, "bad plan or class index");
+    *bits = p->lists[c].bits;
+    return HGP_OK;
+}
 
 hgp_status hgp_plan_class_info(const hgp_plan *p, int32_t c, int32_t *ls, int64_t *nq, int64_t *npq, double *vf,
                                double *pf, int32_t *tier)
@@ -764,10 +795,11 @@ hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_
         if (k.tier == 0) {
             if ((st = mark(&e0))) return st;
             const int64_t chunk = (int64_t)k.block << 20;
+            const launch_jk_fn run = cl.bits == 32 ? k.jk32 : k.jk;
             for (int64_t q0 = 0; q0 < cl.nq; q0 += chunk) {
                 a.quartets = cl.d_q + q0;
                 a.nq = std::min(chunk, cl.nq - q0);
-                k.jk(a, s);
+                run(a, s);
             }
             if ((st = mark(&e1))) return st;
             done((int)li, 0, e0, e1);

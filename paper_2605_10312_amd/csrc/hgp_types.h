@@ -121,6 +121,7 @@ struct ClassKernels {
     launch_eri_fn eri;
     launch_p1_fn p1;        // staged tier only (nullptr otherwise)
     prepare_fn prepare;     // HBM-scratch tier: uploads the class tables to the current device (0 on success)
+    launch_jk_fn jk32;      // register tier: VRR/HRR in FP32, digestion in FP64 (mixed plans), or nullptr
     int block;              // threads per block
     double vrr_flops;       // per primitive quartet (generator count)
     double p2_flops;        // per contracted quartet: HRR + transform

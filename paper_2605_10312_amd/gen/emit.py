@@ -45,6 +45,7 @@ class ClassMeta:
     digest: str = "loads_first"
     reduce: str = "segmented"
     loop: str = "late"
+    mixed: bool = False
 
 
 def tag_of(ls):
@@ -56,16 +57,19 @@ def _fmt(c: float) -> str:
     return r if ("." in r or "e" in r) else r + ".0"
 
 
-def _vrr_lines(g, order, hnames, indent):
-    """Straight-line VRR in `order`; targets are added to their accumulators."""
+def _vrr_lines(g, order, hnames, indent, f32=False):
+    """Straight-line VRR in `order`; targets are added to their accumulators.
+    f32: single precision (coefficients carry an 'f' suffix, base values come
+    from Bf[m], set from the FP64 prefactor and Boys values)."""
     lines = []
     tpos = {tid: k for k, tid in enumerate(g.target_ids)}
     used = set()
+    ty, fma_, sfx, one = ("float", "fmaf", "f", "f") if f32 else ("double", "fma", "", "")
     for v in order:
         nd = g.nodes[v]
         name = f"v{v}"
         if nd.kind == "base":
-            expr = f"base * F[{nd.key[2]}]"
+            expr = f"Bf[{nd.key[2]}]" if f32 else f"base * F[{nd.key[2]}]"
         else:
             p1, p2, p3, p4, p5 = nd.parents
             ax = XYZ[nd.axis]
@@ -74,33 +78,35 @@ def _vrr_lines(g, order, hnames, indent):
             else:
                 c1, c2, o2, rr = f"QC{ax}", f"WQ{ax}", "o2e", "re"
             used.update([c1, c2])
-            expr = f"fma({c1}, v{p1}, {c2} * v{p2})"
+            expr = f"{fma_}({c1}{sfx}, v{p1}, {c2}{sfx} * v{p2})"
             if nd.k_same:
-                k = "" if nd.k_same == 1 else f"{nd.k_same}.0 * "
-                expr = f"fma({k}{o2}, fma(-{rr}, v{p4}, v{p3}), {expr})"
+                k = "" if nd.k_same == 1 else f"{nd.k_same}.0{one} * "
+                expr = f"{fma_}({k}{o2}{sfx}, {fma_}(-{rr}{sfx}, v{p4}, v{p3}), {expr})"
                 used.update([o2, rr])
             if nd.k_cross:
-                k = "" if nd.k_cross == 1 else f"{nd.k_cross}.0 * "
-                expr = f"fma({k}o2ze, v{p5}, {expr})"
+                k = "" if nd.k_cross == 1 else f"{nd.k_cross}.0{one} * "
+                expr = f"{fma_}({k}o2ze{sfx}, v{p5}, {expr})"
                 used.add("o2ze")
-        lines.append(f"{indent}const double {name} = {expr};")
+        lines.append(f"{indent}const {ty} {name} = {expr};")
         if v in tpos:
             lines.append(f"{indent}{hnames[tpos[v]]} += {name};")
     return lines, used
 
 
-def _p2_lines(p2, indent):
+def _p2_lines(p2, indent, f32=False):
     lines = []
+    ty, fma_ = ("float", "fmaf") if f32 else ("double", "fma")
+    fmt = (lambda c: _fmt(c) + "f") if f32 else _fmt
     for op in p2.ops:
         if op[1] == "hrr":
             d, _, hi, lo, coef = op
-            lines.append(f"{indent}const double {d} = fma({coef}, {lo}, {hi});")
+            lines.append(f"{indent}const {ty} {d} = {fma_}({coef}, {lo}, {hi});")
         else:
             d, _, terms = op
-            expr = f"{_fmt(terms[0][0])} * {terms[0][1]}"
+            expr = f"{fmt(terms[0][0])} * {terms[0][1]}"
             for c, s in terms[1:]:
-                expr = f"fma({_fmt(c)}, {s}, {expr})"
-            lines.append(f"{indent}const double {d} = {expr};")
+                expr = f"{fma_}({fmt(c)}, {s}, {expr})"
+            lines.append(f"{indent}const {ty} {d} = {expr};")
     return lines
 
 
@@ -315,8 +321,57 @@ def digest_lines(na, nb, nc, nd, I, J, K, digest="loads_first", reduce="segmente
     return out
 
 
+def _quartet_fn(name, L, g, order, hnames, p2, loop, f32, na, nb, nc, nd):
+    """The device function computing one contracted quartet's spherical
+    block into double I[]: primitive loop (pair combination and Boys always
+    in FP64), VRR + accumulation, Phase 2.  f32: the VRR and the contraction
+    sums run in single precision; the accumulators are widened to FP64
+    before Phase 2, whose horizontal recurrence can cancel heavily between
+    large intermediates and would amplify single-precision rounding."""
+    out = []
+    w = out.append
+    acc = [h + "f" for h in hnames] if f32 else hnames
+    ty = "float" if f32 else "double"
+    zero = "0.0f" if f32 else "0.0"
+    vlines, _ = _vrr_lines(g, order, acc, "        ", f32)
+    w(f"__device__ __forceinline__ void {name}(const PairInfo &pb, const PairGeo &gb, const PairInfo &pk,")
+    w(f"                                              const PairGeo &gk, const PrimPair *__restrict__ prims,")
+    w(f"                                              const double *__restrict__ boys, double *__restrict__ I)")
+    w("{")
+    for k in range(0, len(acc), 8):
+        w(f"    {ty} " + ", ".join(f"{h} = {zero}" for h in acc[k:k + 8]) + ";")
+    out.extend(loop_prelude(L, "    ", loop))
+    if f32:
+        i2 = "        "
+        w(f"{i2}float Bf[{L + 1}];")
+        w(f"{i2}for (int m = 0; m <= {L}; ++m) Bf[m] = (float)(base * F[m]);")
+        for nm in ("PA", "QC", "WP", "WQ"):
+            w(f"{i2}const float " + ", ".join(f"{nm}{a}f = (float){nm}{a}" for a in "xyz") + ";")
+        w(f"{i2}const float o2zf = (float)o2z, o2ef = (float)o2e, o2zef = (float)o2ze, rzf = (float)rz, ref = (float)re;")
+        w(f"{i2}(void)PAxf; (void)PAyf; (void)PAzf; (void)QCxf; (void)QCyf; (void)QCzf; (void)WPxf; (void)WPyf;")
+        w(f"{i2}(void)WPzf; (void)WQxf; (void)WQyf; (void)WQzf; (void)o2zf; (void)o2ef; (void)o2zef; (void)rzf; (void)ref;")
+    out.extend(vlines)
+    out.extend(loop_close("    "))
+    if f32:
+        for k in range(0, len(hnames), 8):
+            w("    const double " + ", ".join(f"{h} = (double){h}f" for h in hnames[k:k + 8]) + ";")
+    w("    const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz;")
+    w("    const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
+    w("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz;")
+    out.extend(_p2_lines(p2, "    "))
+    for mu in range(na):
+        for nu in range(nb):
+            for lam in range(nc):
+                for sig in range(nd):
+                    k = ((mu * nb + nu) * nc + lam) * nd + sig
+                    w(f"    I[{k}] = {p2.out[(mu, nu, lam, sig)]};")
+    w("}")
+    w("")
+    return out
+
+
 def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves=0, digest="loads_first",
-               reduce="segmented", loop="late"):
+               reduce="segmented", loop="late", mixed=True):
     ls = (la, lb, lc, ld)
     tag = tag_of(ls)
     L = sum(ls)
@@ -329,7 +384,6 @@ def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves
     nout = na * nb * nc * nd
     I = {k: v for k, v in p2.out.items()}
 
-    vlines, used = _vrr_lines(g, order, hnames, "        ")
     out = []
     w = out.append
     w(f"// Generated: class ({la}{lb}|{lc}{ld}), axis rule {rule}, VRR order '{sched}' (PeakLive {pl}),")
@@ -340,48 +394,36 @@ def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves
     w("namespace hgp {")
     w("namespace {")
     w("")
-    w(f"__device__ __forceinline__ void quartet_{tag}(const PairInfo &pb, const PairGeo &gb, const PairInfo &pk,")
-    w(f"                                              const PairGeo &gk, const PrimPair *__restrict__ prims,")
-    w(f"                                              const double *__restrict__ boys, double *__restrict__ I)")
-    w("{")
-    for k in range(0, len(hnames), 8):
-        w("    double " + ", ".join(f"{h} = 0.0" for h in hnames[k:k + 8]) + ";")
-    out.extend(loop_prelude(L, "    ", loop))
-    out.extend(vlines)
-    out.extend(loop_close("    "))
-    w("    const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz;")
-    w("    const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
-    w("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz;")
-    out.extend(_p2_lines(p2, "    "))
-    for mu in range(na):
-        for nu in range(nb):
-            for lam in range(nc):
-                for sig in range(nd):
-                    k = ((mu * nb + nu) * nc + lam) * nd + sig
-                    w(f"    I[{k}] = {I[(mu, nu, lam, sig)]};")
-    w("}")
-    w("")
+    out.extend(_quartet_fn(f"quartet_{tag}", L, g, order, hnames, p2, loop, False, na, nb, nc, nd))
+    if mixed:
+        out.extend(_quartet_fn(f"quartet32_{tag}", L, g, order, hnames, p2, loop, True, na, nb, nc, nd))
     # ---------------------------------------------------------------- J/K kernel
     def idx(mu, nu, lam, sig):
         return ((mu * nb + nu) * nc + lam) * nd + sig
 
-    w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void jk_{tag}(JKArgs a)")
-    w("{")
-    w(f"    const int64_t q = (int64_t)blockIdx.x * {block} + threadIdx.x;")
-    w("    if (q >= a.nq) return;")
-    w("    const int2 pq = a.quartets[q];")
-    w("    const PairInfo pb = a.pairs[pq.x], pk = a.pairs[pq.y];")
-    w("    const PairGeo gb = a.geo[pq.x], gk = a.geo[pq.y];")
-    w(f"    double I[{nout}];")
-    w(f"    quartet_{tag}(pb, gb, pk, gk, a.prims, a.boys, I);")
-    w("    const double *__restrict__ D = a.D;")
-    w("    const int N = a.nbf;")
-    w("    const int fa = pb.fa, fb = pb.fb, fc = pk.fa, fd = pk.fb;")
-    w("    const double s = (pb.same ? 0.5 : 1.0) * (pk.same ? 0.5 : 1.0) * (pq.x == pq.y ? 0.5 : 1.0);")
-    out.extend(digest_lines(na, nb, nc, nd, lambda mu, nu, lam, sig: f"I[{idx(mu, nu, lam, sig)}]",
-                            "a.J", "a.K", digest, reduce))
-    w("}")
-    w("")
+    # jk_: FP64 throughout; jk32_: the same with the VRR and contraction in
+    # FP32 (mixed plans route quartets with a small Schwarz bound here);
+    # Phase 2 and digestion in FP64
+    for kname, qname, ity in [(f"jk_{tag}", f"quartet_{tag}", "double")] + \
+            ([(f"jk32_{tag}", f"quartet32_{tag}", "double")] if mixed else []):
+        w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void {kname}(JKArgs a)")
+        w("{")
+        w(f"    const int64_t q = (int64_t)blockIdx.x * {block} + threadIdx.x;")
+        w("    if (q >= a.nq) return;")
+        w("    const int2 pq = a.quartets[q];")
+        w("    const PairInfo pb = a.pairs[pq.x], pk = a.pairs[pq.y];")
+        w("    const PairGeo gb = a.geo[pq.x], gk = a.geo[pq.y];")
+        w(f"    {ity} I[{nout}];")
+        w(f"    {qname}(pb, gb, pk, gk, a.prims, a.boys, I);")
+        w("    const double *__restrict__ D = a.D;")
+        w("    const int N = a.nbf;")
+        w("    const int fa = pb.fa, fb = pb.fb, fc = pk.fa, fd = pk.fb;")
+        w("    const double s = (pb.same ? 0.5 : 1.0) * (pk.same ? 0.5 : 1.0) * (pq.x == pq.y ? 0.5 : 1.0);")
+        cast = "" if ity == "double" else "(double)"
+        out.extend(digest_lines(na, nb, nc, nd, lambda mu, nu, lam, sig: f"{cast}I[{idx(mu, nu, lam, sig)}]",
+                                "a.J", "a.K", digest, reduce))
+        w("}")
+        w("")
     # ---------------------------------------------------------------- integrals-out kernel
     diag_class = (la, lb) == (lc, ld)
     w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void eri_{tag}(EriArgs a)")
@@ -420,10 +462,15 @@ def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves
     w("{")
     w(f"    hipLaunchKernelGGL(eri_{tag}, dim3((unsigned)((a.ntask + {block - 1}) / {block})), dim3({block}), 0, s, a);")
     w("}")
+    if mixed:
+        w(f"void launch_jk32_{tag}(const JKArgs &a, hipStream_t s)")
+        w("{")
+        w(f"    hipLaunchKernelGGL(jk32_{tag}, dim3((unsigned)((a.nq + {block - 1}) / {block})), dim3({block}), 0, s, a);")
+        w("}")
     w("")
     w("}  // namespace hgp")
     meta = ClassMeta(ls, tag, 0, block, len(g.nodes), g.flops(), len(g.targets), pl, sched, p2.flops, nout, rule,
-                     waves=waves, digest=digest, reduce=reduce, loop=loop)
+                     waves=waves, digest=digest, reduce=reduce, loop=loop, mixed=mixed)
     return "\n".join(out) + "\n", meta
 
 
@@ -437,13 +484,16 @@ def emit_table(metas):
             out.append(f"void launch_p1_{m.tag}(const P1Args &, hipStream_t);")
         if m.tier == 2:
             out.append(f"int prepare_{m.tag}();")
+        if m.mixed:
+            out.append(f"void launch_jk32_{m.tag}(const JKArgs &, hipStream_t);")
     out.append("")
     out.append("extern const ClassKernels g_class_table[] = {")
     for m in metas:
         la, lb, lc, ld = m.ls
         p1 = f"launch_p1_{m.tag}" if m.tier == 1 else "nullptr"
         prep = f"prepare_{m.tag}" if m.tier == 2 else "nullptr"
-        out.append(f"    {{{la}, {lb}, {lc}, {ld}, {m.tier}, launch_jk_{m.tag}, launch_eri_{m.tag}, {p1}, {prep}, {m.block}, "
+        jk32 = f"launch_jk32_{m.tag}" if m.mixed else "nullptr"
+        out.append(f"    {{{la}, {lb}, {lc}, {ld}, {m.tier}, launch_jk_{m.tag}, launch_eri_{m.tag}, {p1}, {prep}, {jk32}, {m.block}, "
                    f"{m.vrr_flops}.0, {m.p2_flops}.0, {m.n_hrr}, {m.peak_live}, {m.scratch_slots}, {m.chunks}}},")
     out.append("};")
     out.append(f"extern const int g_num_classes = {len(metas)};")
