@@ -164,6 +164,74 @@ def microbench(args):
         torch.cuda.empty_cache()
 
 
+def batch(args):
+    """Batched uneven systems: many molecules of different size, each with
+    its own plan and density, built one after another on one stream and then
+    as one captured HIP graph (hgp_batch).  One JSON line: contracted ERIs/s
+    over the whole batch for the graph replay, with the sequential time
+    beside it."""
+    import torch
+    import paper_2605_10312_amd as hgp
+    import workloads
+
+    n, natom, nprim = args.batch_n, (5, args.batch_max_atoms), (1, args.batch_max_prim)
+    systems = workloads.batch_systems(seed=1004, n=n, natom=natom, lmax=3, nprim=nprim)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bases, plans, Ds, Js, Ks = [], [], [], [], []
+    eris = 0
+    for bw, D in systems:
+        b = hgp.Basis.from_workload(bw)
+        p = hgp.Plan(b, tau=TAU)
+        bases.append(b)
+        plans.append(p)
+        eris += sum(c["quartets"] * np.prod([nsph(x) for x in c["ls"]]) for c in p.classes())
+        Dt = torch.tensor(D, dtype=torch.float64, device="cuda")
+        Ds.append(Dt)
+        Js.append(torch.empty_like(Dt))
+        Ks.append(torch.empty_like(Dt))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    graph = hgp.Batch(plans, Ds, Js, Ks)
+    capture_s = time.perf_counter() - t0
+
+    def seq():
+        for p, D, J, K in zip(plans, Ds, Js, Ks):
+            p.jk(D, J, K)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / args.steps
+
+    seq_s = timed(seq)
+    ref = [(J.clone(), K.clone()) for J, K in zip(Js, Ks)]
+    graph_s = timed(graph.run)
+    diff = max(max(float((J - r[0]).abs().max()), float((K - r[1]).abs().max())) for J, K, r in zip(Js, Ks, ref))
+    nbf = [int(bw.nbf) for bw, _ in systems]
+    line = {"metric": METRIC, "value": eris / graph_s, "unit": "contracted ERIs/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(graph_s * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"batch{n}_4s3p2d1f: {n} synthetic molecules of U{{{natom[0]}..{natom[1]}}} atoms, "
+                                   f"4s3p2d1f per atom, U{{{nprim[0]}..{nprim[1]}}} primitives per shell, "
+                                   "Schwarz tau=1e-12, J+K in FP64, one HIP graph per step",
+                       "systems": n, "nbf_min": min(nbf), "nbf_max": max(nbf), "nbf_sum": sum(nbf),
+                       "eris_per_step": int(eris)},
+            "sequential_ms": round(seq_s * 1e3, 4), "graph_ms": round(graph_s * 1e3, 4),
+            "graph_speedup": round(seq_s / graph_s, 3), "setup_s": round(setup_s, 3),
+            "capture_s": round(capture_s, 4), "max_abs_graph_vs_sequential": diff}
+    print(json.dumps(line), flush=True)
+    graph.close()
+    for o in plans + bases:
+        o.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,8 +243,12 @@ def main():
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: quartets with Q_ab Q_cd < theta use FP32 VRR/HRR (register tier)")
     ap.add_argument("--theta", type=float, default=None, help="mixed-precision threshold (default: the library's)")
-    ap.add_argument("--workload", choices=("mol30", "microbench"), default="mol30",
-                    help="mol30: the J/K build (one JSON line); microbench: the high-l primitive-quartet classes")
+    ap.add_argument("--workload", choices=("mol30", "microbench", "batch"), default="mol30",
+                    help="mol30: the J/K build (one JSON line); microbench: the high-l primitive-quartet classes; "
+                         "batch: many uneven systems in one HIP graph")
+    ap.add_argument("--batch-n", type=int, default=64, help="batch: number of systems")
+    ap.add_argument("--batch-max-atoms", type=int, default=15, help="batch: atoms per system U{5..this}")
+    ap.add_argument("--batch-max-prim", type=int, default=3, help="batch: primitives per shell U{1..this}")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy kernel (y = 1.0 * x, MIB MiB of FP64 each way), "
                          "a known-size reference for hardware byte counters")
@@ -187,6 +259,9 @@ def main():
 
     if args.workload == "microbench":
         microbench(args)
+        return
+    if args.workload == "batch":
+        batch(args)
         return
 
     import torch

@@ -165,6 +165,36 @@ hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int32_t kernel, int64_t
 hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_stream);
 
 /*
+ * Batched J/K over many systems (the batched-systems growth of the method):
+ * the J/K builds of n plans, each with its own D, J and K, captured once as
+ * one HIP graph in which every system is an independent branch, so the
+ * device overlaps the classes of small and large systems instead of running
+ * them one launch at a time.
+ *   plans[n]          built plans (same device), distinct from one another
+ *   D[n], J[n], K[n]  device pointers per system, N_i x N_i; J[i] or K[i] may
+ *                     be NULL to skip; captured by address, so later runs read
+ *                     the current contents of D[i] and overwrite J[i], K[i]
+ * hgp_batch_create checks the arguments, captures the builds on streams of
+ * its own (so the caller's stream is neither needed nor touched) and
+ * instantiates the graph; nothing runs yet.  Systems are spread over up to 8
+ * branches, largest first, each to the branch with the least estimated work.
+ * Plans with kernel timing on are rejected (events cannot be captured), and
+ * so is a plan given twice (its accumulators would be shared).
+ * hgp_batch_run enqueues one replay on hip_stream (any stream, the null
+ * stream included); J and K are complete when that stream reaches the end of
+ * the replay.  A plan in a batch must not be used concurrently with the
+ * batch's runs.  hgp_batch_destroy frees the graph and the batch's streams,
+ * not the plans or buffers.  Errors: HGP_E_INVALID for bad arguments,
+ * HGP_E_STATE for a broken plan, HGP_E_DEVICE if capture or instantiation
+ * fails (nothing is left allocated).
+ */
+typedef struct hgp_batch hgp_batch;
+hgp_status hgp_batch_create(hgp_plan *const *plans, int32_t n, const double *const *D, double *const *J,
+                            double *const *K, hgp_batch **out);
+hgp_status hgp_batch_run(hgp_batch *b, void *hip_stream);
+hgp_status hgp_batch_destroy(hgp_batch *b);
+
+/*
  * hgp_eri_shell_quartets -- integrals out, any shell order.
  *   quartets[4*nq]  shell indices (i, j, k, l) per quartet          (host)
  *   offsets[nq]     element offset of each block in out             (host)

@@ -32,6 +32,9 @@ SIGNATURES = {
     "hgp_basis_destroy": (ctypes.c_int, [_vp]),
     "hgp_plan_create": (ctypes.c_int, [_vp, _d, _i32, _sz, _vp, ctypes.POINTER(_vp)]),
     "hgp_plan_create_mixed": (ctypes.c_int, [_vp, _d, _d, _sz, _vp, ctypes.POINTER(_vp)]),
+    "hgp_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "hgp_batch_run": (ctypes.c_int, [_vp, _vp]),
+    "hgp_batch_destroy": (ctypes.c_int, [_vp]),
     "hgp_plan_class_precision": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32)]),
     "hgp_plan_destroy": (ctypes.c_int, [_vp]),
     "hgp_plan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
@@ -221,6 +224,37 @@ def eri_shell_quartets(basis: Basis, quartets, offsets, out, stream=None):
     _check(lib().hgp_eri_shell_quartets(basis.handle, int(q.shape[0]), q.ctypes.data_as(ctypes.c_void_p),
                                         off.ctypes.data_as(ctypes.c_void_p), _dptr(out, torch.float64),
                                         ctypes.c_void_p(_stream_ptr(stream))))
+
+
+class Batch:
+    """hgp_batch: the J/K builds of several plans captured as one HIP graph
+    (one branch per system).  D, J, K: lists of device tensors per plan (J or
+    K entries may be None); run() replays the graph on the stream."""
+
+    def __init__(self, plans, D, J, K):
+        import torch
+        n = len(plans)
+        self._keep = (list(plans), list(D), list(J), list(K))
+        arr = lambda xs: (ctypes.c_void_p * n)(*[None if x is None else _dptr(x, torch.float64) for x in xs])
+        self._arrays = (ctypes.c_void_p * n)(*[p.handle.value for p in plans]), arr(D), arr(J), arr(K)
+        h = ctypes.c_void_p()
+        _check(lib().hgp_batch_create(self._arrays[0], n, self._arrays[1], self._arrays[2], self._arrays[3],
+                                      ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, stream=None):
+        _check(lib().hgp_batch_run(self.handle, ctypes.c_void_p(_stream_ptr(stream))))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().hgp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def eri_prim_quartets(ls, centers, exps, out, stream=None):

@@ -1002,4 +1002,112 @@ hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld,
     return HGP_OK;
 }
 
+struct hgp_batch {
+    int device = 0;
+    hipStream_t origin = nullptr;                 // the capture's origin stream
+    std::vector<hipStream_t> branches;
+    std::vector<hipEvent_t> events;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+hgp_status hgp_batch_destroy(hgp_batch *b)
+{
+    if (!b) return HGP_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+    for (hipStream_t st : b->branches) (void)hipStreamDestroy(st);
+    if (b->origin) (void)hipStreamDestroy(b->origin);
+    delete b;
+    return HGP_OK;
+}
+
+hgp_status hgp_batch_create(hgp_plan *const *plans, int32_t n, const double *const *D, double *const *J,
+                            double *const *K, hgp_batch **out)
+{
+    if (!out) return fail(HGP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !plans || !D || !J || !K) return fail(HGP_E_INVALID, "need n >= 1 and the plans, D, J, K arrays");
+    int dev = 0;
+    HGP_HIP(hipGetDevice(&dev));
+    std::vector<std::pair<double, int>> cost((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const hgp_plan *p = plans[i];
+        if (!p) return fail(HGP_E_INVALID, "a plan is NULL");
+        if (p->broken) return fail(HGP_E_STATE, "a plan is unusable after an earlier device failure");
+        if (p->timing) return fail(HGP_E_INVALID, "kernel timing must be off for plans in a batch");
+        if (p->device != dev) return fail(HGP_E_INVALID, "all plans of a batch must be on the current device");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == p) return fail(HGP_E_INVALID, "a plan appears twice in the batch");
+        if (p->b->nbf > 0 && (!D[i] || (!J[i] && !K[i]))) return fail(HGP_E_INVALID, "a system has no D or no output");
+        double c = 0.0;                           // work estimate: VRR + Phase-2 FLOPs of its lists
+        for (const ClassList &cl : p->lists)
+            c += cl.nprimq * g_class_table[cl.cls].vrr_flops + cl.nq * g_class_table[cl.cls].p2_flops;
+        cost[i] = {c, i};
+    }
+    const double *boys = nullptr;                  // the table is built (and allocated) outside the capture
+    if (hgp_status bst = boys_table(dev, &boys)) return bst;
+    auto *b = new hgp_batch();
+    b->device = dev;
+    const int nbranch = std::min(n, 8);
+    auto bail = [&](hgp_status st) { hgp_batch_destroy(b); return st; };
+    if (hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(HGP_E_DEVICE, "creating the capture stream failed"));
+    hipStream_t s = b->origin;
+    for (int k = 0; k < nbranch; ++k) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(HGP_E_DEVICE, "creating a branch stream failed"));
+        b->branches.push_back(st);
+    }
+    for (int k = 0; k <= nbranch; ++k) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(HGP_E_DEVICE, "creating a branch event failed"));
+        b->events.push_back(e);
+    }
+    // largest systems first, each to the branch with the least work so far
+    std::sort(cost.begin(), cost.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    std::vector<double> load((size_t)nbranch, 0.0);
+    std::vector<int> branch_of((size_t)n, 0);
+    for (const auto &ci : cost) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        branch_of[(size_t)ci.second] = k;
+        load[(size_t)k] += ci.first + 1.0;
+    }
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess)
+        return bail(fail(HGP_E_DEVICE, "hipStreamBeginCapture failed"));
+    hgp_status st = HGP_OK;
+    hipError_t e = hipEventRecord(b->events[0], s);
+    for (int k = 0; k < nbranch && e == hipSuccess; ++k) e = hipStreamWaitEvent(b->branches[k], b->events[0], 0);
+    for (const auto &ci : cost) {
+        if (e != hipSuccess || st != HGP_OK) break;
+        const int i = ci.second;
+        st = hgp_jk(plans[i], D[i], J[i], K[i], b->branches[(size_t)branch_of[(size_t)i]]);
+    }
+    for (int k = 0; k < nbranch && e == hipSuccess; ++k) {
+        e = hipEventRecord(b->events[k + 1], b->branches[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, b->events[k + 1], 0);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    b->graph = g;
+    if (st != HGP_OK) return bail(st);
+    if (e != hipSuccess || ec != hipSuccess)
+        return bail(fail(HGP_E_DEVICE, std::string("capturing the batch failed: ") + hipGetErrorString(e != hipSuccess ? e : ec)));
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bail(fail(HGP_E_DEVICE, "hipGraphInstantiate failed"));
+    *out = b;
+    return HGP_OK;
+}
+
+hgp_status hgp_batch_run(hgp_batch *b, void *hip_stream)
+{
+    if (!b || !b->exec) return fail(HGP_E_INVALID, "batch is NULL");
+    const hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    return HGP_OK;
+}
+
 }  // extern "C"

@@ -164,3 +164,20 @@ CONFIGS = {
     "tiny": dict(builder=tiny_system, tau=0.0),
     "mol30_3s2p1d": dict(builder=molecule_3s2p1d, tau=1.0e-12),
 }
+
+
+def batch_systems(seed: int = 1004, n: int = 64, natom=(5, 60), lmax: int = 3, nprim=(1, 8)):
+    """n molecules of U{natom} atoms each, grown like molecule_3s2p1d, with
+    the shell set of the given l_max per atom (l_max 3: 4s3p2d1f) and U{nprim}
+    primitives per shell; exponents log-uniform [0.05, 5e3].  Returns a list
+    of (basis, density), each density from its own stream."""
+    rng = np.random.default_rng(seed)
+    shells = {2: [0, 0, 0, 1, 1, 2], 3: [0, 0, 0, 0, 1, 1, 1, 2, 2, 3],
+              4: [0] * 5 + [1] * 4 + [2] * 3 + [3] * 2 + [4]}[lmax]
+    out = []
+    for k in range(n):
+        na = int(rng.integers(natom[0], natom[1] + 1))
+        atoms = grow_molecule(rng, na) * ANGSTROM_TO_BOHR
+        basis = build_basis(atoms, [(l, nprim) for l in shells], rng, (0.05, 5.0e3))
+        out.append((basis, psd_density(basis.nbf, seed + 1000 + k)))
+    return out
