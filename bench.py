@@ -180,7 +180,9 @@ def batch(args):
     t0 = time.perf_counter()
     bases, plans, Ds, Js, Ks = [], [], [], [], []
     eris = 0
-    for bw, D in systems:
+    for k, (bw, D) in enumerate(systems):
+        if k % 16 == 0:
+            print(f"batch: planning system {k}/{n} (N={bw.nbf})", file=sys.stderr, flush=True)
         b = hgp.Basis.from_workload(bw)
         p = hgp.Plan(b, tau=TAU)
         bases.append(b)
@@ -200,19 +202,20 @@ def batch(args):
         for p, D, J, K in zip(plans, Ds, Js, Ks):
             p.jk(D, J, K)
 
-    def timed(fn):
+    def timed(fn, what):
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(args.steps):
             fn()
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
+            print(f"batch: {what} step done", file=sys.stderr, flush=True)
         return (time.perf_counter() - t) / args.steps
 
-    seq_s = timed(seq)
+    seq_s = timed(seq, "sequential")
     ref = [(J.clone(), K.clone()) for J, K in zip(Js, Ks)]
-    graph_s = timed(graph.run)
+    graph_s = timed(graph.run, "graph")
     diff = max(max(float((J - r[0]).abs().max()), float((K - r[1]).abs().max())) for J, K, r in zip(Js, Ks, ref))
     nbf = [int(bw.nbf) for bw, _ in systems]
     line = {"metric": METRIC, "value": eris / graph_s, "unit": "contracted ERIs/s", "n_gpus": 1,

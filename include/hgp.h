@@ -130,7 +130,7 @@ hgp_status hgp_plan_prim_stats(const hgp_plan *p, int64_t *prim_pairs_kept, int6
 /* Per class list c (0 .. n-1, n = hgp_plan_num_classes, in launch order; a mixed plan can hold two
  * lists of one class): angular momenta ls[4], quartets kept, primitive quartets they hold, the
  * generator's FLOP counts per primitive quartet (VRR + accumulate, unchunked) and per contracted
- * quartet (Phase 2), and the tier (0 register, 1 staged, 2 HBM scratch). */
+ * quartet (Phase 2), and the tier (0 register, 1 staged, 2 HBM scratch, 3 wave-cooperative LDS). */
 int32_t hgp_plan_num_classes(const hgp_plan *p);
 hgp_status hgp_plan_class_info(const hgp_plan *p, int32_t c, int32_t *ls, int64_t *nquartets, int64_t *nprim_quartets,
                                double *vrr_flops, double *phase2_flops, int32_t *tier);

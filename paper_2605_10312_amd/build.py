@@ -153,8 +153,9 @@ def build(lmax: int = DEFAULT_LMAX, jobs: int | None = None, force: bool = False
     if verbose:
         staged = [m.tag for m in metas if m.tier == 1]
         t3 = [m.tag for m in metas if m.tier == 2]
+        t3w = [m.tag for m in metas if m.tier == 3]
         print(f"built {lib} ({len(metas)} classes, l <= {lmax}, staged: {' '.join(staged) or 'none'}, "
-              f"HBM scratch: {' '.join(t3) or 'none'}) "
+              f"HBM scratch: {' '.join(t3) or 'none'}, wave LDS: {' '.join(t3w) or 'none'}) "
               f"in {time.time() - t0:.1f}s", flush=True)
     return lib
 

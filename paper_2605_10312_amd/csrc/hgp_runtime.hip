@@ -80,7 +80,7 @@ int64_t staged_batch(const ClassKernels &k, int64_t doubles)
 // Buffer a staged class needs to run all n items in one batch (capped).
 int64_t staged_need(const ClassKernels &k, int64_t n)
 {
-    if (k.tier == 0 || n <= 0) return 0;
+    if (k.tier == 0 || k.tier == 3 || n <= 0) return 0;      // no HBM buffer
     const int64_t want = (int64_t)k.scratch_slots * (((n + 63) / 64) * 64);
     const int64_t floor64 = (int64_t)k.scratch_slots * 64;
     return std::max(floor64, std::min(want, k.tier == 2 ? T3_SCRATCH_MAX_DOUBLES : SCRATCH_MAX_DOUBLES));
@@ -96,13 +96,13 @@ hgp_status prepare_class(const ClassKernels &k)
     return HGP_OK;
 }
 
-// Integrals-out work of one class: register tier in launches of at most 2^20
-// blocks; staged tier in batches (Phase 1 then Phase 2); HBM-scratch tier in
-// batches of one kernel each.
+// Integrals-out work of one class: register and wave-LDS tiers in launches of
+// at most 2^20 blocks; staged tier in batches (Phase 1 then Phase 2);
+// HBM-scratch tier in batches of one kernel each.
 void run_eri_class(const ClassKernels &k, EriArgs a, int64_t scratch_doubles, hipStream_t s)
 {
     const int64_t ntask = a.ntask;
-    if (k.tier == 0) {
+    if (k.tier == 0 || k.tier == 3) {
         const int64_t chunk = (int64_t)k.block << 20;
         for (int64_t q0 = 0; q0 < ntask; q0 += chunk) {
             EriArgs b = a;
@@ -792,7 +792,7 @@ hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_
         a.D = D; a.J = p->d_Jacc; a.K = p->d_Kacc; a.nbf = n;
         a.want_j = J != nullptr; a.want_k = K != nullptr;
         hipEvent_t e0, e1, e2, e3;
-        if (k.tier == 0) {
+        if (k.tier == 0 || k.tier == 3) {                // register or wave-cooperative LDS tier
             if ((st = mark(&e0))) return st;
             const int64_t chunk = (int64_t)k.block << 20;
             const launch_jk_fn run = cl.bits == 32 ? k.jk32 : k.jk;

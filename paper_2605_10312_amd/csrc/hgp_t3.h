@@ -1,6 +1,7 @@
 // HBM-scratch tier: one generic kernel per mode runs a class's op table (the
 // generator's VRR and Phase-2 programs with slot-packed operands) over a
-// lane-interleaved buffer.  A generated class file holds only the tables
+// lane-interleaved buffer; the wave-cooperative variant runs the same kind
+// of table with the slots of one quartet in LDS.  A generated class file holds only the tables
 // (host data) and two launchers.
 #pragma once
 #include "hgp_types.h"
@@ -26,12 +27,24 @@ struct T3Class {
     const double *coefs;         // host: transform coefficients
     const uint16_t *outslots;    // host: slot of integral (mu, nu, lam, sig), row-major
     int block;                   // threads per block
+    // wave-cooperative LDS variant only (0 for the HBM-scratch variant):
+    int maxblk;                  // largest of the six D/J/K blocks of a quartet
+    int lds_bytes;               // LDS per workgroup (slots, zero and sink slots, coefficients, D blocks, outslots)
 };
+
+// Wave-cooperative LDS variant (tier 3): the same tables regrouped 64 ops a
+// group; one wavefront per quartet holds every slot in LDS and lane j runs op
+// j of each group.  Absent operands name the zero slot nslots; padding ops
+// write the sink slot nslots + 1.
+constexpr int T3W_GROUP = 64;
+constexpr int T3W_PREFETCH = 1;  // groups whose ops are in flight ahead of the running one
 
 // 0 (hipSuccess) once the class's tables are on the current device (uploaded
 // on first call), else the hipError_t of the step that failed.
 int t3_prepare(const T3Class &c);
 void t3_launch_jk(const T3Class &c, const JKArgs &a, hipStream_t s);
 void t3_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s);
+void t3w_launch_jk(const T3Class &c, const JKArgs &a, hipStream_t s);
+void t3w_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s);
 
 }  // namespace hgp

@@ -298,6 +298,319 @@ __global__ __launch_bounds__(64) void t3_eri_kernel(T3Params c, const uint4 *__r
                     o[mu * t.s0 + nu * t.s1 + lam * t.s2 + sig * t.s3] = sb[slot(mu, nu, lam, sig) * S + li];
 }
 
+// ---------------------------------------------------------------------------
+// Wave-cooperative LDS variant.  One 64-lane workgroup per quartet; LDS holds
+// [slots | Z | sink | coefficients | six D blocks] as doubles, then the
+// uint16 output-slot map.  Lane j runs op j of every group.  A group's ops
+// are independent of one another, so each lane reads its operands before any
+// lane of the group writes; successive groups see each other's writes
+// because LDS instructions of one wavefront execute in issue order.  The
+// wave barrier below only stops the compiler from moving LDS accesses
+// across a group boundary (it emits no instruction).
+
+struct T3WParams {
+    int L, na, nb, nc, nd, n_hrr, acc0, n_vrr, n_p2, nslots, ncoef, maxblk, nint;
+};
+
+__device__ __forceinline__ void t3w_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane m <= L writes base * F_m(T) to slot m.  Below T = 36 each order is its
+// own 8-term Taylor expansion about the nearest table point (the table holds
+// orders 0..23, so m + 7 <= 23 for L <= 16); above, the asymptote and the
+// upward recurrence, evaluated by every lane up to its own order.
+__device__ __forceinline__ void t3w_boys(double T, int L, const double *__restrict__ tab, double base,
+                                         double *__restrict__ S, int lane)
+{
+    if (lane > L) return;
+    if (T < BOYS_TMAX) {
+        const int k = (int)(T * BOYS_INV_STEP + 0.5);
+        const double x = (double)k * BOYS_STEP - T;
+        const double *r = tab + k * BOYS_STRIDE + lane;
+        double f = r[7];
+        f = fma(f, x * (1.0 / 7.0), r[6]);
+        f = fma(f, x * (1.0 / 6.0), r[5]);
+        f = fma(f, x * (1.0 / 5.0), r[4]);
+        f = fma(f, x * 0.25, r[3]);
+        f = fma(f, x * (1.0 / 3.0), r[2]);
+        f = fma(f, x * 0.5, r[1]);
+        f = fma(f, x, r[0]);
+        S[lane] = base * f;
+    } else {
+        const double e = (double)__builtin_amdgcn_exp2f((float)(T * -1.4426950408889634));
+        const double h = 0.5 * hgp_rcp(T);
+        double f = 0.88622692545275801365 * hgp_rsqrt(T);
+        for (int m = 0; m < lane; ++m) f = fma((double)(2 * m + 1), f, -e) * h;
+        S[lane] = base * f;
+    }
+}
+
+// One group of ops, o = this lane's op.  Per-primitive quantities come in
+// through q (bra values then ket values).
+struct T3WPrim {
+    double PAx, PAy, PAz, WPx, WPy, WPz, o2z, rz;
+    double QCx, QCy, QCz, WQx, WQy, WQz, o2e, re;
+    double o2ze;
+};
+
+__device__ __forceinline__ void t3w_vrr_group(const uint4 o, const T3WPrim &q, double *__restrict__ S)
+{
+    const uint32_t w0 = o.x & 0xFFFFu;
+    const double v1 = S[o.y & 0xFFFFu], v2 = S[o.y >> 16], v3 = S[o.z & 0xFFFFu], v4 = S[o.z >> 16],
+                 v5 = S[o.w & 0xFFFFu];
+    const bool bra = (w0 & 15u) == (uint32_t)T3_VRR_BRA;
+    const uint32_t axis = (w0 >> 4) & 3u;
+    // value selects (unary + makes each operand a value, so no select of
+    // addresses into the struct is formed)
+    const double X0 = bra ? +q.PAx : +q.QCx, X1 = bra ? +q.PAy : +q.QCy, X2 = bra ? +q.PAz : +q.QCz;
+    const double Y0 = bra ? +q.WPx : +q.WQx, Y1 = bra ? +q.WPy : +q.WQy, Y2 = bra ? +q.WPz : +q.WQz;
+    const double X = axis == 0 ? X0 : (axis == 1 ? X1 : X2);
+    const double Y = axis == 0 ? Y0 : (axis == 1 ? Y1 : Y2);
+    const double o2 = bra ? +q.o2z : +q.o2e, r = bra ? +q.rz : +q.re;
+    double v = fma(X, v1, Y * v2);
+    v = fma((double)((w0 >> 6) & 31u) * o2, fma(-r, v4, v3), v);
+    v = fma((double)((w0 >> 11) & 31u) * q.o2ze, v5, v);
+    S[o.x >> 16] = v;
+}
+
+__device__ __forceinline__ void t3w_acc_group(const uint4 o, double *__restrict__ S)
+{
+    const uint32_t d = o.x >> 16;
+    const double x = S[d], y = S[o.y & 0xFFFFu];
+    S[d] = x + y;
+}
+
+struct T3WHrr {
+    double abx, aby, abz, cdx, cdy, cdz;
+};
+
+__device__ __forceinline__ void t3w_hrr_group(const uint4 o, const T3WHrr &h, double *__restrict__ S)
+{
+    const uint32_t code = o.x & 15u, axis = (o.x >> 4) & 3u;
+    const double hi = S[o.y & 0xFFFFu], lo = S[o.y >> 16];
+    const bool bra = code == (uint32_t)T3_HRR_BRA;
+    const double d0 = bra ? +h.abx : +h.cdx, d1 = bra ? +h.aby : +h.cdy, d2 = bra ? +h.abz : +h.cdz;
+    const double d = axis == 0 ? d0 : (axis == 1 ? d1 : d2);
+    S[o.x >> 16] = fma(d, lo, hi);
+}
+
+__device__ __forceinline__ void t3w_lin_group(const uint4 o, const double *__restrict__ C, double *__restrict__ S)
+{
+    const uint32_t d = o.x >> 16;
+    const double x1 = S[o.y & 0xFFFFu], x2 = S[o.y >> 16], x3 = S[o.z & 0xFFFFu];
+    const double acc = (o.x & 15u) == (uint32_t)T3_LIN_ACC ? S[d] : 0.0;
+    double v = fma(C[o.z >> 16], x1, acc);
+    v = fma(C[o.w & 0xFFFFu], x2, v);
+    v = fma(C[o.w >> 16], x3, v);
+    S[d] = v;
+}
+
+// The quartet's integrals into their output slots (LDS), as t3_quartet.
+__device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__restrict__ ops, const PairInfo &pb,
+                            const PairGeo &gb, const PairInfo &pk, const PairGeo &gk,
+                            const PrimPair *__restrict__ prims, const double *__restrict__ boys, double *__restrict__ S,
+                            const double *__restrict__ C, int lane)
+{
+    for (int k = lane; k < c.n_hrr; k += T3W_GROUP) S[c.acc0 + k] = 0.0;
+    if (lane == 0) S[c.nslots] = 0.0;                       // the zero slot
+    t3w_sync();
+    const uint4 *__restrict__ myops = ops + lane;
+    const PrimPair *__restrict__ pbp = prims + pb.prim_off;
+    const PrimPair *__restrict__ pkp = prims + pk.prim_off;
+    for (int ip = 0; ip < pb.nprim; ++ip) {
+        const PrimPair b = pbp[ip];
+        for (int jp = 0; jp < pk.nprim; ++jp) {
+            const PrimPair e = pkp[jp];
+            T3WPrim q;
+            q.PAx = b.px - gb.ax; q.PAy = b.py - gb.ay; q.PAz = b.pz - gb.az;
+            q.QCx = e.px - gk.ax; q.QCy = e.py - gk.ay; q.QCz = e.pz - gk.az;
+            const double PQx = b.px - e.px, PQy = b.py - e.py, PQz = b.pz - e.pz;
+            const double ze = b.zeta + e.zeta, ize = hgp_rcp(ze);
+            q.rz = e.zeta * ize;
+            q.re = b.zeta * ize;
+            q.o2ze = 0.5 * ize;
+            q.o2z = b.o2z;
+            q.o2e = e.o2z;
+            q.WPx = -q.rz * PQx; q.WPy = -q.rz * PQy; q.WPz = -q.rz * PQz;
+            q.WQx = q.re * PQx; q.WQy = q.re * PQy; q.WQz = q.re * PQz;
+            const double T = b.zeta * q.rz * (PQx * PQx + PQy * PQy + PQz * PQz);
+            t3w_boys(T, c.L, boys, b.k * e.k * hgp_rsqrt(ze), S, lane);
+            t3w_sync();
+            // groups of 64 ops; the next group's op is loaded while this one runs
+            // (the table ends in a padding group)
+            const int ng = c.n_vrr / T3W_GROUP;
+            uint4 nxt = myops[0];
+            for (int g = 0; g < ng; ++g) {
+                const uint4 o = nxt;
+                nxt = myops[(size_t)(g + 1) * T3W_GROUP];
+                if ((__builtin_amdgcn_readfirstlane(o.x) & 15u) == (uint32_t)T3_ACC)
+                    t3w_acc_group(o, S);
+                else
+                    t3w_vrr_group(o, q, S);
+                t3w_sync();
+            }
+        }
+    }
+    // Phase 2: HRR and the stepwise transforms (Eq. hrr, Eqs. bra-sph .. stepwise-sph)
+    const T3WHrr h{gb.abx, gb.aby, gb.abz, gk.abx, gk.aby, gk.abz};
+    const uint4 *__restrict__ p2 = myops + (size_t)c.n_vrr;
+    const int ng = c.n_p2 / T3W_GROUP;
+    uint4 nxt = p2[0];
+    for (int g = 0; g < ng; ++g) {
+        const uint4 o = nxt;
+        nxt = p2[(size_t)(g + 1) * T3W_GROUP];
+        const uint32_t cls = __builtin_amdgcn_readfirstlane(o.x) & 15u;
+        if (cls == (uint32_t)T3_HRR_BRA || cls == (uint32_t)T3_HRR_KET)
+            t3w_hrr_group(o, h, S);
+        else
+            t3w_lin_group(o, C, S);
+        t3w_sync();
+    }
+}
+
+// LDS of one workgroup: S (slots, Z, sink), C (coefficients), Db (six D
+// blocks), O (output slot of integral (mu, nu, lam, sig), row-major).
+struct T3WLds {
+    double *S, *C, *Db;
+    uint16_t *O;
+};
+
+__device__ __forceinline__ T3WLds t3w_lds(const T3WParams &c, double *base, const double *__restrict__ coefs,
+                                          const uint16_t *__restrict__ outslots, int lane)
+{
+    T3WLds l;
+    l.S = base;
+    l.C = base + c.nslots + 2;
+    l.Db = l.C + c.ncoef;
+    l.O = (uint16_t *)(l.Db + 6 * c.maxblk);
+    for (int k = lane; k < c.ncoef; k += T3W_GROUP) l.C[k] = coefs[k];
+    for (int k = lane; k < c.nint; k += T3W_GROUP) l.O[k] = outslots[k];
+    return l;
+}
+
+extern __shared__ double t3w_smem[];
+
+__global__ __launch_bounds__(64) void t3w_jk_kernel(T3WParams c, const uint4 *__restrict__ ops,
+                                                    const double *__restrict__ coefs,
+                                                    const uint16_t *__restrict__ outslots, JKArgs a)
+{
+    const int64_t i = blockIdx.x;
+    if (i >= a.nq) return;
+    const int lane = threadIdx.x;
+    const T3WLds l = t3w_lds(c, t3w_smem, coefs, outslots, lane);
+    const int2 pq = a.quartets[i];
+    const PairInfo pb = a.pairs[pq.x], pk = a.pairs[pq.y];
+    const PairGeo gb = a.geo[pq.x], gk = a.geo[pq.y];
+    // the six D blocks (global reads, overlapping the quartet's evaluation)
+    const double *__restrict__ D = a.D;
+    const int64_t N = a.nbf;
+    const int fa = pb.fa, fb = pb.fb, fc = pk.fa, fd = pk.fb;
+    const int na = c.na, nb = c.nb, nc = c.nc, nd = c.nd, M = c.maxblk;
+    double *Dcd = l.Db, *Dab = l.Db + M, *Dbd = l.Db + 2 * M, *Dad = l.Db + 3 * M, *Dbc = l.Db + 4 * M,
+           *Dac = l.Db + 5 * M;
+    for (int k = lane; k < nc * nd; k += T3W_GROUP) Dcd[k] = D[(fc + k / nd) * N + fd + k % nd];
+    for (int k = lane; k < na * nb; k += T3W_GROUP) Dab[k] = D[(fa + k / nb) * N + fb + k % nb];
+    if (a.want_k) {
+        for (int k = lane; k < nb * nd; k += T3W_GROUP) Dbd[k] = D[(fb + k / nd) * N + fd + k % nd];
+        for (int k = lane; k < na * nd; k += T3W_GROUP) Dad[k] = D[(fa + k / nd) * N + fd + k % nd];
+        for (int k = lane; k < nb * nc; k += T3W_GROUP) Dbc[k] = D[(fb + k / nc) * N + fc + k % nc];
+        for (int k = lane; k < na * nc; k += T3W_GROUP) Dac[k] = D[(fa + k / nc) * N + fc + k % nc];
+    }
+    t3w_quartet(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, lane);
+    const double *__restrict__ S = l.S;
+    const uint16_t *__restrict__ O = l.O;
+    auto I = [&](int mu, int nu, int lam, int sig) -> double {
+        return S[O[((mu * nb + nu) * nc + lam) * nd + sig]];
+    };
+    const double s = (pb.same ? 0.5 : 1.0) * (pk.same ? 0.5 : 1.0) * (pq.x == pq.y ? 0.5 : 1.0);
+    // J'[ab] += 2s sum_cd I D_cd, J'[cd] += 2s sum_ab I D_ab; K'[ac] += s sum I D_bd,
+    // K'[bc] += s sum I D_ad, K'[ad] += s sum I D_bc, K'[bd] += s sum I D_ac
+    // (unsymmetrised, degeneracy-scaled); one output element per lane
+    if (a.want_j) {
+        for (int k = lane; k < na * nb; k += T3W_GROUP) {
+            const int mu = k / nb, nu = k % nb;
+            double t = 0.0;
+            for (int lam = 0; lam < nc; ++lam)
+                for (int sig = 0; sig < nd; ++sig) t = fma(I(mu, nu, lam, sig), Dcd[lam * nd + sig], t);
+            atomicAdd(a.J + (fa + mu) * N + fb + nu, 2.0 * s * t);
+        }
+        for (int k = lane; k < nc * nd; k += T3W_GROUP) {
+            const int lam = k / nd, sig = k % nd;
+            double t = 0.0;
+            for (int mu = 0; mu < na; ++mu)
+                for (int nu = 0; nu < nb; ++nu) t = fma(I(mu, nu, lam, sig), Dab[mu * nb + nu], t);
+            atomicAdd(a.J + (fc + lam) * N + fd + sig, 2.0 * s * t);
+        }
+    }
+    if (a.want_k) {
+        for (int k = lane; k < na * nc; k += T3W_GROUP) {
+            const int mu = k / nc, lam = k % nc;
+            double t = 0.0;
+            for (int nu = 0; nu < nb; ++nu)
+                for (int sig = 0; sig < nd; ++sig) t = fma(I(mu, nu, lam, sig), Dbd[nu * nd + sig], t);
+            atomicAdd(a.K + (fa + mu) * N + fc + lam, s * t);
+        }
+        for (int k = lane; k < nb * nc; k += T3W_GROUP) {
+            const int nu = k / nc, lam = k % nc;
+            double t = 0.0;
+            for (int mu = 0; mu < na; ++mu)
+                for (int sig = 0; sig < nd; ++sig) t = fma(I(mu, nu, lam, sig), Dad[mu * nd + sig], t);
+            atomicAdd(a.K + (fb + nu) * N + fc + lam, s * t);
+        }
+        for (int k = lane; k < na * nd; k += T3W_GROUP) {
+            const int mu = k / nd, sig = k % nd;
+            double t = 0.0;
+            for (int nu = 0; nu < nb; ++nu)
+                for (int lam = 0; lam < nc; ++lam) t = fma(I(mu, nu, lam, sig), Dbc[nu * nc + lam], t);
+            atomicAdd(a.K + (fa + mu) * N + fd + sig, s * t);
+        }
+        for (int k = lane; k < nb * nd; k += T3W_GROUP) {
+            const int nu = k / nd, sig = k % nd;
+            double t = 0.0;
+            for (int mu = 0; mu < na; ++mu)
+                for (int lam = 0; lam < nc; ++lam) t = fma(I(mu, nu, lam, sig), Dac[mu * nc + lam], t);
+            atomicAdd(a.K + (fb + nu) * N + fd + sig, s * t);
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void t3w_eri_kernel(T3WParams c, const uint4 *__restrict__ ops,
+                                                     const double *__restrict__ coefs,
+                                                     const uint16_t *__restrict__ outslots, EriArgs a)
+{
+    const int64_t i = blockIdx.x;
+    if (i >= a.ntask) return;
+    const int lane = threadIdx.x;
+    const T3WLds l = t3w_lds(c, t3w_smem, coefs, outslots, lane);
+    const EriTask t = a.tasks[i];
+    const PairInfo pb = a.pairs[t.bra], pk = a.pairs[t.ket];
+    const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];
+    t3w_quartet(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, lane);
+    const int na = c.na, nb = c.nb, nc = c.nc, nd = c.nd;
+    if (a.mode == 1) {                       // Schwarz factor of a diagonal quartet
+        double m = 0.0;
+        for (int k = lane; k < na * nb; k += T3W_GROUP) {
+            const int mu = k / nb, nu = k % nb;
+            m = fmax(m, fabs(l.S[l.O[((mu * nb + nu) * nc + mu) * nd + nu]]));
+        }
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+        if (lane == 0) a.out[i] = sqrt(m);
+        return;
+    }
+    double *__restrict__ o = a.out + t.off;
+    const int ncd = nc * nd;
+    for (int mu = 0; mu < na; ++mu)
+        for (int nu = 0; nu < nb; ++nu)
+            for (int k = lane; k < ncd; k += T3W_GROUP) {
+                const int lam = k / nd, sig = k % nd;
+                o[mu * t.s0 + nu * t.s1 + lam * t.s2 + sig * t.s3] = l.S[l.O[(mu * nb + nu) * ncd + k]];
+            }
+}
+
 // Device copies of a class's tables, uploaded on first use on each device
 // and kept until the process ends.
 std::mutex g_t3_mutex;
@@ -314,9 +627,13 @@ hipError_t t3_device_tables(const T3Class &c, T3Dev *out)
         *out = it->second;
         return hipSuccess;
     }
+    // zero groups past the end: the wave variant loads group g + 1 while it runs group g
     const size_t nops = (size_t)(c.n_vrr + c.n_p2), nout = (size_t)c.na * c.nb * c.nc * c.nd;
+    const size_t npad = (size_t)T3W_PREFETCH * T3W_GROUP;
     void *ops = nullptr, *coefs = nullptr, *outs = nullptr;
-    if ((e = hipMalloc(&ops, nops * 16)) != hipSuccess || (e = hipMalloc(&coefs, sizeof(double) * c.ncoef)) != hipSuccess ||
+    if ((e = hipMalloc(&ops, (nops + npad) * 16)) != hipSuccess ||
+        (e = hipMemset(ops, 0, (nops + npad) * 16)) != hipSuccess ||
+        (e = hipMalloc(&coefs, sizeof(double) * c.ncoef)) != hipSuccess ||
         (e = hipMalloc(&outs, sizeof(uint16_t) * nout)) != hipSuccess ||
         (e = hipMemcpy(ops, c.ops, nops * 16, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(coefs, c.coefs, sizeof(double) * c.ncoef, hipMemcpyHostToDevice)) != hipSuccess ||
@@ -353,6 +670,31 @@ void t3_launch_jk(const T3Class &c, const JKArgs &a, hipStream_t s)
     if (a.nq <= 0 || t3_device_tables(c, &d) != hipSuccess) return;
     hipLaunchKernelGGL(t3_jk_kernel, dim3((unsigned)((a.nq + c.block - 1) / c.block)), dim3(c.block), 0, s, params(c),
                        d.ops, d.coefs, d.outslots, a);
+}
+
+namespace {
+T3WParams wparams(const T3Class &c)
+{
+    return T3WParams{c.L,      c.na,    c.nb,        c.nc,    c.nd,     c.n_hrr, c.acc0,
+                     c.n_vrr,  c.n_p2,  c.nslots,    c.ncoef, c.maxblk, c.na * c.nb * c.nc * c.nd};
+}
+}  // namespace
+
+// One workgroup per quartet; the runtime keeps a launch under 2^26 quartets.
+void t3w_launch_jk(const T3Class &c, const JKArgs &a, hipStream_t s)
+{
+    T3Dev d;
+    if (a.nq <= 0 || c.lds_bytes <= 0 || t3_device_tables(c, &d) != hipSuccess) return;
+    hipLaunchKernelGGL(t3w_jk_kernel, dim3((unsigned)a.nq), dim3(T3W_GROUP), (unsigned)c.lds_bytes, s, wparams(c),
+                       d.ops, d.coefs, d.outslots, a);
+}
+
+void t3w_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s)
+{
+    T3Dev d;
+    if (a.ntask <= 0 || c.lds_bytes <= 0 || t3_device_tables(c, &d) != hipSuccess) return;
+    hipLaunchKernelGGL(t3w_eri_kernel, dim3((unsigned)a.ntask), dim3(T3W_GROUP), (unsigned)c.lds_bytes, s,
+                       wparams(c), d.ops, d.coefs, d.outslots, a);
 }
 
 void t3_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s)

@@ -482,7 +482,7 @@ def emit_table(metas):
         out.append(f"void launch_eri_{m.tag}(const EriArgs &, hipStream_t);")
         if m.tier == 1:
             out.append(f"void launch_p1_{m.tag}(const P1Args &, hipStream_t);")
-        if m.tier == 2:
+        if m.tier in (2, 3):
             out.append(f"int prepare_{m.tag}();")
         if m.mixed:
             out.append(f"void launch_jk32_{m.tag}(const JKArgs &, hipStream_t);")
@@ -491,7 +491,7 @@ def emit_table(metas):
     for m in metas:
         la, lb, lc, ld = m.ls
         p1 = f"launch_p1_{m.tag}" if m.tier == 1 else "nullptr"
-        prep = f"prepare_{m.tag}" if m.tier == 2 else "nullptr"
+        prep = f"prepare_{m.tag}" if m.tier in (2, 3) else "nullptr"
         jk32 = f"launch_jk32_{m.tag}" if m.mixed else "nullptr"
         out.append(f"    {{{la}, {lb}, {lc}, {ld}, {m.tier}, launch_jk_{m.tag}, launch_eri_{m.tag}, {p1}, {prep}, {jk32}, {m.block}, "
                    f"{m.vrr_flops}.0, {m.p2_flops}.0, {m.n_hrr}, {m.peak_live}, {m.scratch_slots}, {m.chunks}}},")

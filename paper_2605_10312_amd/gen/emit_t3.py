@@ -262,6 +262,61 @@ def build_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None, bundle=BUNDLE)
                     n_real)
 
 
+WAVE = 64               # ops per group of the wave-cooperative variant: one op per lane
+WAVE_LDS_MAX = 65536    # bytes of LDS one workgroup of that variant may take
+
+
+@dataclasses.dataclass
+class WaveTables:
+    """The op tables regrouped 64 ops a group for the wave-cooperative
+    variant (one wavefront per quartet, its slots in LDS, lane j running op
+    j of every group).  Operand fields that the HBM form marks absent name
+    the zero slot Z = nslots; padding ops write the sink slot nslots + 1 and
+    read Z (transform padding reads coefficient 0)."""
+    t: T3Tables
+    ops: list
+    zero: int
+    sink: int
+    lds_doubles: int     # slots, Z, sink, coefficients, six D blocks
+    lds_bytes: int       # lds_doubles * 8 plus the uint16 output-slot map
+    maxblk: int
+
+
+def wave_layout(ls, t):
+    na, nb, nc, nd = (nsph(x) for x in ls)
+    maxblk = max(na * nb, nc * nd, na * nc, nb * nc, na * nd, nb * nd)
+    nint = na * nb * nc * nd
+    doubles = t.nslots + 2 + max(len(t.coefs), 1) + 6 * maxblk
+    return maxblk, doubles, doubles * 8 + ((2 * nint + 15) // 16) * 16
+
+
+def build_wave_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None) -> WaveTables:
+    ls = (la, lb, lc, ld)
+    t = build_tables(la, lb, lc, ld, rule, schedulers, bundle=WAVE)
+    Z, SINK = t.nslots, t.nslots + 1
+    ops = []
+    words = t.ops
+    for g0 in range(0, len(words) // 8, WAVE):
+        first = words[8 * g0] & 15
+        lin = first in (OP_LIN, OP_LIN_ACC)
+        for k in range(g0, g0 + WAVE):
+            w = list(words[8 * k:8 * k + 8])
+            if w[0] == 0:
+                w = [0, SINK, Z, Z, Z] + ([0, 0, 0] if lin else [Z, Z, Z])
+            elif lin:
+                w = w[:2] + [Z if x == NONE else x for x in w[2:5]] + w[5:]
+            else:
+                w = w[:2] + [Z if x == NONE else x for x in w[2:]]
+            ops.extend(w)
+    maxblk, doubles, nbytes = wave_layout(ls, t)
+    return WaveTables(t, ops, Z, SINK, doubles, nbytes, maxblk)
+
+
+def wave_fits(la, lb, lc, ld, rule="ket_zyx") -> bool:
+    t = build_tables(la, lb, lc, ld, rule, bundle=WAVE)
+    return wave_layout((la, lb, lc, ld), t)[2] <= WAVE_LDS_MAX
+
+
 def _u16_lines(vals, per=24):
     out = []
     for k in range(0, len(vals), per):
@@ -269,19 +324,32 @@ def _u16_lines(vals, per=24):
     return out
 
 
-def emit_class_t3(la, lb, lc, ld, rule="ket_zyx", schedulers=None, block=64):
+def emit_class_t3(la, lb, lc, ld, rule="ket_zyx", schedulers=None, block=64, wave="auto"):
     """Host-side tables plus the launchers that hand them to the generic
-    HBM-scratch kernels; no device code is generated for the class."""
+    kernels; no device code is generated for the class.  wave: True for the
+    wave-cooperative LDS variant (tier 3), False for the lane-per-quartet
+    HBM-scratch variant (tier 2), "auto" for the LDS variant wherever its
+    slots fit WAVE_LDS_MAX."""
     ls = (la, lb, lc, ld)
     tag = tag_of(ls)
-    t = build_tables(la, lb, lc, ld, rule, schedulers)
+    wt = None
+    if wave:
+        wt = build_wave_tables(la, lb, lc, ld, rule, schedulers)
+        if wave == "auto" and wt.lds_bytes > WAVE_LDS_MAX:
+            wt = None
+    t = wt.t if wt else build_tables(la, lb, lc, ld, rule, schedulers)
+    words = wt.ops if wt else t.ops
+    tier = 3 if wt else 2
     na, nb, nc, nd = (nsph(x) for x in ls)
-    out = [f"// Generated: class ({la}{lb}|{lc}{ld}) for the HBM-scratch tier, axis rule {rule},",
+    what = (f"the wave-cooperative LDS tier ({wt.lds_bytes} bytes of LDS per quartet)" if wt
+            else "the HBM-scratch tier")
+    out = [f"// Generated: class ({la}{lb}|{lc}{ld}) for {what}, axis rule {rule},",
            f"// VRR order '{t.scheduler}' (PeakLive {t.peak_live}), {t.n_vrr} per-primitive ops,",
-           f"// {t.n_p2} Phase-2 ops, {t.nslots} slots per lane, {len(t.outslots)} spherical integrals.",
+           f"// {t.n_p2} Phase-2 ops, {t.nslots} slots per {'quartet' if wt else 'lane'}, "
+           f"{len(t.outslots)} spherical integrals.",
            '#include "hgp_t3.h"', "", "#if !defined(__HIP_DEVICE_COMPILE__)", "namespace hgp {", "namespace {", ""]
     out.append(f"const uint16_t ops_{tag}[] = {{")
-    out.extend(_u16_lines(t.ops))
+    out.extend(_u16_lines(words))
     out.append("};")
     out.append(f"const uint16_t outslots_{tag}[] = {{")
     out.extend(_u16_lines(t.outslots))
@@ -290,16 +358,19 @@ def emit_class_t3(la, lb, lc, ld, rule="ket_zyx", schedulers=None, block=64):
     for k in range(0, max(len(t.coefs), 1), 4):
         out.append("    " + ", ".join(repr(c) for c in (t.coefs[k:k + 4] or [0.0])) + ",")
     out.append("};")
+    wave_fields = f", {wt.maxblk}, {wt.lds_bytes}" if wt else ""
     out.append(f"T3Class t3_{tag} = {{{la}, {lb}, {lc}, {ld}, {t.L}, {na}, {nb}, {nc}, {nd}, {t.nslots}, {t.n_hrr}, "
-               f"{t.acc0}, {t.n_vrr}, {t.n_p2}, ops_{tag}, {max(len(t.coefs), 1)}, coefs_{tag}, outslots_{tag}, {block}}};")
+               f"{t.acc0}, {t.n_vrr}, {t.n_p2}, ops_{tag}, {max(len(t.coefs), 1)}, coefs_{tag}, outslots_{tag}, {block}"
+               f"{wave_fields}}};")
     out.append("")
     out.append("}  // namespace")
+    pre = "t3w" if wt else "t3"
     out.append(f"int prepare_{tag}() {{ return t3_prepare(t3_{tag}); }}")
-    out.append(f"void launch_jk_{tag}(const JKArgs &a, hipStream_t s) {{ t3_launch_jk(t3_{tag}, a, s); }}")
-    out.append(f"void launch_eri_{tag}(const EriArgs &a, hipStream_t s) {{ t3_launch_eri(t3_{tag}, a, s); }}")
+    out.append(f"void launch_jk_{tag}(const JKArgs &a, hipStream_t s) {{ {pre}_launch_jk(t3_{tag}, a, s); }}")
+    out.append(f"void launch_eri_{tag}(const EriArgs &a, hipStream_t s) {{ {pre}_launch_eri(t3_{tag}, a, s); }}")
     out.append("}  // namespace hgp")
     out.append("#endif")
-    meta = ClassMeta(ls, tag, 2, block, t.n_vrr, t.vrr_flops, t.n_hrr, t.peak_live, t.scheduler, t.p2_flops,
+    meta = ClassMeta(ls, tag, tier, block, t.n_vrr, t.vrr_flops, t.n_hrr, t.peak_live, t.scheduler, t.p2_flops,
                      len(t.outslots), rule, scratch_slots=t.nslots, chunks=1, recompute=1.0, cap=0, digest="",
                      reduce="none", loop="")
     return "\n".join(out) + "\n", meta

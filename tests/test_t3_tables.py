@@ -23,7 +23,9 @@ def _norm(a, l):
     return (2 * a / np.pi) ** 0.75 * (4 * a) ** (0.5 * l) / np.sqrt(df)
 
 
-def run_tables(t, ls, centers, exps):
+def run_tables(t, ls, centers, exps, ops=None, K=None, zero=None):
+    """Run tables t on the quartets; ops/K/zero: the wave-cooperative form
+    (its own words, groups of K ops, absent operands naming slot zero)."""
     n = centers.shape[0]
     A, B, C, D = (centers[:, k, :].T for k in range(4))          # [3, n]
     a, b, c, d = (exps[:, k] for k in range(4))
@@ -37,19 +39,20 @@ def run_tables(t, ls, centers, exps):
     PQ = P - Q
     T = zeta * rz * np.sum(PQ ** 2, 0)
     base = Kab * Kcd / np.sqrt(ze)
-    sb = np.zeros((t.nslots, n))
+    sb = np.zeros((t.nslots + 2, n))
     for m in range(t.L + 1):
         sb[m] = base * hyp1f1(m + 0.5, m + 1.5, -T) / (2 * m + 1)
     PA, QC, WP, WQ = P - A, Q - C, -rz * PQ, re * PQ
     o2z, o2e = 0.5 / zeta, 0.5 / eta
     AB, CD = A - B, C - D
-    ops = np.array(t.ops, dtype=np.int64).reshape(-1, 8)
+    ops = np.array(t.ops if ops is None else ops, dtype=np.int64).reshape(-1, 8)
     coefs = np.array(t.coefs)
-    none = emit_t3.NONE
-    K = emit_t3.BUNDLE
+    none = emit_t3.NONE if zero is None else zero
+    K = emit_t3.BUNDLE if K is None else K
     assert len(ops) % K == 0 and t.n_vrr % K == 0
 
     def val(s):
+        assert s < t.nslots or s == none
         return sb[s] if s != none else sb[0] * 0.0
 
     # a group reads all its operands before it writes anything, as on the GPU
@@ -61,6 +64,7 @@ def run_tables(t, ls, centers, exps):
         for w, r in zip(grp, reads):
             code, axis = w[0] & 15, (w[0] >> 4) & 3
             dst = w[1]
+            assert dst < t.nslots
             if code == emit_t3.OP_ACC:
                 sb[dst] = r[5] + r[0]
             elif code in (emit_t3.OP_VRR_BRA, emit_t3.OP_VRR_KET):
@@ -99,6 +103,39 @@ def test_t3_tables_match_oracle(ls, n):
     print(f"{ls}: {t.nslots} slots, {t.n_vrr} + {t.n_p2} ops, max |I| {np.abs(ref_ld).max():.2e}, "
           f"max |tables - oracle_ld| {err:.2e} (oracle {e_orc:.2e})")
     assert err <= 1e-12 + 8 * e_orc
+
+
+@pytest.mark.parametrize("ls,n", [((1, 0, 1, 0), 4), ((2, 2, 1, 1), 3), ((3, 2, 1, 0), 3), ((3, 3, 2, 1), 2),
+                                  ((4, 1, 3, 0), 2)])
+def test_wave_tables_match_oracle(ls, n):
+    """The wave-cooperative form: 64-op groups, absent operands naming the
+    zero slot, padding ops writing the sink slot and reading only zeros."""
+    w = emit_t3.build_wave_tables(*ls)
+    t = w.t
+    assert w.zero == t.nslots and w.sink == t.nslots + 1
+    words = np.array(w.ops, dtype=np.int64).reshape(-1, 8)
+    assert len(words) == t.n_vrr + t.n_p2 and len(words) % emit_t3.WAVE == 0
+    pad = words[words[:, 0] == 0]
+    assert np.all(pad[:, 1] == w.sink) and np.all(pad[:, 2:5] == w.zero)
+    assert not np.any(words[words[:, 0] != 0][:, 1] >= t.nslots)           # real ops never write Z or the sink
+    assert not np.any(words[:, 2:5] == emit_t3.NONE)
+    for g0 in range(0, len(words), emit_t3.WAVE):                            # one op class per group, lane 0 real
+        assert words[g0, 0] != 0
+    cen, ex = workloads.prim_quartets(max(ls), n, seed=78, box=1.0, exp_range=(0.2, 2.0))
+    got = run_tables(t, ls, cen, ex, ops=w.ops, K=emit_t3.WAVE, zero=w.zero)
+    ref_ld = oracle.eri_prim_quartets(ls, cen, ex, precision="long double")
+    e_orc = np.abs(oracle.eri_prim_quartets(ls, cen, ex) - ref_ld).max()
+    err = np.abs(got - ref_ld).max()
+    print(f"{ls}: {t.nslots} slots, LDS {w.lds_bytes} B, max |tables - oracle_ld| {err:.2e} (oracle {e_orc:.2e})")
+    assert err <= 1e-12 + 8 * e_orc
+
+
+def test_wave_routing():
+    """Every l = 3 class that leaves the register and staged tiers fits the
+    LDS variant; (gg|gg) does not."""
+    assert emit_t3.wave_fits(3, 3, 3, 3)
+    assert emit_t3.wave_fits(4, 3, 3, 2)
+    assert not emit_t3.wave_fits(4, 4, 4, 4)
 
 
 def test_t3_slot_packing():
