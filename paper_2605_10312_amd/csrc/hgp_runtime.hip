@@ -81,6 +81,7 @@ int64_t staged_batch(const ClassKernels &k, int64_t doubles)
 int64_t staged_need(const ClassKernels &k, int64_t n)
 {
     if (k.tier == 0 || k.tier == 3 || n <= 0) return 0;      // no HBM buffer
+    if (k.max_batch > 0 && n < T3G_LANE_MIN) n = std::min(n, (int64_t)k.max_batch);   // wave form only
     const int64_t want = (int64_t)k.scratch_slots * (((n + 63) / 64) * 64);
     const int64_t floor64 = (int64_t)k.scratch_slots * 64;
     return std::max(floor64, std::min(want, k.tier == 2 ? T3_SCRATCH_MAX_DOUBLES : SCRATCH_MAX_DOUBLES));
@@ -91,7 +92,8 @@ hgp_status prepare_class(const ClassKernels &k)
 {
     const int e = k.prepare ? k.prepare() : 0;
     if (e != 0)
-        return fail(HGP_E_DEVICE, std::string("uploading the op tables of an HBM-scratch class failed: ") +
+        return fail(HGP_E_DEVICE, std::string("preparing the op tables of an HBM-scratch or wave-LDS class failed "
+                                              "(upload, or LDS beyond the device's per-block limit): ") +
                                       hipGetErrorString((hipError_t)e));
     return HGP_OK;
 }

@@ -30,14 +30,19 @@ struct T3Class {
     // wave-cooperative LDS variant only (0 for the HBM-scratch variant):
     int maxblk;                  // largest of the six D/J/K blocks of a quartet
     int lds_bytes;               // LDS per workgroup (slots, zero and sink slots, coefficients, D blocks, outslots)
+    int gslots;                  // 1: the slots (nslots + 2 per quartet) live in the scratch buffer, not in LDS
+    const T3Class *lane;         // gslots: the lane-per-quartet tables, run for batches of T3G_LANE_MIN or more
 };
 
-// Wave-cooperative LDS variant (tier 3): the same tables regrouped 64 ops a
+// Wave-cooperative variant (tier 3): the same tables regrouped 64 ops a
 // group; one wavefront per quartet holds every slot in LDS and lane j runs op
 // j of each group.  Absent operands name the zero slot nslots; padding ops
-// write the sink slot nslots + 1.
+// write the sink slot nslots + 1.  A class whose slots do not fit in LDS
+// (gslots = 1, tier 2) keeps them in a per-quartet region of the scratch
+// buffer instead, quartet i of a batch at scratch[i * (nslots + 2)].
 constexpr int T3W_GROUP = 64;
 constexpr int T3W_PREFETCH = 1;  // groups whose ops are in flight ahead of the running one
+constexpr int T3G_CHUNK = 1024;  // quartets per launch of the wave form with its slots in the buffer
 
 // 0 (hipSuccess) once the class's tables are on the current device (uploaded
 // on first call), else the hipError_t of the step that failed.

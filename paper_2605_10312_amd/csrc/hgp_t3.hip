@@ -312,11 +312,22 @@ struct T3WParams {
     int L, na, nb, nc, nd, n_hrr, acc0, n_vrr, n_p2, nslots, ncoef, maxblk, nint;
 };
 
+// G = false: slots in LDS; a compiler-level barrier suffices.  G = true: slots
+// in the quartet's region of global memory; a workgroup-scope release and
+// acquire (the workgroup is this one wave) make each group's stores visible
+// to the next group's loads.
+template <bool G>
 __device__ __forceinline__ void t3w_sync()
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (G) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 }
 
 // Lane m <= L writes base * F_m(T) to slot m.  Below T = 36 each order is its
@@ -410,6 +421,7 @@ __device__ __forceinline__ void t3w_lin_group(const uint4 o, const double *__res
 }
 
 // The quartet's integrals into their output slots (LDS), as t3_quartet.
+template <bool G>
 __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__restrict__ ops, const PairInfo &pb,
                             const PairGeo &gb, const PairInfo &pk, const PairGeo &gk,
                             const PrimPair *__restrict__ prims, const double *__restrict__ boys, double *__restrict__ S,
@@ -417,7 +429,7 @@ __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__r
 {
     for (int k = lane; k < c.n_hrr; k += T3W_GROUP) S[c.acc0 + k] = 0.0;
     if (lane == 0) S[c.nslots] = 0.0;                       // the zero slot
-    t3w_sync();
+    t3w_sync<G>();
     const uint4 *__restrict__ myops = ops + lane;
     const PrimPair *__restrict__ pbp = prims + pb.prim_off;
     const PrimPair *__restrict__ pkp = prims + pk.prim_off;
@@ -439,7 +451,7 @@ __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__r
             q.WQx = q.re * PQx; q.WQy = q.re * PQy; q.WQz = q.re * PQz;
             const double T = b.zeta * q.rz * (PQx * PQx + PQy * PQy + PQz * PQz);
             t3w_boys(T, c.L, boys, b.k * e.k * hgp_rsqrt(ze), S, lane);
-            t3w_sync();
+            t3w_sync<G>();
             // groups of 64 ops; the next group's op is loaded while this one runs
             // (the table ends in a padding group)
             const int ng = c.n_vrr / T3W_GROUP;
@@ -451,7 +463,7 @@ __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__r
                     t3w_acc_group(o, S);
                 else
                     t3w_vrr_group(o, q, S);
-                t3w_sync();
+                t3w_sync<G>();
             }
         }
     }
@@ -468,23 +480,26 @@ __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__r
             t3w_hrr_group(o, h, S);
         else
             t3w_lin_group(o, C, S);
-        t3w_sync();
+        t3w_sync<G>();
     }
 }
 
-// LDS of one workgroup: S (slots, Z, sink), C (coefficients), Db (six D
-// blocks), O (output slot of integral (mu, nu, lam, sig), row-major).
+// LDS of one workgroup: S (slots, Z, sink; in global memory when G),
+// C (coefficients), Db (six D blocks), O (output slot of integral
+// (mu, nu, lam, sig), row-major).
 struct T3WLds {
     double *S, *C, *Db;
     uint16_t *O;
 };
 
-__device__ __forceinline__ T3WLds t3w_lds(const T3WParams &c, double *base, const double *__restrict__ coefs,
-                                          const uint16_t *__restrict__ outslots, int lane)
+template <bool G>
+__device__ __forceinline__ T3WLds t3w_lds(const T3WParams &c, double *base, double *gslots,
+                                          const double *__restrict__ coefs, const uint16_t *__restrict__ outslots,
+                                          int lane)
 {
     T3WLds l;
-    l.S = base;
-    l.C = base + c.nslots + 2;
+    l.S = G ? gslots : base;
+    l.C = G ? base : base + c.nslots + 2;
     l.Db = l.C + c.ncoef;
     l.O = (uint16_t *)(l.Db + 6 * c.maxblk);
     for (int k = lane; k < c.ncoef; k += T3W_GROUP) l.C[k] = coefs[k];
@@ -494,6 +509,8 @@ __device__ __forceinline__ T3WLds t3w_lds(const T3WParams &c, double *base, cons
 
 extern __shared__ double t3w_smem[];
 
+// G: the quartet's slots are a.scratch[blockIdx.x * (nslots + 2) ...].
+template <bool G>
 __global__ __launch_bounds__(64) void t3w_jk_kernel(T3WParams c, const uint4 *__restrict__ ops,
                                                     const double *__restrict__ coefs,
                                                     const uint16_t *__restrict__ outslots, JKArgs a)
@@ -501,7 +518,8 @@ __global__ __launch_bounds__(64) void t3w_jk_kernel(T3WParams c, const uint4 *__
     const int64_t i = blockIdx.x;
     if (i >= a.nq) return;
     const int lane = threadIdx.x;
-    const T3WLds l = t3w_lds(c, t3w_smem, coefs, outslots, lane);
+    const T3WLds l = t3w_lds<G>(c, t3w_smem, G ? a.scratch + (size_t)i * (size_t)(c.nslots + 2) : nullptr, coefs,
+                                outslots, lane);
     const int2 pq = a.quartets[i];
     const PairInfo pb = a.pairs[pq.x], pk = a.pairs[pq.y];
     const PairGeo gb = a.geo[pq.x], gk = a.geo[pq.y];
@@ -520,7 +538,7 @@ __global__ __launch_bounds__(64) void t3w_jk_kernel(T3WParams c, const uint4 *__
         for (int k = lane; k < nb * nc; k += T3W_GROUP) Dbc[k] = D[(fb + k / nc) * N + fc + k % nc];
         for (int k = lane; k < na * nc; k += T3W_GROUP) Dac[k] = D[(fa + k / nc) * N + fc + k % nc];
     }
-    t3w_quartet(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, lane);
+    t3w_quartet<G>(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, lane);
     const double *__restrict__ S = l.S;
     const uint16_t *__restrict__ O = l.O;
     auto I = [&](int mu, int nu, int lam, int sig) -> double {
@@ -578,6 +596,7 @@ __global__ __launch_bounds__(64) void t3w_jk_kernel(T3WParams c, const uint4 *__
     }
 }
 
+template <bool G>
 __global__ __launch_bounds__(64) void t3w_eri_kernel(T3WParams c, const uint4 *__restrict__ ops,
                                                      const double *__restrict__ coefs,
                                                      const uint16_t *__restrict__ outslots, EriArgs a)
@@ -585,11 +604,12 @@ __global__ __launch_bounds__(64) void t3w_eri_kernel(T3WParams c, const uint4 *_
     const int64_t i = blockIdx.x;
     if (i >= a.ntask) return;
     const int lane = threadIdx.x;
-    const T3WLds l = t3w_lds(c, t3w_smem, coefs, outslots, lane);
+    const T3WLds l = t3w_lds<G>(c, t3w_smem, G ? a.scratch + (size_t)i * (size_t)(c.nslots + 2) : nullptr, coefs,
+                                outslots, lane);
     const EriTask t = a.tasks[i];
     const PairInfo pb = a.pairs[t.bra], pk = a.pairs[t.ket];
     const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];
-    t3w_quartet(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, lane);
+    t3w_quartet<G>(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, lane);
     const int na = c.na, nb = c.nb, nc = c.nc, nd = c.nd;
     if (a.mode == 1) {                       // Schwarz factor of a diagonal quartet
         double m = 0.0;
@@ -656,8 +676,36 @@ T3Params params(const T3Class &c)
 
 }  // namespace
 
+// Wave-variant classes: the workgroup's LDS must fit the device's per-block
+// limit (160 KB on gfx950); launches above 64 KB need the kernels' dynamic
+// LDS limit raised once per device.
 int t3_prepare(const T3Class &c)
 {
+    if (c.lane) {
+        const int e = t3_prepare(*c.lane);
+        if (e != 0) return e;
+    }
+    if (c.lds_bytes > 0) {
+        int dev = 0, maxlds = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) return (int)e;
+        if (c.lds_bytes > maxlds) return (int)hipErrorInvalidConfiguration;
+        if (c.lds_bytes > 65536) {
+            static std::mutex mu;
+            static bool raised[64] = {};
+            std::lock_guard<std::mutex> lock(mu);
+            if (dev < 0 || dev >= 64) return (int)hipErrorInvalidDevice;
+            if (!raised[dev]) {
+                if ((e = hipFuncSetAttribute((const void *)t3w_jk_kernel<false>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, maxlds)) != hipSuccess ||
+                    (e = hipFuncSetAttribute((const void *)t3w_eri_kernel<false>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, maxlds)) != hipSuccess)
+                    return (int)e;
+                raised[dev] = true;
+            }
+        }
+    }
     T3Dev d;
     return (int)t3_device_tables(c, &d);
 }
@@ -680,21 +728,50 @@ T3WParams wparams(const T3Class &c)
 }
 }  // namespace
 
-// One workgroup per quartet; the runtime keeps a launch under 2^26 quartets.
+// One workgroup per quartet; the runtime keeps a launch under 2^26 quartets
+// (and, for the global-slot variant, within the batch its buffer holds).
 void t3w_launch_jk(const T3Class &c, const JKArgs &a, hipStream_t s)
 {
     T3Dev d;
     if (a.nq <= 0 || c.lds_bytes <= 0 || t3_device_tables(c, &d) != hipSuccess) return;
-    hipLaunchKernelGGL(t3w_jk_kernel, dim3((unsigned)a.nq), dim3(T3W_GROUP), (unsigned)c.lds_bytes, s, wparams(c),
-                       d.ops, d.coefs, d.outslots, a);
+    if (c.gslots) {
+        if (a.nq >= T3G_LANE_MIN && c.lane) {      // large batch: one lane per quartet, stride a.stride
+            t3_launch_jk(*c.lane, a, s);
+            return;
+        }
+        // launches of at most T3G_CHUNK quartets, each reusing the first regions of the buffer
+        for (int64_t q0 = 0; q0 < a.nq; q0 += T3G_CHUNK) {
+            JKArgs b = a;
+            b.quartets = a.quartets + q0;
+            b.nq = std::min<int64_t>(T3G_CHUNK, a.nq - q0);
+            hipLaunchKernelGGL(t3w_jk_kernel<true>, dim3((unsigned)b.nq), dim3(T3W_GROUP), (unsigned)c.lds_bytes, s,
+                               wparams(c), d.ops, d.coefs, d.outslots, b);
+        }
+    } else
+        hipLaunchKernelGGL(t3w_jk_kernel<false>, dim3((unsigned)a.nq), dim3(T3W_GROUP), (unsigned)c.lds_bytes, s,
+                           wparams(c), d.ops, d.coefs, d.outslots, a);
 }
 
 void t3w_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s)
 {
     T3Dev d;
     if (a.ntask <= 0 || c.lds_bytes <= 0 || t3_device_tables(c, &d) != hipSuccess) return;
-    hipLaunchKernelGGL(t3w_eri_kernel, dim3((unsigned)a.ntask), dim3(T3W_GROUP), (unsigned)c.lds_bytes, s,
-                       wparams(c), d.ops, d.coefs, d.outslots, a);
+    if (c.gslots) {
+        if (a.ntask >= T3G_LANE_MIN && c.lane) {
+            t3_launch_eri(*c.lane, a, s);
+            return;
+        }
+        for (int64_t q0 = 0; q0 < a.ntask; q0 += T3G_CHUNK) {
+            EriArgs b = a;
+            b.tasks = a.tasks + q0;
+            b.ntask = std::min<int64_t>(T3G_CHUNK, a.ntask - q0);
+            if (a.mode == 1) b.out = a.out + q0;
+            hipLaunchKernelGGL(t3w_eri_kernel<true>, dim3((unsigned)b.ntask), dim3(T3W_GROUP), (unsigned)c.lds_bytes,
+                               s, wparams(c), d.ops, d.coefs, d.outslots, b);
+        }
+    } else
+        hipLaunchKernelGGL(t3w_eri_kernel<false>, dim3((unsigned)a.ntask), dim3(T3W_GROUP), (unsigned)c.lds_bytes, s,
+                           wparams(c), d.ops, d.coefs, d.outslots, a);
 }
 
 void t3_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s)

@@ -104,6 +104,10 @@ constexpr int64_t SCRATCH_MAX_DOUBLES = (int64_t)1 << 29;
 // doubles per (gg|gg) quartet), so it may take up to 16 GiB to keep enough
 // quartets in flight; slot offsets stay below 2^32.
 constexpr int64_t T3_SCRATCH_MAX_DOUBLES = (int64_t)1 << 31;
+// HBM-scratch classes with both a wave-cooperative (slots in the buffer, at
+// most max_batch quartets per launch) and a lane-per-quartet form: batches of
+// at least this many quartets take the lane form, smaller ones the wave form.
+constexpr int64_t T3G_LANE_MIN = 65536;
 
 // Launchers run one lane per work item (nq or ntask): the register tier's
 // whole evaluation, or a staged class's Phase 2 + digestion; p1 launchers run
@@ -116,7 +120,8 @@ typedef int (*prepare_fn)();
 
 struct ClassKernels {
     int la, lb, lc, ld;
-    int tier;               // 0 register, 1 staged (chunked Phase 1 + Phase 2), 2 HBM scratch (op tables)
+    int tier;               // 0 register, 1 staged (chunked Phase 1 + Phase 2), 2 HBM scratch (op tables),
+                            // 3 wave-cooperative LDS (op tables)
     launch_jk_fn jk;
     launch_eri_fn eri;
     launch_p1_fn p1;        // staged tier only (nullptr otherwise)
@@ -129,6 +134,7 @@ struct ClassKernels {
     int peak_live;
     int scratch_slots;      // doubles of buffer per quartet (0 for the register tier)
     int chunks;             // Phase-1 target chunks
+    int max_batch;          // > 0: wave-cooperative launches of at most this many quartets (see T3G_LANE_MIN)
 };
 
 }  // namespace hgp

@@ -46,6 +46,7 @@ class ClassMeta:
     reduce: str = "segmented"
     loop: str = "late"
     mixed: bool = False
+    max_batch: int = 0      # quartets per batch at most (0: no limit beyond the buffer)
 
 
 def tag_of(ls):
@@ -494,7 +495,8 @@ def emit_table(metas):
         prep = f"prepare_{m.tag}" if m.tier in (2, 3) else "nullptr"
         jk32 = f"launch_jk32_{m.tag}" if m.mixed else "nullptr"
         out.append(f"    {{{la}, {lb}, {lc}, {ld}, {m.tier}, launch_jk_{m.tag}, launch_eri_{m.tag}, {p1}, {prep}, {jk32}, {m.block}, "
-                   f"{m.vrr_flops}.0, {m.p2_flops}.0, {m.n_hrr}, {m.peak_live}, {m.scratch_slots}, {m.chunks}}},")
+                   f"{m.vrr_flops}.0, {m.p2_flops}.0, {m.n_hrr}, {m.peak_live}, {m.scratch_slots}, {m.chunks}, "
+                   f"{m.max_batch}}},")
     out.append("};")
     out.append(f"extern const int g_num_classes = {len(metas)};")
     out.append("")

@@ -263,7 +263,9 @@ def build_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None, bundle=BUNDLE)
 
 
 WAVE = 64               # ops per group of the wave-cooperative variant: one op per lane
-WAVE_LDS_MAX = 65536    # bytes of LDS one workgroup of that variant may take
+WAVE_LDS_MAX = 163840   # bytes of LDS one workgroup of that variant may take (gfx950: 160 KB per CU)
+GSLOT_MAX_BATCH = 1024  # quartets per launch when the slots live in the scratch buffer (~190 MB for (gg|gg));
+                        # batches of T3G_LANE_MIN (csrc/hgp_types.h) or more run the lane-per-quartet tables
 
 
 @dataclasses.dataclass
@@ -282,11 +284,12 @@ class WaveTables:
     maxblk: int
 
 
-def wave_layout(ls, t):
+def wave_layout(ls, t, gslots=False):
+    """(maxblk, LDS doubles, LDS bytes); gslots: the slots are not in LDS."""
     na, nb, nc, nd = (nsph(x) for x in ls)
     maxblk = max(na * nb, nc * nd, na * nc, nb * nc, na * nd, nb * nd)
     nint = na * nb * nc * nd
-    doubles = t.nslots + 2 + max(len(t.coefs), 1) + 6 * maxblk
+    doubles = (0 if gslots else t.nslots + 2) + max(len(t.coefs), 1) + 6 * maxblk
     return maxblk, doubles, doubles * 8 + ((2 * nint + 15) // 16) * 16
 
 
@@ -326,43 +329,65 @@ def _u16_lines(vals, per=24):
 
 def emit_class_t3(la, lb, lc, ld, rule="ket_zyx", schedulers=None, block=64, wave="auto"):
     """Host-side tables plus the launchers that hand them to the generic
-    kernels; no device code is generated for the class.  wave: True for the
-    wave-cooperative LDS variant (tier 3), False for the lane-per-quartet
-    HBM-scratch variant (tier 2), "auto" for the LDS variant wherever its
-    slots fit WAVE_LDS_MAX."""
+    kernels; no device code is generated for the class.  wave: "lds" for the
+    wave-cooperative LDS variant (tier 3), "global" for the wave-cooperative
+    variant with its slots in the scratch buffer (tier 2), "lane" for the
+    lane-per-quartet HBM-scratch variant (tier 2), "auto" for "lds" wherever
+    the slots fit WAVE_LDS_MAX and "global" elsewhere."""
     ls = (la, lb, lc, ld)
     tag = tag_of(ls)
+    if wave not in ("auto", "lds", "global", "lane"):
+        raise ValueError(f"unknown variant {wave!r}")
     wt = None
-    if wave:
+    gslots = False
+    if wave != "lane":
         wt = build_wave_tables(la, lb, lc, ld, rule, schedulers)
-        if wave == "auto" and wt.lds_bytes > WAVE_LDS_MAX:
-            wt = None
+        if wave == "global" or (wave == "auto" and wt.lds_bytes > WAVE_LDS_MAX):
+            gslots = True
+            wt.maxblk, wt.lds_doubles, wt.lds_bytes = wave_layout(ls, wt.t, gslots=True)
     t = wt.t if wt else build_tables(la, lb, lc, ld, rule, schedulers)
     words = wt.ops if wt else t.ops
-    tier = 3 if wt else 2
+    tier = 3 if wt and not gslots else 2
     na, nb, nc, nd = (nsph(x) for x in ls)
-    what = (f"the wave-cooperative LDS tier ({wt.lds_bytes} bytes of LDS per quartet)" if wt
-            else "the HBM-scratch tier")
+    if wt and not gslots:
+        what = f"the wave-cooperative LDS tier ({wt.lds_bytes} bytes of LDS per quartet)"
+    elif wt:
+        what = (f"the HBM-scratch tier, wave-cooperative with the slots in the scratch buffer "
+                f"({wt.lds_bytes} bytes of LDS per quartet)")
+    else:
+        what = "the HBM-scratch tier, one lane per quartet"
     out = [f"// Generated: class ({la}{lb}|{lc}{ld}) for {what}, axis rule {rule},",
            f"// VRR order '{t.scheduler}' (PeakLive {t.peak_live}), {t.n_vrr} per-primitive ops,",
            f"// {t.n_p2} Phase-2 ops, {t.nslots} slots per {'quartet' if wt else 'lane'}, "
            f"{len(t.outslots)} spherical integrals.",
            '#include "hgp_t3.h"', "", "#if !defined(__HIP_DEVICE_COMPILE__)", "namespace hgp {", "namespace {", ""]
-    out.append(f"const uint16_t ops_{tag}[] = {{")
-    out.extend(_u16_lines(words))
-    out.append("};")
-    out.append(f"const uint16_t outslots_{tag}[] = {{")
-    out.extend(_u16_lines(t.outslots))
-    out.append("};")
-    out.append(f"const double coefs_{tag}[] = {{")
-    for k in range(0, max(len(t.coefs), 1), 4):
-        out.append("    " + ", ".join(repr(c) for c in (t.coefs[k:k + 4] or [0.0])) + ",")
-    out.append("};")
-    wave_fields = f", {wt.maxblk}, {wt.lds_bytes}" if wt else ""
-    out.append(f"T3Class t3_{tag} = {{{la}, {lb}, {lc}, {ld}, {t.L}, {na}, {nb}, {nc}, {nd}, {t.nslots}, {t.n_hrr}, "
-               f"{t.acc0}, {t.n_vrr}, {t.n_p2}, ops_{tag}, {max(len(t.coefs), 1)}, coefs_{tag}, outslots_{tag}, {block}"
-               f"{wave_fields}}};")
-    out.append("")
+    def table(name, tt, ws, extra):
+        lines = [f"const uint16_t ops_{name}[] = {{"]
+        lines.extend(_u16_lines(ws))
+        lines.append("};")
+        lines.append(f"const uint16_t outslots_{name}[] = {{")
+        lines.extend(_u16_lines(tt.outslots))
+        lines.append("};")
+        lines.append(f"const double coefs_{name}[] = {{")
+        for k in range(0, max(len(tt.coefs), 1), 4):
+            lines.append("    " + ", ".join(repr(c) for c in (tt.coefs[k:k + 4] or [0.0])) + ",")
+        lines.append("};")
+        lines.append(f"T3Class t3_{name} = {{{la}, {lb}, {lc}, {ld}, {tt.L}, {na}, {nb}, {nc}, {nd}, {tt.nslots}, "
+                     f"{tt.n_hrr}, {tt.acc0}, {tt.n_vrr}, {tt.n_p2}, ops_{name}, {max(len(tt.coefs), 1)}, "
+                     f"coefs_{name}, outslots_{name}, {block}{extra}}};")
+        lines.append("")
+        return lines
+
+    lane_t = None
+    if gslots:
+        # large batches run the lane-per-quartet kernel on its own tables
+        lane_t = build_tables(la, lb, lc, ld, rule, schedulers)
+        out.extend(table(f"{tag}_lane", lane_t, lane_t.ops, ""))
+    if wt:
+        extra = f", {wt.maxblk}, {wt.lds_bytes}, {1 if gslots else 0}" + (f", &t3_{tag}_lane" if gslots else "")
+    else:
+        extra = ""
+    out.extend(table(tag, t, words, extra))
     out.append("}  // namespace")
     pre = "t3w" if wt else "t3"
     out.append(f"int prepare_{tag}() {{ return t3_prepare(t3_{tag}); }}")
@@ -370,7 +395,9 @@ def emit_class_t3(la, lb, lc, ld, rule="ket_zyx", schedulers=None, block=64, wav
     out.append(f"void launch_eri_{tag}(const EriArgs &a, hipStream_t s) {{ {pre}_launch_eri(t3_{tag}, a, s); }}")
     out.append("}  // namespace hgp")
     out.append("#endif")
+    # the buffer holds, per quartet of a batch, either variant's slots
+    slots_per_quartet = max(t.nslots + 2, lane_t.nslots) if gslots else t.nslots
     meta = ClassMeta(ls, tag, tier, block, t.n_vrr, t.vrr_flops, t.n_hrr, t.peak_live, t.scheduler, t.p2_flops,
-                     len(t.outslots), rule, scratch_slots=t.nslots, chunks=1, recompute=1.0, cap=0, digest="",
-                     reduce="none", loop="")
+                     len(t.outslots), rule, scratch_slots=slots_per_quartet, chunks=1, recompute=1.0, cap=0,
+                     digest="", reduce="none", loop="", max_batch=GSLOT_MAX_BATCH if gslots else 0)
     return "\n".join(out) + "\n", meta

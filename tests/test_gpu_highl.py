@@ -66,7 +66,8 @@ def test_microbench_class_config_inputs(hgp, torch_cuda, l, n):
     assert np.all(e_gpu <= ERI_TOL + 8.0 * e_orc)
 
 
-@pytest.mark.parametrize("ls", [(3, 3, 3, 3), (4, 4, 4, 4), (4, 3, 2, 1), (1, 4, 0, 3), (2, 2, 4, 4), (3, 0, 3, 0)])
+@pytest.mark.parametrize("ls", [(3, 3, 3, 3), (4, 4, 4, 4), (4, 3, 2, 1), (1, 4, 0, 3), (2, 2, 4, 4), (3, 0, 3, 0),
+                                (4, 4, 4, 3), (3, 4, 3, 4), (4, 3, 3, 3)])
 def test_compact_high_l_quartets(hgp, torch_cuda, ls):
     """Compact quartets (1 A box, exponents [0.2, 2]) whose integrals are of
     order one, in canonical and non-canonical shell order."""
@@ -118,3 +119,31 @@ def test_high_l_jk(hgp, torch_cuda, lmax, tau):
     ej, ek = np.abs(J.cpu().numpy() - Jr).max(), np.abs(K.cpu().numpy() - Kr).max()
     print(f"lmax {lmax} tau {tau}: N {bw.nbf}, tiers {tiers}, |dJ| {ej:.2e} |dK| {ek:.2e}")
     assert ej <= JK_TOL and ek <= JK_TOL
+
+
+def test_gggg_large_batch_lane_form(hgp, torch_cuda):
+    """(gg|gg) has two forms: batches below 65536 quartets run one wavefront
+    per quartet with the slots in the scratch buffer, larger batches one lane
+    per quartet.  70 000 quartets take the lane form; a sample of them is
+    checked against the oracle, and the same sample run as a small batch
+    (wave form) must agree with it."""
+    torch = torch_cuda
+    n = 70000
+    cen, ex = workloads.prim_quartets(4, n, seed=93, box=1.0, exp_range=(0.2, 2.0))
+    ls = (4, 4, 4, 4)
+    out = torch.empty((n, 9, 9, 9, 9), dtype=torch.float64, device="cuda")
+    hgp.eri_prim_quartets(ls, torch.tensor(cen, device="cuda"), torch.tensor(ex, device="cuda"), out)
+    torch.cuda.synchronize()
+    pick = np.array([0, 1, 4097, 33333, 65535, 65536, n - 1])
+    big = out[torch.tensor(pick, device="cuda")].cpu().numpy()
+    del out
+    small = torch.empty((len(pick), 9, 9, 9, 9), dtype=torch.float64, device="cuda")
+    hgp.eri_prim_quartets(ls, torch.tensor(cen[pick], device="cuda"), torch.tensor(ex[pick], device="cuda"), small)
+    torch.cuda.synchronize()
+    small = small.cpu().numpy()
+    ref_ld = oracle.eri_prim_quartets(ls, cen[pick], ex[pick], precision="long double")
+    e_orc = np.abs(oracle.eri_prim_quartets(ls, cen[pick], ex[pick]) - ref_ld)
+    e_big, e_small = np.abs(big - ref_ld), np.abs(small - ref_ld)
+    print(f"(gg|gg) x {n}: lane form max |gpu-ld| {e_big.max():.3e}, wave form {e_small.max():.3e}, "
+          f"oracle {e_orc.max():.3e}")
+    assert np.all(e_big <= ERI_TOL + 8.0 * e_orc) and np.all(e_small <= ERI_TOL + 8.0 * e_orc)

@@ -131,11 +131,16 @@ def test_wave_tables_match_oracle(ls, n):
 
 
 def test_wave_routing():
-    """Every l = 3 class that leaves the register and staged tiers fits the
-    LDS variant; (gg|gg) does not."""
+    """Every class that leaves the register and staged tiers fits the LDS
+    variant (160 KB per workgroup) except (gg|gg)."""
     assert emit_t3.wave_fits(3, 3, 3, 3)
     assert emit_t3.wave_fits(4, 3, 3, 2)
-    assert not emit_t3.wave_fits(4, 4, 4, 4)
+    assert emit_t3.wave_fits(4, 4, 4, 3)
+    src, meta = emit_t3.emit_class_t3(4, 4, 4, 4)      # too large: slots in the scratch buffer
+    assert meta.tier == 2 and meta.max_batch == emit_t3.GSLOT_MAX_BATCH
+    w = emit_t3.build_wave_tables(4, 4, 4, 4)
+    assert meta.scratch_slots == w.t.nslots + 2
+    assert "t3w_launch_jk(t3_4444" in src and ", 1, &t3_4444_lane};" in src and "T3Class t3_4444_lane = " in src
 
 
 def test_t3_slot_packing():
