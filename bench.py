@@ -235,6 +235,73 @@ def batch(args):
         o.close()
 
 
+def serving(args):
+    """Serving: Poisson arrivals of new systems, each with closed-loop
+    density updates through one plan, admitted under an HBM budget and run
+    concurrently on several streams.  One JSON line: contracted ERIs/s over
+    the window, with offered/achieved rates and p50/p99 latencies."""
+    import torch
+    import paper_2605_10312_amd as hgp
+    import workloads
+    from paper_2605_10312_amd import serve
+
+    n, nupd = args.serve_requests, args.serve_updates
+    natom = (2, args.serve_max_atoms)
+    theta = hgp.MIXED_THETA_DEFAULT if args.precision == "mixed" else 0.0
+    systems = workloads.batch_systems(seed=1005, n=n, natom=natom, lmax=4, nprim=(1, 3))
+    arrivals = serve.poisson_arrivals(args.serve_rate, n, seed=1005)
+    reqs = []
+    for i, (bw, D) in enumerate(systems):
+        dens = [D] + [workloads.psd_density(bw.nbf, 5000 + 100 * i + k) for k in range(1, nupd)]
+        reqs.append(serve.Request(i, float(arrivals[i]), bw, dens, tau=TAU, theta=theta))
+    check = set(range(0, n, max(1, n // 4)))       # requests whose last update is checked against FP64 alone
+    ex = serve.GpuExecutor(slots=args.serve_slots, keep=lambda rid, k: rid in check and k == nupd - 1)
+    srv = serve.Server(ex, hbm_budget=int(args.serve_budget_gb * (1 << 30)), max_active=args.serve_active,
+                       slots=args.serve_slots)
+    # warm-up: one small request end to end (library load, table uploads)
+    wex = serve.GpuExecutor(slots=1)
+    serve.Server(wex, hbm_budget=1 << 34).run([serve.Request(-1, 0.0, reqs[0].basis, reqs[0].densities[:2],
+                                                             TAU, theta)])
+    torch.cuda.synchronize()
+    print(f"serve: {n} requests x {nupd} updates, offered {args.serve_rate}/s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    recs, ups = srv.run(reqs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ex.close()
+    wex.close()
+    summ = serve.summarize(recs, ups, elapsed)
+    eris = sum(ex.eris[u.rid] for u in ups)
+    err = 0.0
+    for rid in sorted(check):
+        r = reqs[rid]
+        b = hgp.Basis.from_workload(r.basis)
+        p = hgp.Plan(b, tau=TAU)
+        Dt = torch.tensor(r.densities[-1], device="cuda")
+        J, K = torch.empty_like(Dt), torch.empty_like(Dt)
+        p.jk(Dt, J, K)
+        torch.cuda.synchronize()
+        Js, Ks = ex.results[(rid, nupd - 1)]
+        err = max(err, float(np.abs(J.cpu().numpy() - Js).max()), float(np.abs(K.cpu().numpy() - Ks).max()))
+        p.close()
+        b.close()
+    nbf = [int(r.basis.nbf) for r in reqs]
+    line = {"metric": METRIC, "value": eris / elapsed, "unit": "contracted ERIs/s", "n_gpus": 1, "steps": 1,
+            "warmup": 1, "ms_per_step": round(elapsed * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64" if theta == 0 else "f32/f64 mixed", "data": "synthetic",
+            "config": {"workload": f"serve{n}_5s4p3d2f1g: {n} requests, Poisson arrivals at {args.serve_rate}/s, "
+                                   f"each a new synthetic molecule of U{{{natom[0]}..{natom[1]}}} atoms (5s4p3d2f1g, "
+                                   f"U{{1..3}} primitives per shell) with {nupd} closed-loop density updates "
+                                   f"through one plan; HBM budget {args.serve_budget_gb:g} GB, at most "
+                                   f"{args.serve_active} active, {args.serve_slots} streams, Schwarz tau=1e-12, "
+                                   + ("FP64" if theta == 0 else f"mixed (theta {theta:g})"),
+                       "nbf_min": min(nbf), "nbf_max": max(nbf), "eris_total": int(eris)},
+            "serve": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()},
+            "peak_active": srv.peak_active, "peak_plan_bytes": srv.peak_bytes,
+            "max_abs_vs_fp64_alone": err}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,9 +313,16 @@ def main():
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: quartets with Q_ab Q_cd < theta use FP32 VRR/HRR (register tier)")
     ap.add_argument("--theta", type=float, default=None, help="mixed-precision threshold (default: the library's)")
-    ap.add_argument("--workload", choices=("mol30", "microbench", "batch"), default="mol30",
+    ap.add_argument("--workload", choices=("mol30", "microbench", "batch", "serve"), default="mol30",
                     help="mol30: the J/K build (one JSON line); microbench: the high-l primitive-quartet classes; "
-                         "batch: many uneven systems in one HIP graph")
+                         "batch: many uneven systems in one HIP graph; serve: continuous batching of requests")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-updates", type=int, default=10)
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="offered requests per second")
+    ap.add_argument("--serve-max-atoms", type=int, default=6)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-active", type=int, default=16)
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--batch-n", type=int, default=64, help="batch: number of systems")
     ap.add_argument("--batch-max-atoms", type=int, default=15, help="batch: atoms per system U{5..this}")
     ap.add_argument("--batch-max-prim", type=int, default=3, help="batch: primitives per shell U{1..this}")
@@ -265,6 +339,9 @@ def main():
         return
     if args.workload == "batch":
         batch(args)
+        return
+    if args.workload == "serve":
+        serving(args)
         return
 
     import torch

@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("HGP_LIB") or os.path.join(_HERE, "libhgp.so")
 
 STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_UNSUPPORTED_L", -3: "HGP_E_OOM", -4: "HGP_E_DEVICE",
           -5: "HGP_E_STATE"}
+STATUS_OOM = -3
 HGP_FP64 = 0
 HGP_MIXED = 1
 MIXED_THETA_DEFAULT = 1e-8      # HGP_MIXED_THETA_DEFAULT in include/hgp.h

@@ -1,0 +1,311 @@
+"""Serving J/K builds on one GPU: continuous batching of requests.
+
+A request is a new system (basis) with a sequence of density updates.  Its
+plan (pair data, Schwarz factors, class lists) is built once at admission
+and reused for every update; update k + 1 is sent only when update k has
+returned (closed loop).  Requests are admitted first come, first served,
+while their plans fit the HBM budget and the number of active requests is
+below a cap; a plan is freed when its request finishes.  The updates of
+different requests run concurrently on a small set of device streams.
+
+The scheduler (Server) is host logic over an executor interface, so its
+rules are testable with a simulated executor; GpuExecutor drives the C ABI.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float                 # seconds from the start of the run
+    basis: object                  # workloads.Basis (or anything the executor accepts)
+    densities: list                # one N x N array per update
+    tau: float = 1e-12
+    theta: float = 0.0             # > tau: mixed-precision plan
+
+
+@dataclasses.dataclass
+class UpdateRecord:
+    rid: int
+    k: int
+    submit: float
+    done: float
+
+    @property
+    def latency(self):
+        return self.done - self.submit
+
+
+@dataclasses.dataclass
+class RequestRecord:
+    rid: int
+    arrival: float
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    plan_bytes: int = 0
+    rejected: str | None = None
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+class OverBudget(Exception):
+    """The plan does not fit the HBM left right now."""
+
+
+class TooLarge(Exception):
+    """The plan does not fit the whole HBM budget: the request is rejected."""
+
+
+class Server:
+    """Continuous batching: admit, submit, complete, release.
+
+    executor must provide now(), create(request, bytes_left) -> handle
+    (raising OverBudget or TooLarge), plan_bytes(handle), submit(handle,
+    request, k, slot) -> token, done(token) -> bool, finish(token, request,
+    k), release(handle) and idle(until) (wait for progress, at most until
+    the given time).  An executor that also has create_async(request,
+    bytes_left) -> future (done(), result()) builds plans off the scheduling
+    loop, one at a time, so updates keep flowing meanwhile; a plan in the
+    making counts against the budget only once it exists."""
+
+    def __init__(self, executor, hbm_budget: int, max_active: int = 8, slots: int = 4):
+        if hbm_budget <= 0 or max_active < 1 or slots < 1:
+            raise ValueError("need hbm_budget > 0, max_active >= 1, slots >= 1")
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_active = max_active
+        self.slots = slots
+        self.peak_bytes = 0
+        self.peak_active = 0
+
+    def run(self, requests):
+        ex = self.ex
+        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        waiting = collections.deque()
+        active = collections.OrderedDict()        # rid -> [request, handle, k, token, slot, submit time]
+        recs = {r.rid: RequestRecord(r.rid, r.arrival) for r in requests}
+        updates = []
+        used = 0
+        blocked_at = None                         # bytes in use when admission last hit the budget
+        nslot = 0
+        creating = None                           # (future, request) of the plan being built off the loop
+        use_async = hasattr(ex, "create_async")
+        t0 = ex.now()
+
+        def admitted(r, h):
+            nonlocal used, nslot
+            b = ex.plan_bytes(h)
+            used += b
+            self.peak_bytes = max(self.peak_bytes, used)
+            recs[r.rid].admitted = ex.now() - t0
+            recs[r.rid].plan_bytes = b
+            active[r.rid] = [r, h, 0, None, nslot % self.slots, 0.0]
+            nslot += 1
+
+        def refused(r, e, fits_later):
+            # OverBudget with plans alive: wait at the head for a release; else reject
+            nonlocal blocked_at
+            if isinstance(e, OverBudget) and fits_later:
+                blocked_at = used
+                return False
+            waiting.popleft()
+            recs[r.rid].rejected = (str(e) if isinstance(e, TooLarge) and str(e) else "plan exceeds the HBM budget")
+            return True
+
+        while pending or waiting or active or creating:
+            t = ex.now() - t0
+            while pending and pending[0].arrival <= t:
+                waiting.append(pending.popleft())
+            if creating is not None and creating[0].done():
+                fut, r = creating
+                creating = None
+                try:
+                    h = fut.result()
+                except (OverBudget, TooLarge) as e:
+                    refused(r, e, bool(active))
+                else:
+                    waiting.popleft()
+                    admitted(r, h)
+            # admission: first come, first served; a request that does not fit now
+            # waits at the head until a release frees HBM
+            while (creating is None and waiting and len(active) < self.max_active and blocked_at != used):
+                r = waiting[0]
+                if not r.densities:
+                    waiting.popleft()
+                    recs[r.rid].admitted = recs[r.rid].finished = ex.now() - t0
+                    continue
+                if used >= self.budget:
+                    if refused(r, OverBudget(), bool(active)):
+                        continue
+                    break
+                if use_async:
+                    creating = (ex.create_async(r, self.budget - used), r)
+                    break
+                try:
+                    h = ex.create(r, self.budget - used)
+                except (OverBudget, TooLarge) as e:
+                    if refused(r, e, bool(active)):
+                        continue
+                    break
+                waiting.popleft()
+                admitted(r, h)
+            self.peak_active = max(self.peak_active, len(active))
+            # closed loop: each active request has at most one update in flight
+            for st in active.values():
+                if st[3] is None:
+                    st[5] = ex.now() - t0
+                    st[3] = ex.submit(st[1], st[0], st[2], st[4])
+            # completions
+            progressed = False
+            for rid in list(active):
+                st = active[rid]
+                if not ex.done(st[3]):
+                    continue
+                progressed = True
+                tdone = ex.now() - t0
+                ex.finish(st[3], st[0], st[2])
+                updates.append(UpdateRecord(rid, st[2], st[5], tdone))
+                st[2] += 1
+                st[3] = None
+                if st[2] == len(st[0].densities):
+                    ex.release(st[1])
+                    used -= recs[rid].plan_bytes
+                    recs[rid].finished = tdone
+                    del active[rid]
+            if not progressed:
+                nxt = pending[0].arrival + t0 if pending else None
+                if active or creating or nxt is not None:
+                    ex.idle(nxt)
+        return [recs[r.rid] for r in requests], updates
+
+
+def percentile(x, q):
+    """Nearest-rank percentile (q in [0, 100]) of a non-empty sequence."""
+    v = np.sort(np.asarray(x, dtype=float))
+    if v.size == 0:
+        raise ValueError("empty sample")
+    k = int(np.ceil(q / 100.0 * v.size)) - 1
+    return float(v[min(max(k, 0), v.size - 1)])
+
+
+def summarize(reqs, updates, elapsed):
+    done = [r for r in reqs if r.rejected is None]
+    lat_u = [u.latency for u in updates]
+    lat_r = [r.latency for r in done]
+    span = max(r.arrival for r in reqs) if reqs else 0.0
+    return {
+        "requests": len(reqs), "rejected": len(reqs) - len(done), "updates": len(updates),
+        "elapsed_s": elapsed,
+        "offered_req_per_s": (len(reqs) - 1) / span if span > 0 else None,
+        "achieved_req_per_s": len(done) / elapsed if elapsed > 0 else None,
+        "updates_per_s": len(updates) / elapsed if elapsed > 0 else None,
+        "update_p50_ms": 1e3 * percentile(lat_u, 50) if lat_u else None,
+        "update_p99_ms": 1e3 * percentile(lat_u, 99) if lat_u else None,
+        "request_p50_ms": 1e3 * percentile(lat_r, 50) if lat_r else None,
+        "request_p99_ms": 1e3 * percentile(lat_r, 99) if lat_r else None,
+    }
+
+
+def poisson_arrivals(rate: float, n: int, seed: int):
+    """n arrival times (s) of a Poisson process of the given rate, the first at 0."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, n)
+    gaps[0] = 0.0
+    return np.cumsum(gaps)
+
+
+class GpuExecutor:
+    """Runs the plans through the C ABI on `slots` device streams.
+
+    Densities are copied to the device at admission (the request's inputs
+    then stay resident); each update writes the request's J and K buffers.
+    keep(rid, k) -> bool selects updates whose J and K are copied back to
+    the host and kept in self.results[(rid, k)] (True: all of them).
+    self.eris[rid] is the number of contracted ERIs one update evaluates."""
+
+    def __init__(self, slots: int = 4, keep=False, worker: bool = False):
+        import concurrent.futures
+        import torch
+        from . import lib
+        lib()
+        self.torch = torch
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        # worker=True builds and destroys plans on a worker thread, so the
+        # loop keeps feeding the streams meanwhile.  Freeing device memory
+        # waits for the whole device, though, so a worker's plans arrive
+        # slower than the loop's own and fewer requests are active: measured
+        # on the serving benchmark, 4.1 against 6.1 updates/s.  Off by default.
+        self.pool = concurrent.futures.ThreadPoolExecutor(max_workers=1) if worker else None
+        if worker:
+            self.create_async = lambda r, left: self.pool.submit(self.create, r, left)
+        self.keep = (lambda rid, k: True) if keep is True else (keep or (lambda rid, k: False))
+        self.results = {}
+        self.eris = {}
+
+    def now(self):
+        return time.perf_counter()
+
+    def create(self, r, bytes_left):
+        from . import HGPError, STATUS_OOM, Basis, Plan
+        torch = self.torch
+        n = int(np.asarray(r.densities[0]).shape[0])
+        dev_bytes = 8 * n * n * (len(r.densities) + 2)          # densities, J, K
+        if dev_bytes >= bytes_left:
+            raise OverBudget()
+        b = Basis.from_workload(r.basis)
+        try:
+            p = Plan(b, tau=r.tau, hbm_budget=int(bytes_left - dev_bytes), theta=r.theta)
+        except HGPError as e:
+            b.close()
+            if e.status == STATUS_OOM:
+                raise OverBudget() from e
+            raise
+        D = [torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda") for x in r.densities]
+        J = torch.empty_like(D[0])
+        K = torch.empty_like(D[0])
+        self.eris[r.rid] = sum(c["quartets"] * int(np.prod([2 * x + 1 for x in c["ls"]])) for c in p.classes())
+        return {"basis": b, "plan": p, "D": D, "J": J, "K": K, "bytes": p.stats()["device_bytes"] + dev_bytes}
+
+    def plan_bytes(self, h):
+        return h["bytes"]
+
+    def submit(self, h, r, k, slot):
+        s = self.streams[slot]
+        h["plan"].jk(h["D"][k], h["J"], h["K"], stream=s)
+        ev = self.torch.cuda.Event()
+        ev.record(s)
+        return (ev, h)
+
+    def done(self, token):
+        return token[0].query()
+
+    def finish(self, token, r, k):
+        if self.keep(r.rid, k):
+            h = token[1]
+            self.results[(r.rid, k)] = (h["J"].cpu().numpy(), h["K"].cpu().numpy())
+
+    def release(self, h):
+        # the request's last update has completed, so nothing in flight uses these
+        def free():
+            h["plan"].close()
+            h["basis"].close()
+            h["D"] = h["J"] = h["K"] = None
+        if self.pool is not None:
+            self.pool.submit(free)
+        else:
+            free()
+
+    def close(self):
+        if self.pool is not None:
+            self.pool.shutdown(wait=True)
+
+    def idle(self, until):
+        time.sleep(50e-6)
