@@ -217,6 +217,17 @@ def batch(args):
     ref = [(J.clone(), K.clone()) for J, K in zip(Js, Ks)]
     graph_s = timed(graph.run, "graph")
     diff = max(max(float((J - r[0]).abs().max()), float((K - r[1]).abs().max())) for J, K, r in zip(Js, Ks, ref))
+    # one multi-system plan: each class as one launch over every system's quartets
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    union = hgp.Plan.multi(bases, tau=TAU)
+    torch.cuda.synchronize()
+    union_setup_s = time.perf_counter() - t0
+    union_s = timed(lambda: union.jk_multi(Ds, Js, Ks), "multi-system plan")
+    diff_union = max(max(float((J - r[0]).abs().max()), float((K - r[1]).abs().max()))
+                     for J, K, r in zip(Js, Ks, ref))
+    union_stats = union.stats()
+    union.close()
     nbf = [int(bw.nbf) for bw, _ in systems]
     line = {"metric": METRIC, "value": eris / graph_s, "unit": "contracted ERIs/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(graph_s * 1e3, 4),
@@ -228,7 +239,10 @@ def batch(args):
                        "eris_per_step": int(eris)},
             "sequential_ms": round(seq_s * 1e3, 4), "graph_ms": round(graph_s * 1e3, 4),
             "graph_speedup": round(seq_s / graph_s, 3), "setup_s": round(setup_s, 3),
-            "capture_s": round(capture_s, 4), "max_abs_graph_vs_sequential": diff}
+            "capture_s": round(capture_s, 4), "max_abs_graph_vs_sequential": diff,
+            "multi_plan_ms": round(union_s * 1e3, 4), "multi_plan_speedup": round(seq_s / union_s, 3),
+            "multi_plan_setup_s": round(union_setup_s, 3), "max_abs_multi_vs_sequential": diff_union,
+            "multi_plan_quartets_kept": union_stats["quartets_kept"]}
     print(json.dumps(line), flush=True)
     graph.close()
     for o in plans + bases:

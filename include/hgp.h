@@ -165,6 +165,30 @@ hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int32_t kernel, int64_t
 hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_stream);
 
 /*
+ * Several systems in one plan (the batched-systems growth of the method):
+ * the n bases are independent systems; the plan keeps only shell pairs
+ * within a system and quartets whose two pairs are in the same system, so
+ * each class is one launch over the quartets of every system at once
+ * instead of n small launches.  Arguments as hgp_plan_create_mixed
+ * (theta = 0: FP64).  The plan holds a copy of the bases (they may be
+ * destroyed afterwards) and, besides the usual plan data, three buffers of
+ * N_tot * (N_max + 1) doubles (N_tot = sum of the systems' N, N_max the
+ * largest): system s's block of D, J' and K' sits at row offset R_s and
+ * column offset R_s with row stride N_max, so blocks never overlap.
+ * HGP_E_INVALID if N_tot * (N_max + 1) reaches 2^31.
+ */
+hgp_status hgp_plan_create_multi(const hgp_basis *const *bases, int32_t n, double schwarz_tau, double theta,
+                                 size_t hbm_budget_bytes, void *hip_stream, hgp_plan **out);
+/*
+ * hgp_jk_multi -- J and K of every system of a multi-system plan.
+ *   D[n], J[n], K[n]  device pointers, N_s x N_s row-major per system (J or K
+ *                     may be NULL as a whole to skip it)
+ * Stream-ordered like hgp_jk.  hgp_jk on a multi-system plan returns
+ * HGP_E_INVALID; hgp_jk_multi on a one-system plan is hgp_jk.
+ */
+hgp_status hgp_jk_multi(hgp_plan *p, const double *const *D, double *const *J, double *const *K, void *hip_stream);
+
+/*
  * Batched J/K over many systems (the batched-systems growth of the method):
  * the J/K builds of n plans, each with its own D, J and K, captured once as
  * one HIP graph in which every system is an independent branch, so the

@@ -33,6 +33,8 @@ SIGNATURES = {
     "hgp_basis_destroy": (ctypes.c_int, [_vp]),
     "hgp_plan_create": (ctypes.c_int, [_vp, _d, _i32, _sz, _vp, ctypes.POINTER(_vp)]),
     "hgp_plan_create_mixed": (ctypes.c_int, [_vp, _d, _d, _sz, _vp, ctypes.POINTER(_vp)]),
+    "hgp_plan_create_multi": (ctypes.c_int, [_vp, _i32, _d, _d, _sz, _vp, ctypes.POINTER(_vp)]),
+    "hgp_jk_multi": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "hgp_batch_create": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "hgp_batch_run": (ctypes.c_int, [_vp, _vp]),
     "hgp_batch_destroy": (ctypes.c_int, [_vp]),
@@ -199,11 +201,34 @@ class Plan:
             out.append({"ls": info["ls"], "tier": info["tier"], "kernels": ks})
         return out
 
+    @classmethod
+    def multi(cls, bases, tau: float = 1e-12, theta: float = 0.0, hbm_budget: int = 0, stream=None):
+        """One plan over several independent systems (hgp_plan_create_multi):
+        each class runs as one launch over the quartets of every system."""
+        self = cls.__new__(cls)
+        self.basis = None
+        self.bases = list(bases)
+        arr = (ctypes.c_void_p * len(self.bases))(*[b.handle.value for b in self.bases])
+        h = ctypes.c_void_p()
+        _check(lib().hgp_plan_create_multi(arr, len(self.bases), float(tau), float(theta), int(hbm_budget),
+                                           ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)))
+        self.handle = h
+        return self
+
     def jk(self, D, J=None, K=None, stream=None):
         """Enqueue J/K for device density D into device J and/or K (overwritten)."""
         import torch
         _check(lib().hgp_jk(self.handle, _dptr(D, torch.float64), _dptr(J, torch.float64), _dptr(K, torch.float64),
                             ctypes.c_void_p(_stream_ptr(stream))))
+
+    def jk_multi(self, Ds, Js=None, Ks=None, stream=None):
+        """J/K of every system of a multi-system plan: lists of device tensors
+        (Js or Ks None to skip)."""
+        import torch
+        n = len(Ds)
+        arr = lambda xs: (ctypes.c_void_p * n)(*[_dptr(x, torch.float64) for x in xs])
+        _check(lib().hgp_jk_multi(self.handle, arr(Ds), None if Js is None else arr(Js),
+                                  None if Ks is None else arr(Ks), ctypes.c_void_p(_stream_ptr(stream))))
 
     def close(self):
         if getattr(self, "handle", None):

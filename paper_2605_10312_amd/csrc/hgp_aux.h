@@ -12,14 +12,16 @@ void launch_pairs(int npair, const PairInfo *pairs, const double *cen, const int
 void launch_prim_quartet_pairs(int64_t n, const double *centers, const double *exps, const int ls[4],
                                const int perm[4], const int strides[4], int64_t block, PairInfo *pairs,
                                PairGeo *geo, PrimPair *prims, EriTask *tasks, hipStream_t s);
-void launch_screen_count(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau, double hi,
-                         int64_t *counts, hipStream_t s);
+void launch_screen_count(int b0, int nb, int sym, const double *Q, double tau, double hi, const int *psys,
+                         const int *kbeg, const int *kcnt, int64_t *counts, hipStream_t s);
+void launch_screen_write(int b0, int nb, int sym, const double *Q, double tau, double hi, const int *psys,
+                         const int *kbeg, const int *kcnt, const int64_t *offsets, int2 *out, hipStream_t s);
 void launch_scan(int64_t *v, int n, int64_t *total, hipStream_t s);
-void launch_screen_write(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau, double hi,
-                         const int64_t *offsets, int2 *out, hipStream_t s);
 void launch_store_q(int npair, const double *qv, PairGeo *geo, double *Q, hipStream_t s);
 void launch_fill_zero(double *x, int64_t n, hipStream_t s);
-void launch_symmetrize(const double *acc, double *out, int n, hipStream_t s);
+void launch_symmetrize(const double *acc, int64_t astride, double *out, int n, hipStream_t s);
+void launch_block_in(const double *src, int n, double *dst, int64_t dstride, hipStream_t s);
+void launch_block_zero(double *dst, int n, int64_t dstride, hipStream_t s);
 
 extern const ClassKernels g_class_table[];
 extern const int g_num_classes;

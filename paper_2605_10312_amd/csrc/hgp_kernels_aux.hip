@@ -162,18 +162,26 @@ __global__ void prim_quartet_pair_kernel(int64_t n, const double *centers, const
 // Screening and class lists.  For one class, bra pairs are rows
 // [b0, b0+nb) and ket pairs [k0, k0+nk) of the global pair arrays; when
 // the bra and ket pair classes coincide only ket <= bra is a unique quartet.
-// A quartet is kept when Q_bra * Q_ket >= tau.  One block per row.
+// A quartet is kept when tau <= Q_bra * Q_ket < hi.  One block per row.
+// Bra rows b0 .. b0 + nb - 1 of one pair class; the ket candidates of a row
+// are the ket class's pairs of the same system, kbeg[sys] .. kbeg[sys] +
+// kcnt[sys] - 1 (psys: system of each pair); within one class (sym) only
+// those up to the row itself.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int row_len(int row, int k0, int nk, int b0, int sym)
+__device__ __forceinline__ void ket_range(int row, int sym, const int *psys, const int *kbeg, const int *kcnt,
+                                          int *k0, int *len)
 {
-    return sym ? (row - b0 + 1) : nk;
+    const int sy = psys[row];
+    *k0 = kbeg[sy];
+    *len = sym ? (row - kbeg[sy] + 1) : kcnt[sy];
 }
 
-__global__ void screen_count_kernel(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau,
-                                    double hi, int64_t *counts)
+__global__ void screen_count_kernel(int b0, int nb, int sym, const double *Q, double tau, double hi,
+                                    const int *psys, const int *kbeg, const int *kcnt, int64_t *counts)
 {
     const int row = b0 + blockIdx.x;
-    const int len = row_len(row, k0, nk, b0, sym);
+    int k0, len;
+    ket_range(row, sym, psys, kbeg, kcnt, &k0, &len);
     const double qb = Q[row];
     int c = 0;
     for (int j = threadIdx.x; j < len; j += blockDim.x) {
@@ -218,11 +226,13 @@ __global__ void scan_kernel(int64_t *v, int n, int64_t *total)
     if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void screen_write_kernel(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau,
-                                    double hi, const int64_t *offsets, int2 *out)
+__global__ void screen_write_kernel(int b0, int nb, int sym, const double *Q, double tau, double hi,
+                                    const int *psys, const int *kbeg, const int *kcnt, const int64_t *offsets,
+                                    int2 *out)
 {
     const int row = b0 + blockIdx.x;
-    const int len = row_len(row, k0, nk, b0, sym);
+    int k0, len;
+    ket_range(row, sym, psys, kbeg, kcnt, &k0, &len);
     const double qb = Q[row];
     __shared__ int wcount[1024 / 64];
     __shared__ int64_t base;
@@ -264,12 +274,28 @@ __global__ void fill_zero_kernel(double *x, int64_t n)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = 0.0;
 }
 
-// out[i][j] = acc[i][j] + acc[j][i]
-__global__ void symmetrize_kernel(const double *acc, double *out, int n)
+// out[i][j] = acc[i][j] + acc[j][i] for an n x n block; acc rows astride apart
+__global__ void symmetrize_kernel(const double *acc, int64_t astride, double *out, int n)
 {
     const int i = blockIdx.y * 16 + threadIdx.y, j = blockIdx.x * 16 + threadIdx.x;
     if (i >= n || j >= n) return;
-    out[(int64_t)i * n + j] = acc[(int64_t)i * n + j] + acc[(int64_t)j * n + i];
+    out[(int64_t)i * n + j] = acc[(int64_t)i * astride + j] + acc[(int64_t)j * astride + i];
+}
+
+// dst[i * dstride + j] = src[i * n + j] (an n x n block into a strided layout)
+__global__ void block_in_kernel(const double *src, int n, double *dst, int64_t dstride)
+{
+    const int i = blockIdx.y * 16 + threadIdx.y, j = blockIdx.x * 16 + threadIdx.x;
+    if (i >= n || j >= n) return;
+    dst[(int64_t)i * dstride + j] = src[(int64_t)i * n + j];
+}
+
+// zero an n x n block of a strided layout
+__global__ void block_zero_kernel(double *dst, int n, int64_t dstride)
+{
+    const int i = blockIdx.y * 16 + threadIdx.y, j = blockIdx.x * 16 + threadIdx.x;
+    if (i >= n || j >= n) return;
+    dst[(int64_t)i * dstride + j] = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -303,22 +329,23 @@ void launch_prim_quartet_pairs(int64_t n, const double *centers, const double *e
                            make_int4(strides[0], strides[1], strides[2], strides[3]), block, pairs, geo, prims,
                            tasks);
 }
-void launch_screen_count(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau, double hi,
-                         int64_t *counts, hipStream_t s)
+void launch_screen_count(int b0, int nb, int sym, const double *Q, double tau, double hi, const int *psys,
+                         const int *kbeg, const int *kcnt, int64_t *counts, hipStream_t s)
 {
     if (nb > 0)
-        hipLaunchKernelGGL(screen_count_kernel, dim3(nb), dim3(256), 0, s, b0, nb, k0, nk, sym, Q, tau, hi, counts);
+        hipLaunchKernelGGL(screen_count_kernel, dim3(nb), dim3(256), 0, s, b0, nb, sym, Q, tau, hi, psys, kbeg, kcnt,
+                           counts);
+}
+void launch_screen_write(int b0, int nb, int sym, const double *Q, double tau, double hi, const int *psys,
+                         const int *kbeg, const int *kcnt, const int64_t *offsets, int2 *out, hipStream_t s)
+{
+    if (nb > 0)
+        hipLaunchKernelGGL(screen_write_kernel, dim3(nb), dim3(256), 0, s, b0, nb, sym, Q, tau, hi, psys, kbeg, kcnt,
+                           offsets, out);
 }
 void launch_scan(int64_t *v, int n, int64_t *total, hipStream_t s)
 {
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, v, n, total);
-}
-void launch_screen_write(int b0, int nb, int k0, int nk, int sym, const double *Q, double tau, double hi,
-                         const int64_t *offsets, int2 *out, hipStream_t s)
-{
-    if (nb > 0)
-        hipLaunchKernelGGL(screen_write_kernel, dim3(nb), dim3(256), 0, s, b0, nb, k0, nk, sym, Q, tau, hi, offsets,
-                           out);
 }
 void launch_store_q(int npair, const double *qv, PairGeo *geo, double *Q, hipStream_t s)
 {
@@ -332,9 +359,22 @@ void launch_fill_zero(double *x, int64_t n, hipStream_t s)
         hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n);
     }
 }
-void launch_symmetrize(const double *acc, double *out, int n, hipStream_t s)
+void launch_symmetrize(const double *acc, int64_t astride, double *out, int n, hipStream_t s)
 {
-    if (n > 0) hipLaunchKernelGGL(symmetrize_kernel, dim3((n + 15) / 16, (n + 15) / 16), dim3(16, 16), 0, s, acc, out, n);
+    if (n > 0)
+        hipLaunchKernelGGL(symmetrize_kernel, dim3((n + 15) / 16, (n + 15) / 16), dim3(16, 16), 0, s, acc, astride,
+                           out, n);
+}
+void launch_block_in(const double *src, int n, double *dst, int64_t dstride, hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(block_in_kernel, dim3((n + 15) / 16, (n + 15) / 16), dim3(16, 16), 0, s, src, n, dst,
+                           dstride);
+}
+void launch_block_zero(double *dst, int n, int64_t dstride, hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(block_zero_kernel, dim3((n + 15) / 16, (n + 15) / 16), dim3(16, 16), 0, s, dst, n, dstride);
 }
 
 }  // namespace hgp

@@ -205,6 +205,20 @@ struct hgp_plan {
     bool timing = false;
     std::vector<PendingTiming> pending;
     std::vector<hipEvent_t> event_pool;
+    // several systems in one plan (hgp_plan_create_multi): pairs and quartets
+    // stay within a system; system s's functions are R_s .. R_s + N_s - 1 of
+    // the union basis, and D and the accumulators hold its block at
+    // (R_s + i) * stride + R_s + j with stride = max N_s, so blocks of
+    // different systems never overlap
+    hgp_basis *owned = nullptr;              // the union basis
+    std::vector<int> shell_sys;              // system of each shell (empty: one system)
+    int nsys = 1;
+    std::vector<int> sys_R, sys_N;
+    int64_t stride = 0;                      // row stride of D and the accumulators
+    int64_t acc_len = 0;                     // doubles per accumulator
+    double *d_Dunion = nullptr;              // several systems: the densities in the accumulators' layout
+    int *d_psys = nullptr;                   // system of each pair
+    int *d_cbeg = nullptr, *d_ccnt = nullptr;   // [pair class][system]: first pair and count
 };
 
 static hipEvent_t take_event(hgp_plan *p)
@@ -323,7 +337,9 @@ hgp_status hgp_plan_destroy(hgp_plan *p)
     for (hipEvent_t e : p->event_pool) hipEventDestroy(e);
     hipFree(p->d_pairs); hipFree(p->d_geo); hipFree(p->d_prims); hipFree(p->d_Q);
     hipFree(p->d_Jacc); hipFree(p->d_Kacc); hipFree(p->d_scratch);
+    hipFree(p->d_Dunion); hipFree(p->d_psys); hipFree(p->d_cbeg); hipFree(p->d_ccnt);
     for (auto &c : p->lists) hipFree(c.d_q);
+    if (p->owned) hgp_basis_destroy(p->owned);
     delete p;
     return HGP_OK;
 }
@@ -393,10 +409,17 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
     const int npc = pair_class_of(lmax, lmax) + 1;
     // ---- pair lists per pair class, sorted by primitive-pair count (descending)
     std::vector<std::vector<PairInfo>> per(npc);
+    auto sysof = [&](int sh) { return p->shell_sys.empty() ? 0 : p->shell_sys[(size_t)sh]; };
+    // within a pair class: by system, then by primitive-pair count (descending)
+    auto pair_order = [&](const PairInfo &x, const PairInfo &y) {
+        const int sx = sysof(x.sh_a), sy = sysof(y.sh_a);
+        return sx != sy ? sx < sy : x.nprim > y.nprim;
+    };
     for (int i = 0; i < b->nshell; ++i)
         for (int j = 0; j < b->nshell; ++j) {
             const int li = b->l[i], lj = b->l[j];
             if (li < lj || (li == lj && j > i)) continue;
+            if (sysof(i) != sysof(j)) continue;       // no pair across systems
             PairInfo pi{};
             pi.sh_a = i; pi.sh_b = j;
             pi.nprim = b->nprim[i] * b->nprim[j];
@@ -411,8 +434,7 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
         p->pc_count.assign(npc, 0);
         int off = 0;
         for (int c = 0; c < npc; ++c) {
-            std::stable_sort(groups[c].begin(), groups[c].end(),
-                             [](const PairInfo &x, const PairInfo &y) { return x.nprim > y.nprim; });
+            std::stable_sort(groups[c].begin(), groups[c].end(), pair_order);
             p->pc_begin[c] = (int)flat.size();
             p->pc_count[c] = (int)groups[c].size();
             for (auto &pi : groups[c]) {
@@ -425,16 +447,32 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
     };
     std::vector<PairInfo> pairs;
     int prim_off = layout(per, pairs);
-    // candidate unique quartets over all shell pairs, before any screening
-    p->total = 0;
-    for (int bc = 0; bc < npc; ++bc)
-        for (int kc = 0; kc <= bc; ++kc) {
-            const int64_t nb = p->pc_count[bc], nk = p->pc_count[kc];
-            p->total += (bc == kc) ? nb * (nb + 1) / 2 : nb * nk;
-        }
+    // candidate unique quartets over all shell pairs (within each system), before any screening
+    const int nsys = p->nsys;
+    {
+        std::vector<int64_t> cnt((size_t)npc * nsys, 0);
+        for (const PairInfo &x : pairs) ++cnt[(size_t)x.cls * nsys + sysof(x.sh_a)];
+        p->total = 0;
+        for (int bc = 0; bc < npc; ++bc)
+            for (int kc = 0; kc <= bc; ++kc)
+                for (int sy = 0; sy < nsys; ++sy) {
+                    const int64_t nb = cnt[(size_t)bc * nsys + sy], nk = cnt[(size_t)kc * nsys + sy];
+                    p->total += (bc == kc) ? nb * (nb + 1) / 2 : nb * nk;
+                }
+    }
     const int64_t nbf = b->nbf;
+    if (nsys == 1) {
+        p->stride = nbf;
+        p->acc_len = nbf * nbf;
+    } else {
+        p->stride = std::max(1, *std::max_element(p->sys_N.begin(), p->sys_N.end()));
+        p->acc_len = nbf * (p->stride + 1);
+    }
+    if (p->acc_len >= ((int64_t)1 << 31))   // the kernels index D, J and K with 32-bit offsets
+        return fail(HGP_E_INVALID, "basis too large: D/J/K offsets exceed 32 bits");
     const int64_t need = (int64_t)pairs.size() * (sizeof(PairInfo) + sizeof(PairGeo) + 2 * sizeof(double)) +
-                         (int64_t)prim_off * sizeof(PrimPair) + 2 * nbf * nbf * (int64_t)sizeof(double);
+                         (int64_t)prim_off * sizeof(PrimPair) +
+                         (nsys == 1 ? 2 : 3) * p->acc_len * (int64_t)sizeof(double);
     if (budget && (size_t)need > budget) return fail(HGP_E_OOM, "plan exceeds the HBM budget (pair data and accumulators)");
     hgp_status st;
     PairInfo *d_pairs = nullptr;
@@ -516,8 +554,7 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
             p->pc_begin.assign(npc, 0);
             p->pc_count.assign(npc, 0);
             for (int c = 0; c < npc; ++c) {
-                std::stable_sort(groups[c].begin(), groups[c].end(),
-                                 [](const PairInfo &x, const PairInfo &y) { return x.nprim > y.nprim; });
+                std::stable_sort(groups[c].begin(), groups[c].end(), pair_order);
                 p->pc_begin[c] = (int)np.size();
                 p->pc_count[c] = (int)groups[c].size();
                 for (auto &x : groups[c]) {
@@ -551,9 +588,24 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
     p->pairs = pairs;
     p->d_pairs = d_pairs; p->d_geo = d_geo; p->d_prims = d_prims;
     p->bytes += (int64_t)pairs.size() * (sizeof(PairInfo) + sizeof(PairGeo)) + (int64_t)prim_off * sizeof(PrimPair);
-    if ((st = dalloc(&p->d_Q, pairs.size(), &p->bytes)) || (st = dalloc(&p->d_Jacc, (size_t)(nbf * nbf), &p->bytes)) ||
-        (st = dalloc(&p->d_Kacc, (size_t)(nbf * nbf), &p->bytes)))
+    if ((st = dalloc(&p->d_Q, pairs.size(), &p->bytes)) || (st = dalloc(&p->d_Jacc, (size_t)p->acc_len, &p->bytes)) ||
+        (st = dalloc(&p->d_Kacc, (size_t)p->acc_len, &p->bytes)))
         return st;
+    if (nsys > 1 && (st = dalloc(&p->d_Dunion, (size_t)p->acc_len, &p->bytes))) return st;
+    // the system of each pair, and per pair class and system the range of its pairs
+    {
+        std::vector<int> psys(std::max<size_t>(pairs.size(), 1), 0), cbeg((size_t)npc * nsys, 0),
+            ccnt((size_t)npc * nsys, 0);
+        for (int c = 0; c < npc; ++c)
+            for (int k = p->pc_begin[c]; k < p->pc_begin[c] + p->pc_count[c]; ++k) {
+                const int sy = sysof(pairs[(size_t)k].sh_a);
+                psys[(size_t)k] = sy;
+                if (ccnt[(size_t)c * nsys + sy]++ == 0) cbeg[(size_t)c * nsys + sy] = k;
+            }
+        if ((st = upload(&p->d_psys, psys, &p->bytes)) || (st = upload(&p->d_cbeg, cbeg, &p->bytes)) ||
+            (st = upload(&p->d_ccnt, ccnt, &p->bytes)))
+            return st;
+    }
 
     // ---- Schwarz factors of the contracted pairs
     if (p->npair > 0) {
@@ -586,7 +638,7 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
             if (ci < 0) { hipFree(d_counts); hipFree(d_total); return fail(HGP_E_UNSUPPORTED_L, "class kernel not built"); }
             if ((st = prepare_class(g_class_table[ci]))) { hipFree(d_counts); hipFree(d_total); return st; }
             const int sym = (bc == kc);
-            const int b0 = p->pc_begin[bc], k0 = p->pc_begin[kc];
+            const int b0 = p->pc_begin[bc];
             const double t = tau > 0 ? tau : -1.0;
             // bands of Q_ab Q_cd: [t, theta) in FP32 where the class has an FP32
             // kernel and the plan is mixed, the rest in FP64
@@ -600,7 +652,8 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
                 bands.push_back({t, inf, 64});
             }
             for (const Band &bd : bands) {
-            launch_screen_count(b0, nb, k0, nk, sym, p->d_Q, bd.lo, bd.hi, d_counts, s);
+            launch_screen_count(b0, nb, sym, p->d_Q, bd.lo, bd.hi, p->d_psys, p->d_cbeg + (size_t)kc * nsys,
+                                p->d_ccnt + (size_t)kc * nsys, d_counts, s);
             launch_scan(d_counts, nb, d_total, s);
             int64_t total = 0;
             HGP_HIP(hipMemcpyAsync(&total, d_total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -614,7 +667,9 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
                 return fail(HGP_E_OOM, "plan exceeds the HBM budget (quartet lists)");
             }
             if ((st = dalloc(&cl.d_q, (size_t)total, &p->bytes))) { hipFree(d_counts); hipFree(d_total); return st; }
-            if (total > 0) launch_screen_write(b0, nb, k0, nk, sym, p->d_Q, bd.lo, bd.hi, d_counts, cl.d_q, s);
+            if (total > 0)
+                launch_screen_write(b0, nb, sym, p->d_Q, bd.lo, bd.hi, p->d_psys, p->d_cbeg + (size_t)kc * nsys,
+                                    p->d_ccnt + (size_t)kc * nsys, d_counts, cl.d_q, s);
             HGP_HIP(hipGetLastError());
             // primitive-quartet count: sum over kept quartets of nprim(bra) * nprim(ket)
             if (total > 0) {
@@ -678,6 +733,60 @@ hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t preci
     if (precision != HGP_FP64 && precision != HGP_MIXED) return fail(HGP_E_INVALID, "precision must be HGP_FP64 or HGP_MIXED");
     return hgp_plan_create_mixed(b, schwarz_tau, precision == HGP_MIXED ? HGP_MIXED_THETA_DEFAULT : 0.0,
                                  hbm_budget_bytes, hip_stream, out);
+}
+
+hgp_status hgp_plan_create_multi(const hgp_basis *const *bases, int32_t n, double schwarz_tau, double theta,
+                                 size_t hbm_budget_bytes, void *hip_stream, hgp_plan **out)
+{
+    if (!out) return fail(HGP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !bases) return fail(HGP_E_INVALID, "need n >= 1 bases");
+    if (!(schwarz_tau >= 0.0) || !std::isfinite(schwarz_tau)) return fail(HGP_E_INVALID, "schwarz_tau must be >= 0");
+    if (!(theta >= 0.0) || !std::isfinite(theta)) return fail(HGP_E_INVALID, "theta must be >= 0 and finite");
+    std::vector<int32_t> l, nprim, sys;
+    std::vector<double> cen, exps, coefs;
+    std::vector<int> R, N;
+    int dev = -1, nbf = 0;
+    for (int k = 0; k < n; ++k) {
+        const hgp_basis *b = bases[k];
+        if (!b) return fail(HGP_E_INVALID, "a basis is NULL");
+        if (dev >= 0 && b->device != dev) return fail(HGP_E_INVALID, "all bases must be on one device");
+        dev = b->device;
+        l.insert(l.end(), b->l.begin(), b->l.end());
+        nprim.insert(nprim.end(), b->nprim.begin(), b->nprim.end());
+        cen.insert(cen.end(), b->cen.begin(), b->cen.end());
+        exps.insert(exps.end(), b->exps.begin(), b->exps.end());
+        coefs.insert(coefs.end(), b->coefs.begin(), b->coefs.end());
+        sys.insert(sys.end(), (size_t)b->nshell, k);
+        R.push_back(nbf);
+        N.push_back(b->nbf);
+        nbf += b->nbf;
+    }
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || cur != dev) return fail(HGP_E_INVALID, "the bases' device is not current");
+    hgp_basis *u = nullptr;
+    hgp_status st = hgp_basis_create((int32_t)l.size(), l.data(), nprim.data(), cen.data(), exps.data(), coefs.data(), &u);
+    if (st) return st;
+    if (u->lmax > built_max_l()) {
+        hgp_basis_destroy(u);
+        return fail(HGP_E_UNSUPPORTED_L, "basis has l above the classes built into this library");
+    }
+    auto *p = new hgp_plan();
+    p->b = u;
+    p->owned = u;
+    p->device = u->device;
+    p->theta = theta > schwarz_tau ? theta : 0.0;
+    p->nsys = n;
+    p->shell_sys.assign(sys.begin(), sys.end());
+    p->sys_R = R;
+    p->sys_N = N;
+    st = plan_build(p, schwarz_tau, hbm_budget_bytes, (hipStream_t)hip_stream);
+    if (st != HGP_OK) {
+        hgp_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return HGP_OK;
 }
 
 hgp_status hgp_plan_stats(const hgp_plan *p, int64_t *kept, int64_t *total, int64_t *bytes)
@@ -759,21 +868,13 @@ hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int32_t kernel, int64_t
     return HGP_OK;
 }
 
-hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_stream)
+// The class lists of a plan over D (laid out like the accumulators) into the
+// unsymmetrised accumulators, which the caller has cleared.
+static hgp_status jk_classes(hgp_plan *p, const double *D, bool want_j, bool want_k, hipStream_t s)
 {
-    if (!p) return fail(HGP_E_INVALID, "plan is NULL");
-    if (p->broken) return fail(HGP_E_STATE, "plan unusable after an earlier device failure");
-    const int n = p->b->nbf;
-    if (n == 0) return HGP_OK;                       // empty basis: J and K are 0 x 0
-    if (!D) return fail(HGP_E_INVALID, "D is NULL");
-    if (!J && !K) return fail(HGP_E_INVALID, "both J and K are NULL");
-    hipStream_t s = (hipStream_t)hip_stream;
-    const int64_t nn = (int64_t)n * n;
     const double *boys = nullptr;
     hgp_status st = boys_table(p->device, &boys);
     if (st) return st;
-    if (J) launch_fill_zero(p->d_Jacc, nn, s);
-    if (K) launch_fill_zero(p->d_Kacc, nn, s);
     auto mark = [&](hipEvent_t *e) -> hgp_status {
         *e = nullptr;
         if (!p->timing) return HGP_OK;
@@ -791,8 +892,8 @@ hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_
         const ClassKernels &k = g_class_table[cl.cls];
         JKArgs a{};
         a.pairs = p->d_pairs; a.geo = p->d_geo; a.prims = p->d_prims; a.boys = boys;
-        a.D = D; a.J = p->d_Jacc; a.K = p->d_Kacc; a.nbf = n;
-        a.want_j = J != nullptr; a.want_k = K != nullptr;
+        a.D = D; a.J = p->d_Jacc; a.K = p->d_Kacc; a.nbf = (int32_t)p->stride;
+        a.want_j = want_j; a.want_k = want_k;
         hipEvent_t e0, e1, e2, e3;
         if (k.tier == 0 || k.tier == 3) {                // register or wave-cooperative LDS tier
             if ((st = mark(&e0))) return st;
@@ -832,14 +933,80 @@ hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_
             }
         }
     }
-    if (J) launch_symmetrize(p->d_Jacc, J, n, s);
-    if (K) launch_symmetrize(p->d_Kacc, K, n, s);
+    return HGP_OK;
+}
+
+static hgp_status launch_status(hgp_plan *p)
+{
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         p->broken = true;
         return fail(HGP_E_DEVICE, std::string("J/K launch failed: ") + hipGetErrorString(e));
     }
     return HGP_OK;
+}
+
+hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_stream)
+{
+    if (!p) return fail(HGP_E_INVALID, "plan is NULL");
+    if (p->broken) return fail(HGP_E_STATE, "plan unusable after an earlier device failure");
+    if (p->nsys > 1) return fail(HGP_E_INVALID, "the plan covers several systems: use hgp_jk_multi");
+    const int n = p->b->nbf;
+    if (n == 0) return HGP_OK;                       // empty basis: J and K are 0 x 0
+    if (!D) return fail(HGP_E_INVALID, "D is NULL");
+    if (!J && !K) return fail(HGP_E_INVALID, "both J and K are NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (J) launch_fill_zero(p->d_Jacc, p->acc_len, s);
+    if (K) launch_fill_zero(p->d_Kacc, p->acc_len, s);
+    hgp_status st = jk_classes(p, D, J != nullptr, K != nullptr, s);
+    if (st) return st;
+    if (J) launch_symmetrize(p->d_Jacc, n, J, n, s);
+    if (K) launch_symmetrize(p->d_Kacc, n, K, n, s);
+    return launch_status(p);
+}
+
+hgp_status hgp_jk_multi(hgp_plan *p, const double *const *D, double *const *J, double *const *K, void *hip_stream)
+{
+    if (!p) return fail(HGP_E_INVALID, "plan is NULL");
+    if (p->broken) return fail(HGP_E_STATE, "plan unusable after an earlier device failure");
+    if (!D) return fail(HGP_E_INVALID, "D is NULL");
+    const bool want_j = J != nullptr, want_k = K != nullptr;
+    if (!want_j && !want_k) return fail(HGP_E_INVALID, "both J and K are NULL");
+    for (int sy = 0; sy < p->nsys; ++sy) {
+        if (p->sys_N[(size_t)sy] == 0) continue;
+        if (!D[sy] || (want_j && !J[sy]) || (want_k && !K[sy]))
+            return fail(HGP_E_INVALID, "a system of the plan has no D, J or K");
+    }
+    if (p->b->nbf == 0) return HGP_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (p->nsys == 1) {                          // a one-system plan: the plain path
+        if (want_j) launch_fill_zero(p->d_Jacc, p->acc_len, s);
+        if (want_k) launch_fill_zero(p->d_Kacc, p->acc_len, s);
+        hgp_status st = jk_classes(p, D[0], want_j, want_k, s);
+        if (st) return st;
+        const int n = p->b->nbf;
+        if (want_j) launch_symmetrize(p->d_Jacc, n, J[0], n, s);
+        if (want_k) launch_symmetrize(p->d_Kacc, n, K[0], n, s);
+        return launch_status(p);
+    }
+    // each system's density into its block; its accumulator blocks cleared
+    const int64_t S = p->stride;
+    for (int sy = 0; sy < p->nsys; ++sy) {
+        const int n = p->sys_N[(size_t)sy];
+        const int64_t base = (int64_t)p->sys_R[(size_t)sy] * (S + 1);
+        launch_block_in(D[sy], n, p->d_Dunion + base, S, s);
+        if (want_j) launch_block_zero(p->d_Jacc + base, n, S, s);
+        if (want_k) launch_block_zero(p->d_Kacc + base, n, S, s);
+    }
+    hgp_status st = jk_classes(p, p->d_Dunion, want_j, want_k, s);
+    if (st) return st;
+    for (int sy = 0; sy < p->nsys; ++sy) {
+        const int n = p->sys_N[(size_t)sy];
+        const int64_t base = (int64_t)p->sys_R[(size_t)sy] * (S + 1);
+        if (want_j) launch_symmetrize(p->d_Jacc + base, S, J[sy], n, s);
+        if (want_k) launch_symmetrize(p->d_Kacc + base, S, K[sy], n, s);
+    }
+    return launch_status(p);
 }
 
 hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartets, const int64_t *offsets,
