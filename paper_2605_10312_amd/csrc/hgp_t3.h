@@ -34,13 +34,14 @@ struct T3Class {
     const T3Class *lane;         // gslots: the lane-per-quartet tables, run for batches of T3G_LANE_MIN or more
 };
 
-// Wave-cooperative variant (tier 3): the same tables regrouped 64 ops a
-// group; one wavefront per quartet holds every slot in LDS and lane j runs op
-// j of each group.  Absent operands name the zero slot nslots; padding ops
+// Wave-cooperative variant (tier 3): the same tables regrouped T3W_OPS ops a
+// group; one wavefront per quartet holds every slot in LDS and lane j runs
+// ops j and j + 64 of each group.  Absent operands name the zero slot nslots; padding ops
 // write the sink slot nslots + 1.  A class whose slots do not fit in LDS
 // (gslots = 1, tier 2) keeps them in a per-quartet region of the scratch
 // buffer instead, quartet i of a batch at scratch[i * (nslots + 2)].
-constexpr int T3W_GROUP = 64;
+constexpr int T3W_GROUP = 64;    // lanes of the wavefront that runs one quartet
+constexpr int T3W_OPS = 128;     // ops per group: each lane runs ops lane and lane + 64
 constexpr int T3W_PREFETCH = 1;  // groups whose ops are in flight ahead of the running one
 constexpr int T3G_CHUNK = 1024;  // quartets per launch of the wave form with its slots in the buffer
 

@@ -301,9 +301,9 @@ __global__ __launch_bounds__(64) void t3_eri_kernel(T3Params c, const uint4 *__r
 // ---------------------------------------------------------------------------
 // Wave-cooperative LDS variant.  One 64-lane workgroup per quartet; LDS holds
 // [slots | Z | sink | coefficients | six D blocks] as doubles, then the
-// uint16 output-slot map.  Lane j runs op j of every group.  A group's ops
-// are independent of one another, so each lane reads its operands before any
-// lane of the group writes; successive groups see each other's writes
+// uint16 output-slot map.  Lane j runs ops j and j + 64 of every group.  A
+// group's ops are independent of one another, so each lane reads its
+// operands before any lane of the group writes; successive groups see each other's writes
 // because LDS instructions of one wavefront execute in issue order.  The
 // wave barrier below only stops the compiler from moving LDS accesses
 // across a group boundary (it emits no instruction).
@@ -368,11 +368,13 @@ struct T3WPrim {
     double o2ze;
 };
 
-__device__ __forceinline__ void t3w_vrr_group(const uint4 o, const T3WPrim &q, double *__restrict__ S)
+// Each lane runs two ops of a group of T3W_OPS: op lane and op lane + 64.
+// All operand reads of both are issued before either result is computed, so
+// one memory latency covers both; the results are written last.
+__device__ __forceinline__ double t3w_vrr_op(const uint4 o, const double v1, const double v2, const double v3,
+                                             const double v4, const double v5, const T3WPrim &q)
 {
     const uint32_t w0 = o.x & 0xFFFFu;
-    const double v1 = S[o.y & 0xFFFFu], v2 = S[o.y >> 16], v3 = S[o.z & 0xFFFFu], v4 = S[o.z >> 16],
-                 v5 = S[o.w & 0xFFFFu];
     const bool bra = (w0 & 15u) == (uint32_t)T3_VRR_BRA;
     const uint32_t axis = (w0 >> 4) & 3u;
     // value selects (unary + makes each operand a value, so no select of
@@ -385,39 +387,63 @@ __device__ __forceinline__ void t3w_vrr_group(const uint4 o, const T3WPrim &q, d
     double v = fma(X, v1, Y * v2);
     v = fma((double)((w0 >> 6) & 31u) * o2, fma(-r, v4, v3), v);
     v = fma((double)((w0 >> 11) & 31u) * q.o2ze, v5, v);
-    S[o.x >> 16] = v;
+    return v;
 }
 
-__device__ __forceinline__ void t3w_acc_group(const uint4 o, double *__restrict__ S)
+__device__ __forceinline__ void t3w_vrr_group(const uint4 a, const uint4 b, const T3WPrim &q, double *__restrict__ S)
 {
-    const uint32_t d = o.x >> 16;
-    const double x = S[d], y = S[o.y & 0xFFFFu];
-    S[d] = x + y;
+    const double a1 = S[a.y & 0xFFFFu], a2 = S[a.y >> 16], a3 = S[a.z & 0xFFFFu], a4 = S[a.z >> 16],
+                 a5 = S[a.w & 0xFFFFu];
+    const double b1 = S[b.y & 0xFFFFu], b2 = S[b.y >> 16], b3 = S[b.z & 0xFFFFu], b4 = S[b.z >> 16],
+                 b5 = S[b.w & 0xFFFFu];
+    const double ra = t3w_vrr_op(a, a1, a2, a3, a4, a5, q);
+    const double rb = t3w_vrr_op(b, b1, b2, b3, b4, b5, q);
+    S[a.x >> 16] = ra;
+    S[b.x >> 16] = rb;
+}
+
+__device__ __forceinline__ void t3w_acc_group(const uint4 a, const uint4 b, double *__restrict__ S)
+{
+    const uint32_t da = a.x >> 16, db = b.x >> 16;
+    const double xa = S[da], ya = S[a.y & 0xFFFFu], xb = S[db], yb = S[b.y & 0xFFFFu];
+    S[da] = xa + ya;
+    S[db] = xb + yb;
 }
 
 struct T3WHrr {
     double abx, aby, abz, cdx, cdy, cdz;
 };
 
-__device__ __forceinline__ void t3w_hrr_group(const uint4 o, const T3WHrr &h, double *__restrict__ S)
+__device__ __forceinline__ double t3w_hrr_d(const uint4 o, const T3WHrr &h)
 {
     const uint32_t code = o.x & 15u, axis = (o.x >> 4) & 3u;
-    const double hi = S[o.y & 0xFFFFu], lo = S[o.y >> 16];
     const bool bra = code == (uint32_t)T3_HRR_BRA;
     const double d0 = bra ? +h.abx : +h.cdx, d1 = bra ? +h.aby : +h.cdy, d2 = bra ? +h.abz : +h.cdz;
-    const double d = axis == 0 ? d0 : (axis == 1 ? d1 : d2);
-    S[o.x >> 16] = fma(d, lo, hi);
+    return axis == 0 ? d0 : (axis == 1 ? d1 : d2);
 }
 
-__device__ __forceinline__ void t3w_lin_group(const uint4 o, const double *__restrict__ C, double *__restrict__ S)
+__device__ __forceinline__ void t3w_hrr_group(const uint4 a, const uint4 b, const T3WHrr &h, double *__restrict__ S)
 {
-    const uint32_t d = o.x >> 16;
-    const double x1 = S[o.y & 0xFFFFu], x2 = S[o.y >> 16], x3 = S[o.z & 0xFFFFu];
-    const double acc = (o.x & 15u) == (uint32_t)T3_LIN_ACC ? S[d] : 0.0;
-    double v = fma(C[o.z >> 16], x1, acc);
-    v = fma(C[o.w & 0xFFFFu], x2, v);
-    v = fma(C[o.w >> 16], x3, v);
-    S[d] = v;
+    const double ha = S[a.y & 0xFFFFu], la = S[a.y >> 16], hb = S[b.y & 0xFFFFu], lb = S[b.y >> 16];
+    const double ra = fma(t3w_hrr_d(a, h), la, ha), rb = fma(t3w_hrr_d(b, h), lb, hb);
+    S[a.x >> 16] = ra;
+    S[b.x >> 16] = rb;
+}
+
+__device__ __forceinline__ void t3w_lin_group(const uint4 a, const uint4 b, const double *__restrict__ C,
+                                              double *__restrict__ S)
+{
+    const uint32_t da = a.x >> 16, db = b.x >> 16;
+    const double a1 = S[a.y & 0xFFFFu], a2 = S[a.y >> 16], a3 = S[a.z & 0xFFFFu];
+    const double b1 = S[b.y & 0xFFFFu], b2 = S[b.y >> 16], b3 = S[b.z & 0xFFFFu];
+    const double aacc = (a.x & 15u) == (uint32_t)T3_LIN_ACC ? S[da] : 0.0;
+    const double bacc = (b.x & 15u) == (uint32_t)T3_LIN_ACC ? S[db] : 0.0;
+    const double ca1 = C[a.z >> 16], ca2 = C[a.w & 0xFFFFu], ca3 = C[a.w >> 16];
+    const double cb1 = C[b.z >> 16], cb2 = C[b.w & 0xFFFFu], cb3 = C[b.w >> 16];
+    const double ra = fma(ca3, a3, fma(ca2, a2, fma(ca1, a1, aacc)));
+    const double rb = fma(cb3, b3, fma(cb2, b2, fma(cb1, b1, bacc)));
+    S[da] = ra;
+    S[db] = rb;
 }
 
 // The quartet's integrals into their output slots (LDS), as t3_quartet.
@@ -452,17 +478,18 @@ __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__r
             const double T = b.zeta * q.rz * (PQx * PQx + PQy * PQy + PQz * PQz);
             t3w_boys(T, c.L, boys, b.k * e.k * hgp_rsqrt(ze), S, lane);
             t3w_sync<G>();
-            // groups of 64 ops; the next group's op is loaded while this one runs
-            // (the table ends in a padding group)
-            const int ng = c.n_vrr / T3W_GROUP;
-            uint4 nxt = myops[0];
+            // groups of T3W_OPS ops, two per lane; the next group's ops are
+            // loaded while this one runs (the table ends in a padding group)
+            const int ng = c.n_vrr / T3W_OPS;
+            uint4 na = myops[0], nb = myops[T3W_GROUP];
             for (int g = 0; g < ng; ++g) {
-                const uint4 o = nxt;
-                nxt = myops[(size_t)(g + 1) * T3W_GROUP];
-                if ((__builtin_amdgcn_readfirstlane(o.x) & 15u) == (uint32_t)T3_ACC)
-                    t3w_acc_group(o, S);
+                const uint4 oa = na, ob = nb;
+                na = myops[(size_t)(g + 1) * T3W_OPS];
+                nb = myops[(size_t)(g + 1) * T3W_OPS + T3W_GROUP];
+                if ((__builtin_amdgcn_readfirstlane(oa.x) & 15u) == (uint32_t)T3_ACC)
+                    t3w_acc_group(oa, ob, S);
                 else
-                    t3w_vrr_group(o, q, S);
+                    t3w_vrr_group(oa, ob, q, S);
                 t3w_sync<G>();
             }
         }
@@ -470,16 +497,17 @@ __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__r
     // Phase 2: HRR and the stepwise transforms (Eq. hrr, Eqs. bra-sph .. stepwise-sph)
     const T3WHrr h{gb.abx, gb.aby, gb.abz, gk.abx, gk.aby, gk.abz};
     const uint4 *__restrict__ p2 = myops + (size_t)c.n_vrr;
-    const int ng = c.n_p2 / T3W_GROUP;
-    uint4 nxt = p2[0];
+    const int ng = c.n_p2 / T3W_OPS;
+    uint4 na = p2[0], nb = p2[T3W_GROUP];
     for (int g = 0; g < ng; ++g) {
-        const uint4 o = nxt;
-        nxt = p2[(size_t)(g + 1) * T3W_GROUP];
-        const uint32_t cls = __builtin_amdgcn_readfirstlane(o.x) & 15u;
+        const uint4 oa = na, ob = nb;
+        na = p2[(size_t)(g + 1) * T3W_OPS];
+        nb = p2[(size_t)(g + 1) * T3W_OPS + T3W_GROUP];
+        const uint32_t cls = __builtin_amdgcn_readfirstlane(oa.x) & 15u;
         if (cls == (uint32_t)T3_HRR_BRA || cls == (uint32_t)T3_HRR_KET)
-            t3w_hrr_group(o, h, S);
+            t3w_hrr_group(oa, ob, h, S);
         else
-            t3w_lin_group(o, C, S);
+            t3w_lin_group(oa, ob, C, S);
         t3w_sync<G>();
     }
 }
@@ -649,7 +677,7 @@ hipError_t t3_device_tables(const T3Class &c, T3Dev *out)
     }
     // zero groups past the end: the wave variant loads group g + 1 while it runs group g
     const size_t nops = (size_t)(c.n_vrr + c.n_p2), nout = (size_t)c.na * c.nb * c.nc * c.nd;
-    const size_t npad = (size_t)T3W_PREFETCH * T3W_GROUP;
+    const size_t npad = (size_t)T3W_PREFETCH * T3W_OPS;
     void *ops = nullptr, *coefs = nullptr, *outs = nullptr;
     if ((e = hipMalloc(&ops, (nops + npad) * 16)) != hipSuccess ||
         (e = hipMemset(ops, 0, (nops + npad) * 16)) != hipSuccess ||

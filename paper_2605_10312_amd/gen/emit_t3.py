@@ -262,7 +262,7 @@ def build_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None, bundle=BUNDLE)
                     n_real)
 
 
-WAVE = 64               # ops per group of the wave-cooperative variant: one op per lane
+WAVE = 128              # ops per group of the wave-cooperative variant: two per lane of a wavefront
 WAVE_LDS_MAX = 163840   # bytes of LDS one workgroup of that variant may take (gfx950: 160 KB per CU)
 GSLOT_MAX_BATCH = 1024  # quartets per launch when the slots live in the scratch buffer (~190 MB for (gg|gg));
                         # batches of T3G_LANE_MIN (csrc/hgp_types.h) or more run the lane-per-quartet tables
@@ -270,9 +270,9 @@ GSLOT_MAX_BATCH = 1024  # quartets per launch when the slots live in the scratch
 
 @dataclasses.dataclass
 class WaveTables:
-    """The op tables regrouped 64 ops a group for the wave-cooperative
-    variant (one wavefront per quartet, its slots in LDS, lane j running op
-    j of every group).  Operand fields that the HBM form marks absent name
+    """The op tables regrouped WAVE ops a group for the wave-cooperative
+    variant (one wavefront per quartet, its slots in LDS, lane j running ops
+    j and j + 64 of every group).  Operand fields that the HBM form marks absent name
     the zero slot Z = nslots; padding ops write the sink slot nslots + 1 and
     read Z (transform padding reads coefficient 0)."""
     t: T3Tables

@@ -108,7 +108,7 @@ def test_t3_tables_match_oracle(ls, n):
 @pytest.mark.parametrize("ls,n", [((1, 0, 1, 0), 4), ((2, 2, 1, 1), 3), ((3, 2, 1, 0), 3), ((3, 3, 2, 1), 2),
                                   ((4, 1, 3, 0), 2)])
 def test_wave_tables_match_oracle(ls, n):
-    """The wave-cooperative form: 64-op groups, absent operands naming the
+    """The wave-cooperative form: 128-op groups, absent operands naming the
     zero slot, padding ops writing the sink slot and reading only zeros."""
     w = emit_t3.build_wave_tables(*ls)
     t = w.t
