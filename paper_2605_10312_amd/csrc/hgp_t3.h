@@ -41,7 +41,7 @@ struct T3Class {
 // (gslots = 1, tier 2) keeps them in a per-quartet region of the scratch
 // buffer instead, quartet i of a batch at scratch[i * (nslots + 2)].
 constexpr int T3W_GROUP = 64;    // lanes of the wavefront that runs one quartet
-constexpr int T3W_OPS = 128;     // ops per group: each lane runs ops lane and lane + 64
+constexpr int T3W_OPS = 128;     // ops per group: each lane runs ops lane and lane + 64 (four a lane measured slower: more padding)
 constexpr int T3W_PREFETCH = 1;  // groups whose ops are in flight ahead of the running one
 constexpr int T3G_CHUNK = 1024;  // quartets per launch of the wave form with its slots in the buffer
 

@@ -368,46 +368,54 @@ struct T3WPrim {
     double o2ze;
 };
 
-// Each lane runs two ops of a group of T3W_OPS: op lane and op lane + 64.
-// All operand reads of both are issued before either result is computed, so
-// one memory latency covers both; the results are written last.
-__device__ __forceinline__ double t3w_vrr_op(const uint4 o, const double v1, const double v2, const double v3,
-                                             const double v4, const double v5, const T3WPrim &q)
+// Each lane runs T3W_K ops of a group of T3W_OPS: ops lane, lane + 64, ...
+// All operand reads of its ops are issued before any result is computed, so
+// one memory latency covers them all; the results are written last.
+constexpr int T3W_K = T3W_OPS / T3W_GROUP;
+
+// The per-primitive constants of the VRR as an LDS record R (16 doubles):
+// (X, Y) = (P-A, W-P) or (Q-C, W-Q) along axis a at R[2 (3 side + a)], and
+// (1/(2 zeta), rho/zeta) or (1/(2 eta), rho/eta) at R[12 + 2 side], side 0
+// for the bra.  An op reads its pairs with two 16-byte loads instead of
+// selecting among twelve values.
+__device__ __forceinline__ void t3w_vrr_group(const uint4 *o, const double *__restrict__ R, double o2ze,
+                                              double *__restrict__ S)
 {
-    const uint32_t w0 = o.x & 0xFFFFu;
-    const bool bra = (w0 & 15u) == (uint32_t)T3_VRR_BRA;
-    const uint32_t axis = (w0 >> 4) & 3u;
-    // value selects (unary + makes each operand a value, so no select of
-    // addresses into the struct is formed)
-    const double X0 = bra ? +q.PAx : +q.QCx, X1 = bra ? +q.PAy : +q.QCy, X2 = bra ? +q.PAz : +q.QCz;
-    const double Y0 = bra ? +q.WPx : +q.WQx, Y1 = bra ? +q.WPy : +q.WQy, Y2 = bra ? +q.WPz : +q.WQz;
-    const double X = axis == 0 ? X0 : (axis == 1 ? X1 : X2);
-    const double Y = axis == 0 ? Y0 : (axis == 1 ? Y1 : Y2);
-    const double o2 = bra ? +q.o2z : +q.o2e, r = bra ? +q.rz : +q.re;
-    double v = fma(X, v1, Y * v2);
-    v = fma((double)((w0 >> 6) & 31u) * o2, fma(-r, v4, v3), v);
-    v = fma((double)((w0 >> 11) & 31u) * q.o2ze, v5, v);
-    return v;
+    double v[T3W_K][5];
+    double2 xy[T3W_K], or_[T3W_K];
+#pragma unroll
+    for (int k = 0; k < T3W_K; ++k) {
+        const uint32_t side = (o[k].x & 15u) == (uint32_t)T3_VRR_BRA ? 0u : 1u, axis = (o[k].x >> 4) & 3u;
+        v[k][0] = S[o[k].y & 0xFFFFu];
+        v[k][1] = S[o[k].y >> 16];
+        v[k][2] = S[o[k].z & 0xFFFFu];
+        v[k][3] = S[o[k].z >> 16];
+        v[k][4] = S[o[k].w & 0xFFFFu];
+        xy[k] = *(const double2 *)(R + 2 * (3 * side + axis));
+        or_[k] = *(const double2 *)(R + 12 + 2 * side);
+    }
+    double r[T3W_K];
+#pragma unroll
+    for (int k = 0; k < T3W_K; ++k) {
+        const uint32_t w0 = o[k].x;
+        double t = fma(xy[k].x, v[k][0], xy[k].y * v[k][1]);
+        t = fma((double)((w0 >> 6) & 31u) * or_[k].x, fma(-or_[k].y, v[k][3], v[k][2]), t);
+        r[k] = fma((double)((w0 >> 11) & 31u) * o2ze, v[k][4], t);
+    }
+#pragma unroll
+    for (int k = 0; k < T3W_K; ++k) S[o[k].x >> 16] = r[k];
 }
 
-__device__ __forceinline__ void t3w_vrr_group(const uint4 a, const uint4 b, const T3WPrim &q, double *__restrict__ S)
+__device__ __forceinline__ void t3w_acc_group(const uint4 *o, double *__restrict__ S)
 {
-    const double a1 = S[a.y & 0xFFFFu], a2 = S[a.y >> 16], a3 = S[a.z & 0xFFFFu], a4 = S[a.z >> 16],
-                 a5 = S[a.w & 0xFFFFu];
-    const double b1 = S[b.y & 0xFFFFu], b2 = S[b.y >> 16], b3 = S[b.z & 0xFFFFu], b4 = S[b.z >> 16],
-                 b5 = S[b.w & 0xFFFFu];
-    const double ra = t3w_vrr_op(a, a1, a2, a3, a4, a5, q);
-    const double rb = t3w_vrr_op(b, b1, b2, b3, b4, b5, q);
-    S[a.x >> 16] = ra;
-    S[b.x >> 16] = rb;
-}
-
-__device__ __forceinline__ void t3w_acc_group(const uint4 a, const uint4 b, double *__restrict__ S)
-{
-    const uint32_t da = a.x >> 16, db = b.x >> 16;
-    const double xa = S[da], ya = S[a.y & 0xFFFFu], xb = S[db], yb = S[b.y & 0xFFFFu];
-    S[da] = xa + ya;
-    S[db] = xb + yb;
+    double x[T3W_K], y[T3W_K];
+#pragma unroll
+    for (int k = 0; k < T3W_K; ++k) {
+        x[k] = S[o[k].x >> 16];
+        y[k] = S[o[k].y & 0xFFFFu];
+    }
+#pragma unroll
+    for (int k = 0; k < T3W_K; ++k) S[o[k].x >> 16] = x[k] + y[k];
 }
 
 struct T3WHrr {
@@ -422,28 +430,34 @@ __device__ __forceinline__ double t3w_hrr_d(const uint4 o, const T3WHrr &h)
     return axis == 0 ? d0 : (axis == 1 ? d1 : d2);
 }
 
-__device__ __forceinline__ void t3w_hrr_group(const uint4 a, const uint4 b, const T3WHrr &h, double *__restrict__ S)
+__device__ __forceinline__ void t3w_hrr_group(const uint4 *o, const T3WHrr &h, double *__restrict__ S)
 {
-    const double ha = S[a.y & 0xFFFFu], la = S[a.y >> 16], hb = S[b.y & 0xFFFFu], lb = S[b.y >> 16];
-    const double ra = fma(t3w_hrr_d(a, h), la, ha), rb = fma(t3w_hrr_d(b, h), lb, hb);
-    S[a.x >> 16] = ra;
-    S[b.x >> 16] = rb;
+    double hi[T3W_K], lo[T3W_K];
+#pragma unroll
+    for (int k = 0; k < T3W_K; ++k) {
+        hi[k] = S[o[k].y & 0xFFFFu];
+        lo[k] = S[o[k].y >> 16];
+    }
+#pragma unroll
+    for (int k = 0; k < T3W_K; ++k) S[o[k].x >> 16] = fma(t3w_hrr_d(o[k], h), lo[k], hi[k]);
 }
 
-__device__ __forceinline__ void t3w_lin_group(const uint4 a, const uint4 b, const double *__restrict__ C,
-                                              double *__restrict__ S)
+__device__ __forceinline__ void t3w_lin_group(const uint4 *o, const double *__restrict__ C, double *__restrict__ S)
 {
-    const uint32_t da = a.x >> 16, db = b.x >> 16;
-    const double a1 = S[a.y & 0xFFFFu], a2 = S[a.y >> 16], a3 = S[a.z & 0xFFFFu];
-    const double b1 = S[b.y & 0xFFFFu], b2 = S[b.y >> 16], b3 = S[b.z & 0xFFFFu];
-    const double aacc = (a.x & 15u) == (uint32_t)T3_LIN_ACC ? S[da] : 0.0;
-    const double bacc = (b.x & 15u) == (uint32_t)T3_LIN_ACC ? S[db] : 0.0;
-    const double ca1 = C[a.z >> 16], ca2 = C[a.w & 0xFFFFu], ca3 = C[a.w >> 16];
-    const double cb1 = C[b.z >> 16], cb2 = C[b.w & 0xFFFFu], cb3 = C[b.w >> 16];
-    const double ra = fma(ca3, a3, fma(ca2, a2, fma(ca1, a1, aacc)));
-    const double rb = fma(cb3, b3, fma(cb2, b2, fma(cb1, b1, bacc)));
-    S[da] = ra;
-    S[db] = rb;
+    double x[T3W_K][4], c[T3W_K][3];
+#pragma unroll
+    for (int k = 0; k < T3W_K; ++k) {
+        x[k][0] = S[o[k].y & 0xFFFFu];
+        x[k][1] = S[o[k].y >> 16];
+        x[k][2] = S[o[k].z & 0xFFFFu];
+        x[k][3] = (o[k].x & 15u) == (uint32_t)T3_LIN_ACC ? S[o[k].x >> 16] : 0.0;
+        c[k][0] = C[o[k].z >> 16];
+        c[k][1] = C[o[k].w & 0xFFFFu];
+        c[k][2] = C[o[k].w >> 16];
+    }
+#pragma unroll
+    for (int k = 0; k < T3W_K; ++k)
+        S[o[k].x >> 16] = fma(c[k][2], x[k][2], fma(c[k][1], x[k][1], fma(c[k][0], x[k][0], x[k][3])));
 }
 
 // The quartet's integrals into their output slots (LDS), as t3_quartet.
@@ -451,7 +465,7 @@ template <bool G>
 __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__restrict__ ops, const PairInfo &pb,
                             const PairGeo &gb, const PairInfo &pk, const PairGeo &gk,
                             const PrimPair *__restrict__ prims, const double *__restrict__ boys, double *__restrict__ S,
-                            const double *__restrict__ C, int lane)
+                            const double *__restrict__ C, double *__restrict__ R, int lane)
 {
     for (int k = lane; k < c.n_hrr; k += T3W_GROUP) S[c.acc0 + k] = 0.0;
     if (lane == 0) S[c.nslots] = 0.0;                       // the zero slot
@@ -477,19 +491,32 @@ __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__r
             q.WQx = q.re * PQx; q.WQy = q.re * PQy; q.WQz = q.re * PQz;
             const double T = b.zeta * q.rz * (PQx * PQx + PQy * PQy + PQz * PQz);
             t3w_boys(T, c.L, boys, b.k * e.k * hgp_rsqrt(ze), S, lane);
+            if (lane < 16) {                                // the constants record, one value a lane
+                const double rv[16] = {q.PAx, q.WPx, q.PAy, q.WPy, q.PAz, q.WPz, q.QCx, q.WQx,
+                                       q.QCy, q.WQy, q.QCz, q.WQz, q.o2z, q.rz,  q.o2e, q.re};
+                double x = rv[0];
+#pragma unroll
+                for (int j = 1; j < 16; ++j) x = lane == j ? rv[j] : x;
+                R[lane] = x;
+            }
             t3w_sync<G>();
             // groups of T3W_OPS ops, two per lane; the next group's ops are
             // loaded while this one runs (the table ends in a padding group)
             const int ng = c.n_vrr / T3W_OPS;
-            uint4 na = myops[0], nb = myops[T3W_GROUP];
+            uint4 nx[T3W_K];
+#pragma unroll
+            for (int k = 0; k < T3W_K; ++k) nx[k] = myops[k * T3W_GROUP];
             for (int g = 0; g < ng; ++g) {
-                const uint4 oa = na, ob = nb;
-                na = myops[(size_t)(g + 1) * T3W_OPS];
-                nb = myops[(size_t)(g + 1) * T3W_OPS + T3W_GROUP];
-                if ((__builtin_amdgcn_readfirstlane(oa.x) & 15u) == (uint32_t)T3_ACC)
-                    t3w_acc_group(oa, ob, S);
+                uint4 o[T3W_K];
+#pragma unroll
+                for (int k = 0; k < T3W_K; ++k) {
+                    o[k] = nx[k];
+                    nx[k] = myops[(size_t)(g + 1) * T3W_OPS + k * T3W_GROUP];
+                }
+                if ((__builtin_amdgcn_readfirstlane(o[0].x) & 15u) == (uint32_t)T3_ACC)
+                    t3w_acc_group(o, S);
                 else
-                    t3w_vrr_group(oa, ob, q, S);
+                    t3w_vrr_group(o, R, q.o2ze, S);
                 t3w_sync<G>();
             }
         }
@@ -498,25 +525,30 @@ __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__r
     const T3WHrr h{gb.abx, gb.aby, gb.abz, gk.abx, gk.aby, gk.abz};
     const uint4 *__restrict__ p2 = myops + (size_t)c.n_vrr;
     const int ng = c.n_p2 / T3W_OPS;
-    uint4 na = p2[0], nb = p2[T3W_GROUP];
+    uint4 nx[T3W_K];
+#pragma unroll
+    for (int k = 0; k < T3W_K; ++k) nx[k] = p2[k * T3W_GROUP];
     for (int g = 0; g < ng; ++g) {
-        const uint4 oa = na, ob = nb;
-        na = p2[(size_t)(g + 1) * T3W_OPS];
-        nb = p2[(size_t)(g + 1) * T3W_OPS + T3W_GROUP];
-        const uint32_t cls = __builtin_amdgcn_readfirstlane(oa.x) & 15u;
+        uint4 o[T3W_K];
+#pragma unroll
+        for (int k = 0; k < T3W_K; ++k) {
+            o[k] = nx[k];
+            nx[k] = p2[(size_t)(g + 1) * T3W_OPS + k * T3W_GROUP];
+        }
+        const uint32_t cls = __builtin_amdgcn_readfirstlane(o[0].x) & 15u;
         if (cls == (uint32_t)T3_HRR_BRA || cls == (uint32_t)T3_HRR_KET)
-            t3w_hrr_group(oa, ob, h, S);
+            t3w_hrr_group(o, h, S);
         else
-            t3w_lin_group(oa, ob, C, S);
+            t3w_lin_group(o, C, S);
         t3w_sync<G>();
     }
 }
 
 // LDS of one workgroup: S (slots, Z, sink; in global memory when G),
 // C (coefficients), Db (six D blocks), O (output slot of integral
-// (mu, nu, lam, sig), row-major).
+// (mu, nu, lam, sig), row-major), R (the 16 per-primitive VRR constants).
 struct T3WLds {
-    double *S, *C, *Db;
+    double *S, *C, *Db, *R;
     uint16_t *O;
 };
 
@@ -530,6 +562,7 @@ __device__ __forceinline__ T3WLds t3w_lds(const T3WParams &c, double *base, doub
     l.C = G ? base : base + c.nslots + 2;
     l.Db = l.C + c.ncoef;
     l.O = (uint16_t *)(l.Db + 6 * c.maxblk);
+    l.R = (double *)((char *)l.O + ((2 * c.nint + 15) / 16) * 16);      // 16-byte aligned
     for (int k = lane; k < c.ncoef; k += T3W_GROUP) l.C[k] = coefs[k];
     for (int k = lane; k < c.nint; k += T3W_GROUP) l.O[k] = outslots[k];
     return l;
@@ -566,7 +599,7 @@ __global__ __launch_bounds__(64) void t3w_jk_kernel(T3WParams c, const uint4 *__
         for (int k = lane; k < nb * nc; k += T3W_GROUP) Dbc[k] = D[(fb + k / nc) * N + fc + k % nc];
         for (int k = lane; k < na * nc; k += T3W_GROUP) Dac[k] = D[(fa + k / nc) * N + fc + k % nc];
     }
-    t3w_quartet<G>(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, lane);
+    t3w_quartet<G>(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, l.R, lane);
     const double *__restrict__ S = l.S;
     const uint16_t *__restrict__ O = l.O;
     auto I = [&](int mu, int nu, int lam, int sig) -> double {
@@ -637,7 +670,7 @@ __global__ __launch_bounds__(64) void t3w_eri_kernel(T3WParams c, const uint4 *_
     const EriTask t = a.tasks[i];
     const PairInfo pb = a.pairs[t.bra], pk = a.pairs[t.ket];
     const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];
-    t3w_quartet<G>(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, lane);
+    t3w_quartet<G>(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, l.R, lane);
     const int na = c.na, nb = c.nb, nc = c.nc, nd = c.nd;
     if (a.mode == 1) {                       // Schwarz factor of a diagonal quartet
         double m = 0.0;

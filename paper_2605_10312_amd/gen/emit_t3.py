@@ -290,7 +290,8 @@ def wave_layout(ls, t, gslots=False):
     maxblk = max(na * nb, nc * nd, na * nc, nb * nc, na * nd, nb * nd)
     nint = na * nb * nc * nd
     doubles = (0 if gslots else t.nslots + 2) + max(len(t.coefs), 1) + 6 * maxblk
-    return maxblk, doubles, doubles * 8 + ((2 * nint + 15) // 16) * 16
+    # then the uint16 output-slot map (padded to 16 bytes) and the 16-double VRR constants record
+    return maxblk, doubles, doubles * 8 + ((2 * nint + 15) // 16) * 16 + 16 * 8
 
 
 def build_wave_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None) -> WaveTables:
