@@ -269,9 +269,14 @@ def serving(args):
         dens = [D] + [workloads.psd_density(bw.nbf, 5000 + 100 * i + k) for k in range(1, nupd)]
         reqs.append(serve.Request(i, float(arrivals[i]), bw, dens, tau=TAU, theta=theta))
     check = set(range(0, n, max(1, n // 4)))       # requests whose last update is checked against FP64 alone
-    ex = serve.GpuExecutor(slots=args.serve_slots, keep=lambda rid, k: rid in check and k == nupd - 1)
-    srv = serve.Server(ex, hbm_budget=int(args.serve_budget_gb * (1 << 30)), max_active=args.serve_active,
-                       slots=args.serve_slots)
+    keep = lambda rid, k: rid in check and k == nupd - 1
+    budget = int(args.serve_budget_gb * (1 << 30))
+    if args.serve_mode == "iteration":
+        ex = serve.GpuMultiExecutor(keep=keep)
+        srv = serve.IterationServer(ex, hbm_budget=budget, max_active=args.serve_active)
+    else:
+        ex = serve.GpuExecutor(slots=args.serve_slots, keep=keep)
+        srv = serve.Server(ex, hbm_budget=budget, max_active=args.serve_active, slots=args.serve_slots)
     # warm-up: one small request end to end (library load, table uploads)
     wex = serve.GpuExecutor(slots=1)
     serve.Server(wex, hbm_budget=1 << 34).run([serve.Request(-1, 0.0, reqs[0].basis, reqs[0].densities[:2],
@@ -285,7 +290,9 @@ def serving(args):
     ex.close()
     wex.close()
     summ = serve.summarize(recs, ups, elapsed)
-    eris = sum(ex.eris[u.rid] for u in ups)
+    if args.serve_mode == "iteration":
+        summ["plan_rebuilds"] = srv.rebuilds
+    eris = ex.eris_done if args.serve_mode == "iteration" else sum(ex.eris[u.rid] for u in ups)
     err = 0.0
     for rid in sorted(check):
         r = reqs[rid]
@@ -307,11 +314,14 @@ def serving(args):
                                    f"each a new synthetic molecule of U{{{natom[0]}..{natom[1]}}} atoms (5s4p3d2f1g, "
                                    f"U{{1..3}} primitives per shell) with {nupd} closed-loop density updates "
                                    f"through one plan; HBM budget {args.serve_budget_gb:g} GB, at most "
-                                   f"{args.serve_active} active, {args.serve_slots} streams, Schwarz tau=1e-12, "
+                                   f"{args.serve_active} active, "
+                                   + ("iteration-level batching over one multi-system plan, "
+                                      if args.serve_mode == "iteration" else f"{args.serve_slots} streams, ")
+                                   + "Schwarz tau=1e-12, "
                                    + ("FP64" if theta == 0 else f"mixed (theta {theta:g})"),
                        "nbf_min": min(nbf), "nbf_max": max(nbf), "eris_total": int(eris)},
             "serve": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()},
-            "peak_active": srv.peak_active, "peak_plan_bytes": srv.peak_bytes,
+            "peak_active": srv.peak_active, "peak_plan_bytes": getattr(srv, "peak_bytes", None),
             "max_abs_vs_fp64_alone": err}
     print(json.dumps(line), flush=True)
 
@@ -337,6 +347,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-active", type=int, default=16)
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-mode", choices=("continuous", "iteration"), default="iteration",
+                    help="continuous: each request's updates on its own stream; iteration: every step one "
+                         "multi-system plan over the active requests")
     ap.add_argument("--batch-n", type=int, default=64, help="batch: number of systems")
     ap.add_argument("--batch-max-atoms", type=int, default=15, help="batch: atoms per system U{5..this}")
     ap.add_argument("--batch-max-prim", type=int, default=3, help="batch: primitives per shell U{1..this}")

@@ -525,19 +525,25 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
         hipError_t e = hipMemcpy(qp.data(), d_qp, qp.size() * sizeof(double), hipMemcpyDeviceToHost);
         hipFree(d_pp); hipFree(d_pg); hipFree(d_qp);
         if (e != hipSuccess) { free_tmp(); return fail(HGP_E_DEVICE, "copying primitive Schwarz factors"); }
-        double qmax = 0.0;
-        for (double x : qp) qmax = std::max(qmax, x);
-        int pmax = 1;
-        for (const PairInfo &x : pairs) pmax = std::max(pmax, x.nprim);
-        const double cut = PRIM_SCREEN_FRACTION * tau / ((double)pmax * (double)pmax);
+        // largest primitive Schwarz factor and primitive-pair count per system (a
+        // multi-system plan drops exactly what each system's own plan would)
+        std::vector<double> qmax((size_t)nsys, 0.0);
+        std::vector<int> pmax((size_t)nsys, 1);
+        for (const PairInfo &x : pairs) {
+            const int sy = sysof(x.sh_a);
+            pmax[(size_t)sy] = std::max(pmax[(size_t)sy], x.nprim);
+            for (int r = 0; r < x.nprim; ++r) qmax[(size_t)sy] = std::max(qmax[(size_t)sy], qp[(size_t)(x.prim_off + r)]);
+        }
         // rebuild the pairs with only the primitive pairs that matter
         std::vector<std::vector<PairInfo>> kept(npc);
         std::vector<std::vector<int>> keep_recs(pairs.size());
         std::vector<PairGeo> kgeo_by_pair(pairs.size());
         for (size_t pi = 0; pi < pairs.size(); ++pi) {
+            const int sy = sysof(pairs[pi].sh_a);
+            const double cut = PRIM_SCREEN_FRACTION * tau / ((double)pmax[(size_t)sy] * (double)pmax[(size_t)sy]);
             for (int r = 0; r < pairs[pi].nprim; ++r) {
                 const int rr = pairs[pi].prim_off + r;
-                if (qp[(size_t)rr] * qmax >= cut) keep_recs[pi].push_back(rr);
+                if (qp[(size_t)rr] * qmax[(size_t)sy] >= cut) keep_recs[pi].push_back(rr);
             }
             if (keep_recs[pi].empty()) continue;   // no primitive quartet of this pair matters
             PairInfo x = pairs[pi];

@@ -187,6 +187,107 @@ class Server:
         return [recs[r.rid] for r in requests], updates
 
 
+class IterationServer:
+    """Iteration-level batching over one multi-system plan.
+
+    Each step runs the next update of every active request together, as one
+    J/K build of a plan over all their systems (each class one launch over
+    the quartets of every system).  When the active set changes, the plan
+    is rebuilt for the new set.  Admission is first come, first served
+    under max_active; a plan that exceeds the HBM budget sends the most
+    recently admitted requests back to the head of the queue, and a request
+    that cannot fit even alone is rejected.
+
+    executor must provide now(), build(requests, budget) -> plan (raising
+    OverBudget), submit(plan, requests, ks) -> token, done(token),
+    finish(token, requests, ks), release(plan) and idle(until)."""
+
+    def __init__(self, executor, hbm_budget: int, max_active: int = 16):
+        if hbm_budget <= 0 or max_active < 1:
+            raise ValueError("need hbm_budget > 0, max_active >= 1")
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_active = max_active
+        self.peak_active = 0
+        self.rebuilds = 0
+
+    def run(self, requests):
+        ex = self.ex
+        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        waiting = collections.deque()
+        active = []                               # [request, k]
+        recs = {r.rid: RequestRecord(r.rid, r.arrival) for r in requests}
+        updates = []
+        plan = None
+        t0 = ex.now()
+        while pending or waiting or active:
+            t = ex.now() - t0
+            while pending and pending[0].arrival <= t:
+                waiting.append(pending.popleft())
+            changed = plan is None
+            while waiting and len(active) < self.max_active:
+                r = waiting.popleft()
+                if not r.densities:
+                    recs[r.rid].admitted = recs[r.rid].finished = t
+                    continue
+                active.append([r, 0])
+                recs[r.rid].admitted = t
+                changed = True
+            if not active:
+                if pending:
+                    ex.idle(pending[0].arrival + t0)
+                continue
+            if changed:
+                if plan is not None:
+                    ex.release(plan)
+                    plan = None
+                while plan is None:
+                    try:
+                        plan = ex.build([a[0] for a in active], self.budget)
+                    except OverBudget:
+                        if len(active) == 1:          # cannot fit even alone
+                            r = active.pop()[0]
+                            recs[r.rid].rejected = "plan exceeds the HBM budget"
+                            recs[r.rid].admitted = float("nan")
+                            if not active:
+                                break
+                            continue
+                        r = active.pop()[0]           # the latest admitted waits again, at the head
+                        recs[r.rid].admitted = float("nan")
+                        waiting.appendleft(r)
+                if plan is None:
+                    continue
+                self.rebuilds += 1
+            self.peak_active = max(self.peak_active, len(active))
+            reqs = [a[0] for a in active]
+            ks = [a[1] for a in active]
+            ts = ex.now() - t0
+            tok = ex.submit(plan, reqs, ks)
+            while not ex.done(tok):
+                ex.idle(None)
+            td = ex.now() - t0
+            ex.finish(tok, reqs, ks)
+            still = []
+            for a in active:
+                updates.append(UpdateRecord(a[0].rid, a[1], ts, td))
+                a[1] += 1
+                if a[1] == len(a[0].densities):
+                    recs[a[0].rid].finished = td
+                else:
+                    still.append(a)
+            if len(still) != len(active):
+                active = still
+                if plan is not None and not active:
+                    ex.release(plan)
+                    plan = None
+                elif plan is not None:
+                    ex.release(plan)                   # the set changed: rebuild at the next step
+                    plan = None
+        if plan is not None:
+            ex.release(plan)
+        return [recs[r.rid] for r in requests], updates
+
+
 def percentile(x, q):
     """Nearest-rank percentile (q in [0, 100]) of a non-empty sequence."""
     v = np.sort(np.asarray(x, dtype=float))
@@ -303,9 +404,93 @@ class GpuExecutor:
         else:
             free()
 
+    def idle(self, until):
+        time.sleep(50e-6)
+
     def close(self):
         if self.pool is not None:
             self.pool.shutdown(wait=True)
 
+
+class GpuMultiExecutor:
+    """IterationServer's executor: one multi-system plan per active set
+    (hgp_plan_create_multi / hgp_jk_multi).  A request's densities are put
+    on the device when it is first planned and stay there until it
+    finishes; keep(rid, k) as for GpuExecutor.  eris_done counts the
+    contracted ERIs of all completed steps."""
+
+    def __init__(self, keep=False, stream=None):
+        import torch
+        from . import lib
+        lib()
+        self.torch = torch
+        self.stream = stream
+        self.keep = (lambda rid, k: True) if keep is True else (keep or (lambda rid, k: False))
+        self.results = {}
+        self.plan_eris = {}
+        self.eris_done = 0                 # contracted ERIs of all completed steps
+        self.dev = {}                      # rid -> (basis, [D], J, K)
+
+    def now(self):
+        return time.perf_counter()
+
+    def _device(self, r):
+        from . import Basis
+        torch = self.torch
+        if r.rid not in self.dev:
+            D = [torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda") for x in r.densities]
+            self.dev[r.rid] = (Basis.from_workload(r.basis), D, torch.empty_like(D[0]), torch.empty_like(D[0]))
+        return self.dev[r.rid]
+
+    def build(self, reqs, budget):
+        from . import HGPError, STATUS_OOM, Plan
+        held = sum(8 * x[1][0].numel() * (len(x[1]) + 2) for x in self.dev.values())
+        for r in reqs:
+            if r.rid not in self.dev:
+                n = int(np.asarray(r.densities[0]).shape[0])
+                held += 8 * n * n * (len(r.densities) + 2)
+        if held >= budget:
+            raise OverBudget()
+        devs = [self._device(r) for r in reqs]
+        try:
+            p = Plan.multi([d[0] for d in devs], tau=reqs[0].tau, theta=reqs[0].theta, hbm_budget=budget - held,
+                           stream=self.stream)
+        except HGPError as e:
+            if e.status == STATUS_OOM:
+                raise OverBudget() from e
+            raise
+        self.plan_eris[id(p)] = sum(c["quartets"] * int(np.prod([2 * x + 1 for x in c["ls"]])) for c in p.classes())
+        return p
+
+    def submit(self, p, reqs, ks):
+        devs = [self.dev[r.rid] for r in reqs]
+        p.jk_multi([d[1][k] for d, k in zip(devs, ks)], [d[2] for d in devs], [d[3] for d in devs],
+                   stream=self.stream)
+        ev = self.torch.cuda.Event()
+        ev.record(self.torch.cuda.current_stream() if self.stream is None else self.stream)
+        return (ev, self.plan_eris[id(p)])
+
+    def done(self, token):
+        return token[0].query()
+
+    def finish(self, token, reqs, ks):
+        self.eris_done += token[1]
+        for r, k in zip(reqs, ks):
+            d = self.dev[r.rid]
+            if self.keep(r.rid, k):
+                self.results[(r.rid, k)] = (d[2].cpu().numpy(), d[3].cpu().numpy())
+            if k == len(r.densities) - 1:
+                d[0].close()
+                del self.dev[r.rid]
+
+    def release(self, p):
+        self.plan_eris.pop(id(p), None)
+        p.close()
+
     def idle(self, until):
         time.sleep(50e-6)
+
+    def close(self):
+        for d in self.dev.values():
+            d[0].close()
+        self.dev.clear()

@@ -94,3 +94,26 @@ def test_served_equals_alone(hgp, torch_cuda, theta, worker):
     Jr, Kr = oracle.jk(small.basis, small.densities[1], tau=small.tau)
     J, K = ex.results[(small.rid, 1)]
     assert np.abs(J - Jr).max() <= JK_TOL and np.abs(K - Kr).max() <= JK_TOL
+
+
+def test_iteration_served_equals_alone(hgp, torch_cuda):
+    """Iteration-level batching: every step one multi-system plan over the
+    active requests; each served J/K equals its own plan alone (1e-12)."""
+    from paper_2605_10312_amd import serve
+    reqs = _requests(serve, 8, 3, lmax=4, theta=0.0, seed=1006)
+    for r in reqs[::3]:
+        r.densities = r.densities[:2]                 # uneven update counts: the active set changes
+    alone = [_alone(hgp, torch_cuda, r, 0.0) for r in reqs]
+    ex = serve.GpuMultiExecutor(keep=True)
+    srv = serve.IterationServer(ex, hbm_budget=8 << 30, max_active=4)
+    recs, ups = srv.run(reqs)
+    ex.close()
+    assert all(r.rejected is None for r in recs)
+    assert len(ups) == sum(len(r.densities) for r in reqs)
+    worst = 0.0
+    for r, (res, _) in zip(reqs, alone):
+        for k in range(len(r.densities)):
+            J, K = ex.results[(r.rid, k)]
+            worst = max(worst, np.abs(J - res[k][0]).max(), np.abs(K - res[k][1]).max())
+    print(f"iteration server: peak active {srv.peak_active}, rebuilds {srv.rebuilds}, max |served - alone| {worst:.2e}")
+    assert worst <= SAME_TOL and srv.peak_active == 4

@@ -185,3 +185,78 @@ def test_async_plan_building_overlaps_updates():
     # request 0's updates ran while request 1's plan was being built
     first1 = recs[1].admitted
     assert any(u.rid == 0 and u.done <= first1 + 1e-12 for u in ups)
+
+
+class IterSimExecutor:
+    """Simulated multi-system executor: a step costs the sum of its members'
+    costs times `merge` (merged launches are cheaper than separate ones);
+    a plan over a set takes the sum of the members' bytes."""
+
+    def __init__(self, bytes_, cost, merge=0.5):
+        self.t = 0.0
+        self.bytes, self.cost, self.merge = bytes_, cost, merge
+        self.end = None
+        self.log = []
+
+    def now(self):
+        return self.t
+
+    def build(self, reqs, budget):
+        if sum(self.bytes[r.rid] for r in reqs) > budget:
+            raise serve.OverBudget()
+        self.log.append(("build", tuple(r.rid for r in reqs), self.t))
+        return tuple(r.rid for r in reqs)
+
+    def submit(self, plan, reqs, ks):
+        assert tuple(r.rid for r in reqs) == plan
+        self.end = self.t + self.merge * sum(self.cost[r.rid] for r in reqs)
+        self.log.append(("step", plan, tuple(ks), self.t))
+        return self.end
+
+    def done(self, tok):
+        return self.t >= tok - 1e-12
+
+    def finish(self, tok, reqs, ks):
+        pass
+
+    def release(self, plan):
+        self.log.append(("release", plan, self.t))
+
+    def idle(self, until):
+        if self.end is not None and self.end > self.t:
+            self.t = self.end if until is None else min(self.end, until)
+        elif until is not None:
+            self.t = max(self.t, until)
+        else:
+            self.t += 1e-3
+
+
+def test_iteration_server_runs_every_update_once_in_order():
+    reqs = [serve.Request(i, 0.01 * i, None, [None] * (2 + i % 3)) for i in range(7)]
+    ex = IterSimExecutor({i: 10 for i in range(7)}, {i: 0.004 for i in range(7)})
+    srv = serve.IterationServer(ex, hbm_budget=1000, max_active=3)
+    recs, ups = srv.run(reqs)
+    assert all(r.rejected is None for r in recs)
+    assert len(ups) == sum(len(r.densities) for r in reqs)
+    for r in reqs:
+        mine = sorted((u for u in ups if u.rid == r.rid), key=lambda u: u.submit)
+        assert [u.k for u in mine] == list(range(len(r.densities)))     # closed loop, in order
+        assert recs[r.rid].finished == pytest.approx(mine[-1].done)
+    assert srv.peak_active <= 3
+    # every step ran exactly the active set its plan was built for, and plans were rebuilt on change
+    steps = [e for e in ex.log if e[0] == "step"]
+    assert all(len(e[1]) <= 3 for e in steps) and srv.rebuilds >= 3
+
+
+def test_iteration_server_budget_pushes_back_and_rejects():
+    reqs = [serve.Request(i, 0.0, None, [None] * 2) for i in range(5)]
+    bytes_ = {0: 40, 1: 40, 2: 40, 3: 500, 4: 30}
+    ex = IterSimExecutor(bytes_, {i: 0.01 for i in range(5)})
+    srv = serve.IterationServer(ex, hbm_budget=100, max_active=4)
+    recs, ups = srv.run(reqs)
+    assert recs[3].rejected is not None
+    assert all(recs[i].rejected is None for i in (0, 1, 2, 4))
+    for e in ex.log:
+        if e[0] == "build":
+            assert sum(bytes_[i] for i in e[1]) <= 100
+    assert len(ups) == 8
