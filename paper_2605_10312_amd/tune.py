@@ -7,6 +7,9 @@ schedules the digestion, so the choices are checked on the hardware.
     python -m paper_2605_10312_amd.tune build             (CPU: variant libraries)
     python -m paper_2605_10312_amd.tune measure --out F   (GPU: time every variant)
     python -m paper_2605_10312_amd.tune select F          (CPU: write the tuning table)
+    python -m paper_2605_10312_amd.tune refine --variants V.. --out F
+                                                          (GPU: time variants beside the current
+                                                           library; adopt clear per-class wins)
 
 `build` generates one complete library per variant into _variants/.  A
 variant is a set of generator options applied to every class (waves per
@@ -45,6 +48,9 @@ VARIANTS = {
     "staged": {"digest": "loads_first", "reduce": "segmented", "tier": 1},
     "plain": {"digest": "interleaved", "reduce": "none"},
 }
+# Measured and dropped: 6 or 8 waves per SIMD forced on every l <= 2 class
+# (block 64, with and without prefetch) spills and ran 1.04-15x slower than
+# the tuned choice on every class.
 
 
 def build_variants(names, lmax):
@@ -107,6 +113,52 @@ def measure(names, out, steps, warmup, timeout):
             json.dump(results, fh, indent=1)
 
 
+def refine(names, out, steps, warmup, timeout, margin=0.02, table=TABLE):
+    """Time the current library (the package's libhgp.so, built from the
+    tuning table) beside the named variants in one session, and adopt a
+    variant's options for a class only where it beats the current choice by
+    more than `margin`."""
+    from . import LIB_PATH
+    results = {}
+    for name, lib in [("current", LIB_PATH)] + [(n, os.path.join(VARIANTS_DIR, f"libhgp_{n}.so")) for n in names]:
+        if not os.path.exists(lib):
+            raise FileNotFoundError(lib)
+        print(f"== {name}", flush=True)
+        r = subprocess.run([sys.executable, "-m", "paper_2605_10312_amd.tune", "_time", "--steps", str(steps),
+                            "--warmup", str(warmup)], env=dict(os.environ, HGP_LIB=lib), capture_output=True,
+                           text=True, timeout=timeout)
+        if r.returncode != 0:
+            print(r.stderr[-3000:], flush=True)
+            raise SystemExit(f"{name} failed with status {r.returncode}")
+        results[name] = json.loads(r.stdout.strip().splitlines()[-1])
+        print(f"   {results[name]['ms_per_build']:.2f} ms per J/K build", flush=True)
+    with open(out, "w") as fh:
+        json.dump(results, fh, indent=1)
+    apply_refine(out, margin, table)
+
+
+def apply_refine(path, margin=0.02, table=TABLE):
+    """The table update of `refine`, from its saved timings."""
+    results = json.load(open(path))
+    cur = json.load(open(table))
+    for tag, c in results["current"]["classes"].items():
+        best = min(((r["classes"][tag]["ms"], n) for n, r in results.items()
+                    if n != "current" and tag in r["classes"] and r["classes"][tag]["tier"] == c["tier"]),
+                   default=None)
+        if best and best[0] < (1.0 - margin) * c["ms"]:
+            opts = {"tier": c["tier"]}
+            opts.update(VARIANTS[best[1]])
+            if opts["tier"] == 1:
+                opts = {k: v for k, v in opts.items() if k in ("tier", "cap", "waves", "reduce", "loop")}
+            opts["variant"] = best[1]
+            opts["ms"] = round(best[0], 4)
+            print(f"{tag}: {c['ms']:.3f} -> {best[0]:.3f} ms with {best[1]}")
+            cur["classes"][tag] = opts
+    with open(table, "w") as fh:
+        json.dump(cur, fh, indent=1)
+    print(f"updated {table}")
+
+
 def select(path, table=TABLE):
     res = json.load(open(path))
     classes = sorted({t for r in res.values() for t in r["classes"]})
@@ -140,6 +192,14 @@ def main(argv=None):
     pm.add_argument("--steps", type=int, default=3)
     pm.add_argument("--warmup", type=int, default=1)
     pm.add_argument("--timeout", type=float, default=120.0)
+    pr = sub.add_parser("refine")
+    pr.add_argument("--variants", nargs="*", required=True)
+    pr.add_argument("--out", required=True)
+    pr.add_argument("--steps", type=int, default=3)
+    pr.add_argument("--warmup", type=int, default=1)
+    pr.add_argument("--timeout", type=float, default=180.0)
+    pa = sub.add_parser("apply")
+    pa.add_argument("results")
     ps = sub.add_parser("select")
     ps.add_argument("results")
     pt = sub.add_parser("_time")
@@ -150,6 +210,10 @@ def main(argv=None):
         build_variants(a.variants, a.lmax)
     elif a.cmd == "measure":
         measure(a.variants, a.out, a.steps, a.warmup, a.timeout)
+    elif a.cmd == "refine":
+        refine(a.variants, a.out, a.steps, a.warmup, a.timeout)
+    elif a.cmd == "apply":
+        apply_refine(a.results)
     elif a.cmd == "select":
         select(a.results)
     else:
