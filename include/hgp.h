@@ -139,7 +139,9 @@ hgp_status hgp_plan_class_precision(const hgp_plan *p, int32_t c, int32_t *bits)
 
 /* The plan's Schwarz factors by shell: Q[i*nshell + j] = Q[j*nshell + i] =
  * sqrt(max |(mn|mn)|) over m in shell i, n in shell j (host array, nshell^2),
- * from the primitive pairs the plan kept; 0 for a shell pair with none kept. */
+ * from the primitive pairs the plan kept; 0 for a shell pair with none kept
+ * (and for shells of different systems of a multi-system plan, whose shells
+ * are numbered over the bases in the order given). */
 hgp_status hgp_plan_schwarz(const hgp_plan *p, double *Q);
 
 /*
@@ -148,8 +150,9 @@ hgp_status hgp_plan_schwarz(const hgp_plan *p, double *Q);
  * unchanged).  hgp_plan_set_timing(p, 1) also resets the counters.
  * hgp_plan_class_timing waits for the recorded events and returns, for class
  * c and kernel k, the number of timed launches and their summed duration in
- * milliseconds.  k = 0: the register tier's kernel or a staged class's Phase-1
- * kernel; k = 1: a staged class's Phase-2 + digestion kernel.
+ * milliseconds.  k = 0: the one kernel of a register, wave-LDS or HBM-scratch
+ * class, or a staged class's Phase-1 kernel; k = 1: a staged class's Phase-2 +
+ * digestion kernel.  hgp_jk_multi records the same events.
  */
 hgp_status hgp_plan_set_timing(hgp_plan *p, int32_t enable);
 hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int32_t kernel, int64_t *launches, double *total_ms);
@@ -169,7 +172,10 @@ hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_
  * the n bases are independent systems; the plan keeps only shell pairs
  * within a system and quartets whose two pairs are in the same system, so
  * each class is one launch over the quartets of every system at once
- * instead of n small launches.  Arguments as hgp_plan_create_mixed
+ * instead of n small launches.  Every screening decision (primitive pairs
+ * included) is taken per system exactly as the system's own plan would, so
+ * each system's J and K equal its own plan's up to the order of the FP64
+ * additions.  Arguments as hgp_plan_create_mixed
  * (theta = 0: FP64).  The plan holds a copy of the bases (they may be
  * destroyed afterwards) and, besides the usual plan data, three buffers of
  * N_tot * (N_max + 1) doubles (N_tot = sum of the systems' N, N_max the

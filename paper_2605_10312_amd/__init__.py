@@ -178,7 +178,7 @@ class Plan:
 
     def schwarz(self):
         """Schwarz factors by shell pair, [nshell, nshell]."""
-        n = int(self.basis.l.shape[0])
+        n = int(self.basis.l.shape[0]) if self.basis is not None else sum(int(b.l.shape[0]) for b in self.bases)
         q = np.zeros((n, n))
         _check(lib().hgp_plan_schwarz(self.handle, q.ctypes.data_as(ctypes.c_void_p)))
         return q
