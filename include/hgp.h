@@ -67,7 +67,7 @@ typedef struct hgp_plan hgp_plan;    /* pair data, Schwarz factors and screened 
 
 #define HGP_FP64 0
 #define HGP_MIXED 1               /* FP32 VRR/HRR for quartets with a small Schwarz bound (see hgp_plan_create_mixed) */
-#define HGP_MIXED_THETA_DEFAULT 1e-8
+#define HGP_MIXED_THETA_DEFAULT 1e-10
 
 /* Library version and the highest l built into this library's class kernels. */
 int32_t hgp_version(void);
@@ -114,11 +114,12 @@ hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t preci
  * contraction over primitives in FP32.  The pair quantities, the Boys
  * function, the horizontal recurrence and transforms (which cancel between
  * large intermediates) and the J/K digestion stay FP64.  Larger-bound
- * quartets and the staged and HBM-scratch classes run wholly in FP64.
- * theta <= schwarz_tau gives an FP64 plan.  The deviation from the FP64
- * result grows roughly in proportion to theta; the default threshold is
- * the largest that keeps it below 1e-9 on the benchmark workload.  Other
- * arguments as hgp_plan_create.
+ * quartets and the staged, wave-LDS and HBM-scratch classes run wholly in
+ * FP64.  theta <= schwarz_tau gives an FP64 plan.  The deviation from the
+ * FP64 result grows roughly in proportion to theta and depends on the basis
+ * (tight, high-l primitives raise it): 1e-8 keeps it near 3e-10 on a
+ * 3s2p1d molecule but gives ~3e-8 on small 5s4p3d2f1g molecules, so the
+ * default is 1e-10.  Other arguments as hgp_plan_create.
  */
 hgp_status hgp_plan_create_mixed(const hgp_basis *b, double schwarz_tau, double theta, size_t hbm_budget_bytes,
                                  void *hip_stream, hgp_plan **out);

@@ -21,7 +21,7 @@ STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_UNSUPPORTED_L", -3: "HGP_
 STATUS_OOM = -3
 HGP_FP64 = 0
 HGP_MIXED = 1
-MIXED_THETA_DEFAULT = 1e-8      # HGP_MIXED_THETA_DEFAULT in include/hgp.h
+MIXED_THETA_DEFAULT = 1e-10     # HGP_MIXED_THETA_DEFAULT in include/hgp.h
 
 # exported symbol -> (restype, argtypes)
 _vp, _i32, _i64, _d, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
