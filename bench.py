@@ -353,6 +353,9 @@ def main():
     ap.add_argument("--batch-n", type=int, default=64, help="batch: number of systems")
     ap.add_argument("--batch-max-atoms", type=int, default=15, help="batch: atoms per system U{5..this}")
     ap.add_argument("--batch-max-prim", type=int, default=3, help="batch: primitives per shell U{1..this}")
+    ap.add_argument("--serial", action="store_true",
+                    help="run the timed J/K builds with every class on one stream (for kernel profiles whose "
+                         "per-kernel durations must match the event-timed ones)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy kernel (y = 1.0 * x, MIB MiB of FP64 each way), "
                          "a known-size reference for hardware byte counters")
@@ -402,15 +405,25 @@ def main():
     for _ in range(args.warmup):
         plan.jk(Dt, J, K)
     torch.cuda.synchronize()
-    plan.set_timing(True)
+    # timed steps: the plan runs its scratch-free class lists concurrently on
+    # several streams (with --serial, all on one stream, as while timing kernels)
+    plan.set_timing(args.serial)
     t = time.perf_counter()
     for _ in range(args.steps):
         plan.jk(Dt, J, K)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
+    ms_per_step = 1e3 * elapsed / args.steps
+    # per-kernel durations: HIP events around each class kernel, which makes the
+    # plan run every class on the one stream so that no kernel's interval is
+    # stretched by another's (the timed steps above were concurrent unless --serial)
+    if not args.serial:
+        plan.set_timing(True)
+        for _ in range(args.steps):
+            plan.jk(Dt, J, K)
+        torch.cuda.synchronize()
     timing = plan.class_timing()
     plan.set_timing(False)
-    ms_per_step = 1e3 * elapsed / args.steps
 
     # one entry per kernel: register tier jk_<class>; staged tier p1_<class> (Phase 1)
     # and jk_<class> (Phase 2 + digestion); average duration per launch from HIP events
@@ -496,6 +509,7 @@ def main():
         "setup_s": round(setup_s, 3),
         "step_tflops": round(total_flops / (ms_per_step * 1e-3) / 1e12, 3),
         "kernel_ms_sum": round(total_kernel_ms, 4),
+        "class_streams": "one" if args.serial else "concurrent (caller's stream + 3 side streams)",
         "err": err,
         "err_vs_fp64": err_fp64,
         "kernels": per_kernel,

@@ -219,6 +219,10 @@ struct hgp_plan {
     double *d_Dunion = nullptr;              // several systems: the densities in the accumulators' layout
     int *d_psys = nullptr;                   // system of each pair
     int *d_cbeg = nullptr, *d_ccnt = nullptr;   // [pair class][system]: first pair and count
+    // register- and wave-tier class lists run concurrently on these side
+    // streams (forked from and joined back into the caller's stream)
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_ev;         // [0] fork, [1 + k] join of side stream k
 };
 
 static hipEvent_t take_event(hgp_plan *p)
@@ -335,6 +339,8 @@ hgp_status hgp_plan_destroy(hgp_plan *p)
         p->event_pool.push_back(t.stop);
     }
     for (hipEvent_t e : p->event_pool) hipEventDestroy(e);
+    for (hipEvent_t e : p->side_ev) hipEventDestroy(e);
+    for (hipStream_t st : p->side) hipStreamDestroy(st);
     hipFree(p->d_pairs); hipFree(p->d_geo); hipFree(p->d_prims); hipFree(p->d_Q);
     hipFree(p->d_Jacc); hipFree(p->d_Kacc); hipFree(p->d_scratch);
     hipFree(p->d_Dunion); hipFree(p->d_psys); hipFree(p->d_cbeg); hipFree(p->d_ccnt);
@@ -401,6 +407,9 @@ static hgp_status schwarz_factors(const PairInfo *d_pairs, const PairGeo *d_geo,
 // of a contracted quartet: what is dropped from one integral stays below a
 // tenth of the Schwarz threshold tau.
 constexpr double PRIM_SCREEN_FRACTION = 0.1;
+// Register- and wave-tier class lists of one J/K build run on the caller's
+// stream and this many more (the device runs four hardware queues a process).
+constexpr int HGP_SIDE_STREAMS = 3;
 
 static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t s)
 {
@@ -703,6 +712,17 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
         return fail(HGP_E_OOM, "plan exceeds the HBM budget (staged-tier buffer)");
     if ((st = dalloc(&p->d_scratch, (size_t)sbuf, &p->bytes))) return st;
     p->scratch_doubles = sbuf;
+    // side streams for concurrent class lists (default priority, non-blocking)
+    for (int k = 0; k < HGP_SIDE_STREAMS; ++k) {
+        hipStream_t ss = nullptr;
+        HGP_HIP(hipStreamCreateWithFlags(&ss, hipStreamNonBlocking));
+        p->side.push_back(ss);
+    }
+    for (int k = 0; k <= HGP_SIDE_STREAMS; ++k) {
+        hipEvent_t e = nullptr;
+        HGP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        p->side_ev.push_back(e);
+    }
     // heaviest classes first
     std::stable_sort(p->lists.begin(), p->lists.end(), [](const ClassList &x, const ClassList &y) {
         const double cx = x.nprimq * g_class_table[x.cls].vrr_flops + x.nq * g_class_table[x.cls].p2_flops;
@@ -879,11 +899,39 @@ hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int32_t kernel, int64_t
 
 // The class lists of a plan over D (laid out like the accumulators) into the
 // unsymmetrised accumulators, which the caller has cleared.
-static hgp_status jk_classes(hgp_plan *p, const double *D, bool want_j, bool want_k, hipStream_t s)
+static hgp_status jk_classes(hgp_plan *p, const double *D, bool want_j, bool want_k, hipStream_t s0)
 {
     const double *boys = nullptr;
     hgp_status st = boys_table(p->device, &boys);
     if (st) return st;
+    // class lists that use no scratch buffer go to the least-loaded of the
+    // caller's stream and the side streams (lists come heaviest first).  Not
+    // while kernel timing is on (concurrent kernels would stretch each
+    // other's timed intervals) and not while the stream is being captured
+    // into a graph (the side-stream fork and join under capture crashed the
+    // HIP runtime on the host): then every list runs on the caller's stream.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(s0, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
+    const int nside = (p->timing || capturing) ? 0 : (int)p->side.size();
+    std::vector<double> load((size_t)nside + 1, 0.0);
+    std::vector<int> where(p->lists.size(), 0);
+    bool any_side = false;
+    for (size_t li = 0; li < p->lists.size(); ++li) {
+        const ClassList &cl = p->lists[li];
+        const ClassKernels &k = g_class_table[cl.cls];
+        const double c = cl.nprimq * k.vrr_flops + cl.nq * k.p2_flops;
+        int w = 0;
+        if (cl.nq > 0 && (k.tier == 0 || k.tier == 3))
+            w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[(size_t)w] += c;
+        where[li] = w;
+        any_side = any_side || w > 0;
+    }
+    if (any_side) {
+        HGP_HIP(hipEventRecord(p->side_ev[0], s0));
+        for (int k = 0; k < nside; ++k) HGP_HIP(hipStreamWaitEvent(p->side[(size_t)k], p->side_ev[0], 0));
+    }
+    hipStream_t s = s0;
     auto mark = [&](hipEvent_t *e) -> hgp_status {
         *e = nullptr;
         if (!p->timing) return HGP_OK;
@@ -899,6 +947,7 @@ static hgp_status jk_classes(hgp_plan *p, const double *D, bool want_j, bool wan
         const ClassList &cl = p->lists[li];
         if (cl.nq == 0) continue;
         const ClassKernels &k = g_class_table[cl.cls];
+        s = where[li] == 0 ? s0 : p->side[(size_t)where[li] - 1];
         JKArgs a{};
         a.pairs = p->d_pairs; a.geo = p->d_geo; a.prims = p->d_prims; a.boys = boys;
         a.D = D; a.J = p->d_Jacc; a.K = p->d_Kacc; a.nbf = (int32_t)p->stride;
@@ -940,6 +989,12 @@ static hgp_status jk_classes(hgp_plan *p, const double *D, bool want_j, bool wan
                 done((int)li, 0, e0, e1);
                 done((int)li, 1, e2, e3);
             }
+        }
+    }
+    if (any_side) {
+        for (int k = 0; k < nside; ++k) {
+            HGP_HIP(hipEventRecord(p->side_ev[(size_t)k + 1], p->side[(size_t)k]));
+            HGP_HIP(hipStreamWaitEvent(s0, p->side_ev[(size_t)k + 1], 0));
         }
     }
     return HGP_OK;

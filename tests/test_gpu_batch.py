@@ -3,9 +3,10 @@
 alone, the replays must follow the current densities, and eager work between
 replays must not disturb them.
 
-Bars: 1e-12 absolute between the batched and the per-system results of the
-same plans (only the order of the FP64 atomic additions differs), 1e-9
-absolute against the oracle on the systems small enough for it."""
+Bars: 1e-12 absolute plus 1e-14 of the largest entry between the batched
+and the per-system results of the same plans (only the order of the FP64
+atomic additions differs), 1e-9 absolute against the oracle on the systems
+small enough for it."""
 import numpy as np
 import pytest
 
@@ -16,6 +17,14 @@ pytestmark = pytest.mark.gpu
 
 SAME_TOL = 1e-12
 JK_TOL = 1e-9
+
+
+def same_tol(results):
+    """Bar for the same terms summed in another order: 1e-12 absolute plus
+    1e-14 of the largest entry (a plan runs its classes concurrently, so the
+    FP64 atomic additions land in a different order from run to run)."""
+    big = max(max(np.abs(r[0]).max(), np.abs(r[1]).max()) for r in results)
+    return SAME_TOL + 1e-14 * big
 
 
 @pytest.fixture(scope="module")
@@ -82,7 +91,7 @@ def test_batch_matches_each_system_alone(hgp, torch_cuda, lmax, tau):
           f"system {small} vs oracle |dJ| {ej:.2e} |dK| {ek:.2e}")
     batch.close()
     _close(plans + bases)
-    assert worst <= SAME_TOL
+    assert worst <= same_tol(ref)
     assert ej <= JK_TOL and ek <= JK_TOL
 
 
@@ -117,13 +126,13 @@ def test_batch_replays_follow_density_and_survive_eager_work(hgp, torch_cuda):
             else:
                 assert np.all(Ks[i].cpu().numpy() == 7.0)
         print(f"replay {r} (D x {sc}): max |batch - scaled alone| {worst:.2e}")
-        assert worst <= SAME_TOL * max(1.0, abs(sc))
+        assert worst <= same_tol(ref) * max(1.0, abs(sc))
     # a plan of the batch still runs alone between replays, with the same result
     for D in Ds:
         D.div_(prev)
     again = _alone(torch, plans, Ds)
     for a, b in zip(again, ref):
-        assert np.abs(a[0] - b[0]).max() <= SAME_TOL and np.abs(a[1] - b[1]).max() <= SAME_TOL
+        assert np.abs(a[0] - b[0]).max() <= same_tol(ref) and np.abs(a[1] - b[1]).max() <= same_tol(ref)
     batch.close()
     _close(plans + bases)
 
@@ -138,7 +147,7 @@ def test_batch_mixed_precision_plans(hgp, torch_cuda):
         torch_cuda.cuda.synchronize()
         worst = max(max(np.abs(J.cpu().numpy() - r[0]).max(), np.abs(K.cpu().numpy() - r[1]).max())
                     for J, K, r in zip(Js, Ks, ref))
-        assert worst <= SAME_TOL
+        assert worst <= same_tol(ref)
     batch.close()
     _close(plans + bases)
 

@@ -2,8 +2,8 @@
 class runs once over the quartets of every system.  Screening (primitive
 pairs included) is decided per system, so the plan evaluates exactly the
 quartets and primitive pairs of the systems' own plans: every system's J/K
-must equal its own plan's within 1e-12 (only the order of the FP64 atomic
-additions differs), the counts must add up, and quartets never cross
+must equal its own plan's within 1e-12 plus 1e-14 of the largest entry (only
+the order of the FP64 atomic additions differs), the counts must add up, and quartets never cross
 systems."""
 import numpy as np
 import pytest
@@ -15,6 +15,14 @@ pytestmark = pytest.mark.gpu
 
 SAME_TOL = 1e-12
 JK_TOL = 1e-9
+
+
+def same_tol(results):
+    """Bar for the same terms summed in another order: 1e-12 absolute plus
+    1e-14 of the largest entry (the classes run concurrently and the FP64
+    atomic additions land in a different order)."""
+    big = max(max(np.abs(r[0]).max(), np.abs(r[1]).max()) for r in results)
+    return SAME_TOL + 1e-14 * big
 
 
 @pytest.fixture(scope="module")
@@ -63,12 +71,13 @@ def test_multi_plan_equals_each_system(hgp, torch_cuda, lmax, tau):
     st = plan.stats()
     worst = max(max(np.abs(J.cpu().numpy() - a[0]).max(), np.abs(K.cpu().numpy() - a[1]).max())
                 for J, K, a in zip(Js, Ks, alone))
+    tol = same_tol(alone)
     print(f"lmax {lmax} tau {tau}: N = {[bw.nbf for bw, _ in systems]}, kept {st['quartets_kept']} "
           f"(alone {sum(a[2]['quartets_kept'] for a in alone)}), max |multi - alone| {worst:.2e}")
     assert st["quartets_total"] == sum(a[2]["quartets_total"] for a in alone)
     assert st["quartets_kept"] == sum(a[2]["quartets_kept"] for a in alone)
     assert st["prim_pairs_kept"] == sum(a[2]["prim_pairs_kept"] for a in alone)
-    assert worst <= SAME_TOL
+    assert worst <= tol
     small = int(np.argmin([bw.nbf for bw, _ in systems]))
     Jr, Kr = oracle.jk(systems[small][0], systems[small][1], tau=tau)
     assert np.abs(Js[small].cpu().numpy() - Jr).max() <= JK_TOL
@@ -80,9 +89,9 @@ def test_multi_plan_equals_each_system(hgp, torch_cuda, lmax, tau):
     plan.jk_multi(Ds, None, Ko)
     torch.cuda.synchronize()
     for a, b in zip(Jo, Js):
-        assert torch.equal(a, b) or (a - b).abs().max().item() <= SAME_TOL
+        assert (a - b).abs().max().item() <= tol
     for a, b in zip(Ko, Ks):
-        assert (a - b).abs().max().item() <= SAME_TOL
+        assert (a - b).abs().max().item() <= tol
     plan.close()
 
 
@@ -100,7 +109,7 @@ def test_multi_plan_errors(hgp, torch_cuda):
     one.jk_multi([D], [J1], None)
     ref = _alone(hgp, torch, systems[0][0], systems[0][1], 0.0)
     torch.cuda.synchronize()
-    assert np.abs(J1.cpu().numpy() - ref[0]).max() <= SAME_TOL
+    assert np.abs(J1.cpu().numpy() - ref[0]).max() <= same_tol([ref])
     one.close()
     for b in bases:
         b.close()

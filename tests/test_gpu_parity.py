@@ -204,3 +204,28 @@ def test_prim_quartets_noncanonical_order(hgp, torch_cuda):
         hgp.eri_prim_quartets(ls, torch_cuda.tensor(cen, device="cuda"), torch_cuda.tensor(ex, device="cuda"), out)
         torch_cuda.cuda.synchronize()
         assert np.abs(out.cpu().numpy() - ref).max() <= ERI_TOL, ls
+
+
+def test_concurrent_class_streams_match_one_stream(hgp, torch_cuda):
+    """A plan runs its scratch-free class lists concurrently on several
+    streams, and all of them on one stream while kernel timing is on; the
+    two must agree within 1e-12 plus 1e-14 of the largest entry (only the
+    order of the FP64 atomic additions differs)."""
+    torch = torch_cuda
+    bw = workloads.random_small_basis(seed=31, natom=4, lmax=2, maxprim=3)
+    D = workloads.psd_density(bw.nbf, 31)
+    b = hgp.Basis.from_workload(bw)
+    p = hgp.Plan(b, tau=1e-12)
+    Dt = torch.tensor(D, device="cuda")
+    J1, K1, J2, K2 = (torch.empty_like(Dt) for _ in range(4))
+    p.jk(Dt, J1, K1)
+    p.set_timing(True)
+    p.jk(Dt, J2, K2)
+    torch.cuda.synchronize()
+    p.set_timing(False)
+    p.close()
+    b.close()
+    tol = 1e-12 + 1e-14 * max(J2.abs().max().item(), K2.abs().max().item())
+    assert (J1 - J2).abs().max().item() <= tol and (K1 - K2).abs().max().item() <= tol
+    Jr, Kr = oracle.jk(bw, D, tau=1e-12)
+    assert np.abs(J1.cpu().numpy() - Jr).max() <= JK_TOL and np.abs(K1.cpu().numpy() - Kr).max() <= JK_TOL

@@ -1,8 +1,8 @@
 """Serving (continuous batching on several streams, plans reused across
 closed-loop density updates, HBM-budget admission): every served J/K must
-equal what the same plan gives for that density alone, 1e-12 absolute for
-FP64 plans (only the order of FP64 atomic additions differs); for mixed
-plans also within 1e-9 of the FP64 plan alone."""
+equal what the same plan gives for that density alone, 1e-12 absolute plus
+1e-14 of the largest entry (only the order of FP64 atomic additions
+differs); for mixed plans also within 1e-9 of the FP64 plan alone."""
 import numpy as np
 import pytest
 
@@ -13,6 +13,14 @@ pytestmark = pytest.mark.gpu
 
 SAME_TOL = 1e-12
 JK_TOL = 1e-9
+
+
+def same_tol(results):
+    """Bar for the same terms summed in another order: 1e-12 absolute plus
+    1e-14 of the largest entry (a plan runs its classes concurrently, so the
+    FP64 atomic additions land in a different order from run to run)."""
+    big = max(max(np.abs(r[0]).max(), np.abs(r[1]).max()) for r in results)
+    return SAME_TOL + 1e-14 * big
 
 
 @pytest.fixture(scope="module")
@@ -78,9 +86,10 @@ def test_served_equals_alone(hgp, torch_cuda, theta, worker):
             J, K = ex.results[(r.rid, k)]
             worst = max(worst, np.abs(J - res[k][0]).max(), np.abs(K - res[k][1]).max())
     s = serve.summarize(recs, ups, max(u.done for u in ups))
+    tol = same_tol([x for a in alone for x in a[0]])
     print(f"theta {theta} worker {worker}: N = {[r.basis.nbf for r in reqs]}, peak active {srv.peak_active}, "
           f"max |served - alone| {worst:.2e}, update p50/p99 {s['update_p50_ms']:.2f}/{s['update_p99_ms']:.2f} ms")
-    assert worst <= SAME_TOL
+    assert worst <= tol
     if theta > 0:
         # the mixed results against the FP64 plan alone, and the smallest system against the oracle
         err = 0.0
@@ -116,4 +125,4 @@ def test_iteration_served_equals_alone(hgp, torch_cuda):
             J, K = ex.results[(r.rid, k)]
             worst = max(worst, np.abs(J - res[k][0]).max(), np.abs(K - res[k][1]).max())
     print(f"iteration server: peak active {srv.peak_active}, rebuilds {srv.rebuilds}, max |served - alone| {worst:.2e}")
-    assert worst <= SAME_TOL and srv.peak_active == 4
+    assert worst <= same_tol([x for a in alone for x in a[0]]) and srv.peak_active == 4
