@@ -28,22 +28,41 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-ato
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", CSRC, "-I", INCLUDE]
 DEFAULT_LMAX = 4
+# the compiler's per-kernel resource report (registers, scratch, LDS, occupancy)
+REMARKS = ["-Rpass-analysis=kernel-resource-usage"]
 
 
 REGISTER_OPTS = ("waves", "digest", "reduce", "loop", "block")
 STAGED_OPTS = ("cap", "waves", "reduce", "loop")
 
 
+_EMITTED: dict = {}     # (class, options) -> (source, meta), so a rerouting pass regenerates only what changed
+
+
+def _emit(ls, r):
+    from .gen import emit, emit_staged, emit_t3
+    key = (tuple(ls), json.dumps(r, sort_keys=True, default=str))
+    if key not in _EMITTED:
+        if r["tier"] in (2, 3):
+            _EMITTED[key] = emit_t3.emit_class_t3(*ls)
+        elif r["tier"] == 1:
+            _EMITTED[key] = emit_staged.emit_class_staged(*ls, **{k: r[k] for k in STAGED_OPTS if k in r})
+        else:
+            _EMITTED[key] = emit.emit_class(*ls, **{k: r[k] for k in REGISTER_OPTS if k in r})
+    return _EMITTED[key]
+
+
 def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overrides=None, gen_dir: str = GEN,
-             defaults=None):
+             defaults=None, reroute=None):
     """Write one .hip per canonical class plus the class table into gen_dir.
     Each class is routed to the register or staged tier (gen/router.py).
     defaults (generator options for every class) are applied first, then
     the router's choice (tuning table, else the register model), then
     overrides, a map from class tag to options that wins over both.
     Register-tier options: waves, digest, reduce, loop, block; staged: cap,
-    waves, reduce, loop."""
-    from .gen import emit, emit_staged, emit_t3, router
+    waves, reduce, loop.  reroute (class tag -> options) is applied last:
+    the build's answer to a compiler resource report that showed spills."""
+    from .gen import emit, router
     from .gen.cart import canonical_classes
 
     GEN = gen_dir
@@ -58,12 +77,14 @@ def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overri
                 r[k] = v
         if overrides and tag in overrides:
             r.update(overrides[tag])
-        if r["tier"] == 2:
-            src, meta = emit_t3.emit_class_t3(*ls)
-        elif r["tier"] == 1:
-            src, meta = emit_staged.emit_class_staged(*ls, **{k: r[k] for k in STAGED_OPTS if k in r})
-        else:
-            src, meta = emit.emit_class(*ls, **{k: r[k] for k in REGISTER_OPTS if k in r})
+        if reroute and tag in reroute:
+            rr = reroute[tag]
+            if rr.get("tier") == 1 and "cap" not in rr and r.get("tier") != 1:
+                r["cap"] = router.model_cap(ls)
+            r.update(rr)
+        src, meta = _emit(ls, r)
+        meta.route = {k: v for k, v in r.items() if k not in ("variant", "ms")}
+        meta.route["rerouted"] = bool(reroute and tag in reroute)
         path = os.path.join(GEN, f"class_{meta.tag}.hip")
         _write_if_changed(path, src)
         files.append(path)
@@ -114,42 +135,164 @@ def _compile(src: str, force: bool):
     for d in deps:
         h.update(open(d, "rb").read())
     obj = os.path.join(OBJ, os.path.basename(src) + "." + h.hexdigest()[:16] + ".o")
-    if os.path.exists(obj) and not force:
+    if os.path.exists(obj) and os.path.exists(obj + ".res.json") and not force:
         return obj, 0.0
     t = time.time()
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj + ".tmp"]
+    cmd = [HIPCC] + FLAGS + REMARKS + ["-c", src, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")
+    with open(obj + ".res.json", "w") as fh:
+        json.dump(parse_resource_remarks(r.stderr), fh)
     os.replace(obj + ".tmp", obj)
     return obj, time.time() - t
 
 
+_REMARK_KEYS = {"TotalSGPRs": "sgpr", "VGPRs": "vgpr", "AGPRs": "agpr", "ScratchSize [bytes/lane]": "scratch",
+                "Occupancy [waves/SIMD]": "occupancy", "SGPRs Spill": "sgpr_spill", "VGPRs Spill": "vgpr_spill",
+                "LDS Size [bytes/block]": "lds", "Dynamic Stack": "dynamic_stack"}
+
+
+def _demangle_kernel(name: str) -> str:
+    """The kernel's own identifier out of an Itanium-mangled name (enough for
+    the library's kernels: plain or namespaced functions, templates reported
+    with their arguments appended)."""
+    if not name.startswith("_Z"):
+        return name
+    import re
+    parts = []
+    s = name[2:]
+    if s.startswith("N"):
+        s = s[1:]
+        while s and s[0].isdigit():
+            m = re.match(r"(\d+)", s)
+            n = int(m.group(1))
+            s = s[m.end():]
+            parts.append(s[:n])
+            s = s[n:]
+        base = parts[-1] if parts else name
+    else:
+        m = re.match(r"(\d+)", s)
+        base = s[m.end():m.end() + int(m.group(1))] if m else name
+        s = s[m.end() + int(m.group(1)):] if m else ""
+    tmpl = ""
+    m = re.search(r"ILi(\d+)EE", name)
+    if m:
+        tmpl = f"<{m.group(1)}>"
+    elif re.search(r"ILb1EE", name):
+        tmpl = "<true>"
+    elif re.search(r"ILb0EE", name):
+        tmpl = "<false>"
+    return base + tmpl
+
+
+def parse_resource_remarks(stderr: str) -> dict:
+    """{kernel: {vgpr, agpr, sgpr, scratch, occupancy, lds, vgpr_spill, ...}}
+    from the compiler's kernel-resource-usage remarks."""
+    out, cur = {}, None
+    for line in stderr.splitlines():
+        if "remark:" not in line or "kernel-resource-usage" not in line:
+            continue
+        body = line.split("remark:", 1)[1].rsplit("[-Rpass-analysis", 1)[0].strip()
+        if body.startswith("Function Name:"):
+            mangled = body.split(":", 1)[1].strip()
+            cur = {"mangled": mangled}
+            out[_demangle_kernel(mangled) + ("" if _demangle_kernel(mangled) not in out else "#" + mangled)] = cur
+            continue
+        if cur is None or ":" not in body:
+            continue
+        k, v = body.rsplit(":", 1)
+        k = k.strip()
+        if k in _REMARK_KEYS:
+            v = v.strip()
+            cur[_REMARK_KEYS[k]] = (v == "True") if v in ("True", "False") else int(v)
+    return out
+
+
+def check_resources(res: dict) -> list[str]:
+    """Kernels that use private scratch (register spills or stack): the
+    library's kernels must compile with none."""
+    return sorted(k for k, r in res.items() if r.get("scratch", 0) > 0 or r.get("dynamic_stack", False))
+
+
+def resources_path(lib: str) -> str:
+    """The compiler's per-kernel resource report written beside a library."""
+    return (lib[:-3] if lib.endswith(".so") else lib) + ".resources.json"
+
+
+def class_scratch(res: dict, tag: str) -> int:
+    """Largest private scratch (bytes per lane) of the kernels of class `tag`
+    (a spill into accumulation registers uses none and is not counted)."""
+    return max((r.get("scratch", 0) for k, r in res.items() if k.split("#")[0].endswith("_" + tag)), default=0)
+
+
+def _spilled_classes(res: dict) -> dict:
+    """class tag -> names of its kernels that use private scratch."""
+    out: dict = {}
+    for k in check_resources(res):
+        name = k.split("#")[0]
+        if "_" in name and name.rsplit("_", 1)[1].isdigit():
+            out.setdefault(name.rsplit("_", 1)[1], []).append(name)
+    return out
+
+
 def build(lmax: int = DEFAULT_LMAX, jobs: int | None = None, force: bool = False, verbose: bool = True,
-          overrides=None, out: str | None = None, gen_dir: str = GEN, defaults=None, table=None) -> str:
+          overrides=None, out: str | None = None, gen_dir: str = GEN, defaults=None, table=None,
+          allow_scratch: bool = False) -> str:
     """Generate, compile and link; out (default: the package's libhgp.so)
-    and gen_dir let a tuning run build variant libraries side by side."""
+    and gen_dir let a tuning run build variant libraries side by side.
+    A kernel compiled with private scratch (a register spill) fails the
+    build unless allow_scratch (tuning variants: the tuner then leaves that
+    class's variant out)."""
+    from .gen import router
     t0 = time.time()
     os.makedirs(OBJ, exist_ok=True)
-    gen_files, metas = generate(lmax, verbose=False, overrides=overrides, gen_dir=gen_dir, defaults=defaults,
-                                table=table)
-    srcs = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")] + gen_files
     jobs = jobs or min(8, os.cpu_count() or 4)
-    objs = []
-    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = {ex.submit(_compile, s, force): s for s in srcs}
-        for f in cf.as_completed(futs):
-            obj, dt = f.result()
-            objs.append(obj)
-            if verbose and dt > 0:
-                print(f"  compiled {os.path.basename(futs[f])} in {dt:.1f}s", flush=True)
-    objs.sort()
+    reroute: dict = {}
+    compiled: set = set()
+    for attempt in range(8):
+        gen_files, metas = generate(lmax, verbose=False, overrides=overrides, gen_dir=gen_dir, defaults=defaults,
+                                    table=table, reroute=reroute)
+        srcs = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")] + gen_files
+        objs = []
+        with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+            # force recompiles each source once per build, not once per rerouting pass
+            futs = {ex.submit(_compile, s, force and s not in compiled): s for s in srcs}
+            for f in cf.as_completed(futs):
+                obj, dt = f.result()
+                objs.append(obj)
+                compiled.add(futs[f])
+                if verbose and dt > 0:
+                    print(f"  compiled {os.path.basename(futs[f])} in {dt:.1f}s", flush=True)
+        objs.sort()
+        res = {}
+        for o in objs:
+            with open(o + ".res.json") as fh:
+                res.update(json.load(fh))
+        # the compiler's resource report has the last word on the register
+        # model: a class whose kernels spill moves down the router's ladder
+        spilled = _spilled_classes(res)
+        if not spilled or allow_scratch:
+            break
+        by_tag = {m.tag: m for m in metas}
+        for tag, kernels in sorted(spilled.items()):
+            nxt = router.fallback(by_tag[tag].route, kernels)
+            if nxt is None:
+                continue
+            if verbose:
+                print(f"  class {tag}: {', '.join(sorted(kernels))} use private scratch; rerouting {nxt}", flush=True)
+            reroute[tag] = nxt
+    bad = check_resources(res)
+    if bad and not allow_scratch:
+        raise RuntimeError("kernels compiled with private scratch (register spill or stack), which the library "
+                           "does not allow: " + ", ".join(f"{k} ({res[k].get('scratch')} B/lane)" for k in bad))
     lib = out or LIB
     tmp = lib + ".tmp"
     r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
     os.replace(tmp, lib)
+    _write_if_changed(resources_path(lib), json.dumps(res, indent=0, sort_keys=True))
     if verbose:
         staged = [m.tag for m in metas if m.tier == 1]
         t3 = [m.tag for m in metas if m.tier == 2]

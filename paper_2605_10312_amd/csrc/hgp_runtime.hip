@@ -37,16 +37,40 @@ int pair_class_of(int la, int lb) { return la * (la + 1) / 2 + lb; }   // la >= 
 std::mutex g_mu;
 double *g_boys[64] = {};
 
+// The Boys table lives in a file-scope device array, one copy per device, so
+// building it allocates nothing.  Host code uses the address returned by
+// hipGetSymbolAddress on that device, never the array's name.
+__device__ __align__(256) double boys_store[BOYS_NPTS * BOYS_STRIDE];
+
+// Runs fn with device dev current, then restores the caller's device.
+template <class F>
+hipError_t on_device(int dev, F fn)
+{
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    e = fn();
+    if (cur != dev) {
+        const hipError_t r = hipSetDevice(cur);
+        if (e == hipSuccess) e = r;
+    }
+    return e;
+}
+
 hgp_status boys_table(int dev, const double **out)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     if (dev < 0 || dev >= 64) return fail(HGP_E_DEVICE, "device index out of range");
     if (!g_boys[dev]) {
         double *t = nullptr;
-        HGP_HIP(hipMalloc(&t, sizeof(double) * BOYS_NPTS * BOYS_STRIDE));
-        launch_boys_table(t, 0);
-        HGP_HIP(hipGetLastError());
-        HGP_HIP(hipStreamSynchronize(0));
+        HGP_HIP(on_device(dev, [&]() {
+            hipError_t e = hipGetSymbolAddress((void **)&t, HIP_SYMBOL(boys_store));
+            if (e != hipSuccess) return e;
+            launch_boys_table(t, 0);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            return hipStreamSynchronize(0);
+        }));
         g_boys[dev] = t;
     }
     *out = g_boys[dev];
@@ -1167,8 +1191,19 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
     return HGP_OK;
 }
 
-hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64_t n, const double *centers,
-                                 const double *exps, double *out, int32_t precision, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+// Validated class and layout of one hgp_eri_prim_quartets call.
+struct PrimCall {
+    int ci = -1;              // class table index
+    int ls[4], pos[4], cs[4];
+    int64_t blk = 0;          // integrals per quartet
+};
+
+hgp_status prim_call_setup(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64_t n, const double *centers,
+                           const double *exps, double *out, int32_t precision, PrimCall *c)
 {
     const int lin[4] = {la, lb, lc, ld};
     for (int r = 0; r < 4; ++r) {
@@ -1177,24 +1212,51 @@ hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld,
     }
     if (precision != HGP_FP64) return fail(HGP_E_INVALID, "only HGP_FP64 is supported");
     if (n < 0) return fail(HGP_E_INVALID, "n < 0");
-    if (n == 0) return HGP_OK;
-    if (!centers || !exps || !out) return fail(HGP_E_INVALID, "NULL argument");
+    if (n > 0 && (!centers || !exps || !out)) return fail(HGP_E_INVALID, "NULL argument");
     if (n > (int64_t)1 << 30) return fail(HGP_E_INVALID, "n too large for one call");
-    int pos[4] = {0, 1, 2, 3};
+    int *pos = c->pos;
+    for (int r = 0; r < 4; ++r) pos[r] = r;
     if (lin[0] < lin[1]) std::swap(pos[0], pos[1]);
     if (lin[2] < lin[3]) std::swap(pos[2], pos[3]);
     if (pair_class_of(lin[pos[0]], lin[pos[1]]) < pair_class_of(lin[pos[2]], lin[pos[3]])) {
         std::swap(pos[0], pos[2]);
         std::swap(pos[1], pos[3]);
     }
-    int ls[4], nn[4], stride[4], cs[4];
-    for (int r = 0; r < 4; ++r) { ls[r] = lin[pos[r]]; nn[r] = nsph(lin[r]); }
-    const int ci = class_index(ls[0], ls[1], ls[2], ls[3]);
-    if (ci < 0) return fail(HGP_E_UNSUPPORTED_L, "class kernel not built into this library");
-    if (hgp_status pst = prepare_class(g_class_table[ci])) return pst;
+    int nn[4], stride[4];
+    for (int r = 0; r < 4; ++r) { c->ls[r] = lin[pos[r]]; nn[r] = nsph(lin[r]); }
+    c->ci = class_index(c->ls[0], c->ls[1], c->ls[2], c->ls[3]);
+    if (c->ci < 0) return fail(HGP_E_UNSUPPORTED_L, "class kernel not built into this library");
     stride[3] = 1; stride[2] = nn[3]; stride[1] = nn[2] * nn[3]; stride[0] = nn[1] * nn[2] * nn[3];
-    for (int r = 0; r < 4; ++r) cs[r] = stride[pos[r]];
-    const int64_t blk = (int64_t)nn[0] * nn[1] * nn[2] * nn[3];
+    for (int r = 0; r < 4; ++r) c->cs[r] = stride[pos[r]];
+    c->blk = (int64_t)nn[0] * nn[1] * nn[2] * nn[3];
+    return HGP_OK;
+}
+
+// Pair records of the n quartets, then the class kernels (in batches through
+// the scratch buffer for the staged and op-table tiers).
+void prim_call_run(const PrimCall &c, int64_t n, const double *centers, const double *exps, double *out,
+                   const double *boys, PairInfo *d_pairs, PairGeo *d_geo, PrimPair *d_prims, EriTask *d_tasks,
+                   double *d_scr, int64_t scr_doubles, hipStream_t s)
+{
+    launch_prim_quartet_pairs(n, centers, exps, c.ls, c.pos, c.cs, c.blk, d_pairs, d_geo, d_prims, d_tasks, s);
+    EriArgs a{};
+    a.tasks = d_tasks; a.ntask = n; a.pairs = d_pairs; a.geo = d_geo; a.prims = d_prims; a.boys = boys;
+    a.out = out; a.mode = 0;
+    a.scratch = d_scr;
+    run_eri_class(g_class_table[c.ci], a, scr_doubles, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64_t n, const double *centers,
+                                 const double *exps, double *out, int32_t precision, void *hip_stream)
+{
+    PrimCall c;
+    if (hgp_status st = prim_call_setup(la, lb, lc, ld, n, centers, exps, out, precision, &c)) return st;
+    if (n == 0) return HGP_OK;
+    if (hgp_status pst = prepare_class(g_class_table[c.ci])) return pst;
     hipStream_t s = (hipStream_t)hip_stream;
     int dev = 0;
     HGP_HIP(hipGetDevice(&dev));
@@ -1206,7 +1268,7 @@ hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld,
     PrimPair *d_prims = nullptr;
     EriTask *d_tasks = nullptr;
     double *d_scr = nullptr;
-    const int64_t sneed = staged_need(g_class_table[ci], n);
+    const int64_t sneed = staged_need(g_class_table[c.ci], n);
     hipError_t e = hipMallocAsync((void **)&d_pairs, sizeof(PairInfo) * 2 * n, s);
     if (e == hipSuccess) e = hipMallocAsync((void **)&d_geo, sizeof(PairGeo) * 2 * n, s);
     if (e == hipSuccess) e = hipMallocAsync((void **)&d_prims, sizeof(PrimPair) * 2 * n, s);
@@ -1219,12 +1281,7 @@ hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld,
         if (d_tasks) hipFreeAsync(d_tasks, s);
         return fail(HGP_E_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
     }
-    launch_prim_quartet_pairs(n, centers, exps, ls, pos, cs, blk, d_pairs, d_geo, d_prims, d_tasks, s);
-    EriArgs a{};
-    a.tasks = d_tasks; a.ntask = n; a.pairs = d_pairs; a.geo = d_geo; a.prims = d_prims; a.boys = boys;
-    a.out = out; a.mode = 0;
-    a.scratch = d_scr;
-    run_eri_class(g_class_table[ci], a, sneed, s);
+    prim_call_run(c, n, centers, exps, out, boys, d_pairs, d_geo, d_prims, d_tasks, d_scr, sneed, s);
     e = hipGetLastError();
     if (d_scr) hipFreeAsync(d_scr, s);
     hipFreeAsync(d_pairs, s);

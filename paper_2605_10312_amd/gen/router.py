@@ -102,8 +102,30 @@ def route(ls, table=None):
     t = dict(table.get(tag, {}))
     tier = t.get("tier", model_tier(ls))
     cap = model_cap(ls) if tier == 1 else DEFAULT_CAP
+    if tier == 1 and "cap" in t:
+        cap = t["cap"]
     r = {"tier": tier, "cap": cap, "waves": 0, "source": "model"}
     if t:                      # measured entries win; what they leave out comes from the model
         r.update({k: v for k, v in t.items() if k not in ("variant", "ms")})
         r["source"] = "table"
     return r
+
+
+def fallback(route, spilled):
+    """The next choice for a class whose kernels `spilled` (names) compiled
+    with private scratch under `route` (the options it was generated with), or
+    None when there is none.  Register tier -> staged tier; staged tier whose
+    Phase-1 chunks spill -> the next smaller chunk cap; staged tier whose
+    Phase-2 kernels spill (their per-column working set does not fit) ->
+    the op-table tiers, which keep every value in LDS or HBM."""
+    tier = route.get("tier", 0)
+    if tier == 0:
+        return {"tier": 1}
+    if tier == 1:
+        if all(k.startswith("p1_") for k in spilled):
+            cap = route.get("cap", DEFAULT_CAP)
+            smaller = [c for c in CAPS if c < cap]
+            if smaller:
+                return {"tier": 1, "cap": smaller[0]}
+        return {"tier": 2}
+    return None

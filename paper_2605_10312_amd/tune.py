@@ -60,7 +60,7 @@ def build_variants(names, lmax):
         t = time.time()
         gen = os.path.join(b.ROOT, "_build", "gen_" + name)
         out = os.path.join(VARIANTS_DIR, f"libhgp_{name}.so")
-        b.build(lmax, verbose=False, out=out, gen_dir=gen, defaults=VARIANTS[name], table={})
+        b.build(lmax, verbose=False, out=out, gen_dir=gen, defaults=VARIANTS[name], table={}, allow_scratch=True)
         print(f"built variant {name} -> {out} in {time.time() - t:.1f}s", flush=True)
 
 
@@ -137,13 +137,25 @@ def refine(names, out, steps, warmup, timeout, margin=0.02, table=TABLE):
     apply_refine(out, margin, table)
 
 
+def spills(name, tag):
+    """True when variant `name` compiled class `tag` with private scratch (a
+    register spill): such a variant is never adopted, however fast."""
+    from . import build as b
+    lib = os.path.join(VARIANTS_DIR, f"libhgp_{name}.so")
+    path = b.resources_path(lib)
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path}: the variant's resource report is missing; rebuild it")
+    return b.class_scratch(json.load(open(path)), tag) > 0
+
+
 def apply_refine(path, margin=0.02, table=TABLE):
     """The table update of `refine`, from its saved timings."""
     results = json.load(open(path))
     cur = json.load(open(table))
     for tag, c in results["current"]["classes"].items():
         best = min(((r["classes"][tag]["ms"], n) for n, r in results.items()
-                    if n != "current" and tag in r["classes"] and r["classes"][tag]["tier"] == c["tier"]),
+                    if n != "current" and tag in r["classes"] and r["classes"][tag]["tier"] == c["tier"]
+                    and not spills(n, tag)),
                    default=None)
         if best and best[0] < (1.0 - margin) * c["ms"]:
             opts = {"tier": c["tier"]}
@@ -164,7 +176,12 @@ def select(path, table=TABLE):
     classes = sorted({t for r in res.values() for t in r["classes"]})
     chosen = {}
     for tag in classes:
-        best = min((r["classes"][tag]["ms"], name) for name, r in res.items() if tag in r["classes"])
+        cands = [(r["classes"][tag]["ms"], name) for name, r in res.items()
+                 if tag in r["classes"] and not spills(name, tag)]
+        if not cands:
+            print(f"{tag}: every variant spills; left to the model")
+            continue
+        best = min(cands)
         opts = {"tier": res[best[1]]["classes"][tag]["tier"]}
         opts.update({k: v for k, v in VARIANTS[best[1]].items()})
         if opts["tier"] == 1:

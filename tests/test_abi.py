@@ -79,3 +79,4 @@ def test_null_arguments_rejected():
     assert L.hgp_eri_prim_quartets(5, 0, 0, 0, 1, None, None, None, 0, None) == -2
     assert L.hgp_eri_prim_quartets(0, 0, 0, 0, -1, None, None, None, 0, None) == -1
     assert L.hgp_eri_prim_quartets(0, 0, 0, 0, 0, None, None, None, 0, None) == 0
+

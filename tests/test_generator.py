@@ -93,11 +93,50 @@ def test_tuner_select(tmp_path, monkeypatch):
     path = tmp_path / "r.json"
     path.write_text(json.dumps(res))
     table = tmp_path / "t.json"
+    monkeypatch.setattr(tune, "VARIANTS_DIR", str(tmp_path))
+    clean = {"jk_1000": {"scratch": 0}, "p1_2222": {"scratch": 0}, "jk_2222": {"scratch": 0}}
+    for v in ("a", "b"):
+        (tmp_path / f"libhgp_{v}.resources.json").write_text(json.dumps(clean))
     tune.select(str(path), table=str(table))
     got = json.loads(table.read_text())["classes"]
     assert got["1000"]["variant"] == "a" and got["1000"]["reduce"] == "none"
     # a staged class keeps only the options its emitter takes
     assert got["2222"]["variant"] == "b" and got["2222"]["waves"] == 2 and "digest" not in got["2222"]
+    # a variant that compiled the class with private scratch is never chosen, however fast
+    spill = dict(clean, p1_2222={"scratch": 16})
+    (tmp_path / "libhgp_b.resources.json").write_text(json.dumps(spill))
+    tune.select(str(path), table=str(table))
+    got = json.loads(table.read_text())["classes"]
+    assert got["2222"]["variant"] == "a"
+
+
+def test_router_fallback_ladder():
+    from paper_2605_10312_amd.gen import router
+    assert router.fallback({"tier": 0}, ["jk_2120"]) == {"tier": 1}
+    assert router.fallback({"tier": 1, "cap": 96}, ["p1_2222"]) == {"tier": 1, "cap": 64}
+    assert router.fallback({"tier": 1, "cap": 16}, ["p1_2222"]) == {"tier": 2}
+    assert router.fallback({"tier": 1, "cap": 96}, ["jk_4410", "p1_4410"]) == {"tier": 2}
+    assert router.fallback({"tier": 2}, ["t3_jk_kernel"]) is None
+
+
+def test_resource_remarks_parse():
+    from paper_2605_10312_amd import build
+    err = "\n".join([
+        "x.hip:3:1: remark: Function Name: _ZN3hgp12_GLOBAL__N_17jk_2120ENS_6JKArgsE [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:3:1: remark:     VGPRs: 256 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:3:1: remark:     AGPRs: 121 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:3:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:3:1: remark:     Dynamic Stack: False [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:3:1: remark:     Occupancy [waves/SIMD]: 1 [-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark: Function Name: _ZN3hgp12_GLOBAL__N_114t3w_eri_kernelILb0EEEvNS_7EriArgsE "
+        "[-Rpass-analysis=kernel-resource-usage]",
+        "x.hip:9:1: remark:     ScratchSize [bytes/lane]: 24 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    res = build.parse_resource_remarks(err)
+    assert res["jk_2120"]["vgpr"] == 256 and res["jk_2120"]["agpr"] == 121 and res["jk_2120"]["occupancy"] == 1
+    assert res["jk_2120"]["dynamic_stack"] is False
+    assert build.check_resources(res) == ["t3w_eri_kernel<false>"]
+    assert build.class_scratch(res, "2120") == 0
 
 
 def test_generate_applies_defaults_and_overrides(tmp_path):
