@@ -246,6 +246,27 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
 hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64_t n, const double *centers,
                                  const double *exps, double *out, int32_t precision, void *hip_stream);
 
+/*
+ * hgp_eri_prim_quartets_noalloc -- hgp_eri_prim_quartets for callers that
+ * cannot allocate device memory during the call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, layout and results.  The pair and task records and the staged
+ * tier's batch buffer come from one fixed 64 MiB device buffer that the
+ * library holds per device until the process ends (set up on the first call
+ * on a device, together with the Boys table; no call allocates).
+ * Limits: register- and staged-tier classes only (HGP_E_UNSUPPORTED_L for a
+ * class on an op-table tier); n at most hgp_eri_prim_quartets_noalloc_max for
+ * the class (about 190 000 for register-tier classes), HGP_E_INVALID beyond.
+ * Every call on a device shares that device's buffer: calls that overlap on
+ * one device (two streams, two host threads) race and must be serialised by
+ * the caller; the buffer keeps the last call's contents.
+ */
+hgp_status hgp_eri_prim_quartets_noalloc(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64_t n,
+                                         const double *centers, const double *exps, double *out, int32_t precision,
+                                         void *hip_stream);
+/* Largest n hgp_eri_prim_quartets_noalloc accepts for class (la lb|lc ld); -1 if it cannot run the class. */
+int64_t hgp_eri_prim_quartets_noalloc_max(int32_t la, int32_t lb, int32_t lc, int32_t ld);
+
 /* Thread-local description of the last non-OK status (never NULL). */
 const char *hgp_last_error(void);
 

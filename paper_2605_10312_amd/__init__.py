@@ -51,6 +51,8 @@ SIGNATURES = {
     "hgp_jk": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "hgp_eri_shell_quartets": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
     "hgp_eri_prim_quartets": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i64, _vp, _vp, _vp, _i32, _vp]),
+    "hgp_eri_prim_quartets_noalloc": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i64, _vp, _vp, _vp, _i32, _vp]),
+    "hgp_eri_prim_quartets_noalloc_max": (_i64, [_i32, _i32, _i32, _i32]),
     "hgp_last_error": (ctypes.c_char_p, []),
 }
 
@@ -291,6 +293,20 @@ def eri_prim_quartets(ls, centers, exps, out, stream=None):
     _check(lib().hgp_eri_prim_quartets(*[int(x) for x in ls], n, _dptr(centers, torch.float64),
                                        _dptr(exps, torch.float64), _dptr(out, torch.float64), HGP_FP64,
                                        ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def eri_prim_quartets_noalloc(ls, centers, exps, out, stream=None):
+    """eri_prim_quartets through the entry point that allocates nothing (the
+    library's fixed per-device buffer; see hgp_eri_prim_quartets_noalloc)."""
+    import torch
+    n = int(centers.shape[0])
+    _check(lib().hgp_eri_prim_quartets_noalloc(*[int(x) for x in ls], n, _dptr(centers, torch.float64),
+                                               _dptr(exps, torch.float64), _dptr(out, torch.float64), HGP_FP64,
+                                               ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def eri_prim_quartets_noalloc_max(ls) -> int:
+    return int(lib().hgp_eri_prim_quartets_noalloc_max(*[int(x) for x in ls]))
 
 
 def max_l() -> int:

@@ -1246,6 +1246,38 @@ void prim_call_run(const PrimCall &c, int64_t n, const double *centers, const do
     run_eri_class(g_class_table[c.ci], a, scr_doubles, s);
 }
 
+// hgp_eri_prim_quartets_noalloc's buffer: file-scope device memory, one copy
+// per device, held until the process ends.  Host code reaches it only through
+// the per-device address hipGetSymbolAddress returns (g_scratch_ptr).
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+unsigned char *g_scratch_ptr[64] = {};
+
+hgp_status noalloc_scratch(int dev, unsigned char **out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (dev < 0 || dev >= 64) return fail(HGP_E_DEVICE, "device index out of range");
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HGP_HIP(on_device(dev, [&]() { return hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)); }));
+        if (!ptr) return fail(HGP_E_DEVICE, "hipGetSymbolAddress returned no address for the scratch buffer");
+        g_scratch_ptr[dev] = (unsigned char *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HGP_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of the fixed buffer that n quartets of class k take: pair and task
+// records, plus room for one 64-quartet batch of a staged class.
+size_t noalloc_need(const ClassKernels &k, int64_t n)
+{
+    const size_t rec = align256(sizeof(PairInfo) * 2 * n) + align256(sizeof(PairGeo) * 2 * n) +
+                       align256(sizeof(PrimPair) * 2 * n) + align256(sizeof(EriTask) * n);
+    return rec + (k.tier == 1 ? sizeof(double) * (size_t)k.scratch_slots * 64 : 0);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1288,6 +1320,63 @@ hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld,
     hipFreeAsync(d_geo, s);
     hipFreeAsync(d_prims, s);
     hipFreeAsync(d_tasks, s);
+    if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("microbench launch: ") + hipGetErrorString(e));
+    return HGP_OK;
+}
+
+int64_t hgp_eri_prim_quartets_noalloc_max(int32_t la, int32_t lb, int32_t lc, int32_t ld)
+{
+    PrimCall c;
+    double dummy = 0.0;
+    if (prim_call_setup(la, lb, lc, ld, 0, &dummy, &dummy, &dummy, HGP_FP64, &c)) return -1;
+    const ClassKernels &k = g_class_table[c.ci];
+    if (k.tier != 0 && k.tier != 1) return -1;
+    int64_t lo = 0, hi = (int64_t)(NOALLOC_BYTES / 64);
+    while (lo < hi) {                       // largest n whose records fit
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (noalloc_need(k, mid) <= NOALLOC_BYTES) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+hgp_status hgp_eri_prim_quartets_noalloc(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64_t n,
+                                         const double *centers, const double *exps, double *out, int32_t precision,
+                                         void *hip_stream)
+{
+    PrimCall c;
+    if (hgp_status st = prim_call_setup(la, lb, lc, ld, n, centers, exps, out, precision, &c)) return st;
+    const ClassKernels &k = g_class_table[c.ci];
+    if (k.tier != 0 && k.tier != 1)
+        return fail(HGP_E_UNSUPPORTED_L, "this class runs on an op-table tier, whose tables are uploaded to the "
+                                         "device on first use; use hgp_eri_prim_quartets");
+    const size_t need = noalloc_need(k, n);
+    if (need > NOALLOC_BYTES)
+        return fail(HGP_E_INVALID, "n = " + std::to_string(n) + " needs " + std::to_string(need) +
+                                       " bytes of the fixed buffer (" + std::to_string(NOALLOC_BYTES) +
+                                       "); at most " + std::to_string(hgp_eri_prim_quartets_noalloc_max(la, lb, lc, ld)) +
+                                       " quartets of this class per call");
+    if (n == 0) return HGP_OK;
+    int dev = 0;
+    HGP_HIP(hipGetDevice(&dev));
+    const double *boys = nullptr;
+    if (hgp_status st = boys_table(dev, &boys)) return st;
+    unsigned char *base = nullptr;
+    if (hgp_status st = noalloc_scratch(dev, &base)) return st;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) { unsigned char *p = base + off; off += align256(bytes); return p; };
+    PairInfo *d_pairs = (PairInfo *)carve(sizeof(PairInfo) * 2 * n);
+    PairGeo *d_geo = (PairGeo *)carve(sizeof(PairGeo) * 2 * n);
+    PrimPair *d_prims = (PrimPair *)carve(sizeof(PrimPair) * 2 * n);
+    EriTask *d_tasks = (EriTask *)carve(sizeof(EriTask) * n);
+    double *d_scr = nullptr;
+    int64_t scr_doubles = 0;
+    if (k.tier == 1) {
+        d_scr = (double *)(base + off);
+        scr_doubles = std::min((int64_t)((NOALLOC_BYTES - off) / sizeof(double)), staged_need(k, n));
+    }
+    prim_call_run(c, n, centers, exps, out, boys, d_pairs, d_geo, d_prims, d_tasks, d_scr, scr_doubles,
+                  (hipStream_t)hip_stream);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("microbench launch: ") + hipGetErrorString(e));
     return HGP_OK;
 }

@@ -80,3 +80,20 @@ def test_null_arguments_rejected():
     assert L.hgp_eri_prim_quartets(0, 0, 0, 0, -1, None, None, None, 0, None) == -1
     assert L.hgp_eri_prim_quartets(0, 0, 0, 0, 0, None, None, None, 0, None) == 0
 
+
+def test_noalloc_rejections_before_device_work():
+    """The allocation-free integrals entry rejects, with no HIP call: l > 4, a
+    class on an op-table tier, and more quartets than its fixed buffer holds."""
+    import paper_2605_10312_amd as hgp
+    h = hgp.lib()
+    fake = ctypes.c_void_p(16)        # never dereferenced: every case fails validation first
+    assert h.hgp_eri_prim_quartets_noalloc(5, 0, 0, 0, 1, fake, fake, fake, 0, None) == -2
+    assert h.hgp_eri_prim_quartets_noalloc(0, 0, 0, 0, -1, fake, fake, fake, 0, None) == -1
+    assert h.hgp_eri_prim_quartets_noalloc(0, 0, 0, 0, 4, fake, fake, fake, 1, None) == -1
+    nmax = h.hgp_eri_prim_quartets_noalloc_max(0, 0, 0, 0)
+    assert 100_000 <= nmax <= 1 << 20
+    assert h.hgp_eri_prim_quartets_noalloc(0, 0, 0, 0, nmax + 1, fake, fake, fake, 0, None) == -1
+    assert "quartets of this class per call" in h.hgp_last_error().decode()
+    assert h.hgp_eri_prim_quartets_noalloc_max(2, 2, 2, 2) > 0
+    assert h.hgp_eri_prim_quartets_noalloc_max(5, 0, 0, 0) == -1
+    assert h.hgp_eri_prim_quartets_noalloc(0, 0, 0, 0, 0, fake, fake, fake, 0, None) == 0
