@@ -128,6 +128,17 @@ def eri_shell_quartet(basis, i, j, k, l, precision: str = "double") -> np.ndarra
     return out
 
 
+def eri_deriv_shell_quartet(basis, i, j, k, l, precision: str = "double") -> np.ndarray:
+    """First derivatives of the spherical block (ij|kl) with respect to the
+    centres of shells i, j, k, l: array [4 centres, 3 axes, ni, nj, nk, nl]."""
+    keep, args = _basis_args(basis)
+    shape = [4, 3] + [nsph(int(basis.l[s])) for s in (i, j, k, l)]
+    out = np.zeros(shape)
+    rc = _fn("eri_deriv_shell_quartet", precision)(*args, *[ctypes.c_int(int(s)) for s in (i, j, k, l)], _p(out))
+    _check(rc, "eri_deriv_shell_quartet")
+    return out
+
+
 def eri_prim_quartets(ls, centers, exps, precision: str = "double") -> np.ndarray:
     """centers [n,4,3] bohr, exps [n,4]; normalised primitives; spherical blocks [n, ...]."""
     cen = np.ascontiguousarray(centers, np.float64)

@@ -63,8 +63,9 @@ typedef double real;
 
 #define PI_R ((real)3.14159265358979323846264338327950288L)
 #define LMAX 4                 /* highest shell angular momentum accepted   */
-#define NMAX (2 * LMAX)        /* highest |e| in a pair, la + lb            */
-#define NGMAX 165              /* monomials of degree <= NMAX: ncum(NMAX+1) */
+#define LINT (LMAX + 1)        /* highest l evaluated inside (first derivatives raise one shell by one) */
+#define NMAX (2 * LINT)        /* highest |e| in a pair, la + lb            */
+#define NGMAX 286              /* monomials of degree <= NMAX: ncum(NMAX+1) */
 
 /* ------------------------------------------------------------------ */
 /* Cartesian bookkeeping                                               */
@@ -299,7 +300,7 @@ static int quartet_cart(work_t *w, const int L4[4], const double *cen4[4], const
     real *V = w->V, *H = w->H;
     memset(H, 0, sizeof(real) * (size_t)NE * NF);
 #define VV(m, e, f) V[((size_t)(m) * NE + (e)) * NF + (f)]
-    real F[4 * LMAX + 2];
+    real F[4 * LINT + 2];
 
     /* ---- Phase 1: primitive loops, OS vertical recurrence, contraction ---- */
     for (int pa = 0; pa < n4[0]; ++pa)
@@ -437,6 +438,92 @@ static int quartet_sph(work_t *w, const basis_t *b, int i, int j, int k, int l, 
     return 0;
 }
 
+/* First derivatives of the spherical block (i j|k l) with respect to the
+ * centre coordinates of each of its four shells.  Differentiating a Cartesian
+ * primitive (x - A_x)^a_x ... exp(-alpha |r - A|^2) with respect to A_t gives
+ * 2 alpha times the primitive with a + 1_t minus a_t times the primitive with
+ * a - 1_t, so for the contracted shell (coefficients c_k, exponents alpha_k)
+ *   d/dA_t (a b|c d) = (a+1_t b|c d)_w - a_t (a-1_t b|c d),
+ * where the subscript w marks the contraction of that shell with weights
+ * 2 alpha_k c_k; likewise for the other three centres.  Each Cartesian
+ * derivative block is then transformed to spherical functions (materialise
+ * then transform).  out: [4 centres][3 axes][nsph(li)][nsph(lj)][nsph(lk)][nsph(ll)]. */
+static int quartet_deriv_sph(work_t *w, const basis_t *b, int i, int j, int k, int l, real *out)
+{
+    int sh[4] = {i, j, k, l}, L4[4], n4[4];
+    const double *cen4[4], *e4[4];
+    const real *c4[4];
+    for (int q = 0; q < 4; ++q) {
+        L4[q] = b->l[sh[q]]; n4[q] = b->nprim[sh[q]];
+        cen4[q] = b->cen + 3 * sh[q]; e4[q] = b->exps + b->poff[sh[q]]; c4[q] = b->c + b->poff[sh[q]];
+    }
+    int nc[4], ns[4];
+    size_t ncc = 1, nss = 1;
+    for (int q = 0; q < 4; ++q) { nc[q] = ncart(L4[q]); ns[q] = nsph(L4[q]); ncc *= nc[q]; nss *= ns[q]; }
+    if (grow(&w->C, &w->nC, ncc) || grow(&w->S1, &w->nS1, ncc) || grow(&w->S2, &w->nS2, ncc)) return -3;
+    int rc = 0;
+    for (int r = 0; r < 4 && !rc; ++r) {
+        int Lp[4], Lm[4], np_[4], nm_[4];
+        size_t sp = 1, sm = 1;
+        for (int q = 0; q < 4; ++q) { Lp[q] = Lm[q] = L4[q]; }
+        Lp[r] += 1; Lm[r] -= 1;
+        for (int q = 0; q < 4; ++q) { np_[q] = ncart(Lp[q]); sp *= np_[q]; nm_[q] = Lm[r] >= 0 ? ncart(Lm[q]) : 0; }
+        if (Lm[r] >= 0) for (int q = 0; q < 4; ++q) sm *= nm_[q]; else sm = 0;
+        real *cw = malloc(sizeof(real) * (size_t)n4[r]);
+        real *Xp = malloc(sizeof(real) * sp);
+        real *Xm = sm ? malloc(sizeof(real) * sm) : NULL;
+        if (!cw || !Xp || (sm && !Xm)) rc = -3;
+        if (!rc) {
+            for (int kk = 0; kk < n4[r]; ++kk) cw[kk] = 2 * (real)e4[r][kk] * c4[r][kk];
+            const real *c4p[4] = {c4[0], c4[1], c4[2], c4[3]};
+            c4p[r] = cw;
+            rc = quartet_cart(w, Lp, cen4, e4, c4p, n4, Xp);
+            if (!rc && sm) rc = quartet_cart(w, Lm, cen4, e4, c4, n4, Xm);
+        }
+        for (int t = 0; t < 3 && !rc; ++t) {
+            /* Cartesian derivative block along axis t of centre r */
+            real *Dc = w->C;
+            int q4[4];
+            for (q4[0] = 0; q4[0] < nc[0]; ++q4[0])
+            for (q4[1] = 0; q4[1] < nc[1]; ++q4[1])
+            for (q4[2] = 0; q4[2] < nc[2]; ++q4[2])
+            for (q4[3] = 0; q4[3] < nc[3]; ++q4[3]) {
+                /* exponents of shell r's component q4[r] (x descending, then y descending) */
+                int cnt = 0, ex[3] = {0, 0, 0};
+                for (int x = L4[r]; x >= 0 && cnt <= q4[r]; --x)
+                    for (int y = L4[r] - x; y >= 0; --y, ++cnt)
+                        if (cnt == q4[r]) { ex[0] = x; ex[1] = y; ex[2] = L4[r] - x - y; }
+                int up[3] = {ex[0], ex[1], ex[2]};
+                up[t] += 1;
+                int pidx[4] = {q4[0], q4[1], q4[2], q4[3]};
+                pidx[r] = cidx(up[1], up[2]);
+                size_t op = (((size_t)pidx[0] * np_[1] + pidx[1]) * np_[2] + pidx[2]) * np_[3] + pidx[3];
+                real v = Xp[op];
+                if (ex[t] > 0) {
+                    int dn[3] = {ex[0], ex[1], ex[2]};
+                    dn[t] -= 1;
+                    int midx[4] = {q4[0], q4[1], q4[2], q4[3]};
+                    midx[r] = cidx(dn[1], dn[2]);
+                    size_t om = (((size_t)midx[0] * nm_[1] + midx[1]) * nm_[2] + midx[2]) * nm_[3] + midx[3];
+                    v -= (real)ex[t] * Xm[om];
+                }
+                Dc[(((size_t)q4[0] * nc[1] + q4[1]) * nc[2] + q4[2]) * nc[3] + q4[3]] = v;
+            }
+            int n[4] = {nc[0], nc[1], nc[2], nc[3]};
+            real *src = w->C, *dst = w->S1;
+            for (int q = 0; q < 4; ++q) {
+                transform_index(src, dst, n, q, L4[q]);
+                n[q] = ns[q];
+                src = dst;
+                dst = (dst == w->S1) ? w->S2 : w->S1;
+            }
+            memcpy(out + (size_t)(r * 3 + t) * nss, src, sizeof(real) * nss);
+        }
+        free(cw); free(Xp); free(Xm);
+    }
+    return rc;
+}
+
 /* ------------------------------------------------------------------ */
 /* Exported entry points                                               */
 /* ------------------------------------------------------------------ */
@@ -510,6 +597,27 @@ int PFX(eri_shell_quartet)(int nshell, const int *l, const int *nprim, const dou
     real *tmp = malloc(sizeof(real) * n);
     work_t w; memset(&w, 0, sizeof(w));
     rc = tmp ? quartet_sph(&w, &b, i, j, k, ll, tmp) : -3;
+    for (size_t q = 0; q < n && !rc; ++q) out[q] = (double)tmp[q];
+    free(tmp); work_free(&w); basis_free(&b);
+    return rc;
+}
+
+/* First derivatives of the contracted spherical block of shells (i j|k l)
+ * with respect to the centre of each shell: out[4][3][ni][nj][nk][nl]
+ * (centre of shell i, j, k, l; axis x, y, z), bohr^-1 hartree. */
+int PFX(eri_deriv_shell_quartet)(int nshell, const int *l, const int *nprim, const double *centers,
+                                 const double *exps, const double *coefs, int i, int j, int k, int ll,
+                                 double *out)
+{
+    basis_t b;
+    int rc = basis_make(&b, nshell, l, nprim, centers, exps, coefs);
+    if (!rc && (i < 0 || j < 0 || k < 0 || ll < 0 || i >= nshell || j >= nshell || k >= nshell || ll >= nshell))
+        rc = -1;
+    if (rc) { basis_free(&b); return rc; }
+    size_t n = 12 * (size_t)nsph(l[i]) * nsph(l[j]) * nsph(l[k]) * nsph(l[ll]);
+    real *tmp = malloc(sizeof(real) * n);
+    work_t w; memset(&w, 0, sizeof(w));
+    rc = tmp ? quartet_deriv_sph(&w, &b, i, j, k, ll, tmp) : -3;
     for (size_t q = 0; q < n && !rc; ++q) out[q] = (double)tmp[q];
     free(tmp); work_free(&w); basis_free(&b);
     return rc;

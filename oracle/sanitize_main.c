@@ -76,6 +76,12 @@ int main(void)
     if (check_finite(blk, 9 * 7 * 5 * 9, "eri_shell_quartet")) return 1;
     CHECK(PFX(eri_shell_quartet)(nshell, l, np, cen, exps, coefs, 0, 1, 2, 7, blk), -1);
 
+    double *dblk = malloc(sizeof(double) * 12 * 9 * 7 * 5 * 9);
+    if (!dblk) return 1;
+    CHECK(PFX(eri_deriv_shell_quartet)(nshell, l, np, cen, exps, coefs, 3, 5, 2, 3, dblk), 0);
+    if (check_finite(dblk, 12 * 9 * 7 * 5 * 9, "eri_deriv_shell_quartet")) return 1;
+    free(dblk);
+
     const double pc[24] = {0, 0, 0, 0.3, 0, 0, 0, 0.4, 0, 0, 0, 0.5, 1, 1, 1, 1.2, 1, 1, 1, 1.3, 1, 1, 1, 1.4};
     const double pe[8] = {0.5, 1.5, 2.5, 3.5, 0.7, 1.1, 4.0, 0.2};
     double pq[2 * 7 * 5 * 3 * 9];
