@@ -116,52 +116,125 @@ def cpu_baseline(bw, target_s, seed=7):
                       f"integrals only (no J/K digestion), {dt:.1f} s"}
 
 
+def kernel_resources():
+    """The compiler's resource report of the loaded library (VGPR, AGPR,
+    private scratch, LDS, occupancy per kernel), written beside it by the build."""
+    import paper_2605_10312_amd as hgp
+    from paper_2605_10312_amd import build as hb
+    path = hb.resources_path(hgp.LIB_PATH)
+    if not os.path.exists(path):
+        return {}
+    return {k.split("#")[0]: {x: v.get(x) for x in ("vgpr", "agpr", "scratch", "lds", "occupancy")}
+            for k, v in json.load(open(path)).items()}
+
+
+GOLDEN_BLOCKS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "fullsize_jk_blocks.json")
+
+
+def block_errors(bw, J, K):
+    """J/K against the oracle on the 64 stored blocks of this workload (every
+    ordered pair of shell angular momenta; written by the oracle alone, in
+    double and long double): max abs and RMS over their entries, relative
+    Frobenius norm, and the FP64 oracle's own error against long double."""
+    gold = json.load(open(GOLDEN_BLOCKS))
+    off = bw.shell_offsets()
+    mj = mk = eo = sq = nj = nk = 0.0
+    cnt = 0
+    for k, (p, r) in enumerate(gold["pairs"]):
+        shp = (off[p + 1] - off[p], off[r + 1] - off[r])
+        sl = (slice(off[p], off[p + 1]), slice(off[r], off[r + 1]))
+        jb, kb = np.reshape(gold["J"][k], shp), np.reshape(gold["K"][k], shp)
+        dj, dk = J[sl] - jb, K[sl] - kb
+        mj, mk = max(mj, float(np.abs(dj).max())), max(mk, float(np.abs(dk).max()))
+        sq += float(np.sum(dj ** 2) + np.sum(dk ** 2))
+        nj += float(np.sum(jb ** 2))
+        nk += float(np.sum(kb ** 2))
+        cnt += 2 * dj.size
+        eo = max(eo, float(np.abs(jb - np.reshape(gold["J_ld"][k], shp)).max()),
+                 float(np.abs(kb - np.reshape(gold["K_ld"][k], shp)).max()))
+    return {"blocks": len(gold["pairs"]), "entries": cnt, "J_max_abs": mj, "K_max_abs": mk,
+            "rms": (sq / max(cnt, 1)) ** 0.5, "rel_frobenius": (sq / max(nj + nk, 1e-300)) ** 0.5,
+            "oracle_fp64_vs_long_double_max_abs": eo, "reference": "CPU oracle, J/K blocks from their definition"}
+
+
 MICRO_N = 100_000
 
 
-def microbench(args):
+def microbench_runs(steps, warmup, check=64, ls_list=((2, 2, 2, 2), (3, 3, 3, 3), (4, 4, 4, 4))):
     """High-l class microbench: 1e5 independent normalised primitive quartets
     per class, (dd|dd), (ff|ff), (gg|gg), centres in a 6 A box, exponents
-    log-uniform [0.1, 100]; inputs and outputs device-resident.  One JSON line
-    per class: primitive-quartet spherical integrals per second and the
-    generator's FLOP count per quartet against the FP64 VALU peak."""
+    log-uniform [0.1, 100]; inputs and outputs device-resident.  Per class:
+    primitive-quartet spherical integrals per second, the generator's FLOP
+    count per quartet against the FP64 VALU peak, and the error against the
+    CPU oracle on `check` sampled quartets (max abs, RMS, max relative over
+    |I| > 1e-10, and the FP64 oracle's own error against long double)."""
     import torch
+    import oracle
     import paper_2605_10312_amd as hgp
     import workloads
     from paper_2605_10312_amd.gen import phase2 as p2mod, vrr as vrrmod
 
-    for l in (2, 3, 4):
-        ls = (l, l, l, l)
+    out = []
+    for ls in ls_list:
+        l = ls[0]
         cen, ex = workloads.prim_quartets(l, MICRO_N)
         ct = torch.tensor(cen, device="cuda")
         et = torch.tensor(ex, device="cuda")
-        n_sph = (2 * l + 1) ** 4
-        out = torch.empty((MICRO_N, n_sph), dtype=torch.float64, device="cuda")
-        for _ in range(args.warmup):
-            hgp.eri_prim_quartets(ls, ct, et, out)
+        n_sph = int(np.prod([2 * x + 1 for x in ls]))
+        res = torch.empty((MICRO_N, n_sph), dtype=torch.float64, device="cuda")
+        for _ in range(warmup):
+            hgp.eri_prim_quartets(ls, ct, et, res)
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(args.steps):
-            hgp.eri_prim_quartets(ls, ct, et, out)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            hgp.eri_prim_quartets(ls, ct, et, res)
+        ev1.record()
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / args.steps
+        dt = ev0.elapsed_time(ev1) * 1e-3 / steps
         g = vrrmod.VRRGraph(*ls)
         tg = {tt: f"h{k}" for k, tt in enumerate(g.targets)}
         p2 = p2mod.Phase2(*ls, hname=lambda e, f: tg[(e, f)])
-        flop = g.flops() + overhead_flops(4 * l) + p2.flops
-        line = {"metric": "primitive-quartet spherical ERIs/s (high-l class microbench)", "value": MICRO_N * n_sph / dt,
-                "unit": "ERIs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-                "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                "dtype": "f64", "data": "synthetic",
-                "config": {"workload": f"microbench_{l}{l}{l}{l}: {MICRO_N} primitive quartets ({'spdfg'[l]}{'spdfg'[l]}|"
-                                       f"{'spdfg'[l]}{'spdfg'[l]}), 6 A box, exponents log-uniform [0.1, 100], FP64",
-                           "flop_per_quartet": flop},
-                "roofline": {"bound": "alu", "achieved": round(MICRO_N * flop / dt / 1e12, 3),
-                             "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                             "frac": round(MICRO_N * flop / dt / 1e12 / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None}}
-        print(json.dumps(line), flush=True)
-        del out, ct, et
+        flop = g.flops() + overhead_flops(sum(ls)) + p2.flops
+        err = None
+        if check:
+            idx = np.random.default_rng(11).choice(MICRO_N, check, replace=False)
+            got = res[torch.tensor(idx, device="cuda")].cpu().numpy()
+            ref = oracle.eri_prim_quartets(ls, cen[idx], ex[idx]).reshape(check, -1)
+            ref_ld = oracle.eri_prim_quartets(ls, cen[idx], ex[idx], precision="long double").reshape(check, -1)
+            d = got - ref
+            big = np.abs(ref) > 1e-10
+            err = {"quartets_checked": int(check), "max_abs": float(np.abs(d).max()),
+                   "rms": float(np.sqrt(np.mean(d ** 2))),
+                   "max_rel": float((np.abs(d[big]) / np.abs(ref[big])).max()) if big.any() else 0.0,
+                   "oracle_fp64_vs_long_double_max_abs": float(np.abs(ref - ref_ld).max()),
+                   "max_abs_vs_long_double": float(np.abs(got - ref_ld).max())}
+        tag = "".join(str(x) for x in ls)
+        nm = "".join("spdfg"[x] for x in ls)
+        out.append({"class": f"({nm[:2]}|{nm[2:]})", "tag": tag, "quartets": MICRO_N, "ms_per_step": round(dt * 1e3, 4),
+                    "eris_per_s": MICRO_N * n_sph / dt, "flop_per_quartet": flop,
+                    "tflops": round(MICRO_N * flop / dt / 1e12, 3),
+                    "frac": round(MICRO_N * flop / dt / 1e12 / FP64_VALU_PEAK_TFLOPS, 4), "err": err})
+        del res, ct, et
         torch.cuda.empty_cache()
+    return out
+
+
+def microbench(args):
+    """One JSON line per high-l class (see microbench_runs)."""
+    for r in microbench_runs(args.steps, args.warmup):
+        l = int(r["tag"][0])
+        line = {"metric": "primitive-quartet spherical ERIs/s (high-l class microbench)", "value": r["eris_per_s"],
+                "unit": "ERIs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f64", "data": "synthetic",
+                "config": {"workload": f"microbench_{r['tag']}: {MICRO_N} primitive quartets {r['class']}, 6 A box, "
+                                       "exponents log-uniform [0.1, 100], FP64",
+                           "flop_per_quartet": r["flop_per_quartet"]},
+                "roofline": {"bound": "alu", "achieved": r["tflops"], "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": r["frac"], "traffic": None},
+                "err": r["err"]}
+        print(json.dumps(line), flush=True)
 
 
 def batch(args):
@@ -334,6 +407,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-high-l", action="store_true", help="skip the high-l class microbench in the default run")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: quartets with Q_ab Q_cd < theta use FP32 VRR/HRR (register tier)")
     ap.add_argument("--theta", type=float, default=None, help="mixed-precision threshold (default: the library's)")
@@ -424,7 +498,6 @@ def main():
             plan.jk(Dt, J, K)
         torch.cuda.synchronize()
     timing = plan.class_timing()
-    plan.set_timing(False)
 
     # one entry per kernel: register tier jk_<class>; staged tier p1_<class> (Phase 1)
     # and jk_<class> (Phase 2 + digestion); average duration per launch from HIP events
@@ -447,6 +520,9 @@ def main():
                                "gflop_per_launch": round(fl / launches_per_step / 1e9, 3),
                                "tflops": round(fl / launches_per_step / (avg * 1e-3) / 1e12, 3) if avg > 0 else None})
     per_kernel.sort(key=lambda x: -x["ms_per_step"])
+    res = kernel_resources()
+    for x in per_kernel:
+        x.update(res.get(x["kernel"], {}))
     dom = per_kernel[0]
     achieved = dom["tflops"]
     roofline = {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
@@ -469,19 +545,16 @@ def main():
                                                 max(1, sum(c["quartets"] for c in classes)), 4), "theta": theta}
         p64.close()
 
-    err = None
-    if not args.no_check:
-        import oracle
-        off = bw.shell_offsets()
-        ss = np.where(bw.l == 0)[0]
-        pr = (int(ss[7]), int(ss[30]))
-        Js, Ks = oracle.jk_blocks(bw, D, [pr], tau=TAU)
-        Jg, Kg = J.cpu().numpy(), K.cpu().numpy()
-        sl = (slice(off[pr[0]], off[pr[0] + 1]), slice(off[pr[1]], off[pr[1] + 1]))
-        err = {"jk_block_max_abs": float(max(np.abs(Jg[sl] - Js[0]).max(), np.abs(Kg[sl] - Ks[0]).max())),
-               "block": list(pr)}
+    # J/K of the configuration that was timed (concurrent class lists unless
+    # --serial): the per-kernel timing pass above ran every class on one stream
+    plan.set_timing(False)
+    plan.jk(Dt, J, K)
+    torch.cuda.synchronize()
+    err = None if args.no_check else block_errors(bw, J.cpu().numpy(), K.cpu().numpy())
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(bw, args.cpu_seconds)
+    # the high-l classes, which this workload (l <= 2) does not reach
+    high_l = None if args.no_high_l else microbench_runs(2, 1, check=0 if args.no_check else 32)
 
     line = {
         "metric": METRIC,
@@ -514,6 +587,7 @@ def main():
         "err": err,
         "err_vs_fp64": err_fp64,
         "kernels": per_kernel,
+        "high_l_microbench": high_l,
     }
     print(json.dumps(line), flush=True)
 

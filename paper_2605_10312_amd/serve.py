@@ -200,7 +200,10 @@ class IterationServer:
 
     executor must provide now(), build(requests, budget) -> plan (raising
     OverBudget), submit(plan, requests, ks) -> token, done(token),
-    finish(token, requests, ks), release(plan) and idle(until)."""
+    finish(token, requests, ks), release(plan) and idle(until); drop(request),
+    if it has one, is called when a request leaves the active set unfinished
+    (sent back to the queue or rejected) so that it can free the request's
+    device data."""
 
     def __init__(self, executor, hbm_budget: int, max_active: int = 16):
         if hbm_budget <= 0 or max_active < 1:
@@ -213,6 +216,7 @@ class IterationServer:
 
     def run(self, requests):
         ex = self.ex
+        drop = getattr(ex, "drop", lambda r: None)
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         waiting = collections.deque()
         active = []                               # [request, k]
@@ -249,11 +253,13 @@ class IterationServer:
                             r = active.pop()[0]
                             recs[r.rid].rejected = "plan exceeds the HBM budget"
                             recs[r.rid].admitted = float("nan")
+                            drop(r)
                             if not active:
                                 break
                             continue
                         r = active.pop()[0]           # the latest admitted waits again, at the head
                         recs[r.rid].admitted = float("nan")
+                        drop(r)                       # its device data is made again when it is next planned
                         waiting.appendleft(r)
                 if plan is None:
                     continue
@@ -442,13 +448,17 @@ class GpuMultiExecutor:
             self.dev[r.rid] = (Basis.from_workload(r.basis), D, torch.empty_like(D[0]), torch.empty_like(D[0]))
         return self.dev[r.rid]
 
+    @staticmethod
+    def _bytes(r):
+        """Device bytes of a request's densities and its J, K buffers."""
+        n = int(np.asarray(r.densities[0]).shape[0])
+        return 8 * n * n * (len(r.densities) + 2)
+
     def build(self, reqs, budget):
+        """One multi-system plan over `reqs` within `budget`, charging the
+        densities and J/K buffers of exactly these requests."""
         from . import HGPError, STATUS_OOM, Plan
-        held = sum(8 * x[1][0].numel() * (len(x[1]) + 2) for x in self.dev.values())
-        for r in reqs:
-            if r.rid not in self.dev:
-                n = int(np.asarray(r.densities[0]).shape[0])
-                held += 8 * n * n * (len(r.densities) + 2)
+        held = sum(self._bytes(r) for r in reqs)
         if held >= budget:
             raise OverBudget()
         devs = [self._device(r) for r in reqs]
@@ -486,6 +496,12 @@ class GpuMultiExecutor:
     def release(self, p):
         self.plan_eris.pop(id(p), None)
         p.close()
+
+    def drop(self, r):
+        """Free the device data of a request that left the active set unfinished."""
+        d = self.dev.pop(r.rid, None)
+        if d is not None:
+            d[0].close()
 
     def idle(self, until):
         time.sleep(50e-6)

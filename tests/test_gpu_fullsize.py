@@ -2,11 +2,13 @@
 times: 30-atom 3s2p1d molecule (N = 420, 180 shells, 16 290 shell pairs),
 Schwarz tau = 1e-12, J and K built together.
 
-The oracle cannot digest all ~1.3e8 quartets in seconds, so it computes
-sampled J/K blocks directly from their definitions (every ordered shell pair
-(R,S) of the sum, same screening rule) and the screened quartet count by
-brute force over its own Schwarz factors; the rest is checked through
-properties that hold at any size (symmetry, positivity of tr(DJ), tr(DK))."""
+The oracle cannot digest all ~1.3e8 quartets in seconds.  A committed script
+(tests/golden/make_fullsize_blocks.py, oracle only) stored 64 J/K blocks
+computed directly from their definitions (every ordered shell pair (R,S) of
+the sum, same screening rule), in double and long double; the screened
+quartet count is checked by brute force over the plan's Schwarz factors; the
+rest through properties that hold at any size (symmetry, positivity of
+tr(DJ), tr(DK))."""
 import numpy as np
 import pytest
 
@@ -95,17 +97,44 @@ def test_jk_properties(built):
     assert np.trace(D @ J) > 0 and np.trace(D @ K) > 0
 
 
-def test_sampled_blocks_vs_oracle(built):
-    bw, D, J, K = built["bw"], built["D"], built["J"], built["K"]
+def load_golden_blocks():
+    """The oracle's J/K blocks of this workload, written by
+    tests/golden/make_fullsize_blocks.py (which calls only the oracle)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize_jk_blocks.json")
+    return json.load(open(path))
+
+
+def compare_blocks(bw, J, K, gold):
+    """Per block: max |GPU - oracle|, and the FP64 oracle's own error against
+    its long-double build; returns the rows and the RMS over every entry."""
     off = bw.shell_offsets()
-    ds = np.where(bw.l == 2)[0]
-    ps = np.where(bw.l == 1)[0]
-    ss = np.where(bw.l == 0)[0]
-    pairs = [(int(ds[3]), int(ds[17])), (int(ps[5]), int(ss[40])), (int(ss[7]), int(ss[7]))]
-    Js, Ks = oracle.jk_blocks(bw, D, pairs, tau=TAU)
-    for (p, r), jb, kb in zip(pairs, Js, Ks):
-        gj = J[off[p]:off[p + 1], off[r]:off[r + 1]]
-        gk = K[off[p]:off[p + 1], off[r]:off[r + 1]]
-        ej, ek = np.abs(gj - jb).max(), np.abs(gk - kb).max()
-        print(f"block ({p},{r}) l=({bw.l[p]},{bw.l[r]}): |dJ| {ej:.2e} |dK| {ek:.2e} (|J| {np.abs(jb).max():.2e})")
-        assert ej <= JK_TOL and ek <= JK_TOL
+    rows, sq, cnt = [], 0.0, 0
+    for k, (p, r) in enumerate(gold["pairs"]):
+        sl = (slice(off[p], off[p + 1]), slice(off[r], off[r + 1]))
+        shp = (off[p + 1] - off[p], off[r + 1] - off[r])
+        jb, kb = np.reshape(gold["J"][k], shp), np.reshape(gold["K"][k], shp)
+        jl, kl = np.reshape(gold["J_ld"][k], shp), np.reshape(gold["K_ld"][k], shp)
+        dj, dk = J[sl] - jb, K[sl] - kb
+        sq += float(np.sum(dj ** 2) + np.sum(dk ** 2))
+        cnt += 2 * dj.size
+        rows.append(((p, r), (int(bw.l[p]), int(bw.l[r])), float(np.abs(dj).max()), float(np.abs(dk).max()),
+                     float(max(np.abs(jb - jl).max(), np.abs(kb - kl).max()))))
+    return rows, (sq / max(cnt, 1)) ** 0.5
+
+
+def test_sampled_blocks_vs_oracle(built):
+    """64 blocks of J and K covering every ordered pair of shell angular
+    momenta, diagonal, same-atom and distant blocks, element by element."""
+    bw, J, K = built["bw"], built["J"], built["K"]
+    gold = load_golden_blocks()
+    assert len(gold["pairs"]) >= 64 and gold["tau"] == TAU
+    assert {tuple(x) for x in gold["l"]} == {(a, b) for a in range(3) for b in range(3)}
+    rows, rms = compare_blocks(bw, J, K, gold)
+    worst = max(rows, key=lambda r: max(r[2], r[3]))
+    print(f"{len(rows)} blocks: max |dJ| {max(r[2] for r in rows):.2e}, max |dK| {max(r[3] for r in rows):.2e}, "
+          f"RMS {rms:.2e}; worst block {worst[0]} l={worst[1]}; FP64 oracle vs long double "
+          f"{max(r[4] for r in rows):.2e}")
+    for pr, ls, ej, ek, eo in rows:
+        assert ej <= JK_TOL and ek <= JK_TOL, (pr, ls, ej, ek)

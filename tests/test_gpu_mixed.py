@@ -92,10 +92,9 @@ def test_mixed_full_size(hgp, torch_cuda):
     print(f"default theta {hgp.MIXED_THETA_DEFAULT}: FP32 share {frac:.3f}, max |J_mixed - J_fp64| {dj:.2e}, "
           f"max |K_mixed - K_fp64| {dk:.2e}")
     assert dj <= JK_TOL and dk <= JK_TOL
-    off = bw.shell_offsets()
-    ds, ps, ss = (np.where(bw.l == l)[0] for l in (2, 1, 0))
-    pairs = [(int(ds[3]), int(ds[17])), (int(ps[5]), int(ss[40])), (int(ss[7]), int(ss[7]))]
-    Js, Ks = oracle.jk_blocks(bw, D, pairs, tau=1e-12)
-    for (p, r), jb, kb in zip(pairs, Js, Ks):
-        sl = (slice(off[p], off[p + 1]), slice(off[r], off[r + 1]))
-        assert np.abs(Jm[sl] - jb).max() <= JK_TOL and np.abs(Km[sl] - kb).max() <= JK_TOL
+    from tests.test_gpu_fullsize import compare_blocks, load_golden_blocks
+    rows, rms = compare_blocks(bw, Jm, Km, load_golden_blocks())
+    print(f"mixed vs oracle over {len(rows)} blocks: max |dJ| {max(r[2] for r in rows):.2e}, "
+          f"max |dK| {max(r[3] for r in rows):.2e}, RMS {rms:.2e}")
+    for pr, ls, ej, ek, eo in rows:
+        assert ej <= JK_TOL and ek <= JK_TOL, (pr, ls, ej, ek)

@@ -126,3 +126,39 @@ def test_iteration_served_equals_alone(hgp, torch_cuda):
             worst = max(worst, np.abs(J - res[k][0]).max(), np.abs(K - res[k][1]).max())
     print(f"iteration server: peak active {srv.peak_active}, rebuilds {srv.rebuilds}, max |served - alone| {worst:.2e}")
     assert worst <= same_tol([x for a in alone for x in a[0]]) and srv.peak_active == 4
+
+
+def test_iteration_budget_pushes_back_and_rejects(hgp, torch_cuda):
+    """Iteration-level batching under a budget that holds each small request
+    alone but not all of them together, and not the one large request even
+    alone: the large request is rejected (its device data freed), requests
+    that do not fit beside the others are sent back to the queue and run
+    later, and every served result equals its own plan alone."""
+    from paper_2605_10312_amd import serve
+    systems = workloads.batch_systems(seed=1007, n=5, natom=(1, 2), lmax=3, nprim=(1, 2))
+    systems += workloads.batch_systems(seed=1008, n=1, natom=(6, 6), lmax=3, nprim=(2, 2))
+    reqs = [serve.Request(i, 0.0, bw, [D, workloads.psd_density(bw.nbf, 77 + i)], tau=1e-12, theta=0.0)
+            for i, (bw, D) in enumerate(systems)]
+    alone = [_alone(hgp, torch_cuda, r, 0.0) for r in reqs]
+    s = sorted(a[1] for a in alone)
+    big = max(range(len(reqs)), key=lambda i: alone[i][1])
+    assert s[-1] > s[-2]
+    budget = s[-2] + (min(s[-1], s[-2] + s[-3]) - s[-2]) // 2
+    ex = serve.GpuMultiExecutor(keep=True)
+    srv = serve.IterationServer(ex, hbm_budget=budget, max_active=6)
+    recs, ups = srv.run(reqs)
+    assert ex.dev == {}                               # finished, pushed-back and rejected data all freed
+    ex.close()
+    assert recs[big].rejected is not None
+    assert all(r.rejected is None for i, r in enumerate(recs) if i != big)
+    assert srv.peak_active < 5                        # not every request fitted at once
+    worst = 0.0
+    for i, (r, (res, _)) in enumerate(zip(reqs, alone)):
+        if i == big:
+            continue
+        for k in range(2):
+            J, K = ex.results[(r.rid, k)]
+            worst = max(worst, np.abs(J - res[k][0]).max(), np.abs(K - res[k][1]).max())
+    print(f"budget {budget / 2**20:.1f} MiB: rejected request {big} ({alone[big][1] / 2**20:.1f} MiB), "
+          f"peak active {srv.peak_active}, rebuilds {srv.rebuilds}, max |served - alone| {worst:.2e}")
+    assert worst <= same_tol([x for i, a in enumerate(alone) if i != big for x in a[0]])

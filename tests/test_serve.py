@@ -222,6 +222,9 @@ class IterSimExecutor:
     def release(self, plan):
         self.log.append(("release", plan, self.t))
 
+    def drop(self, r):
+        self.log.append(("drop", r.rid, self.t))
+
     def idle(self, until):
         if self.end is not None and self.end > self.t:
             self.t = self.end if until is None else min(self.end, until)
@@ -260,3 +263,8 @@ def test_iteration_server_budget_pushes_back_and_rejects():
         if e[0] == "build":
             assert sum(bytes_[i] for i in e[1]) <= 100
     assert len(ups) == 8
+    # the executor is told about every request that leaves the active set unfinished:
+    # the rejected one, and each one pushed back to the queue
+    drops = [e[1] for e in ex.log if e[0] == "drop"]
+    assert 3 in drops
+    assert len(drops) >= 2
