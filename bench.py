@@ -222,7 +222,7 @@ def microbench_runs(steps, warmup, check=64, ls_list=((2, 2, 2, 2), (3, 3, 3, 3)
 
 def microbench(args):
     """One JSON line per high-l class (see microbench_runs)."""
-    for r in microbench_runs(args.steps, args.warmup):
+    for r in microbench_runs(args.steps, args.warmup, check=0 if args.no_check else 64):
         l = int(r["tag"][0])
         line = {"metric": "primitive-quartet spherical ERIs/s (high-l class microbench)", "value": r["eris_per_s"],
                 "unit": "ERIs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

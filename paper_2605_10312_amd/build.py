@@ -34,69 +34,99 @@ REMARKS = ["-Rpass-analysis=kernel-resource-usage"]
 
 REGISTER_OPTS = ("waves", "digest", "reduce", "loop", "block")
 STAGED_OPTS = ("cap", "waves", "reduce", "loop")
+ROW_OPTS = ("budget", "waves", "reduce", "loop")
 
 
-_EMITTED: dict = {}     # (class, options) -> (source, meta), so a rerouting pass regenerates only what changed
+_EMITTED: dict = {}     # (class, routing inputs) -> (source, meta): a rerouting pass regenerates only what changed
 
 
-def _emit(ls, r):
-    from .gen import emit, emit_staged, emit_t3
-    key = (tuple(ls), json.dumps(r, sort_keys=True, default=str))
-    if key not in _EMITTED:
-        if r["tier"] in (2, 3):
-            _EMITTED[key] = emit_t3.emit_class_t3(*ls)
-        elif r["tier"] == 1:
-            _EMITTED[key] = emit_staged.emit_class_staged(*ls, **{k: r[k] for k in STAGED_OPTS if k in r})
-        else:
-            _EMITTED[key] = emit.emit_class(*ls, **{k: r[k] for k in REGISTER_OPTS if k in r})
-    return _EMITTED[key]
+def _route_and_emit(ls, table, defaults, override, reroute):
+    """Route one class (router model or tuning table, then defaults,
+    overrides and the build's rerouting) and emit its source."""
+    from .gen import emit, emit_row, emit_staged, emit_t3, router
+    r = router.route(ls, table)
+    for k, v in (defaults or {}).items():
+        if r["source"] == "model" or k not in r:    # a tuning-table entry wins over defaults
+            r[k] = v
+    if override:
+        r.update(override)
+    if reroute:
+        if reroute.get("tier") == 1 and r.get("tier") != 1 and "form" not in reroute:
+            r["form"] = router.model_form(ls)
+            if r["form"] == "row":
+                r["budget"] = router.ROW_BUDGET
+            elif "cap" not in reroute:
+                r["cap"] = router.model_cap(ls)
+        r.update(reroute)
+    if r["tier"] in (2, 3):
+        src, meta = emit_t3.emit_class_t3(*ls)
+    elif r["tier"] == 1 and r.get("form") == "row":
+        src, meta = emit_row.emit_class_row(*ls, **{k: r[k] for k in ROW_OPTS if k in r})
+    elif r["tier"] == 1:
+        src, meta = emit_staged.emit_class_staged(*ls, **{k: r[k] for k in STAGED_OPTS if k in r})
+    else:
+        src, meta = emit.emit_class(*ls, **{k: r[k] for k in REGISTER_OPTS if k in r})
+    meta.route = {k: v for k, v in r.items() if k not in ("variant", "ms")}
+    meta.route["rerouted"] = bool(reroute)
+    return src, meta
 
 
 def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overrides=None, gen_dir: str = GEN,
-             defaults=None, reroute=None):
+             defaults=None, reroute=None, jobs: int | None = None):
     """Write one .hip per canonical class plus the class table into gen_dir.
-    Each class is routed to the register or staged tier (gen/router.py).
-    defaults (generator options for every class) are applied first, then
-    the router's choice (tuning table, else the register model), then
-    overrides, a map from class tag to options that wins over both.
-    Register-tier options: waves, digest, reduce, loop, block; staged: cap,
-    waves, reduce, loop.  reroute (class tag -> options) is applied last:
-    the build's answer to a compiler resource report that showed spills."""
+    Each class is routed to a tier (gen/router.py): defaults (generator
+    options for every class) are applied first, then the router's choice
+    (tuning table, else the register model), then overrides, a map from
+    class tag to options that wins over both.  Register-tier options: waves,
+    digest, reduce, loop, block; staged: cap, waves, reduce, loop; row form:
+    budget, waves, reduce, loop.  reroute (class tag -> options) is applied
+    last: the build's answer to a compiler resource report that showed
+    spills.  Classes are generated in parallel processes."""
     from .gen import emit, router
     from .gen.cart import canonical_classes
 
     GEN = gen_dir
     os.makedirs(GEN, exist_ok=True)
+    tbl = router.load_table() if table is None else table
+    jobs = jobs or min(8, os.cpu_count() or 4)
+    classes = list(canonical_classes(lmax))
+    args = {}
+    for ls in classes:
+        tag = "".join(str(x) for x in ls)
+        a = (tuple(ls), {tag: tbl[tag]} if tag in tbl else {}, defaults, (overrides or {}).get(tag),
+             (reroute or {}).get(tag))
+        args[tag] = (json.dumps(a, sort_keys=True, default=str), a)
+    todo = [t for t, (key, _) in args.items() if key not in _EMITTED]
+    if todo:
+        import multiprocessing as mp
+        # the slowest classes first so that the pool ends together
+        todo.sort(key=lambda t: -sum(int(c) for c in t))
+        with cf.ProcessPoolExecutor(max_workers=jobs, mp_context=mp.get_context("fork")) as ex:
+            futs = {ex.submit(_route_and_emit, *args[t][1]): t for t in todo}
+            for f in cf.as_completed(futs):
+                _EMITTED[args[futs[f]][0]] = f.result()
     metas = []
     files = []
-    for ls in canonical_classes(lmax):
+    for ls in classes:
         tag = "".join(str(x) for x in ls)
-        r = router.route(ls, table)
-        for k, v in (defaults or {}).items():
-            if r["source"] == "model" or k not in r:    # a tuning-table entry wins over defaults
-                r[k] = v
-        if overrides and tag in overrides:
-            r.update(overrides[tag])
-        if reroute and tag in reroute:
-            rr = reroute[tag]
-            if rr.get("tier") == 1 and "cap" not in rr and r.get("tier") != 1:
-                r["cap"] = router.model_cap(ls)
-            r.update(rr)
-        src, meta = _emit(ls, r)
-        meta.route = {k: v for k, v in r.items() if k not in ("variant", "ms")}
-        meta.route["rerouted"] = bool(reroute and tag in reroute)
+        src, meta = _EMITTED[args[tag][0]]
         path = os.path.join(GEN, f"class_{meta.tag}.hip")
         _write_if_changed(path, src)
         files.append(path)
+        for sfx, extra in sorted(getattr(meta, "extra_sources", {}).items()):
+            epath = os.path.join(GEN, f"class_{meta.tag}_{sfx}.hip")
+            _write_if_changed(epath, extra)
+            files.append(epath)
         metas.append(meta)
         if verbose:
             print(f"  class {meta.tag}: {meta.vrr_nodes} VRR nodes, PeakLive {meta.peak_live} ({meta.scheduler}), "
                   f"N_hrr {meta.n_hrr}", flush=True)
-    table = os.path.join(GEN, "class_table.hip")
-    _write_if_changed(table, emit.emit_table(metas))
-    files.append(table)
+    table_path = os.path.join(GEN, "class_table.hip")
+    _write_if_changed(table_path, emit.emit_table(metas))
+    files.append(table_path)
     _write_if_changed(os.path.join(GEN, "classes.json"),
-                      json.dumps([m.__dict__ for m in metas], indent=1, default=list))
+                      json.dumps([{k: v for k, v in m.__dict__.items() if k != "extra_sources"} for m in metas],
+                                 indent=1, default=list))
     for f in os.listdir(GEN):          # drop classes of an earlier, larger lmax
         p = os.path.join(GEN, f)
         if f.endswith(".hip") and p not in files:
@@ -223,16 +253,20 @@ def resources_path(lib: str) -> str:
 def class_scratch(res: dict, tag: str) -> int:
     """Largest private scratch (bytes per lane) of the kernels of class `tag`
     (a spill into accumulation registers uses none and is not counted)."""
-    return max((r.get("scratch", 0) for k, r in res.items() if k.split("#")[0].endswith("_" + tag)), default=0)
+    import re
+    return max((r.get("scratch", 0) for k, r in res.items()
+                if re.search(r"_" + tag + r"(?:p\d+)?$", k.split("#")[0])), default=0)
 
 
 def _spilled_classes(res: dict) -> dict:
     """class tag -> names of its kernels that use private scratch."""
+    import re
     out: dict = {}
     for k in check_resources(res):
         name = k.split("#")[0]
-        if "_" in name and name.rsplit("_", 1)[1].isdigit():
-            out.setdefault(name.rsplit("_", 1)[1], []).append(name)
+        m = re.search(r"_(\d{4})(?:p\d+)?$", name)        # class kernels, Phase-1 parts included
+        if m:
+            out.setdefault(m.group(1), []).append(name)
     return out
 
 

@@ -273,14 +273,77 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
     for (mu, nu, a0, a1) in p2.ket_stages:
         ket_stage(mu, nu, a0, a1, store_sink)
 
-    def I(mu, nu, lam, sig):
-        return f"sb[{islot(mu, nu, lam, sig)}u * S32 + li]"
+    out.extend(slot_digestion(na, nb, nc, nd, lambda mu, nu, lam, sig: f"sb[{islot(mu, nu, lam, sig)}u * S32 + li]",
+                              reduce))
+    w("}")
+    w("")
+    # ---------------------------------------------------------------- Phase 2 + integrals-out kernel
+    diag_class = (la, lb) == (lc, ld)
+    w(f"__global__ __launch_bounds__({block}) void eri_{tag}(EriArgs a)")
+    w("{")
+    w(f"    const int64_t i = (int64_t)blockIdx.x * {block} + threadIdx.x;")
+    w("    if (i >= a.ntask) return;")
+    w("    double *const sb = a.scratch;")
+    w("    const uint32_t S32 = (uint32_t)a.stride;")
+    w("    uint32_t li = (uint32_t)i;")
+    w("    const EriTask t = a.tasks[i];")
+    w("    const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];")
+    w(f"    bra_stage_{tag}(gb, sb, li, S32);")
+    w("    const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
+    w("    (void)CDx; (void)CDy; (void)CDz;")
+    w("    double *__restrict__ o = a.out + t.off;")
+    if diag_class:
+        w("    double dmax = 0.0;")
+
+    def eri_sink(mu, nu, lam, sig, name, ind):
+        if diag_class and (mu, nu) == (lam, sig):
+            w(f"{ind}dmax = fmax(dmax, fabs({name}));")
+        w(f"{ind}if (a.mode == 0) o[{mu} * t.s0 + {nu} * t.s1 + {lam} * t.s2 + {sig} * t.s3] = {name};")
+
+    for (mu, nu, a0, a1) in p2.ket_stages:
+        ket_stage(mu, nu, a0, a1, eri_sink)
+    if diag_class:
+        w("    if (a.mode == 1) a.out[i] = sqrt(dmax);")
+    w("}")
+    w("")
+    w("}  // namespace")
+    w("")
+    w(f"void launch_p1_{tag}(const P1Args &a, hipStream_t s)")
+    w("{")
+    w(f"    const int64_t blocks = (a.n + {block - 1}) / {block};")
+    w(f"    if (blocks > 0) hipLaunchKernelGGL(p1_{tag}, dim3((unsigned)(blocks * {nch})), dim3({block}), 0, s, a);")
+    w("}")
+    for kind, cnt in (("jk", "nq"), ("eri", "ntask")):
+        args = "JKArgs" if kind == "jk" else "EriArgs"
+        w(f"void launch_{kind}_{tag}(const {args} &a, hipStream_t s)")
+        w("{")
+        w(f"    const int64_t blocks = (a.{cnt} + {block - 1}) / {block};")
+        w(f"    if (blocks > 0) hipLaunchKernelGGL({kind}_{tag}, dim3((unsigned)blocks), dim3({block}), 0, s, a);")
+        w("}")
+    w("")
+    w("}  // namespace hgp")
+    meta = ClassMeta(ls, tag, 1, block, len(g.nodes), full, n_h, pl, sched, p2.flops, nout, rule,
+                     scratch_slots=nslots, chunks=len(chunks), recompute=recompute, cap=cap, waves=waves,
+                     digest="", reduce=reduce, loop=loop)
+    return "\n".join(out) + "\n", meta
+
+
+def slot_digestion(na, nb, nc, nd, I, reduce="segmented"):
+    """J/K digestion of one quartet whose spherical integrals sit in the slot
+    buffer (I(mu, nu, lam, sig) -> C expression of the stored value), with
+    the 8-fold symmetric Scatter: six contractions, each streaming the
+    integrals back, one output element at a time (a dot product with D
+    entries, then one atomic):
+      J'[ab] += 2s sum_ls I D[cd],  J'[cd] += 2s sum_mn I D[ab],
+      K'[ac] += s sum_ns I D[bd],   K'[bc] += s sum_ms I D[ad],
+      K'[ad] += s sum_nl I D[bc],   K'[bd] += s sum_ml I D[ac].
+    In scope: s-scaled sj, sk, pq, pk, fa..fd, N, D, li.  reduce='segmented':
+    J'[ab], K'[ac] and K'[bc] terms are first summed along the wave's runs of
+    lanes with the same target and the run's last lane adds them."""
+    out = []
+    w = out.append
 
     def contraction(outer, inner, target, scale, seg=None):
-        """One output element at a time: a dot product of integrals streamed
-        from the buffer with D entries, then one atomic.  seg = (first lane,
-        last-lane flag, name): the values are first summed along the wave's
-        runs of lanes with the same target and the run's last lane adds them."""
         vals = []
         for k, o in enumerate(outer):
             terms = inner(*o)
@@ -338,54 +401,4 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
                                  for mu in range(na) for lam in range(nc)],
                 lambda nu, sig: f"a.K + (int64_t)(fb + {nu}) * N + fd + {sig}", "sk")
     w("    }")
-    w("}")
-    w("")
-    # ---------------------------------------------------------------- Phase 2 + integrals-out kernel
-    diag_class = (la, lb) == (lc, ld)
-    w(f"__global__ __launch_bounds__({block}) void eri_{tag}(EriArgs a)")
-    w("{")
-    w(f"    const int64_t i = (int64_t)blockIdx.x * {block} + threadIdx.x;")
-    w("    if (i >= a.ntask) return;")
-    w("    double *const sb = a.scratch;")
-    w("    const uint32_t S32 = (uint32_t)a.stride;")
-    w("    uint32_t li = (uint32_t)i;")
-    w("    const EriTask t = a.tasks[i];")
-    w("    const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];")
-    w(f"    bra_stage_{tag}(gb, sb, li, S32);")
-    w("    const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
-    w("    (void)CDx; (void)CDy; (void)CDz;")
-    w("    double *__restrict__ o = a.out + t.off;")
-    if diag_class:
-        w("    double dmax = 0.0;")
-
-    def eri_sink(mu, nu, lam, sig, name, ind):
-        if diag_class and (mu, nu) == (lam, sig):
-            w(f"{ind}dmax = fmax(dmax, fabs({name}));")
-        w(f"{ind}if (a.mode == 0) o[{mu} * t.s0 + {nu} * t.s1 + {lam} * t.s2 + {sig} * t.s3] = {name};")
-
-    for (mu, nu, a0, a1) in p2.ket_stages:
-        ket_stage(mu, nu, a0, a1, eri_sink)
-    if diag_class:
-        w("    if (a.mode == 1) a.out[i] = sqrt(dmax);")
-    w("}")
-    w("")
-    w("}  // namespace")
-    w("")
-    w(f"void launch_p1_{tag}(const P1Args &a, hipStream_t s)")
-    w("{")
-    w(f"    const int64_t blocks = (a.n + {block - 1}) / {block};")
-    w(f"    if (blocks > 0) hipLaunchKernelGGL(p1_{tag}, dim3((unsigned)(blocks * {nch})), dim3({block}), 0, s, a);")
-    w("}")
-    for kind, cnt in (("jk", "nq"), ("eri", "ntask")):
-        args = "JKArgs" if kind == "jk" else "EriArgs"
-        w(f"void launch_{kind}_{tag}(const {args} &a, hipStream_t s)")
-        w("{")
-        w(f"    const int64_t blocks = (a.{cnt} + {block - 1}) / {block};")
-        w(f"    if (blocks > 0) hipLaunchKernelGGL({kind}_{tag}, dim3((unsigned)blocks), dim3({block}), 0, s, a);")
-        w("}")
-    w("")
-    w("}  // namespace hgp")
-    meta = ClassMeta(ls, tag, 1, block, len(g.nodes), full, n_h, pl, sched, p2.flops, nout, rule,
-                     scratch_slots=nslots, chunks=len(chunks), recompute=recompute, cap=cap, waves=waves,
-                     digest="", reduce=reduce, loop=loop)
-    return "\n".join(out) + "\n", meta
+    return out

@@ -9,19 +9,20 @@ model here is
     demand = N_hrr + PeakLive + 40      (40: pair/Boys/VRR coefficients)
 
     register tier (one kernel, everything in VGPR/AGPR)   if demand <= 240
-    staged tier (Phase-1 chunks + HBM-staged Phase 2)     if the VRR graph has
-                                                          <= 3000 nodes and
+    staged tier, e-chunked form (Phase-1 chunks of        if the VRR graph has
+      accumulators + HBM-staged Phase 2)                  <= 3000 nodes and
                                                           N_hrr <= 1024
-    HBM-scratch tier (slot-packed op tables)              otherwise
+    staged tier, row form (whole bra rows per chunk with  otherwise, while a
+      the ket stage fused, gen/emit_row.py)               ket row has <= 80
+                                                          components
+    op tables (slot-packed, LDS or HBM scratch)           otherwise
 
-The 240-double line was set from the compiler's resource reports: every
-class at or under it compiles without scratch, every class above it spilled.
-The staged tier recomputes, per chunk of accumulators, the part of the VRR
-graph the chunk needs and emits it as straight-line code; past (dd|dd)'s
-size (2330 nodes, 961 accumulators) the recomputation and the code grow
-faster than they pay, so larger classes go to the HBM-scratch tier, whose
-code does not grow with the class.  A tuning table measured on the GPU
-(tuning/gfx950.json) overrides the model per class.
+The 240-double line was set from the compiler's resource reports, which have
+the last word: the build compiles every class, reads the report, and moves a
+class whose kernels use private scratch down a ladder (register -> staged;
+staged chunk cap or row budget down a step; last, the op tables), see
+fallback().  A tuning table measured on the GPU (tuning/gfx950.json)
+overrides the model per class.
 """
 from __future__ import annotations
 
@@ -45,11 +46,38 @@ def model_demand(ls):
     return g.n_hrr() + pl + 40
 
 
+# The row form keeps whole rows of ket components f (lc <= |f| <= lc + ld) in
+# registers where it can.  Past this many per row (a (gf| or (gg| ket: 100,
+# 145) almost every row is cut into small tiles, each recomputing most of the
+# recurrence (x11.8 for (gg|gg)), and the class takes the op tables instead.
+ROW_MAX_KET = 80
+# A (gg| bra (145 components) needs the second kernel's bra stage split into
+# groups that each redo part of the HRR; the generated code then takes tens
+# of minutes to compile, so those classes stay on the op tables as well.
+ROW_MAX_BRA = 100
+# Row-form chunks: accumulators + the chunk's PeakLive + 40 within this many
+# doubles.  The register-tier line (240) left some (ff|ff) chunks spilling: the
+# compiler's schedule keeps more values live than the graph order needs.
+ROW_BUDGET = 220
+
+
 def model_tier(ls):
+    """0 register, 1 staged (e-chunked, or the row form for classes past the
+    e-chunked form's size), 2 op tables."""
     g = vrrmod.VRRGraph(*ls)
     if len(g.nodes) > STAGED_MAX_NODES or g.n_hrr() > STAGED_MAX_HRR:
-        return 0 if g.n_hrr() + 40 <= REGISTER_DOUBLES and model_demand(ls) <= REGISTER_DOUBLES else 2
+        if g.n_hrr() + 40 <= REGISTER_DOUBLES and model_demand(ls) <= REGISTER_DOUBLES:
+            return 0
+        n_bra = sum((l + 1) * (l + 2) // 2 for l in range(ls[0], ls[0] + ls[1] + 1))
+        n_ket = sum((l + 1) * (l + 2) // 2 for l in range(ls[2], ls[2] + ls[3] + 1))
+        return 1 if n_ket <= ROW_MAX_KET and n_bra <= ROW_MAX_BRA else 2
     return 0 if model_demand(ls) <= REGISTER_DOUBLES else 1
+
+
+def model_form(ls):
+    """Staged classes past the e-chunked form's size take the row form."""
+    g = vrrmod.VRRGraph(*ls)
+    return "row" if len(g.nodes) > STAGED_MAX_NODES or g.n_hrr() > STAGED_MAX_HRR else "chunk"
 
 
 def load_table(path=TABLE):
@@ -101,10 +129,15 @@ def route(ls, table=None):
     table = load_table() if table is None else table
     t = dict(table.get(tag, {}))
     tier = t.get("tier", model_tier(ls))
-    cap = model_cap(ls) if tier == 1 else DEFAULT_CAP
+    form = t.get("form", model_form(ls)) if tier == 1 else None
+    cap = model_cap(ls) if tier == 1 and form == "chunk" else DEFAULT_CAP
     if tier == 1 and "cap" in t:
         cap = t["cap"]
     r = {"tier": tier, "cap": cap, "waves": 0, "source": "model"}
+    if tier == 1:
+        r["form"] = form
+        if form == "row":
+            r["budget"] = ROW_BUDGET
     if t:                      # measured entries win; what they leave out comes from the model
         r.update({k: v for k, v in t.items() if k not in ("variant", "ms")})
         r["source"] = "table"
@@ -121,6 +154,11 @@ def fallback(route, spilled):
     tier = route.get("tier", 0)
     if tier == 0:
         return {"tier": 1}
+    if tier == 1 and route.get("form") == "row":
+        budget = route.get("budget", ROW_BUDGET)
+        if all(k.startswith("p1_") for k in spilled) and budget > 160:
+            return {"tier": 1, "form": "row", "budget": budget - 20}
+        return {"tier": 2}
     if tier == 1:
         if all(k.startswith("p1_") for k in spilled):
             cap = route.get("cap", DEFAULT_CAP)

@@ -117,6 +117,16 @@ def test_router_fallback_ladder():
     assert router.fallback({"tier": 1, "cap": 16}, ["p1_2222"]) == {"tier": 2}
     assert router.fallback({"tier": 1, "cap": 96}, ["jk_4410", "p1_4410"]) == {"tier": 2}
     assert router.fallback({"tier": 2}, ["t3_jk_kernel"]) is None
+    assert router.fallback({"tier": 1, "form": "row", "budget": 240}, ["p1_3333"]) == \
+        {"tier": 1, "form": "row", "budget": 220}
+    assert router.fallback({"tier": 1, "form": "row", "budget": 220}, ["p1_3333p3"]) == \
+        {"tier": 1, "form": "row", "budget": 200}
+    assert router.fallback({"tier": 1, "form": "row", "budget": 160}, ["p1_3333"]) == {"tier": 2}
+    assert router.fallback({"tier": 1, "form": "row", "budget": 240}, ["jk_4444"]) == {"tier": 2}
+    assert router.route((3, 3, 3, 3), {})["form"] == "row" and router.route((2, 2, 2, 1), {})["form"] == "chunk"
+    assert router.route((4, 3, 2, 1), {})["form"] == "row"
+    assert router.route((4, 4, 2, 1), {})["tier"] == 2             # a (gg| bra stays on the op tables
+    assert router.route((4, 4, 4, 3), {})["tier"] == 2             # a (gg| ket: rows of 145 do not fit
 
 
 def test_resource_remarks_parse():
@@ -137,6 +147,10 @@ def test_resource_remarks_parse():
     assert res["jk_2120"]["dynamic_stack"] is False
     assert build.check_resources(res) == ["t3w_eri_kernel<false>"]
     assert build.class_scratch(res, "2120") == 0
+    # Phase-1 parts of a row-form class count for their class
+    assert build._spilled_classes({"p1_3333p2": {"scratch": 8}, "jk_3333": {"scratch": 0},
+                                   "jk_2120": {"scratch": 4}}) == {"3333": ["p1_3333p2"], "2120": ["jk_2120"]}
+    assert build.class_scratch({"p1_3333p1": {"scratch": 12}}, "3333") == 12
 
 
 def test_generate_applies_defaults_and_overrides(tmp_path):

@@ -128,6 +128,18 @@ def test_iteration_served_equals_alone(hgp, torch_cuda):
     assert worst <= same_tol([x for a in alone for x in a[0]]) and srv.peak_active == 4
 
 
+def _multi_need(hgp, reqs):
+    """Bytes GpuMultiExecutor charges for one multi-system plan over reqs:
+    the plan's device bytes plus each request's densities and J, K."""
+    bases = [hgp.Basis.from_workload(r.basis) for r in reqs]
+    p = hgp.Plan.multi(bases, tau=reqs[0].tau)
+    need = p.stats()["device_bytes"] + sum(8 * r.basis.nbf ** 2 * (len(r.densities) + 2) for r in reqs)
+    p.close()
+    for b in bases:
+        b.close()
+    return need
+
+
 def test_iteration_budget_pushes_back_and_rejects(hgp, torch_cuda):
     """Iteration-level batching under a budget that holds each small request
     alone but not all of them together, and not the one large request even
@@ -140,10 +152,11 @@ def test_iteration_budget_pushes_back_and_rejects(hgp, torch_cuda):
     reqs = [serve.Request(i, 0.0, bw, [D, workloads.psd_density(bw.nbf, 77 + i)], tau=1e-12, theta=0.0)
             for i, (bw, D) in enumerate(systems)]
     alone = [_alone(hgp, torch_cuda, r, 0.0) for r in reqs]
-    s = sorted(a[1] for a in alone)
-    big = max(range(len(reqs)), key=lambda i: alone[i][1])
-    assert s[-1] > s[-2]
-    budget = s[-2] + (min(s[-1], s[-2] + s[-3]) - s[-2]) // 2
+    big = len(reqs) - 1
+    single = max(_multi_need(hgp, [r]) for r in reqs[:big])
+    all_small = _multi_need(hgp, reqs[:big])
+    budget = int(single * 1.05)
+    assert all_small > budget and _multi_need(hgp, [reqs[big]]) > budget
     ex = serve.GpuMultiExecutor(keep=True)
     srv = serve.IterationServer(ex, hbm_budget=budget, max_active=6)
     recs, ups = srv.run(reqs)
@@ -159,6 +172,6 @@ def test_iteration_budget_pushes_back_and_rejects(hgp, torch_cuda):
         for k in range(2):
             J, K = ex.results[(r.rid, k)]
             worst = max(worst, np.abs(J - res[k][0]).max(), np.abs(K - res[k][1]).max())
-    print(f"budget {budget / 2**20:.1f} MiB: rejected request {big} ({alone[big][1] / 2**20:.1f} MiB), "
-          f"peak active {srv.peak_active}, rebuilds {srv.rebuilds}, max |served - alone| {worst:.2e}")
+    print(f"budget {budget / 2**20:.1f} MiB (all five small together {all_small / 2**20:.1f} MiB): rejected "
+          f"request {big}, peak active {srv.peak_active}, rebuilds {srv.rebuilds}, max |served - alone| {worst:.2e}")
     assert worst <= same_tol([x for i, a in enumerate(alone) if i != big for x in a[0]])
