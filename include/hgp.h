@@ -65,6 +65,7 @@ typedef enum {
 typedef struct hgp_basis hgp_basis;  /* validated shells, normalised coefficients, device copies */
 typedef struct hgp_plan hgp_plan;    /* pair data, Schwarz factors and screened class quartet lists */
 
+#define HGP_NORMALIZE 1           /* hgp_basis_create: normalise the raw contraction coefficients */
 #define HGP_FP64 0
 #define HGP_MIXED 1               /* FP32 VRR/HRR for quartets with a small Schwarz bound (see hgp_plan_create_mixed) */
 #define HGP_MIXED_THETA_DEFAULT 1e-10
@@ -75,16 +76,22 @@ int32_t hgp_max_l(void);
 
 /*
  * hgp_basis_create -- ingest nshell shells (Alg. 2's input: shells with
- * primitives {(alpha_i, c_i)}) onto the current HIP device.
+ * primitives {(alpha_i, c_i)}, Sec. II-A) onto the current HIP device.
  *   l[nshell]         angular momentum per shell, 0..4              (host)
  *   nprim[nshell]     primitives per shell, 1..64                   (host)
  *   centers[3*nshell] x, y, z per shell, bohr                       (host)
  *   exps[sum nprim]   exponents, shell by shell, > 0                (host)
- *   coefs[sum nprim]  raw contraction coefficients                  (host)
- * Normalisation runs in a device kernel.  nshell = 0 is allowed (N = 0).
+ *   coefs[sum nprim]  contraction coefficients                      (host)
+ *   flags             HGP_NORMALIZE: coefs are raw; a device kernel scales
+ *                     them by N(alpha, l) and the contraction norm (see
+ *                     Conventions).  0: coefs are used as given, i.e. they are
+ *                     already those scaled coefficients (what HGP_NORMALIZE
+ *                     would compute); the functions are then whatever they
+ *                     define.  Anything else: HGP_E_INVALID.
+ * nshell = 0 is allowed (N = 0).  The host arrays are copied.
  */
 hgp_status hgp_basis_create(int32_t nshell, const int32_t *l, const int32_t *nprim, const double *centers,
-                            const double *exps, const double *coefs, hgp_basis **out);
+                            const double *exps, const double *coefs, int32_t flags, hgp_basis **out);
 /* Number of spherical functions; shell_offsets[nshell+1] (host, may be NULL) gets each shell's first function. */
 hgp_status hgp_basis_nbf(const hgp_basis *b, int32_t *nbf, int32_t *shell_offsets);
 hgp_status hgp_basis_destroy(hgp_basis *b);
@@ -241,7 +248,9 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
  *   centers[12*n]  A, B, C, D per quartet, bohr                      (device)
  *   exps[4*n]      a, b, c, d per quartet                            (device)
  *   out[n * nsph(la) nsph(lb) nsph(lc) nsph(ld)]  spherical blocks   (device)
- * Stream-ordered; returns after enqueueing.
+ * Stream-ordered; returns after enqueueing.  Its temporary buffers come from
+ * the device's default memory pool, whose release threshold the library
+ * raises on the first call (freed blocks stay in the pool for the next call).
  */
 hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64_t n, const double *centers,
                                  const double *exps, double *out, int32_t precision, void *hip_stream);

@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("HGP_LIB") or os.path.join(_HERE, "libhgp.so")
 STATUS = {0: "HGP_OK", -1: "HGP_E_INVALID", -2: "HGP_E_UNSUPPORTED_L", -3: "HGP_E_OOM", -4: "HGP_E_DEVICE",
           -5: "HGP_E_STATE"}
 STATUS_OOM = -3
+HGP_NORMALIZE = 1
 HGP_FP64 = 0
 HGP_MIXED = 1
 MIXED_THETA_DEFAULT = 1e-10     # HGP_MIXED_THETA_DEFAULT in include/hgp.h
@@ -28,7 +29,7 @@ _vp, _i32, _i64, _d, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctyp
 SIGNATURES = {
     "hgp_version": (_i32, []),
     "hgp_max_l": (_i32, []),
-    "hgp_basis_create": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "hgp_basis_create": (ctypes.c_int, [_i32, _vp, _vp, _vp, _vp, _vp, _i32, ctypes.POINTER(_vp)]),
     "hgp_basis_nbf": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), _vp]),
     "hgp_basis_destroy": (ctypes.c_int, [_vp]),
     "hgp_plan_create": (ctypes.c_int, [_vp, _d, _i32, _sz, _vp, ctypes.POINTER(_vp)]),
@@ -112,15 +113,17 @@ def _host(a, dtype):
 
 
 class Basis:
-    """hgp_basis: shells l[n], nprim[n], centres [n,3] (bohr), exponents and raw
-    coefficients (flat, shell by shell)."""
+    """hgp_basis: shells l[n], nprim[n], centres [n,3] (bohr), exponents and
+    coefficients (flat, shell by shell); raw coefficients normalised by the
+    library (normalize=True, HGP_NORMALIZE) or used as given."""
 
-    def __init__(self, l, nprim, centers, exps, coefs):
+    def __init__(self, l, nprim, centers, exps, coefs, normalize: bool = True):
         self._keep = [_host(l, np.int32), _host(nprim, np.int32), _host(centers, np.float64),
                       _host(exps, np.float64), _host(coefs, np.float64)]
         ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in self._keep]
         h = ctypes.c_void_p()
-        _check(lib().hgp_basis_create(int(self._keep[0].shape[0]), *ptrs, ctypes.byref(h)))
+        _check(lib().hgp_basis_create(int(self._keep[0].shape[0]), *ptrs, HGP_NORMALIZE if normalize else 0,
+                                      ctypes.byref(h)))
         self.handle = h
         n = ctypes.c_int32()
         self.shell_offsets = np.zeros(self._keep[0].shape[0] + 1, np.int32)

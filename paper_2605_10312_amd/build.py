@@ -34,7 +34,7 @@ REMARKS = ["-Rpass-analysis=kernel-resource-usage"]
 
 REGISTER_OPTS = ("waves", "digest", "reduce", "loop", "block")
 STAGED_OPTS = ("cap", "waves", "reduce", "loop")
-ROW_OPTS = ("budget", "waves", "reduce", "loop")
+ROW_OPTS = ("budget", "waves", "reduce", "loop", "eri_layout")
 
 
 _EMITTED: dict = {}     # (class, routing inputs) -> (source, meta): a rerouting pass regenerates only what changed
@@ -282,7 +282,10 @@ def build(lmax: int = DEFAULT_LMAX, jobs: int | None = None, force: bool = False
     t0 = time.time()
     os.makedirs(OBJ, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 4)
-    reroute: dict = {}
+    # start from the routes earlier builds settled on (only for the library's
+    # own table: variant builds with an explicit table start from the model)
+    main_table = table is None and defaults is None and overrides is None
+    reroute: dict = dict(router.load_reroutes()) if main_table else {}
     compiled: set = set()
     for attempt in range(8):
         gen_files, metas = generate(lmax, verbose=False, overrides=overrides, gen_dir=gen_dir, defaults=defaults,
@@ -317,6 +320,8 @@ def build(lmax: int = DEFAULT_LMAX, jobs: int | None = None, force: bool = False
                 print(f"  class {tag}: {', '.join(sorted(kernels))} use private scratch; rerouting {nxt}", flush=True)
             reroute[tag] = nxt
     bad = check_resources(res)
+    if not bad and main_table and out is None and router.save_reroutes(reroute) and verbose:
+        print(f"  recorded {len(reroute)} rerouted classes in {router.TABLE}", flush=True)
     if bad and not allow_scratch:
         raise RuntimeError("kernels compiled with private scratch (register spill or stack), which the library "
                            "does not allow: " + ", ".join(f"{k} ({res[k].get('scratch')} B/lane)" for k in bad))

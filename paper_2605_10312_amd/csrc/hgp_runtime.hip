@@ -143,8 +143,10 @@ void run_eri_class(const ClassKernels &k, EriArgs a, int64_t scratch_doubles, hi
     for (int64_t q0 = 0; q0 < ntask; q0 += B) {
         const int64_t nb = std::min(B, ntask - q0);
         if (k.tier == 1) {
+            // row-form classes run their integrals-out kernel one wave per
+            // quartet over a quartet-major buffer
             P1Args pa{(const int32_t *)(a.tasks + q0), (int64_t)(sizeof(EriTask) / sizeof(int32_t)), nb, a.pairs,
-                      a.geo, a.prims, a.boys, a.scratch, B};
+                      a.geo, a.prims, a.boys, a.scratch, B, k.eri_wave};
             k.p1(pa, s);
         }
         EriArgs b = a;
@@ -152,6 +154,7 @@ void run_eri_class(const ClassKernels &k, EriArgs a, int64_t scratch_doubles, hi
         b.ntask = nb;
         if (a.mode == 1) b.out = a.out + q0;
         b.stride = B;
+        if (k.eri_tiles) k.eri_tiles(b, s);
         k.eri(b, s);
     }
 }
@@ -186,6 +189,7 @@ hgp_status upload(T **p, const std::vector<T> &v, int64_t *bytes = nullptr)
 // ---------------------------------------------------------------------------
 struct hgp_basis {
     int device = 0;
+    int flags = HGP_NORMALIZE;  // coefficients normalised by the library (else used as given)
     int nshell = 0, nbf = 0, lmax = 0;
     std::vector<int32_t> l, nprim, poff, foff;
     std::vector<double> cen, exps, coefs;
@@ -292,14 +296,16 @@ hgp_status hgp_basis_destroy(hgp_basis *b)
 }
 
 hgp_status hgp_basis_create(int32_t nshell, const int32_t *l, const int32_t *nprim, const double *centers,
-                            const double *exps, const double *coefs, hgp_basis **out)
+                            const double *exps, const double *coefs, int32_t flags, hgp_basis **out)
 {
     if (!out) return fail(HGP_E_INVALID, "out is NULL");
     *out = nullptr;
     if (nshell < 0) return fail(HGP_E_INVALID, "nshell < 0");
+    if (flags != 0 && flags != HGP_NORMALIZE) return fail(HGP_E_INVALID, "flags: HGP_NORMALIZE or 0");
     if (nshell > 0 && (!l || !nprim || !centers || !exps || !coefs)) return fail(HGP_E_INVALID, "NULL shell array");
     auto *b = new hgp_basis();
     b->nshell = nshell;
+    b->flags = flags;
     b->poff.assign(1, 0);
     b->foff.assign(1, 0);
     for (int s = 0; s < nshell; ++s) {
@@ -337,7 +343,12 @@ hgp_status hgp_basis_create(int32_t nshell, const int32_t *l, const int32_t *npr
         hgp_basis_destroy(b);
         return st;
     }
-    launch_normalize(nshell, b->d_l, b->d_nprim, b->d_poff, b->d_exps, b->d_coefs, b->d_ncoef, 0);
+    if (flags & HGP_NORMALIZE)
+        launch_normalize(nshell, b->d_l, b->d_nprim, b->d_poff, b->d_exps, b->d_coefs, b->d_ncoef, 0);
+    else if (np > 0 && hipMemcpy(b->d_ncoef, b->d_coefs, sizeof(double) * np, hipMemcpyDeviceToDevice) != hipSuccess) {
+        hgp_basis_destroy(b);
+        return fail(HGP_E_DEVICE, "copying the coefficients failed");
+    }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(0) != hipSuccess) {
         hgp_basis_destroy(b);
         return fail(HGP_E_DEVICE, "normalisation kernel failed");
@@ -804,6 +815,7 @@ hgp_status hgp_plan_create_multi(const hgp_basis *const *bases, int32_t n, doubl
         const hgp_basis *b = bases[k];
         if (!b) return fail(HGP_E_INVALID, "a basis is NULL");
         if (dev >= 0 && b->device != dev) return fail(HGP_E_INVALID, "all bases must be on one device");
+        if (b->flags != bases[0]->flags) return fail(HGP_E_INVALID, "all bases must be created with the same flags");
         dev = b->device;
         l.insert(l.end(), b->l.begin(), b->l.end());
         nprim.insert(nprim.end(), b->nprim.begin(), b->nprim.end());
@@ -818,7 +830,8 @@ hgp_status hgp_plan_create_multi(const hgp_basis *const *bases, int32_t n, doubl
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess || cur != dev) return fail(HGP_E_INVALID, "the bases' device is not current");
     hgp_basis *u = nullptr;
-    hgp_status st = hgp_basis_create((int32_t)l.size(), l.data(), nprim.data(), cen.data(), exps.data(), coefs.data(), &u);
+    hgp_status st = hgp_basis_create((int32_t)l.size(), l.data(), nprim.data(), cen.data(), exps.data(), coefs.data(),
+                                     bases[0]->flags, &u);
     if (st) return st;
     if (u->lmax > built_max_l()) {
         hgp_basis_destroy(u);
@@ -1004,7 +1017,7 @@ static hgp_status jk_classes(hgp_plan *p, const double *D, bool want_j, bool wan
                     continue;
                 }
                 P1Args pa{(const int32_t *)(cl.d_q + q0), 2, nb, p->d_pairs, p->d_geo, p->d_prims, boys,
-                          p->d_scratch, B};
+                          p->d_scratch, B, 0};
                 if ((st = mark(&e0))) return st;
                 k.p1(pa, s);
                 if ((st = mark(&e1)) || (st = mark(&e2))) return st;
@@ -1269,6 +1282,28 @@ hgp_status noalloc_scratch(int dev, unsigned char **out)
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// The stream-ordered buffers of hgp_eri_prim_quartets (up to several GB for
+// high-l classes) come from the device's default memory pool.  With the
+// pool's default release threshold of zero every synchronisation hands that
+// memory back to the driver and the next call maps it again, which cost more
+// than the kernels themselves; the library raises the threshold once per
+// device so freed blocks stay in the pool for reuse.
+bool g_pool_kept[64] = {};
+
+hgp_status keep_pool(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (dev < 0 || dev >= 64) return fail(HGP_E_DEVICE, "device index out of range");
+    if (!g_pool_kept[dev]) {
+        hipMemPool_t pool = nullptr;
+        HGP_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+        uint64_t thr = UINT64_MAX;
+        HGP_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+        g_pool_kept[dev] = true;
+    }
+    return HGP_OK;
+}
+
 // Bytes of the fixed buffer that n quartets of class k take: pair and task
 // records, plus room for one 64-quartet batch of a staged class.
 size_t noalloc_need(const ClassKernels &k, int64_t n)
@@ -1292,6 +1327,7 @@ hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld,
     hipStream_t s = (hipStream_t)hip_stream;
     int dev = 0;
     HGP_HIP(hipGetDevice(&dev));
+    if (hgp_status kst = keep_pool(dev)) return kst;
     const double *boys = nullptr;
     hgp_status st = boys_table(dev, &boys);
     if (st) return st;

@@ -74,7 +74,9 @@ struct EriArgs {
 };
 
 // Phase-1 kernel of a staged class: items i < n, pair indices at idx[i*istride]
-// (bra) and idx[i*istride + 1] (ket); accumulators to scratch[slot*stride + i].
+// (bra) and idx[i*istride + 1] (ket); accumulators to scratch[slot*stride + i]
+// (slot-major), or, with qmajor set (row-form classes in integrals-out mode),
+// to scratch[i*slots + slot] (the quartet's values contiguous).
 struct P1Args {
     const int32_t *idx;
     int64_t istride;
@@ -85,6 +87,7 @@ struct P1Args {
     const double *boys;
     double *scratch;
     int64_t stride;
+    int32_t qmajor;
 };
 
 // Boys table: F_m(T_k) for T_k = k * BOYS_STEP, k = 0 .. BOYS_NPTS-1, m = 0 .. BOYS_NORD-1,
@@ -135,6 +138,9 @@ struct ClassKernels {
     int scratch_slots;      // doubles of buffer per quartet (0 for the register tier)
     int chunks;             // Phase-1 target chunks
     int max_batch;          // > 0: wave-cooperative launches of at most this many quartets (see T3G_LANE_MIN)
+    int eri_wave;           // 1: row-form class whose integrals-out kernel runs one wave per quartet over a
+                            // quartet-major buffer (Phase 1 with qmajor set)
+    launch_eri_fn eri_tiles;  // row form, integrals out: ket stage of the tiled rows, before eri (or nullptr)
 };
 
 }  // namespace hgp

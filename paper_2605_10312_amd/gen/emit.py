@@ -487,6 +487,8 @@ def emit_table(metas):
             out.append(f"int prepare_{m.tag}();")
         if m.mixed:
             out.append(f"void launch_jk32_{m.tag}(const JKArgs &, hipStream_t);")
+        if getattr(m, "eri_tiles", False):
+            out.append(f"void launch_erit_{m.tag}(const EriArgs &, hipStream_t);")
     out.append("")
     out.append("extern const ClassKernels g_class_table[] = {")
     for m in metas:
@@ -494,9 +496,10 @@ def emit_table(metas):
         p1 = f"launch_p1_{m.tag}" if m.tier == 1 else "nullptr"
         prep = f"prepare_{m.tag}" if m.tier in (2, 3) else "nullptr"
         jk32 = f"launch_jk32_{m.tag}" if m.mixed else "nullptr"
+        tiles = f"launch_erit_{m.tag}" if getattr(m, "eri_tiles", False) else "nullptr"
         out.append(f"    {{{la}, {lb}, {lc}, {ld}, {m.tier}, launch_jk_{m.tag}, launch_eri_{m.tag}, {p1}, {prep}, {jk32}, {m.block}, "
                    f"{m.vrr_flops}.0, {m.p2_flops}.0, {m.n_hrr}, {m.peak_live}, {m.scratch_slots}, {m.chunks}, "
-                   f"{m.max_batch}}},")
+                   f"{m.max_batch}, {1 if getattr(m, 'eri_wave', False) else 0}, {tiles}}},")
     out.append("};")
     out.append(f"extern const int g_num_classes = {len(metas)};")
     out.append("")

@@ -214,6 +214,21 @@ class RowPlan:
             groups.append((ops, {f: f"in_{k}" for k, f in enumerate(F)}, outs))
         return groups
 
+    def wave_bra(self):
+        """The integrals-out kernel's bra stage, one ket function per lane:
+        the same ops for every (lam, sig), inputs (e|lam sig) for each bra
+        component e.  -> (ops, {e: input name}, {(mu, nu): output name})."""
+        E = self.E
+        ops, outs = side_stage(self.ls[0], self.ls[1], lambda e: f"in_{E.index(e)}", ("ABx", "ABy", "ABz"), "w")
+        return ops, {e: f"in_{k}" for k, e in enumerate(E)}, outs
+
+    def wave_ket(self):
+        """The ket stage of one tiled row, the same ops for every row: inputs
+        H[e, f] for each ket component f -> (ops, {f: name}, {(lam, sig): name})."""
+        F = self.F
+        ops, outs = side_stage(self.ls[2], self.ls[3], lambda f: f"in_{F.index(f)}", ("CDx", "CDy", "CDz"), "t")
+        return ops, {f: f"in_{k}" for k, f in enumerate(F)}, outs
+
     @property
     def ncd(self):
         return self.nc * self.nd
@@ -323,7 +338,12 @@ def _vrr_lines(g, order, tnames, ind):
 
 
 def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", block=64, waves=0, reduce="segmented",
-                   loop="late", plan=None):
+                   loop="late", plan=None, eri_layout="quartet"):
+    """eri_layout: how Phase 1 hands the (e|lam sig) values to the
+    integrals-out kernel: 'quartet' (each quartet's values contiguous: the
+    one-wave-per-quartet kernel reads them with coalesced loads, Phase 1
+    stores them a row per lane) or 'slot' (slot-major as for J/K: Phase 1
+    stores coalesced, the integrals-out kernel gathers)."""
     ls = (la, lb, lc, ld)
     tag = tag_of(ls)
     plan = plan or plan_rows(la, lb, lc, ld, budget, rule)
@@ -409,8 +429,10 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
         pw("    const PrimPair *__restrict__ prims = a.prims;")
         pw("    const double *__restrict__ boys = a.boys;")
         pw("    double *const sb = a.scratch;")
-        pw("    const uint32_t S32 = (uint32_t)a.stride;")
-        pw("    uint32_t li = (uint32_t)i;")
+        pw("    // slot k of item i: sb[k * S32 + li] with S32 the batch stride (slot-major), or with")
+        pw(f"    // S32 = 1 and li = i * {plan.nslots} (quartet-major, integrals out)")
+        pw(f"    const uint32_t S32 = a.qmajor ? 1u : (uint32_t)a.stride;")
+        pw(f"    uint32_t li = a.qmajor ? (uint32_t)i * {plan.nslots}u : (uint32_t)i;")
         pw("    switch (chunk) {")
         for lci, ci in enumerate(idxs):
             ch = plan.chunks[ci]
@@ -499,33 +521,101 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
                         lambda key, x, i2, lam=lam, sig=sig: sink(key[0], key[1], lam, sig, x, i2), ind))
         return lines
 
-    # ---------------------------------------------------------------- kernel 2: integrals out
+    # ---------------------------------------------------------------- kernel 2: integrals out, one wave per quartet
+    # Phase 1 wrote the quartet's values contiguously (quartet-major).  Lane j
+    # takes ket function j = (lam, sig): it reads (e|lam sig) for every e (the
+    # lanes read consecutive doubles), runs the bra HRR + T(la) T(lb), and
+    # writes the (mu nu|lam sig) values, which for a fixed (mu, nu) lie next
+    # to each other in the caller's block, so the stores are coalesced too.
     diag_class = (la, lb) == (lc, ld)
-    w(f"__global__ __launch_bounds__({block}) void eri_{tag}(EriArgs a)")
+    ncd = plan.ncd
+    assert ncd <= 64, "one ket function per lane"
+    NS = plan.nslots
+    wops, wins, wouts = plan.wave_bra()
+    w(f"__global__ __launch_bounds__(64) void eri_{tag}(EriArgs a)")
     w("{")
-    w(f"    const int64_t i = (int64_t)blockIdx.x * {block} + threadIdx.x;")
+    w("    const int64_t i = blockIdx.x;                 // quartet of the batch")
     w("    if (i >= a.ntask) return;")
-    w("    double *const sb = a.scratch;")
-    w("    const uint32_t S32 = (uint32_t)a.stride;")
-    w("    uint32_t li = (uint32_t)i;")
+    w("    const int j = threadIdx.x;")
     w("    const EriTask t = a.tasks[i];")
-    w("    const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];")
-    w("    double *__restrict__ o = a.out + t.off;")
+    w("    const PairGeo gb = a.geo[t.bra];")
+    w("    const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz;")
+    w("    (void)ABx; (void)ABy; (void)ABz;")
+    if eri_layout == "quartet":
+        w(f"    const double *__restrict__ zq = a.scratch + (uint64_t)i * {NS}u;")
+        w("    const uint32_t ZS = 1u;")
+    else:
+        w("    const double *__restrict__ zq = a.scratch + i;")
+        w("    const uint32_t ZS = (uint32_t)a.stride;")
+    w("    double dg = 0.0;")
+    w(f"    if (j < {ncd}) {{")
+    w(f"        const int lam = j / {nd}, sig = j - lam * {nd};")
+    used = {n for op in wops for n in _names_in(op)} | set(wouts.values())
+    for k, e in enumerate(E):
+        nm = wins[e]
+        if nm in used:
+            w(f"        const double {nm} = zq[({plan.zslot(k, 0, 0)}u + j) * ZS];")
+    for op in wops:
+        w("        " + _op_line(op, {}))
+    w("        if (a.mode == 0) {")
+    w("            double *__restrict__ o = a.out + t.off + lam * t.s2 + sig * t.s3;")
+    for mu in range(na):
+        for nu in range(nb):
+            w(f"            o[{mu} * t.s0 + {nu} * t.s1] = {wouts[(mu, nu)]};")
+    w("        }")
     if diag_class:
-        w("    double dmax = 0.0;")
-
-    def eri_sink(mu, nu, lam, sig, x, ind):
-        r = []
-        if diag_class and (mu, nu) == (lam, sig):
-            r.append(f"{ind}dmax = fmax(dmax, fabs({x}));")
-        r.append(f"{ind}if (a.mode == 0) o[{mu} * t.s0 + {nu} * t.s1 + {lam} * t.s2 + {sig} * t.s3] = {x};")
-        return r
-
-    out.extend(phase2_lines(eri_sink))
+        for mu in range(na):
+            for nu in range(nb):
+                w(f"        if (lam == {mu} && sig == {nu}) dg = fabs({wouts[(mu, nu)]});")
+    w("    }")
     if diag_class:
-        w("    if (a.mode == 1) a.out[i] = sqrt(dmax);")
+        w("    if (a.mode == 1) {                             // Schwarz factor: largest diagonal element")
+        w("#pragma unroll")
+        w("        for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o, 64));")
+        w("        if (j == 0) a.out[i] = sqrt(dg);")
+        w("    }")
+    w("    (void)dg;")
     w("}")
     w("")
+    if plan.tile_rows:
+        # the ket stage of the tiled rows (integrals out), one lane per (quartet, tiled row)
+        tops, tins, touts = plan.wave_ket()
+        nt = len(plan.tile_rows)
+        w(f"__global__ __launch_bounds__(64) void erit_{tag}(EriArgs a)")
+        w("{")
+        w("    const int64_t item = (int64_t)blockIdx.x * 64 + threadIdx.x;")
+        w(f"    const int64_t i = item / {nt};")
+        w(f"    const int tr = (int)(item - i * {nt});")
+        w("    if (i >= a.ntask) return;")
+        if eri_layout == "quartet":
+            w(f"    double *__restrict__ zq = a.scratch + (uint64_t)i * {NS}u;")
+            w("    const uint32_t ZS = 1u;")
+        else:
+            w("    double *__restrict__ zq = a.scratch + i;")
+            w("    const uint32_t ZS = (uint32_t)a.stride;")
+        w("    const PairGeo gk = a.geo[a.tasks[i].ket];")
+        w("    const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
+        w("    (void)CDx; (void)CDy; (void)CDz;")
+        w("    int erow = 0;                                 // bra component of tiled row tr")
+        w("    switch (tr) {")
+        for ti, e in enumerate(plan.tile_rows):
+            w(f"    case {ti}: erow = {eidx[e]}; break;")
+        w("    default: break;")
+        w("    }")
+        w(f"    const double *__restrict__ hrow = zq + ({plan.hslot(0, 0)}u + tr * {len(F)}u) * ZS;")
+        w(f"    double *__restrict__ zrow = zq + erow * {ncd}u * ZS;")
+        tused = {n for op in tops for n in _names_in(op)} | set(touts.values())
+        for k, f in enumerate(F):
+            nm = tins[f]
+            if nm in tused:
+                w(f"    const double {nm} = hrow[{k}u * ZS];")
+        for op in tops:
+            w("    " + _op_line(op, {}))
+        for lam in range(nc):
+            for sig in range(nd):
+                w(f"    zrow[{lam * nd + sig}u * ZS] = {touts[(lam, sig)]};")
+        w("}")
+        w("")
     # ---------------------------------------------------------------- kernel 2: J/K (own translation unit)
     jo = []
     jw = jo.append
@@ -577,9 +667,14 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
     w("}")
     w(f"void launch_eri_{tag}(const EriArgs &a, hipStream_t s)")
     w("{")
-    w(f"    const int64_t blocks = (a.ntask + {block - 1}) / {block};")
-    w(f"    if (blocks > 0) hipLaunchKernelGGL(eri_{tag}, dim3((unsigned)blocks), dim3({block}), 0, s, a);")
+    w(f"    if (a.ntask > 0) hipLaunchKernelGGL(eri_{tag}, dim3((unsigned)a.ntask), dim3(64), 0, s, a);")
     w("}")
+    if plan.tile_rows:
+        w(f"void launch_erit_{tag}(const EriArgs &a, hipStream_t s)")
+        w("{")
+        w(f"    const int64_t blocks = (a.ntask * {len(plan.tile_rows)} + 63) / 64;")
+        w(f"    if (blocks > 0) hipLaunchKernelGGL(erit_{tag}, dim3((unsigned)blocks), dim3(64), 0, s, a);")
+        w("}")
     w("")
     w("}  // namespace hgp")
     pl_max = max(c.peak_live for c in plan.chunks)
@@ -587,6 +682,8 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
                      scratch_slots=plan.nslots, chunks=nch, recompute=rec, cap=budget, waves=waves, digest="",
                      reduce=reduce, loop=loop)
     meta.form = "row"
+    meta.eri_wave = eri_layout == "quartet"        # Phase 1 writes quartet-major for integrals out
+    meta.eri_tiles = bool(plan.tile_rows)
     meta.parts = len(parts)
     meta.extra_sources = part_src
     return "\n".join(out) + "\n", meta

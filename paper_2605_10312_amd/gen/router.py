@@ -87,6 +87,27 @@ def load_table(path=TABLE):
     return {}
 
 
+def load_reroutes(path=TABLE):
+    """Routes the build's compile-feedback pass settled on (class tag ->
+    options), recorded beside the measured table so that a fresh build starts
+    from them instead of compiling the spilling forms again."""
+    if path and os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh).get("rerouted", {})
+    return {}
+
+
+def save_reroutes(reroute, path=TABLE):
+    data = json.load(open(path)) if os.path.exists(path) else {"device": "gfx950", "classes": {}}
+    if data.get("rerouted", {}) == reroute:
+        return False
+    data["rerouted"] = {k: reroute[k] for k in sorted(reroute)}
+    with open(path + ".tmp", "w") as fh:
+        json.dump(data, fh, indent=1)
+    os.replace(path + ".tmp", path)
+    return True
+
+
 CAPS = (128, 96, 64, 48, 32, 24, 16)
 
 

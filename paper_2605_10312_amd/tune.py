@@ -172,6 +172,8 @@ def apply_refine(path, margin=0.02, table=TABLE):
 
 
 def select(path, table=TABLE):
+    from .gen import router
+    rerouted = router.load_reroutes(table)      # kept: the build's compile-feedback routes
     res = json.load(open(path))
     classes = sorted({t for r in res.values() for t in r["classes"]})
     chosen = {}
@@ -193,7 +195,8 @@ def select(path, table=TABLE):
               "  ".join(f"{n}={r['classes'][tag]['ms']:.3f}" for n, r in res.items() if tag in r["classes"]))
     os.makedirs(os.path.dirname(table), exist_ok=True)
     with open(table, "w") as fh:
-        json.dump({"device": "gfx950", "workload": "mol30_3s2p1d, tau 1e-12", "classes": chosen}, fh, indent=1)
+        json.dump({"device": "gfx950", "workload": "mol30_3s2p1d, tau 1e-12", "classes": chosen,
+                   "rerouted": rerouted}, fh, indent=1)
     print(f"wrote {table}; estimated J/K build {sum(c['ms'] for c in chosen.values()):.2f} ms")
 
 

@@ -43,7 +43,7 @@ def _create(l, nprim, cen, exps, coefs):
     arrs = [np.ascontiguousarray(l, np.int32), np.ascontiguousarray(nprim, np.int32),
             np.ascontiguousarray(cen, np.float64), np.ascontiguousarray(exps, np.float64),
             np.ascontiguousarray(coefs, np.float64)]
-    rc = hgp.lib().hgp_basis_create(len(arrs[0]), *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs], ctypes.byref(h))
+    rc = hgp.lib().hgp_basis_create(len(arrs[0]), *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs], 1, ctypes.byref(h))
     return rc, h
 
 
@@ -73,7 +73,12 @@ def test_basis_validation(case, status):
 def test_null_arguments_rejected():
     import paper_2605_10312_amd as hgp
     L = hgp.lib()
-    assert L.hgp_basis_create(1, None, None, None, None, None, ctypes.byref(ctypes.c_void_p())) == -1
+    assert L.hgp_basis_create(1, None, None, None, None, None, 1, ctypes.byref(ctypes.c_void_p())) == -1
+    one = np.ones(1)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    zi = np.zeros(1, np.int32)
+    assert L.hgp_basis_create(1, ptr(zi), ptr(np.ones(1, np.int32)), ptr(np.zeros(3)), ptr(one), ptr(one), 7,
+                              ctypes.byref(ctypes.c_void_p())) == -1          # unknown flags
     assert L.hgp_plan_create(None, 1e-12, 0, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
     assert L.hgp_jk(None, None, None, None, None) == -1
     assert L.hgp_eri_prim_quartets(5, 0, 0, 0, 1, None, None, None, 0, None) == -2

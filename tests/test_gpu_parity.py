@@ -229,3 +229,36 @@ def test_concurrent_class_streams_match_one_stream(hgp, torch_cuda):
     assert (J1 - J2).abs().max().item() <= tol and (K1 - K2).abs().max().item() <= tol
     Jr, Kr = oracle.jk(bw, D, tau=1e-12)
     assert np.abs(J1.cpu().numpy() - Jr).max() <= JK_TOL and np.abs(K1.cpu().numpy() - Kr).max() <= JK_TOL
+
+
+def test_basis_flags_given_coefficients(hgp, torch_cuda):
+    """hgp_basis_create with flags = 0 takes the coefficients as given: with
+    the oracle's normalised coefficients (N(a, l) and the contraction norm
+    applied) it must reproduce the HGP_NORMALIZE basis built from the raw
+    ones, integrals and J/K alike."""
+    bw = workloads.random_small_basis(seed=31, natom=3, lmax=3, maxprim=3)
+    D = workloads.psd_density(bw.nbf, 31)
+    off = bw.prim_offsets()
+    given = np.concatenate([oracle.norm_coefs(int(bw.l[s]), bw.exps[off[s]:off[s + 1]], bw.coefs[off[s]:off[s + 1]])
+                            for s in range(bw.nshell)])
+    Dt = torch_cuda.tensor(D, device="cuda")
+    res = []
+    for normalize, coefs in ((True, bw.coefs), (False, given)):
+        b = hgp.Basis(bw.l, bw.nprim, bw.centers, bw.exps, coefs, normalize=normalize)
+        p = hgp.Plan(b, tau=0.0)
+        J, K = torch_cuda.empty_like(Dt), torch_cuda.empty_like(Dt)
+        p.jk(Dt, J, K)
+        q = [(0, 1, 2, 3), (5, 4, 3, 2), (7, 7, 1, 0)]
+        sizes = [int(np.prod([2 * bw.l[s] + 1 for s in x])) for x in q]
+        offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        out = torch_cuda.empty(int(sum(sizes)), dtype=torch_cuda.float64, device="cuda")
+        hgp.eri_shell_quartets(b, np.array(q, np.int32), offs, out)
+        torch_cuda.cuda.synchronize()
+        res.append((J.cpu().numpy(), K.cpu().numpy(), out.cpu().numpy()))
+        p.close()
+        b.close()
+    dj = np.abs(res[0][0] - res[1][0]).max()
+    dk = np.abs(res[0][1] - res[1][1]).max()
+    de = np.abs(res[0][2] - res[1][2]).max()
+    print(f"flags 0 vs HGP_NORMALIZE: |dJ| {dj:.2e} |dK| {dk:.2e} |dERI| {de:.2e}")
+    assert dj <= 1e-12 and dk <= 1e-12 and de <= 1e-13

@@ -25,7 +25,10 @@ def _norm(a, l):
     return (2 * a / np.pi) ** 0.75 * (4 * a) ** (0.5 * l) / np.sqrt(df)
 
 
-def run_row_plan(plan, centers, exps):
+def run_row_plan(plan, centers, exps, wave=False):
+    """wave: kernel 2 as the integrals-out kernels run it (the tiled rows' ket
+    stage and the bra stage each as one op list shared by every row or ket
+    function); otherwise as the J/K kernel runs it."""
     ls = plan.ls
     g = plan.g
     A, B, C, D = (centers[:, k, :].T for k in range(4))
@@ -96,6 +99,24 @@ def run_row_plan(plan, centers, exps):
                 f = g.nodes[t].key[1]
                 store(plan.hslot(tr, plan.F.index(f)), acc[f"h{g.target_ids.index(t)}"])
     assert sorted(covered) == sorted(g.target_ids)       # every target in exactly one chunk
+    if wave:
+        tops, tins, touts = plan.wave_ket()
+        for tr, e in enumerate(plan.tile_rows):
+            vals = {nm: sb[plan.hslot(tr, plan.F.index(f))] for f, nm in tins.items()}
+            run_ops(tops, vals)
+            for (lam, sig), nm in touts.items():
+                store(plan.zslot(eidx[e], lam, sig), vals[nm])
+        assert written[:plan.nslots_ints].all()
+        wops, wins, wouts = plan.wave_bra()
+        out = np.full((n, plan.na, plan.nb, plan.nc, plan.nd), np.nan)
+        for lam in range(plan.nc):
+            for sig in range(plan.nd):
+                vals = {nm: sb[plan.zslot(eidx[e], lam, sig)] for e, nm in wins.items()}
+                run_ops(wops, vals)
+                for (mu, nu), nm in wouts.items():
+                    out[:, mu, nu, lam, sig] = vals[nm]
+        assert not np.isnan(out).any()
+        return out
     # kernel 2: the tiled rows' ket stage, then the bra stage per ket function,
     # group by group as emitted (each group reads its inputs from the buffer)
     for tr, e in enumerate(plan.tile_rows):
@@ -127,6 +148,7 @@ def test_row_plan_matches_oracle(ls, budget):
         assert len(ch.targets) + ch.peak_live + 40 <= budget or (ch.kind == "tile" and len(ch.targets) == 1)
     cen, ex = workloads.prim_quartets(max(ls), 3, seed=91, box=1.5, exp_range=(0.3, 3.0))
     got = run_row_plan(plan, cen, ex)
+    gw = run_row_plan(plan, cen, ex, wave=True)            # the integrals-out form of kernel 2
     ref = oracle.eri_prim_quartets(ls, cen, ex)
     ref_ld = oracle.eri_prim_quartets(ls, cen, ex, precision="long double")
     e_orc = np.abs(ref - ref_ld).max()
@@ -135,6 +157,7 @@ def test_row_plan_matches_oracle(ls, budget):
     print(f"{ls}: {len(plan.chunks)} chunks ({rows} of rows, {len(plan.tile_rows)} rows tiled), "
           f"recompute x{emit_row.recompute_factor(plan):.2f}, {plan.nslots} slots, err {err:.2e} (oracle {e_orc:.2e})")
     assert err <= 1e-12 + 8 * e_orc
+    assert np.abs(gw - ref_ld).max() <= 1e-12 + 8 * e_orc
 
 
 def test_row_plan_grouped_stages():
@@ -176,6 +199,11 @@ def test_row_emitter_source():
     parts = {k: v for k, v in meta.extra_sources.items() if k != "jk"}
     assert len(parts) == meta.parts and all(f"void p1_2221p{k}(P1Args a)" in parts[f"p{k}"] for k in range(meta.parts))
     assert sum(p.count("case ") for p in parts.values()) == meta.chunks
-    src, meta = emit_row.emit_class_row(3, 3, 3, 3)         # many chunks: several Phase-1 parts
+    src, meta = emit_row.emit_class_row(3, 3, 3, 3, budget=200)   # many chunks: several Phase-1 parts
     assert meta.parts == -(-meta.chunks // emit_row.P1_PART_CHUNKS) > 1
     assert all(f"launch_p1_3333p{k}(a, s);" in src for k in range(meta.parts))
+    # integrals out: one wave per quartet, a tile kernel for the tiled rows
+    assert meta.eri_wave and meta.eri_tiles and "void erit_3333(EriArgs a)" in src and "if (j < 49)" in src
+    from paper_2605_10312_amd.gen import emit
+    table = emit.emit_table([meta])
+    assert "launch_erit_3333}" in table and ", 1, launch_erit_3333}" in table
