@@ -346,6 +346,7 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
     stores coalesced, the integrals-out kernel gathers)."""
     ls = (la, lb, lc, ld)
     tag = tag_of(ls)
+    assert block == 64, "Phase 1 stages its quartet-major stores per wave"
     plan = plan or plan_rows(la, lb, lc, ld, budget, rule)
     g, E, F, kp2 = plan.g, plan.E, plan.F, plan.kp2
     na, nb, nc, nd = plan.na, plan.nb, plan.nc, plan.nd
@@ -393,11 +394,26 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
         ren = {h: f"r_{h}" for h in used}
         for op in ops:
             lines.append(f"{ind}    " + _op_line(op, ren))
-        for (lam, sig) in outs:
-            nm = kp2.s2[(lam, sig, e)]
-            lines.append(f"{ind}    sb[{plan.zslot(eidx[e], lam, sig)}u * S32 + li] = {ren.get(nm, nm)};")
+        vals = [ren.get(kp2.s2[(lam, sig, e)], kp2.s2[(lam, sig, e)]) for (lam, sig) in outs]
+        lines.extend(run_store(plan.zslot(eidx[e], 0, 0), vals, ind + "    "))
         lines.append(f"{ind}}}")
         lines.append(f"{ind}HGP_STAGE(li);")
+        return lines
+
+    def run_store(base, vals, ind):
+        """Store vals to the consecutive slots base, base+1, ...: slot-major,
+        one store per value, or (quartet-major, integrals out) through the
+        wave's LDS tile so that each quartet's run is written by consecutive
+        lanes (coalesced)."""
+        cnt = len(vals)
+        lines = [f"{ind}if (a.qmajor) {{"]
+        for c, v in enumerate(vals):
+            lines.append(f"{ind}    zt[threadIdx.x * {cnt} + {c}] = {v};")
+        lines.append(f"{ind}    hgp_store_runs<{cnt}>(zt, sb, i0, a.n, {plan.nslots}u, {base}u);")
+        lines.append(f"{ind}}} else {{")
+        for c, v in enumerate(vals):
+            lines.append(f"{ind}    sb[{base + c}u * S32 + li] = {v};")
+        lines.append(f"{ind}}}")
         return lines
 
     # ---------------------------------------------------------------- Phase 1 (+ fused ket stage)
@@ -417,12 +433,32 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
         pw("namespace {")
         pw("")
         npc = len(idxs)
+        zmax = max([plan.ncd] + [len(plan.chunks[ci].targets) for ci in idxs if plan.chunks[ci].kind == "tile"])
+        pw("// Quartet-major stores: a run of CNT consecutive slots of each of the wave's")
+        pw("// quartets, staged by every lane in zt[lane * CNT + c], written by consecutive")
+        pw("// lanes one quartet at a time.")
+        pw("template <int CNT>")
+        pw("__device__ __forceinline__ void hgp_store_runs(double *zt, double *sb, int64_t i0, int64_t n, uint32_t ns,")
+        pw("                                               uint32_t base)")
+        pw("{")
+        pw("    __syncthreads();")
+        pw("    for (int q = 0; q < 64 && i0 + q < n; ++q)")
+        pw("        for (int c = threadIdx.x; c < CNT; c += 64)")
+        pw("            sb[(uint64_t)(i0 + q) * ns + base + c] = zt[q * CNT + c];")
+        pw("    __syncthreads();")
+        pw("}")
+        pw("")
         pw(f"// item (block / {npc}) * {block} + thread, chunk = block % {npc}.")
         pw(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void p1_{tag}p{pi}(P1Args a)")
         pw("{")
+        pw(f"    __shared__ double zt[64 * {zmax}];")
         pw(f"    const int chunk = (int)(blockIdx.x % {npc});")
-        pw(f"    const int64_t i = (int64_t)(blockIdx.x / {npc}) * {block} + threadIdx.x;")
-        pw("    if (i >= a.n) return;")
+        pw(f"    const int64_t i0 = (int64_t)(blockIdx.x / {npc}) * 64;")
+        pw("    const int64_t iraw = i0 + threadIdx.x;")
+        pw("    // quartet-major: every lane stays for the wave's cooperative stores (lanes past")
+        pw("    // the end redo the last item and store nothing of their own)")
+        pw("    if (iraw >= a.n && !a.qmajor) return;")
+        pw("    const int64_t i = iraw < a.n ? iraw : a.n - 1;")
         pw("    const int bra = a.idx[i * a.istride], ket = a.idx[i * a.istride + 1];")
         pw("    const PairInfo pb = a.pairs[bra], pk = a.pairs[ket];")
         pw("    const PairGeo gb = a.geo[bra], gk = a.geo[ket];")
@@ -453,9 +489,9 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
                     po.extend(ket_stage_lines(e, lambda f, e=e: plan.hname(e, f), "        "))
             else:
                 e = ch.rows[0]
-                for t in ch.targets:
-                    f = g.nodes[t].key[1]
-                    pw(f"        sb[{plan.hslot(tile_index[e], fidx[f])}u * S32 + li] = h{tslot[t]};")
+                fs = [fidx[g.nodes[t].key[1]] for t in ch.targets]
+                assert fs == list(range(fs[0], fs[0] + len(fs))), "a tile is a contiguous run of ket components"
+                po.extend(run_store(plan.hslot(tile_index[e], fs[0]), [f"h{tslot[t]}" for t in ch.targets], "        "))
             pw("        break;")
             pw("    }")
         pw("    default:")
@@ -522,38 +558,69 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
         return lines
 
     # ---------------------------------------------------------------- kernel 2: integrals out, one wave per quartet
-    # Phase 1 wrote the quartet's values contiguously (quartet-major).  Lane j
-    # takes ket function j = (lam, sig): it reads (e|lam sig) for every e (the
-    # lanes read consecutive doubles), runs the bra HRR + T(la) T(lb), and
-    # writes the (mu nu|lam sig) values, which for a fixed (mu, nu) lie next
-    # to each other in the caller's block, so the stores are coalesced too.
+    # Phase 1 wrote the quartet's values contiguously (quartet-major).  First
+    # the lanes take the tiled rows, one each: ket HRR + T(lc) T(ld) from the
+    # row's raw accumulators into the LDS tile zt.  Then lane j takes ket
+    # function j = (lam, sig): it reads (e|lam sig) for every e (from zt for
+    # tiled rows, else from the buffer, where the lanes read consecutive
+    # doubles), runs the bra HRR + T(la) T(lb), and writes the (mu nu|lam sig)
+    # values, which for a fixed (mu, nu) lie next to each other in the
+    # caller's block, so the stores are coalesced too.
     diag_class = (la, lb) == (lc, ld)
     ncd = plan.ncd
     assert ncd <= 64, "one ket function per lane"
     NS = plan.nslots
     wops, wins, wouts = plan.wave_bra()
+    nt = len(plan.tile_rows)
     w(f"__global__ __launch_bounds__(64) void eri_{tag}(EriArgs a)")
     w("{")
+    if nt:
+        w(f"    __shared__ double zt[{nt * ncd}];")
     w("    const int64_t i = blockIdx.x;                 // quartet of the batch")
     w("    if (i >= a.ntask) return;")
     w("    const int j = threadIdx.x;")
     w("    const EriTask t = a.tasks[i];")
-    w("    const PairGeo gb = a.geo[t.bra];")
-    w("    const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz;")
-    w("    (void)ABx; (void)ABy; (void)ABz;")
     if eri_layout == "quartet":
         w(f"    const double *__restrict__ zq = a.scratch + (uint64_t)i * {NS}u;")
         w("    const uint32_t ZS = 1u;")
     else:
         w("    const double *__restrict__ zq = a.scratch + i;")
         w("    const uint32_t ZS = (uint32_t)a.stride;")
+    if nt:
+        tops, tins, touts = plan.wave_ket()
+        w("    {")
+        w("        const PairGeo gk = a.geo[t.ket];")
+        w("        const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
+        w("        (void)CDx; (void)CDy; (void)CDz;")
+        w(f"        for (int tr = j; tr < {nt}; tr += 64) {{   // tiled row tr")
+        w(f"            const double *__restrict__ hrow = zq + ({plan.hslot(0, 0)}u + tr * {len(F)}u) * ZS;")
+        tused = {n for op in tops for n in _names_in(op)} | set(touts.values())
+        for k, f in enumerate(F):
+            nm = tins[f]
+            if nm in tused:
+                w(f"            const double {nm} = hrow[{k}u * ZS];")
+        for op in tops:
+            w("            " + _op_line(op, {}))
+        for lam in range(nc):
+            for sig in range(nd):
+                w(f"            zt[tr * {ncd} + {lam * nd + sig}] = {touts[(lam, sig)]};")
+        w("        }")
+        w("    }")
+        w("    __syncthreads();")
+    w("    const PairGeo gb = a.geo[t.bra];")
+    w("    const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz;")
+    w("    (void)ABx; (void)ABy; (void)ABz;")
     w("    double dg = 0.0;")
     w(f"    if (j < {ncd}) {{")
     w(f"        const int lam = j / {nd}, sig = j - lam * {nd};")
     used = {n for op in wops for n in _names_in(op)} | set(wouts.values())
     for k, e in enumerate(E):
         nm = wins[e]
-        if nm in used:
+        if nm not in used:
+            continue
+        if e in tile_index:
+            w(f"        const double {nm} = zt[{tile_index[e] * ncd} + j];")
+        else:
             w(f"        const double {nm} = zq[({plan.zslot(k, 0, 0)}u + j) * ZS];")
     for op in wops:
         w("        " + _op_line(op, {}))
@@ -577,45 +644,6 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
     w("    (void)dg;")
     w("}")
     w("")
-    if plan.tile_rows:
-        # the ket stage of the tiled rows (integrals out), one lane per (quartet, tiled row)
-        tops, tins, touts = plan.wave_ket()
-        nt = len(plan.tile_rows)
-        w(f"__global__ __launch_bounds__(64) void erit_{tag}(EriArgs a)")
-        w("{")
-        w("    const int64_t item = (int64_t)blockIdx.x * 64 + threadIdx.x;")
-        w(f"    const int64_t i = item / {nt};")
-        w(f"    const int tr = (int)(item - i * {nt});")
-        w("    if (i >= a.ntask) return;")
-        if eri_layout == "quartet":
-            w(f"    double *__restrict__ zq = a.scratch + (uint64_t)i * {NS}u;")
-            w("    const uint32_t ZS = 1u;")
-        else:
-            w("    double *__restrict__ zq = a.scratch + i;")
-            w("    const uint32_t ZS = (uint32_t)a.stride;")
-        w("    const PairGeo gk = a.geo[a.tasks[i].ket];")
-        w("    const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
-        w("    (void)CDx; (void)CDy; (void)CDz;")
-        w("    int erow = 0;                                 // bra component of tiled row tr")
-        w("    switch (tr) {")
-        for ti, e in enumerate(plan.tile_rows):
-            w(f"    case {ti}: erow = {eidx[e]}; break;")
-        w("    default: break;")
-        w("    }")
-        w(f"    const double *__restrict__ hrow = zq + ({plan.hslot(0, 0)}u + tr * {len(F)}u) * ZS;")
-        w(f"    double *__restrict__ zrow = zq + erow * {ncd}u * ZS;")
-        tused = {n for op in tops for n in _names_in(op)} | set(touts.values())
-        for k, f in enumerate(F):
-            nm = tins[f]
-            if nm in tused:
-                w(f"    const double {nm} = hrow[{k}u * ZS];")
-        for op in tops:
-            w("    " + _op_line(op, {}))
-        for lam in range(nc):
-            for sig in range(nd):
-                w(f"    zrow[{lam * nd + sig}u * ZS] = {touts[(lam, sig)]};")
-        w("}")
-        w("")
     # ---------------------------------------------------------------- kernel 2: J/K (own translation unit)
     jo = []
     jw = jo.append
@@ -669,12 +697,7 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
     w("{")
     w(f"    if (a.ntask > 0) hipLaunchKernelGGL(eri_{tag}, dim3((unsigned)a.ntask), dim3(64), 0, s, a);")
     w("}")
-    if plan.tile_rows:
-        w(f"void launch_erit_{tag}(const EriArgs &a, hipStream_t s)")
-        w("{")
-        w(f"    const int64_t blocks = (a.ntask * {len(plan.tile_rows)} + 63) / 64;")
-        w(f"    if (blocks > 0) hipLaunchKernelGGL(erit_{tag}, dim3((unsigned)blocks), dim3(64), 0, s, a);")
-        w("}")
+
     w("")
     w("}  // namespace hgp")
     pl_max = max(c.peak_live for c in plan.chunks)
@@ -683,7 +706,7 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
                      reduce=reduce, loop=loop)
     meta.form = "row"
     meta.eri_wave = eri_layout == "quartet"        # Phase 1 writes quartet-major for integrals out
-    meta.eri_tiles = bool(plan.tile_rows)
+    meta.eri_tiles = False          # the tiled rows' ket stage runs inside the integrals-out kernel
     meta.parts = len(parts)
     meta.extra_sources = part_src
     return "\n".join(out) + "\n", meta

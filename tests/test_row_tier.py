@@ -202,8 +202,9 @@ def test_row_emitter_source():
     src, meta = emit_row.emit_class_row(3, 3, 3, 3, budget=200)   # many chunks: several Phase-1 parts
     assert meta.parts == -(-meta.chunks // emit_row.P1_PART_CHUNKS) > 1
     assert all(f"launch_p1_3333p{k}(a, s);" in src for k in range(meta.parts))
-    # integrals out: one wave per quartet, a tile kernel for the tiled rows
-    assert meta.eri_wave and meta.eri_tiles and "void erit_3333(EriArgs a)" in src and "if (j < 49)" in src
+    # integrals out: one wave per quartet; the tiled rows' ket stage runs in it, into LDS
+    assert meta.eri_wave and not meta.eri_tiles and "if (j < 49)" in src and "__shared__ double zt[" in src
     from paper_2605_10312_amd.gen import emit
     table = emit.emit_table([meta])
-    assert "launch_erit_3333}" in table and ", 1, launch_erit_3333}" in table
+    assert ", 1, nullptr}" in table
+    assert all("hgp_store_runs<" in meta.extra_sources[f"p{k}"] for k in range(meta.parts))
