@@ -160,14 +160,16 @@ def block_errors(bw, J, K):
 MICRO_N = 100_000
 
 
-def microbench_runs(steps, warmup, check=64, ls_list=((2, 2, 2, 2), (3, 3, 3, 3), (4, 4, 4, 4))):
+def microbench_runs(steps, warmup, check=64, ls_list=((2, 2, 2, 2), (3, 3, 3, 3), (4, 4, 4, 4)), precision="fp64"):
     """High-l class microbench: 1e5 independent normalised primitive quartets
     per class, (dd|dd), (ff|ff), (gg|gg), centres in a 6 A box, exponents
     log-uniform [0.1, 100]; inputs and outputs device-resident.  Per class:
     primitive-quartet spherical integrals per second, the generator's FLOP
     count per quartet against the FP64 VALU peak, and the error against the
     CPU oracle on `check` sampled quartets (max abs, RMS, max relative over
-    |I| > 1e-10, and the FP64 oracle's own error against long double)."""
+    |I| > 1e-10, and the FP64 oracle's own error against long double).
+    precision "mixed": the library's HGP_MIXED form (FP32 VRR and contraction
+    for the classes that have it; the row records which ran)."""
     import torch
     import oracle
     import paper_2605_10312_amd as hgp
@@ -182,13 +184,14 @@ def microbench_runs(steps, warmup, check=64, ls_list=((2, 2, 2, 2), (3, 3, 3, 3)
         et = torch.tensor(ex, device="cuda")
         n_sph = int(np.prod([2 * x + 1 for x in ls]))
         res = torch.empty((MICRO_N, n_sph), dtype=torch.float64, device="cuda")
+        prec = hgp.HGP_MIXED if precision == "mixed" else hgp.HGP_FP64
         for _ in range(warmup):
-            hgp.eri_prim_quartets(ls, ct, et, res)
+            hgp.eri_prim_quartets(ls, ct, et, res, precision=prec)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
         for _ in range(steps):
-            hgp.eri_prim_quartets(ls, ct, et, res)
+            hgp.eri_prim_quartets(ls, ct, et, res, precision=prec)
         ev1.record()
         torch.cuda.synchronize()
         dt = ev0.elapsed_time(ev1) * 1e-3 / steps
@@ -214,7 +217,8 @@ def microbench_runs(steps, warmup, check=64, ls_list=((2, 2, 2, 2), (3, 3, 3, 3)
         out.append({"class": f"({nm[:2]}|{nm[2:]})", "tag": tag, "quartets": MICRO_N, "ms_per_step": round(dt * 1e3, 4),
                     "eris_per_s": MICRO_N * n_sph / dt, "flop_per_quartet": flop,
                     "tflops": round(MICRO_N * flop / dt / 1e12, 3),
-                    "frac": round(MICRO_N * flop / dt / 1e12 / FP64_VALU_PEAK_TFLOPS, 4), "err": err})
+                    "frac": round(MICRO_N * flop / dt / 1e12 / FP64_VALU_PEAK_TFLOPS, 4), "err": err,
+                    "precision": precision, "fp32_form": bool(precision == "mixed" and hgp.class_has_fp32(ls))})
         del res, ct, et
         torch.cuda.empty_cache()
     return out
@@ -222,14 +226,16 @@ def microbench_runs(steps, warmup, check=64, ls_list=((2, 2, 2, 2), (3, 3, 3, 3)
 
 def microbench(args):
     """One JSON line per high-l class (see microbench_runs)."""
-    for r in microbench_runs(args.steps, args.warmup, check=0 if args.no_check else 64):
+    for r in microbench_runs(args.steps, args.warmup, check=0 if args.no_check else 64, precision=args.precision):
         l = int(r["tag"][0])
+        mixed = r["fp32_form"]
         line = {"metric": "primitive-quartet spherical ERIs/s (high-l class microbench)", "value": r["eris_per_s"],
                 "unit": "ERIs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                 "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                "dtype": "f64", "data": "synthetic",
+                "dtype": "f32/f64 mixed" if mixed else "f64", "data": "synthetic",
                 "config": {"workload": f"microbench_{r['tag']}: {MICRO_N} primitive quartets {r['class']}, 6 A box, "
-                                       "exponents log-uniform [0.1, 100], FP64",
+                                       "exponents log-uniform [0.1, 100], " +
+                                       ("FP32 VRR and contraction, FP64 Boys/HRR" if mixed else "FP64"),
                            "flop_per_quartet": r["flop_per_quartet"]},
                 "roofline": {"bound": "alu", "achieved": r["tflops"], "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": r["frac"], "traffic": None},

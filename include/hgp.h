@@ -67,7 +67,7 @@ typedef struct hgp_plan hgp_plan;    /* pair data, Schwarz factors and screened 
 
 #define HGP_NORMALIZE 1           /* hgp_basis_create: normalise the raw contraction coefficients */
 #define HGP_FP64 0
-#define HGP_MIXED 1               /* FP32 VRR/HRR for quartets with a small Schwarz bound (see hgp_plan_create_mixed) */
+#define HGP_MIXED 1               /* FP32 VRR and primitive contraction where a class has that form; Boys, HRR, J/K in FP64 */
 #define HGP_MIXED_THETA_DEFAULT 1e-10
 
 /* Library version and the highest l built into this library's class kernels. */
@@ -118,11 +118,14 @@ hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t preci
 /*
  * hgp_plan_create_mixed -- a plan whose register-tier classes evaluate the
  * quartets with schwarz_tau <= Q_ab Q_cd < theta with the VRR and the
- * contraction over primitives in FP32.  The pair quantities, the Boys
- * function, the horizontal recurrence and transforms (which cancel between
- * large intermediates) and the J/K digestion stay FP64.  Larger-bound
- * quartets and the staged, wave-LDS and HBM-scratch classes run wholly in
- * FP64.  theta <= schwarz_tau gives an FP64 plan.  The deviation from the
+ * contraction over primitives in FP32 (the reduced-precision option of
+ * Sec. III, applied below a Schwarz threshold).  The pair quantities, the
+ * Boys function, the horizontal recurrence and transforms (which cancel
+ * between large intermediates) and the J/K digestion stay FP64.
+ * Larger-bound quartets and the staged, wave-LDS and HBM-scratch classes run
+ * wholly in FP64: for the staged row-form classes the HRR's cancellation
+ * lifts the FP32 rounding of the VRR values beyond what the Schwarz bound
+ * controls.  theta <= schwarz_tau gives an FP64 plan.  The deviation from the
  * FP64 result grows roughly in proportion to theta and depends on the basis
  * (tight, high-l primitives raise it): 1e-8 keeps it near 3e-10 on a
  * 3s2p1d molecule but gives ~3e-8 on small 5s4p3d2f1g molecules, so the
@@ -233,11 +236,22 @@ hgp_status hgp_batch_run(hgp_batch *b, void *hip_stream);
 hgp_status hgp_batch_destroy(hgp_batch *b);
 
 /*
- * hgp_eri_shell_quartets -- integrals out, any shell order.
- *   quartets[4*nq]  shell indices (i, j, k, l) per quartet          (host)
- *   offsets[nq]     element offset of each block in out             (host)
+ * hgp_eri_shell_quartets -- integrals out, any shell order: the contracted
+ * spherical integrals (ij|kl) of the basis's shells (Sec. II-A, the
+ * definition of the ERI and of contracted shells).
+ *   quartets[4*nq]  shell indices (i, j, k, l) per quartet          (device)
+ *   offsets[nq]     element offset of each block in out             (device)
  *   out             blocks [n_i][n_j][n_k][n_l] row-major at out + offsets[q] (device)
- * Waits for the stream before returning (temporary device buffers are freed).
+ * The quartets are classified on the device (class and canonical order per
+ * quartet); the call then waits once for hip_stream, to read the per-class
+ * counts that size the class launches, enqueues the pair precompute and the
+ * class kernels, and returns.  out is complete when hip_stream reaches the
+ * end of that work; quartets and offsets must stay valid until then.
+ * Temporary buffers are taken from and returned to the device's default
+ * memory pool on hip_stream.  Blocks must not overlap (each is written, not
+ * accumulated).  Errors: HGP_E_INVALID for NULL pointers, nq < 0 or beyond
+ * 2^28, a shell index out of range or a negative offset (nothing written);
+ * HGP_E_OOM if the pool cannot supply the buffers.
  */
 hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartets, const int64_t *offsets,
                                   double *out, void *hip_stream);
@@ -248,12 +262,32 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
  *   centers[12*n]  A, B, C, D per quartet, bohr                      (device)
  *   exps[4*n]      a, b, c, d per quartet                            (device)
  *   out[n * nsph(la) nsph(lb) nsph(lc) nsph(ld)]  spherical blocks   (device)
+ *   precision      HGP_FP64, or HGP_MIXED: the VRR and the contraction in
+ *                  FP32 for the classes that have that form (hgp_class_form;
+ *                  register tier and the staged row form), with the pair
+ *                  quantities, Boys function, HRR and transforms in FP64;
+ *                  other classes wholly FP64.  The FP32 error is the FP64
+ *                  path's own rounding error scaled by about 2^29 (the ratio
+ *                  of the unit roundoffs): about 1e-6 of the largest integral
+ *                  for low-l register classes, 1e-4 for (dd|dd), and for
+ *                  high-l classes with distant centres (HRR cancellation)
+ *                  more than the integrals; see hgp_plan_create_mixed for the
+ *                  screened form used in J/K builds.
  * Stream-ordered; returns after enqueueing.  Its temporary buffers come from
  * the device's default memory pool, whose release threshold the library
  * raises on the first call (freed blocks stay in the pool for the next call).
  */
 hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64_t n, const double *centers,
                                  const double *exps, double *out, int32_t precision, void *hip_stream);
+
+/*
+ * hgp_class_form -- how this library evaluates class (la lb|lc ld) (any
+ * order of the four): *tier 0 register, 1 staged, 2 HBM-scratch op tables,
+ * 3 wave-LDS op tables; *has_fp32 1 if the class has the FP32
+ * VRR-and-contraction form that HGP_MIXED uses.  Either pointer may be NULL.
+ * Errors: HGP_E_INVALID for negative l, HGP_E_UNSUPPORTED_L beyond l = 4.
+ */
+hgp_status hgp_class_form(int32_t la, int32_t lb, int32_t lc, int32_t ld, int32_t *tier, int32_t *has_fp32);
 
 /*
  * hgp_eri_prim_quartets_noalloc -- hgp_eri_prim_quartets for callers that

@@ -54,6 +54,7 @@ SIGNATURES = {
     "hgp_eri_prim_quartets": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i64, _vp, _vp, _vp, _i32, _vp]),
     "hgp_eri_prim_quartets_noalloc": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i64, _vp, _vp, _vp, _i32, _vp]),
     "hgp_eri_prim_quartets_noalloc_max": (_i64, [_i32, _i32, _i32, _i32]),
+    "hgp_class_form": (ctypes.c_int, [_i32, _i32, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "hgp_last_error": (ctypes.c_char_p, []),
 }
 
@@ -248,13 +249,29 @@ class Plan:
 
 
 def eri_shell_quartets(basis: Basis, quartets, offsets, out, stream=None):
-    """Spherical blocks of the listed shell quartets into device tensor `out`."""
+    """Spherical blocks of the listed shell quartets into device tensor `out`.
+    quartets [nq, 4] (int32) and offsets [nq] (int64, elements) are device
+    tensors, or host arrays that are copied to the device first."""
     import torch
-    q = _host(quartets, np.int32).reshape(-1, 4)
-    off = _host(offsets, np.int64).reshape(-1)
-    _check(lib().hgp_eri_shell_quartets(basis.handle, int(q.shape[0]), q.ctypes.data_as(ctypes.c_void_p),
-                                        off.ctypes.data_as(ctypes.c_void_p), _dptr(out, torch.float64),
-                                        ctypes.c_void_p(_stream_ptr(stream))))
+    made = []
+
+    def dev(a, np_dt, t_dt):
+        if isinstance(a, torch.Tensor) and a.is_cuda:
+            if a.dtype != t_dt:
+                raise ValueError(f"expected dtype {t_dt}, got {a.dtype}")
+            return a.contiguous()
+        t = torch.from_numpy(_host(a, np_dt)).to("cuda")      # a blocking copy
+        made.append(t)
+        return t
+    q = dev(quartets, np.int32, torch.int32).reshape(-1, 4)
+    off = dev(offsets, np.int64, torch.int64).reshape(-1)
+    if off.shape[0] != q.shape[0]:
+        raise ValueError("one offset per quartet")
+    sp = _stream_ptr(stream)
+    _check(lib().hgp_eri_shell_quartets(basis.handle, int(q.shape[0]), _dptr(q), _dptr(off), _dptr(out, torch.float64),
+                                        ctypes.c_void_p(sp)))
+    if made and sp != torch.cuda.current_stream().cuda_stream:
+        torch.cuda.synchronize()     # the copies are freed on return: let the other stream finish reading them
 
 
 class Batch:
@@ -288,13 +305,15 @@ class Batch:
             pass
 
 
-def eri_prim_quartets(ls, centers, exps, out, stream=None):
+def eri_prim_quartets(ls, centers, exps, out, stream=None, precision=None):
     """n normalised primitive quartets of class ls: device centres [n,4,3],
-    exponents [n,4] and output [n, nsph...]."""
+    exponents [n,4] and output [n, nsph...].  precision HGP_FP64 (default)
+    or HGP_MIXED."""
     import torch
     n = int(centers.shape[0])
+    prec = HGP_FP64 if precision is None else int(precision)
     _check(lib().hgp_eri_prim_quartets(*[int(x) for x in ls], n, _dptr(centers, torch.float64),
-                                       _dptr(exps, torch.float64), _dptr(out, torch.float64), HGP_FP64,
+                                       _dptr(exps, torch.float64), _dptr(out, torch.float64), prec,
                                        ctypes.c_void_p(_stream_ptr(stream))))
 
 
@@ -306,6 +325,17 @@ def eri_prim_quartets_noalloc(ls, centers, exps, out, stream=None):
     _check(lib().hgp_eri_prim_quartets_noalloc(*[int(x) for x in ls], n, _dptr(centers, torch.float64),
                                                _dptr(exps, torch.float64), _dptr(out, torch.float64), HGP_FP64,
                                                ctypes.c_void_p(_stream_ptr(stream))))
+
+
+def class_form(ls):
+    """(tier, has_fp32) of class ls in this library."""
+    tier, f32 = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().hgp_class_form(*[int(x) for x in ls], ctypes.byref(tier), ctypes.byref(f32)))
+    return int(tier.value), bool(f32.value)
+
+
+def class_has_fp32(ls) -> bool:
+    return class_form(ls)[1]
 
 
 def eri_prim_quartets_noalloc_max(ls) -> int:

@@ -17,6 +17,17 @@ void launch_screen_count(int b0, int nb, int sym, const double *Q, double tau, d
 void launch_screen_write(int b0, int nb, int sym, const double *Q, double tau, double hi, const int *psys,
                          const int *kbeg, const int *kcnt, const int64_t *offsets, int2 *out, hipStream_t s);
 void launch_scan(int64_t *v, int n, int64_t *total, hipStream_t s);
+// class of each (la, lb, lc, ld) in canonical order, index ((la*5 + lb)*5 + lc)*5 + ld, -1 if not built;
+// passed by value to the classify kernel
+struct ClassOf {
+    int16_t c[625];
+};
+void launch_sq_classify(int64_t nq, const int32_t *quartets, const int64_t *offsets, int nshell, const int *l,
+                        const int *nprim, const ClassOf &class_of, int32_t *code, int64_t *primcnt,
+                        unsigned long long *counts, unsigned long long *err, hipStream_t s);
+void launch_sq_scatter(int64_t nq, const int32_t *quartets, const int64_t *offsets, const int *l, const int *nprim,
+                       const int *foff, const int32_t *code, const int64_t *prim_off, const int64_t *class_base,
+                       unsigned long long *cursor, PairInfo *pairs, EriTask *tasks, hipStream_t s);
 void launch_store_q(int npair, const double *qv, PairGeo *geo, double *Q, hipStream_t s);
 void launch_fill_zero(double *x, int64_t n, hipStream_t s);
 void launch_symmetrize(const double *acc, int64_t astride, double *out, int n, hipStream_t s);

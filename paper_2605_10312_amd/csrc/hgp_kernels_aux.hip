@@ -201,6 +201,98 @@ __global__ void screen_count_kernel(int b0, int nb, int sym, const double *Q, do
 }
 
 // exclusive scan of n counts in place (single block), total into *total
+// ---------------------------------------------------------------------------
+// Shell quartets given on the device (integrals out, any shell order).
+// Classify: one thread per quartet validates its shells and offset, puts the
+// four shells in the canonical order of the class kernels (the larger l
+// first within each pair, then the pair of higher pair class as bra), looks
+// up the class and counts it.  code = class << 8 | pos[0] | pos[1] << 2 |
+// pos[2] << 4 | pos[3] << 6, pos[r] = requested position of canonical role r.
+// ---------------------------------------------------------------------------
+__device__ inline int dev_pair_class(int la, int lb) { return la * (la + 1) / 2 + lb; }
+
+__global__ void sq_classify_kernel(int64_t nq, const int32_t *quartets, const int64_t *offsets, int nshell,
+                                   const int *l, const int *nprim, ClassOf class_of, int32_t *code,
+                                   int64_t *primcnt, unsigned long long *counts, unsigned long long *err)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    int sh[4];
+    bool bad = offsets[q] < 0;
+    for (int r = 0; r < 4; ++r) {
+        sh[r] = quartets[4 * q + r];
+        bad = bad || sh[r] < 0 || sh[r] >= nshell;
+    }
+    if (bad) {
+        atomicOr(err, 1ull);
+        code[q] = -1;
+        primcnt[q] = 0;
+        return;
+    }
+    int L[4];
+    for (int r = 0; r < 4; ++r) L[r] = l[sh[r]];
+    int pos[4] = {0, 1, 2, 3};
+    if (L[0] < L[1]) { pos[0] = 1; pos[1] = 0; }
+    if (L[2] < L[3]) { pos[2] = 3; pos[3] = 2; }
+    if (dev_pair_class(L[pos[0]], L[pos[1]]) < dev_pair_class(L[pos[2]], L[pos[3]])) {
+        int t = pos[0]; pos[0] = pos[2]; pos[2] = t;
+        t = pos[1]; pos[1] = pos[3]; pos[3] = t;
+    }
+    const int ci = class_of.c[((L[pos[0]] * 5 + L[pos[1]]) * 5 + L[pos[2]]) * 5 + L[pos[3]]];
+    if (ci < 0) {
+        atomicOr(err, 2ull);
+        code[q] = -1;
+        primcnt[q] = 0;
+        return;
+    }
+    atomicAdd(&counts[ci], 1ull);
+    code[q] = ci << 8 | pos[0] | pos[1] << 2 | pos[2] << 4 | pos[3] << 6;
+    primcnt[q] = (int64_t)nprim[sh[0]] * nprim[sh[1]] + (int64_t)nprim[sh[2]] * nprim[sh[3]];
+}
+
+// Scatter: the two pair records of quartet q (2q bra, 2q + 1 ket, primitive
+// records from prim_off[q], an exclusive scan of the classify counts) and its
+// task, placed in its class's range (class_base, an exclusive scan of the
+// class counts) at a slot taken from that class's cursor.
+__global__ void sq_scatter_kernel(int64_t nq, const int32_t *quartets, const int64_t *offsets, const int *l,
+                                  const int *nprim, const int *foff, const int32_t *code, const int64_t *prim_off,
+                                  const int64_t *class_base, unsigned long long *cursor, PairInfo *pairs,
+                                  EriTask *tasks)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const int32_t c = code[q];
+    const int ci = c >> 8;
+    int sh[4], pos[4], n[4], stride[4];
+    for (int r = 0; r < 4; ++r) {
+        sh[r] = quartets[4 * q + r];
+        pos[r] = (c >> (2 * r)) & 3;
+        n[r] = 2 * l[sh[r]] + 1;
+    }
+    stride[3] = 1; stride[2] = n[3]; stride[1] = n[2] * n[3]; stride[0] = n[1] * n[2] * n[3];
+    int64_t po = prim_off[q];
+    for (int side = 0; side < 2; ++side) {
+        PairInfo pi;
+        pi.sh_a = sh[pos[2 * side]];
+        pi.sh_b = sh[pos[2 * side + 1]];
+        pi.prim_off = (int32_t)po;
+        pi.nprim = nprim[pi.sh_a] * nprim[pi.sh_b];
+        pi.fa = foff[pi.sh_a];
+        pi.fb = foff[pi.sh_b];
+        pi.same = pi.sh_a == pi.sh_b;
+        pi.cls = dev_pair_class(l[pi.sh_a], l[pi.sh_b]);
+        po += pi.nprim;
+        pairs[2 * q + side] = pi;
+    }
+    const int64_t slot = class_base[ci] + (int64_t)atomicAdd(&cursor[ci], 1ull);
+    EriTask t;
+    t.bra = (int32_t)(2 * q);
+    t.ket = (int32_t)(2 * q + 1);
+    t.off = offsets[q];
+    t.s0 = stride[pos[0]]; t.s1 = stride[pos[1]]; t.s2 = stride[pos[2]]; t.s3 = stride[pos[3]];
+    tasks[slot] = t;
+}
+
 __global__ void scan_kernel(int64_t *v, int n, int64_t *total)
 {
     __shared__ int64_t buf[1024];
@@ -346,6 +438,22 @@ void launch_screen_write(int b0, int nb, int sym, const double *Q, double tau, d
 void launch_scan(int64_t *v, int n, int64_t *total, hipStream_t s)
 {
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, v, n, total);
+}
+void launch_sq_classify(int64_t nq, const int32_t *quartets, const int64_t *offsets, int nshell, const int *l,
+                        const int *nprim, const ClassOf &class_of, int32_t *code, int64_t *primcnt,
+                        unsigned long long *counts, unsigned long long *err, hipStream_t s)
+{
+    if (nq > 0)
+        hipLaunchKernelGGL(sq_classify_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, quartets,
+                           offsets, nshell, l, nprim, class_of, code, primcnt, counts, err);
+}
+void launch_sq_scatter(int64_t nq, const int32_t *quartets, const int64_t *offsets, const int *l, const int *nprim,
+                       const int *foff, const int32_t *code, const int64_t *prim_off, const int64_t *class_base,
+                       unsigned long long *cursor, PairInfo *pairs, EriTask *tasks, hipStream_t s)
+{
+    if (nq > 0)
+        hipLaunchKernelGGL(sq_scatter_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, quartets,
+                           offsets, l, nprim, foff, code, prim_off, class_base, cursor, pairs, tasks);
 }
 void launch_store_q(int npair, const double *qv, PairGeo *geo, double *Q, hipStream_t s)
 {

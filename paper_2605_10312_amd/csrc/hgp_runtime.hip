@@ -77,6 +77,28 @@ hgp_status boys_table(int dev, const double **out)
     return HGP_OK;
 }
 
+// The stream-ordered buffers of hgp_eri_prim_quartets (up to several GB for
+// high-l classes) come from the device's default memory pool.  With the
+// pool's default release threshold of zero every synchronisation hands that
+// memory back to the driver and the next call maps it again, which cost more
+// than the kernels themselves; the library raises the threshold once per
+// device so freed blocks stay in the pool for reuse.
+bool g_pool_kept[64] = {};
+
+hgp_status keep_pool(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (dev < 0 || dev >= 64) return fail(HGP_E_DEVICE, "device index out of range");
+    if (!g_pool_kept[dev]) {
+        hipMemPool_t pool = nullptr;
+        HGP_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+        uint64_t thr = UINT64_MAX;
+        HGP_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+        g_pool_kept[dev] = true;
+    }
+    return HGP_OK;
+}
+
 int class_index(int la, int lb, int lc, int ld)
 {
     for (int c = 0; c < g_num_classes; ++c) {
@@ -124,21 +146,24 @@ hgp_status prepare_class(const ClassKernels &k)
 
 // Integrals-out work of one class: register and wave-LDS tiers in launches of
 // at most 2^20 blocks; staged tier in batches (Phase 1 then Phase 2);
-// HBM-scratch tier in batches of one kernel each.
-void run_eri_class(const ClassKernels &k, EriArgs a, int64_t scratch_doubles, hipStream_t s)
+// HBM-scratch tier in batches of one kernel each.  f32: the class's FP32
+// VRR-and-contraction kernels where it has them (register tier, row form).
+void run_eri_class(const ClassKernels &k, EriArgs a, int64_t scratch_doubles, hipStream_t s, bool f32 = false)
 {
     const int64_t ntask = a.ntask;
     if (k.tier == 0 || k.tier == 3) {
+        const launch_eri_fn run = f32 && k.eri32 ? k.eri32 : k.eri;
         const int64_t chunk = (int64_t)k.block << 20;
         for (int64_t q0 = 0; q0 < ntask; q0 += chunk) {
             EriArgs b = a;
             b.tasks = a.tasks + q0;
             b.ntask = std::min(chunk, ntask - q0);
             if (a.mode == 1) b.out = a.out + q0;
-            k.eri(b, s);
+            run(b, s);
         }
         return;
     }
+    const launch_p1_fn p1 = f32 && k.p1_32 ? k.p1_32 : k.p1;
     const int64_t B = staged_batch(k, scratch_doubles);
     for (int64_t q0 = 0; q0 < ntask; q0 += B) {
         const int64_t nb = std::min(B, ntask - q0);
@@ -147,7 +172,7 @@ void run_eri_class(const ClassKernels &k, EriArgs a, int64_t scratch_doubles, hi
             // quartet over a quartet-major buffer
             P1Args pa{(const int32_t *)(a.tasks + q0), (int64_t)(sizeof(EriTask) / sizeof(int32_t)), nb, a.pairs,
                       a.geo, a.prims, a.boys, a.scratch, B, k.eri_wave};
-            k.p1(pa, s);
+            p1(pa, s);
         }
         EriArgs b = a;
         b.tasks = a.tasks + q0;
@@ -193,13 +218,13 @@ struct hgp_basis {
     int nshell = 0, nbf = 0, lmax = 0;
     std::vector<int32_t> l, nprim, poff, foff;
     std::vector<double> cen, exps, coefs;
-    int *d_l = nullptr, *d_nprim = nullptr, *d_poff = nullptr;
+    int *d_l = nullptr, *d_nprim = nullptr, *d_poff = nullptr, *d_foff = nullptr;
     double *d_cen = nullptr, *d_exps = nullptr, *d_coefs = nullptr, *d_ncoef = nullptr;
 };
 
 struct ClassList {
     int cls;          // index into g_class_table
-    int bits = 64;    // 64: FP64 kernel; 32: VRR/HRR in FP32 (mixed plans, Q_ab Q_cd below theta)
+    int bits = 64;    // 64: FP64 kernel; 32: VRR and contraction in FP32 (mixed plans, Q_ab Q_cd below theta)
     int64_t nq = 0;   // unique quartets kept
     int64_t nprimq = 0;
     int2 *d_q = nullptr;
@@ -289,7 +314,7 @@ const char *hgp_last_error(void) { return g_err.c_str(); }
 hgp_status hgp_basis_destroy(hgp_basis *b)
 {
     if (!b) return HGP_OK;
-    hipFree(b->d_l); hipFree(b->d_nprim); hipFree(b->d_poff);
+    hipFree(b->d_l); hipFree(b->d_nprim); hipFree(b->d_poff); hipFree(b->d_foff);
     hipFree(b->d_cen); hipFree(b->d_exps); hipFree(b->d_coefs); hipFree(b->d_ncoef);
     delete b;
     return HGP_OK;
@@ -338,6 +363,7 @@ hgp_status hgp_basis_create(int32_t nshell, const int32_t *l, const int32_t *npr
     }
     hgp_status st;
     if ((st = upload(&b->d_l, b->l)) || (st = upload(&b->d_nprim, b->nprim)) || (st = upload(&b->d_poff, b->poff)) ||
+        (st = upload(&b->d_foff, b->foff)) ||
         (st = upload(&b->d_cen, b->cen)) || (st = upload(&b->d_exps, b->exps)) || (st = upload(&b->d_coefs, b->coefs)) ||
         (st = dalloc(&b->d_ncoef, (size_t)std::max(np, 1)))) {
         hgp_basis_destroy(b);
@@ -693,8 +719,13 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
             const int sym = (bc == kc);
             const int b0 = p->pc_begin[bc];
             const double t = tau > 0 ? tau : -1.0;
-            // bands of Q_ab Q_cd: [t, theta) in FP32 where the class has an FP32
-            // kernel and the plan is mixed, the rest in FP64
+            // bands of Q_ab Q_cd: [t, theta) in FP32 where the class has a
+            // register-tier FP32 kernel and the plan is mixed, the rest in FP64.
+            // The row-form classes' FP32 Phase 1 stays out of J/K plans: their
+            // HRR cancels between intermediates far larger than the integrals,
+            // which lifts the FP32 rounding of the VRR values (per primitive
+            // quartet about 1e-4 of the block's largest integral for (dd|dd),
+            // more than the integrals themselves for (ff|ff))
             struct Band { double lo, hi; int bits; };
             std::vector<Band> bands;
             const double inf = std::numeric_limits<double>::infinity();
@@ -1122,84 +1153,100 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
     const double *boys = nullptr;
     hgp_status st = boys_table(b->device, &boys);
     if (st) return st;
-    std::vector<PairInfo> pairs((size_t)(2 * nq));
-    std::vector<std::vector<EriTask>> per(g_num_classes);
-    int prim_off = 0;
-    for (int64_t q = 0; q < nq; ++q) {
-        int sh[4];
-        for (int r = 0; r < 4; ++r) {
-            sh[r] = quartets[4 * q + r];
-            if (sh[r] < 0 || sh[r] >= b->nshell) return fail(HGP_E_INVALID, "shell index out of range");
-        }
-        if (offsets[q] < 0) return fail(HGP_E_INVALID, "negative offset");
-        int n[4], stride[4];
-        for (int r = 0; r < 4; ++r) n[r] = nsph(b->l[sh[r]]);
-        stride[3] = 1; stride[2] = n[3]; stride[1] = n[2] * n[3]; stride[0] = n[1] * n[2] * n[3];
-        int pos[4] = {0, 1, 2, 3};   // canonical role -> requested position
-        if (b->l[sh[0]] < b->l[sh[1]]) std::swap(pos[0], pos[1]);
-        if (b->l[sh[2]] < b->l[sh[3]]) std::swap(pos[2], pos[3]);
-        const int cb = pair_class_of(b->l[sh[pos[0]]], b->l[sh[pos[1]]]);
-        const int ck = pair_class_of(b->l[sh[pos[2]]], b->l[sh[pos[3]]]);
-        if (cb < ck) { std::swap(pos[0], pos[2]); std::swap(pos[1], pos[3]); }
-        int ls[4];
-        for (int r = 0; r < 4; ++r) ls[r] = b->l[sh[pos[r]]];
-        const int ci = class_index(ls[0], ls[1], ls[2], ls[3]);
-        if (ci < 0) return fail(HGP_E_UNSUPPORTED_L, "class kernel not built");
-        for (int side = 0; side < 2; ++side) {
-            PairInfo &pi = pairs[(size_t)(2 * q + side)];
-            pi.sh_a = sh[pos[2 * side]];
-            pi.sh_b = sh[pos[2 * side + 1]];
-            pi.prim_off = prim_off;
-            pi.nprim = b->nprim[pi.sh_a] * b->nprim[pi.sh_b];
-            pi.fa = b->foff[pi.sh_a]; pi.fb = b->foff[pi.sh_b];
-            pi.same = pi.sh_a == pi.sh_b;
-            pi.cls = pair_class_of(ls[2 * side], ls[2 * side + 1]);
-            prim_off += pi.nprim;
-        }
-        per[ci].push_back(EriTask{(int32_t)(2 * q), (int32_t)(2 * q + 1), offsets[q], stride[pos[0]], stride[pos[1]],
-                                  stride[pos[2]], stride[pos[3]]});
+    if ((st = keep_pool(b->device))) return st;
+    ClassOf cof;
+    for (int k = 0; k < 625; ++k) cof.c[k] = -1;
+    for (int c = 0; c < g_num_classes; ++c) {
+        const ClassKernels &k = g_class_table[c];
+        cof.c[((k.la * 5 + k.lb) * 5 + k.lc) * 5 + k.ld] = (int16_t)c;
     }
+    const int ncls = g_num_classes;
+    // stream-ordered temporaries; every exit below frees them on the stream
+    int32_t *d_code = nullptr;
+    int64_t *d_poff = nullptr, *d_ptotal = nullptr, *d_base = nullptr, *d_btotal = nullptr;
+    unsigned long long *d_counts = nullptr, *d_cursor = nullptr, *d_err = nullptr;
     PairInfo *d_pairs = nullptr;
     PairGeo *d_geo = nullptr;
     PrimPair *d_prims = nullptr;
     EriTask *d_tasks = nullptr;
     double *d_scr = nullptr;
-    int64_t sneed = 0;
-    for (int c = 0; c < g_num_classes; ++c) sneed = std::max(sneed, staged_need(g_class_table[c], (int64_t)per[c].size()));
-    std::vector<EriTask> all;
-    std::vector<std::pair<int, int64_t>> ranges;
-    for (int c = 0; c < g_num_classes; ++c)
-        if (!per[c].empty()) {
-            ranges.push_back({c, (int64_t)all.size()});
-            all.insert(all.end(), per[c].begin(), per[c].end());
-        }
-    auto cleanup = [&]() { hipFree(d_pairs); hipFree(d_geo); hipFree(d_prims); hipFree(d_tasks); hipFree(d_scr); };
-    if ((st = upload(&d_pairs, pairs)) || (st = dalloc(&d_geo, pairs.size())) || (st = dalloc(&d_prims, (size_t)prim_off)) ||
-        (st = upload(&d_tasks, all)) || (st = dalloc(&d_scr, (size_t)sneed))) {
-        cleanup();
-        return st;
+    std::vector<void *> held;
+    auto get = [&](void **p, size_t bytes) {
+        const hipError_t e = hipMallocAsync(p, bytes, s);
+        if (e == hipSuccess) held.push_back(*p);
+        return e;
+    };
+    auto release = [&]() {
+        for (void *p : held) hipFreeAsync(p, s);
+        held.clear();
+    };
+    const size_t nc8 = (size_t)ncls;
+    hipError_t e = get((void **)&d_code, sizeof(int32_t) * nq);
+    if (e == hipSuccess) e = get((void **)&d_poff, sizeof(int64_t) * nq);
+    if (e == hipSuccess) e = get((void **)&d_ptotal, sizeof(int64_t));
+    if (e == hipSuccess) e = get((void **)&d_base, sizeof(int64_t) * nc8);
+    if (e == hipSuccess) e = get((void **)&d_btotal, sizeof(int64_t));
+    // counts, cursors and the error word in one zeroed block
+    if (e == hipSuccess) e = get((void **)&d_counts, sizeof(unsigned long long) * (2 * nc8 + 1));
+    if (e != hipSuccess) {
+        release();
+        return fail(HGP_E_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
     }
-    launch_pairs((int)pairs.size(), d_pairs, b->d_cen, b->d_poff, b->d_exps, b->d_ncoef, d_geo, d_prims, s);
-    for (size_t r = 0; r < ranges.size(); ++r) {
-        const int c = ranges[r].first;
-        const int64_t begin = ranges[r].second;
-        const int64_t end = (r + 1 < ranges.size()) ? ranges[r + 1].second : (int64_t)all.size();
+    d_cursor = d_counts + nc8;
+    d_err = d_counts + 2 * nc8;
+    launch_fill_zero((double *)d_counts, (int64_t)(2 * nc8 + 1), s);      // all-zero bits
+    launch_sq_classify(nq, quartets, offsets, b->nshell, b->d_l, b->d_nprim, cof, d_code, d_poff, d_counts, d_err, s);
+    launch_scan(d_poff, (int)nq, d_ptotal, s);
+    HGP_HIP(hipMemcpyAsync(d_base, d_counts, sizeof(int64_t) * nc8, hipMemcpyDeviceToDevice, s));
+    launch_scan(d_base, ncls, d_btotal, s);
+    // the one wait: per-class counts, the error word and the primitive total size the launches
+    std::vector<unsigned long long> h((size_t)(nc8 + 1));
+    int64_t ptotal = 0;
+    e = hipMemcpyAsync(h.data(), d_counts, sizeof(unsigned long long) * nc8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h[nc8], d_err, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&ptotal, d_ptotal, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        release();
+        return fail(HGP_E_DEVICE, std::string("classifying the quartets: ") + hipGetErrorString(e));
+    }
+    if (h[nc8] & 1ull) { release(); return fail(HGP_E_INVALID, "shell index out of range or negative offset"); }
+    if (h[nc8] & 2ull) { release(); return fail(HGP_E_UNSUPPORTED_L, "class kernel not built"); }
+    if (ptotal > INT32_MAX) { release(); return fail(HGP_E_INVALID, "too many primitive pairs in one call"); }
+    int64_t sneed = 0;
+    for (int c = 0; c < ncls; ++c)
+        if (h[(size_t)c]) {
+            if ((st = prepare_class(g_class_table[c]))) { release(); return st; }
+            sneed = std::max(sneed, staged_need(g_class_table[c], (int64_t)h[(size_t)c]));
+        }
+    e = get((void **)&d_pairs, sizeof(PairInfo) * 2 * nq);
+    if (e == hipSuccess) e = get((void **)&d_geo, sizeof(PairGeo) * 2 * nq);
+    if (e == hipSuccess) e = get((void **)&d_prims, sizeof(PrimPair) * (size_t)std::max<int64_t>(ptotal, 1));
+    if (e == hipSuccess) e = get((void **)&d_tasks, sizeof(EriTask) * nq);
+    if (e == hipSuccess && sneed) e = get((void **)&d_scr, sizeof(double) * sneed);
+    if (e != hipSuccess) {
+        release();
+        return fail(HGP_E_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    }
+    launch_sq_scatter(nq, quartets, offsets, b->d_l, b->d_nprim, b->d_foff, d_code, d_poff, d_base, d_cursor, d_pairs,
+                      d_tasks, s);
+    launch_pairs((int)(2 * nq), d_pairs, b->d_cen, b->d_poff, b->d_exps, b->d_ncoef, d_geo, d_prims, s);
+    int64_t begin = 0;
+    for (int c = 0; c < ncls; ++c) {
+        const int64_t cnt = (int64_t)h[(size_t)c];
+        if (!cnt) continue;
         EriArgs a{};
         a.tasks = d_tasks + begin;
-        a.ntask = end - begin;
+        a.ntask = cnt;
         a.pairs = d_pairs; a.geo = d_geo; a.prims = d_prims; a.boys = boys;
         a.out = out;
         a.mode = 0;
         a.scratch = d_scr;
-        if ((st = prepare_class(g_class_table[c]))) {
-            cleanup();
-            return st;
-        }
         run_eri_class(g_class_table[c], a, sneed, s);
+        begin += cnt;
     }
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    cleanup();
+    e = hipGetLastError();
+    release();
     if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("integral kernels: ") + hipGetErrorString(e));
     return HGP_OK;
 }
@@ -1213,6 +1260,7 @@ struct PrimCall {
     int ci = -1;              // class table index
     int ls[4], pos[4], cs[4];
     int64_t blk = 0;          // integrals per quartet
+    bool f32 = false;         // HGP_MIXED: FP32 VRR and contraction where the class has that form
 };
 
 hgp_status prim_call_setup(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64_t n, const double *centers,
@@ -1223,7 +1271,8 @@ hgp_status prim_call_setup(int32_t la, int32_t lb, int32_t lc, int32_t ld, int64
         if (lin[r] < 0) return fail(HGP_E_INVALID, "negative l");
         if (lin[r] > 4) return fail(HGP_E_UNSUPPORTED_L, "l > 4");
     }
-    if (precision != HGP_FP64) return fail(HGP_E_INVALID, "only HGP_FP64 is supported");
+    if (precision != HGP_FP64 && precision != HGP_MIXED) return fail(HGP_E_INVALID, "precision must be HGP_FP64 or HGP_MIXED");
+    c->f32 = precision == HGP_MIXED;
     if (n < 0) return fail(HGP_E_INVALID, "n < 0");
     if (n > 0 && (!centers || !exps || !out)) return fail(HGP_E_INVALID, "NULL argument");
     if (n > (int64_t)1 << 30) return fail(HGP_E_INVALID, "n too large for one call");
@@ -1256,7 +1305,7 @@ void prim_call_run(const PrimCall &c, int64_t n, const double *centers, const do
     a.tasks = d_tasks; a.ntask = n; a.pairs = d_pairs; a.geo = d_geo; a.prims = d_prims; a.boys = boys;
     a.out = out; a.mode = 0;
     a.scratch = d_scr;
-    run_eri_class(g_class_table[c.ci], a, scr_doubles, s);
+    run_eri_class(g_class_table[c.ci], a, scr_doubles, s, c.f32);
 }
 
 // hgp_eri_prim_quartets_noalloc's buffer: file-scope device memory, one copy
@@ -1281,28 +1330,6 @@ hgp_status noalloc_scratch(int dev, unsigned char **out)
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
-
-// The stream-ordered buffers of hgp_eri_prim_quartets (up to several GB for
-// high-l classes) come from the device's default memory pool.  With the
-// pool's default release threshold of zero every synchronisation hands that
-// memory back to the driver and the next call maps it again, which cost more
-// than the kernels themselves; the library raises the threshold once per
-// device so freed blocks stay in the pool for reuse.
-bool g_pool_kept[64] = {};
-
-hgp_status keep_pool(int dev)
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (dev < 0 || dev >= 64) return fail(HGP_E_DEVICE, "device index out of range");
-    if (!g_pool_kept[dev]) {
-        hipMemPool_t pool = nullptr;
-        HGP_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
-        uint64_t thr = UINT64_MAX;
-        HGP_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
-        g_pool_kept[dev] = true;
-    }
-    return HGP_OK;
-}
 
 // Bytes of the fixed buffer that n quartets of class k take: pair and task
 // records, plus room for one 64-quartet batch of a staged class.
@@ -1357,6 +1384,17 @@ hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld,
     hipFreeAsync(d_prims, s);
     hipFreeAsync(d_tasks, s);
     if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("microbench launch: ") + hipGetErrorString(e));
+    return HGP_OK;
+}
+
+hgp_status hgp_class_form(int32_t la, int32_t lb, int32_t lc, int32_t ld, int32_t *tier, int32_t *has_fp32)
+{
+    PrimCall c;
+    double dummy = 0.0;
+    if (hgp_status st = prim_call_setup(la, lb, lc, ld, 0, &dummy, &dummy, &dummy, HGP_FP64, &c)) return st;
+    const ClassKernels &k = g_class_table[c.ci];
+    if (tier) *tier = k.tier;
+    if (has_fp32) *has_fp32 = (k.tier == 0 && k.eri32) || (k.tier == 1 && k.p1_32) ? 1 : 0;
     return HGP_OK;
 }
 

@@ -141,6 +141,8 @@ struct ClassKernels {
     int eri_wave;           // 1: row-form class whose integrals-out kernel runs one wave per quartet over a
                             // quartet-major buffer (Phase 1 with qmajor set)
     launch_eri_fn eri_tiles;  // row form, integrals out: ket stage of the tiled rows, before eri (or nullptr)
+    launch_p1_fn p1_32;     // row form: Phase 1 with the VRR and contraction in FP32 (mixed precision), or nullptr
+    launch_eri_fn eri32;    // register tier: integrals out with the VRR and contraction in FP32, or nullptr
 };
 
 }  // namespace hgp

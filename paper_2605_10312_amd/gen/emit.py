@@ -425,7 +425,26 @@ def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves
                                 "a.J", "a.K", digest, reduce))
         w("}")
         w("")
-    # ---------------------------------------------------------------- integrals-out kernel
+    # ---------------------------------------------------------------- integrals-out kernels
+    # eri_: FP64; eri32_ (mixed precision): the VRR and contraction in FP32
+    if mixed:
+        w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void eri32_{tag}(EriArgs a)")
+        w("{")
+        w(f"    const int64_t q = (int64_t)blockIdx.x * {block} + threadIdx.x;")
+        w("    if (q >= a.ntask) return;")
+        w("    const EriTask t = a.tasks[q];")
+        w("    const PairInfo pb = a.pairs[t.bra], pk = a.pairs[t.ket];")
+        w("    const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];")
+        w(f"    double I[{nout}];")
+        w(f"    quartet32_{tag}(pb, gb, pk, gk, a.prims, a.boys, I);")
+        w("    double *__restrict__ o = a.out + t.off;")
+        for mu in range(na):
+            for nu in range(nb):
+                for lam in range(nc):
+                    for sig in range(nd):
+                        w(f"    o[{mu} * t.s0 + {nu} * t.s1 + {lam} * t.s2 + {sig} * t.s3] = I[{idx(mu, nu, lam, sig)}];")
+        w("}")
+        w("")
     diag_class = (la, lb) == (lc, ld)
     w(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void eri_{tag}(EriArgs a)")
     w("{")
@@ -468,6 +487,10 @@ def emit_class(la, lb, lc, ld, rule="ket_zyx", block=256, schedulers=None, waves
         w("{")
         w(f"    hipLaunchKernelGGL(jk32_{tag}, dim3((unsigned)((a.nq + {block - 1}) / {block})), dim3({block}), 0, s, a);")
         w("}")
+        w(f"void launch_eri32_{tag}(const EriArgs &a, hipStream_t s)")
+        w("{")
+        w(f"    hipLaunchKernelGGL(eri32_{tag}, dim3((unsigned)((a.ntask + {block - 1}) / {block})), dim3({block}), 0, s, a);")
+        w("}")
     w("")
     w("}  // namespace hgp")
     meta = ClassMeta(ls, tag, 0, block, len(g.nodes), g.flops(), len(g.targets), pl, sched, p2.flops, nout, rule,
@@ -489,6 +512,10 @@ def emit_table(metas):
             out.append(f"void launch_jk32_{m.tag}(const JKArgs &, hipStream_t);")
         if getattr(m, "eri_tiles", False):
             out.append(f"void launch_erit_{m.tag}(const EriArgs &, hipStream_t);")
+        if getattr(m, "p1_32", False):
+            out.append(f"void launch_p1f_{m.tag}(const P1Args &, hipStream_t);")
+        if m.mixed and m.tier == 0:
+            out.append(f"void launch_eri32_{m.tag}(const EriArgs &, hipStream_t);")
     out.append("")
     out.append("extern const ClassKernels g_class_table[] = {")
     for m in metas:
@@ -499,7 +526,9 @@ def emit_table(metas):
         tiles = f"launch_erit_{m.tag}" if getattr(m, "eri_tiles", False) else "nullptr"
         out.append(f"    {{{la}, {lb}, {lc}, {ld}, {m.tier}, launch_jk_{m.tag}, launch_eri_{m.tag}, {p1}, {prep}, {jk32}, {m.block}, "
                    f"{m.vrr_flops}.0, {m.p2_flops}.0, {m.n_hrr}, {m.peak_live}, {m.scratch_slots}, {m.chunks}, "
-                   f"{m.max_batch}, {1 if getattr(m, 'eri_wave', False) else 0}, {tiles}}},")
+                   f"{m.max_batch}, {1 if getattr(m, 'eri_wave', False) else 0}, {tiles}, "
+                   f"{'launch_p1f_' + m.tag if getattr(m, 'p1_32', False) else 'nullptr'}, "
+                   f"{'launch_eri32_' + m.tag if m.mixed and m.tier == 0 else 'nullptr'}}},")
     out.append("};")
     out.append(f"extern const int g_num_classes = {len(metas)};")
     out.append("")

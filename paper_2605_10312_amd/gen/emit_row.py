@@ -311,12 +311,16 @@ def recompute_factor(plan):
     return tot / plan.g.flops()
 
 
-def _vrr_lines(g, order, tnames, ind):
+def _vrr_lines(g, order, tnames, ind, f32=False):
+    """Straight-line VRR of one chunk in `order`; the chunk's own targets
+    (tnames) are added to their accumulators.  f32: single precision, with the
+    coefficients' float copies (suffix f) and the base values Bf[m]."""
     lines = []
+    ty, fm, sfx, one = ("float", "fmaf", "f", "f") if f32 else ("double", "fma", "", "")
     for v in order:
         nd = g.nodes[v]
         if nd.kind == "base":
-            expr = f"base * F[{nd.key[2]}]"
+            expr = f"Bf[{nd.key[2]}]" if f32 else f"base * F[{nd.key[2]}]"
         else:
             p1, p2, p3, p4, p5 = nd.parents
             ax = XYZ[nd.axis]
@@ -324,17 +328,33 @@ def _vrr_lines(g, order, tnames, ind):
                 c1, c2, o2, rr = f"PA{ax}", f"WP{ax}", "o2z", "rz"
             else:
                 c1, c2, o2, rr = f"QC{ax}", f"WQ{ax}", "o2e", "re"
-            expr = f"fma({c1}, v{p1}, {c2} * v{p2})"
+            expr = f"{fm}({c1}{sfx}, v{p1}, {c2}{sfx} * v{p2})"
             if nd.k_same:
-                k = "" if nd.k_same == 1 else f"{nd.k_same}.0 * "
-                expr = f"fma({k}{o2}, fma(-{rr}, v{p4}, v{p3}), {expr})"
+                k = "" if nd.k_same == 1 else f"{nd.k_same}.0{one} * "
+                expr = f"{fm}({k}{o2}{sfx}, {fm}(-{rr}{sfx}, v{p4}, v{p3}), {expr})"
             if nd.k_cross:
-                k = "" if nd.k_cross == 1 else f"{nd.k_cross}.0 * "
-                expr = f"fma({k}o2ze, v{p5}, {expr})"
-        lines.append(f"{ind}const double v{v} = {expr};")
+                k = "" if nd.k_cross == 1 else f"{nd.k_cross}.0{one} * "
+                expr = f"{fm}({k}o2ze{sfx}, v{p5}, {expr})"
+        lines.append(f"{ind}const {ty} v{v} = {expr};")
         if v in tnames:
             lines.append(f"{ind}{tnames[v]} += v{v};")
     return lines
+
+
+def _f32_prelude(L, ind):
+    """Float copies of one primitive quartet's VRR coefficients and base values
+    (the pair quantities and the Boys function stay FP64)."""
+    return [
+        f"{ind}float Bf[{L + 1}];",
+        f"{ind}for (int m = 0; m <= {L}; ++m) Bf[m] = (float)(base * F[m]);",
+        f"{ind}const float PAxf = (float)PAx, PAyf = (float)PAy, PAzf = (float)PAz;",
+        f"{ind}const float QCxf = (float)QCx, QCyf = (float)QCy, QCzf = (float)QCz;",
+        f"{ind}const float WPxf = (float)WPx, WPyf = (float)WPy, WPzf = (float)WPz;",
+        f"{ind}const float WQxf = (float)WQx, WQyf = (float)WQy, WQzf = (float)WQz;",
+        f"{ind}const float o2zf = (float)o2z, o2ef = (float)o2e, o2zef = (float)o2ze, rzf = (float)rz, ref = (float)re;",
+        f"{ind}(void)PAxf; (void)PAyf; (void)PAzf; (void)QCxf; (void)QCyf; (void)QCzf; (void)WPxf; (void)WPyf;",
+        f"{ind}(void)WPzf; (void)WQxf; (void)WQyf; (void)WQzf; (void)o2zf; (void)o2ef; (void)o2zef; (void)rzf; (void)ref;",
+    ]
 
 
 def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", block=64, waves=0, reduce="segmented",
@@ -422,11 +442,14 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
     # part, and the parts compile in parallel.
     parts = split(nch, -(-nch // P1_PART_CHUNKS))
     part_src = {}
-    for pi, idxs in enumerate(parts):
+    for (prec, pfx, key), (pi, idxs) in [(x, y) for x in (("f64", "p1_", "p"), ("f32", "p1f_", "q"))
+                                         for y in enumerate(parts)]:
+        f32 = prec == "f32"
         po = []
         pw = po.append
         pw(f"// Generated: class ({la}{lb}|{lc}{ld}), row tier, Phase-1 part {pi} of {len(parts)} "
-           f"(chunks {idxs[0]}..{idxs[-1]} of {nch}).")
+           f"(chunks {idxs[0]}..{idxs[-1]} of {nch})" +
+           (", VRR and contraction in FP32 (pair quantities, Boys, ket stage in FP64)." if f32 else "."))
         pw('#include "hgp_device.h"')
         pw("")
         pw("namespace hgp {")
@@ -449,7 +472,7 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
         pw("}")
         pw("")
         pw(f"// item (block / {npc}) * {block} + thread, chunk = block % {npc}.")
-        pw(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void p1_{tag}p{pi}(P1Args a)")
+        pw(f"__global__ __launch_bounds__({block}){waves_attr(waves)} void {pfx}{tag}p{pi}(P1Args a)")
         pw("{")
         pw(f"    __shared__ double zt[64 * {zmax}];")
         pw(f"    const int chunk = (int)(blockIdx.x % {npc});")
@@ -477,11 +500,19 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
             pw(f"    case {lci}: {{   // chunk {ci}, {ch.kind}: rows {[eidx[e] for e in ch.rows]}, "
                f"{len(ch.targets)} accumulators, {len(ch.order)} VRR nodes, PeakLive {ch.peak_live}")
             names = [tnames[t] for t in ch.targets]
-            for k in range(0, len(names), 8):
-                pw("        double " + ", ".join(f"{h} = 0.0" for h in names[k:k + 8]) + ";")
+            acc = {t: (f"{tnames[t]}f" if f32 else tnames[t]) for t in ch.targets}
+            ty, zero = ("float", "0.0f") if f32 else ("double", "0.0")
+            anames = [acc[t] for t in ch.targets]
+            for k in range(0, len(anames), 8):
+                pw(f"        {ty} " + ", ".join(f"{h} = {zero}" for h in anames[k:k + 8]) + ";")
             po.extend(loop_prelude(Lc, "        ", loop))
-            po.extend(_vrr_lines(g, ch.order, tnames, "            "))
+            if f32:
+                po.extend(_f32_prelude(Lc, "            "))
+            po.extend(_vrr_lines(g, ch.order, acc, "            ", f32))
             po.extend(loop_close("        "))
+            if f32:
+                for k in range(0, len(names), 8):
+                    pw("        const double " + ", ".join(f"{h} = (double){h}f" for h in names[k:k + 8]) + ";")
             if ch.kind == "rows":
                 pw("        const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
                 pw("        (void)CDx; (void)CDy; (void)CDz;")
@@ -501,14 +532,14 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
         pw("")
         pw("}  // namespace")
         pw("")
-        pw(f"void launch_p1_{tag}p{pi}(const P1Args &a, hipStream_t s)")
+        pw(f"void launch_{pfx}{tag}p{pi}(const P1Args &a, hipStream_t s)")
         pw("{")
         pw(f"    const int64_t blocks = (a.n + {block - 1}) / {block};")
-        pw(f"    if (blocks > 0) hipLaunchKernelGGL(p1_{tag}p{pi}, dim3((unsigned)(blocks * {npc})), dim3({block}), 0, s, a);")
+        pw(f"    if (blocks > 0) hipLaunchKernelGGL({pfx}{tag}p{pi}, dim3((unsigned)(blocks * {npc})), dim3({block}), 0, s, a);")
         pw("}")
         pw("")
         pw("}  // namespace hgp")
-        part_src[f"p{pi}"] = "\n".join(po) + "\n"
+        part_src[f"{key}{pi}"] = "\n".join(po) + "\n"
 
     # ---------------------------------------------------------------- Phase 2 (bra half)
     def group_lines(ops, ins, outs, load, sink, ind):
@@ -686,13 +717,14 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
 
     w("}  // namespace")
     w("")
-    for pi in range(len(parts)):
-        w(f"void launch_p1_{tag}p{pi}(const P1Args &a, hipStream_t s);")
-    w(f"void launch_p1_{tag}(const P1Args &a, hipStream_t s)")
-    w("{")
-    for pi in range(len(parts)):
-        w(f"    launch_p1_{tag}p{pi}(a, s);")
-    w("}")
+    for pfx in ("p1_", "p1f_"):
+        for pi in range(len(parts)):
+            w(f"void launch_{pfx}{tag}p{pi}(const P1Args &a, hipStream_t s);")
+        w(f"void launch_{pfx}{tag}(const P1Args &a, hipStream_t s)")
+        w("{")
+        for pi in range(len(parts)):
+            w(f"    launch_{pfx}{tag}p{pi}(a, s);")
+        w("}")
     w(f"void launch_eri_{tag}(const EriArgs &a, hipStream_t s)")
     w("{")
     w(f"    if (a.ntask > 0) hipLaunchKernelGGL(eri_{tag}, dim3((unsigned)a.ntask), dim3(64), 0, s, a);")
@@ -705,6 +737,7 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
                      scratch_slots=plan.nslots, chunks=nch, recompute=rec, cap=budget, waves=waves, digest="",
                      reduce=reduce, loop=loop)
     meta.form = "row"
+    meta.p1_32 = True                # Phase 1 also in FP32 (launch_p1f_<class>) for mixed precision
     meta.eri_wave = eri_layout == "quartet"        # Phase 1 writes quartet-major for integrals out
     meta.eri_tiles = False          # the tiled rows' ket stage runs inside the integrals-out kernel
     meta.parts = len(parts)

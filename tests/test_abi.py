@@ -94,7 +94,7 @@ def test_noalloc_rejections_before_device_work():
     fake = ctypes.c_void_p(16)        # never dereferenced: every case fails validation first
     assert h.hgp_eri_prim_quartets_noalloc(5, 0, 0, 0, 1, fake, fake, fake, 0, None) == -2
     assert h.hgp_eri_prim_quartets_noalloc(0, 0, 0, 0, -1, fake, fake, fake, 0, None) == -1
-    assert h.hgp_eri_prim_quartets_noalloc(0, 0, 0, 0, 4, fake, fake, fake, 1, None) == -1
+    assert h.hgp_eri_prim_quartets_noalloc(0, 0, 0, 0, 4, fake, fake, fake, 2, None) == -1   # no such precision
     nmax = h.hgp_eri_prim_quartets_noalloc_max(0, 0, 0, 0)
     assert 100_000 <= nmax <= 1 << 20
     assert h.hgp_eri_prim_quartets_noalloc(0, 0, 0, 0, nmax + 1, fake, fake, fake, 0, None) == -1
@@ -102,3 +102,20 @@ def test_noalloc_rejections_before_device_work():
     assert h.hgp_eri_prim_quartets_noalloc_max(2, 2, 2, 2) > 0
     assert h.hgp_eri_prim_quartets_noalloc_max(5, 0, 0, 0) == -1
     assert h.hgp_eri_prim_quartets_noalloc(0, 0, 0, 0, 0, fake, fake, fake, 0, None) == 0
+
+
+def test_class_form_query():
+    """hgp_class_form reports each class's tier and FP32 form (host-only;
+    the four l in any order name the same class)."""
+    import paper_2605_10312_amd as hgp
+    assert hgp.class_form((0, 0, 0, 0)) == (0, True)           # register tier, FP32 form for mixed plans
+    assert hgp.class_form((1, 0, 0, 0)) == hgp.class_form((0, 0, 0, 1)) == hgp.class_form((0, 0, 1, 0))
+    tier, f32 = hgp.class_form((2, 2, 2, 2))
+    assert tier == 1 and f32                                    # row form: Phase 1 in FP32 for mixed
+    tier, f32 = hgp.class_form((4, 4, 4, 4))
+    assert tier in (2, 3) and not f32                           # op tables: FP64 only
+    h = hgp.lib()
+    t = ctypes.c_int32()
+    assert h.hgp_class_form(5, 0, 0, 0, ctypes.byref(t), None) == -2
+    assert h.hgp_class_form(-1, 0, 0, 0, None, None) == -1
+    assert h.hgp_class_form(1, 1, 0, 0, None, None) == 0

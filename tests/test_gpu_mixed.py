@@ -1,8 +1,9 @@
-"""Mixed precision (FP32 VRR/HRR for quartets whose Schwarz bound is below
-theta, FP64 Boys, pair quantities and J/K accumulation): J/K within the
-1e-9 bar of the oracle, the FP32 lists present where they should be, and
-the full-size workload against both the oracle's sampled blocks and the
-plan's own FP64 result."""
+"""Mixed precision (FP32 VRR and primitive contraction for quartets whose
+Schwarz bound is below theta; FP64 Boys, pair quantities, HRR, transforms and
+J/K accumulation): J/K within the 1e-9 bar of the oracle, the FP32 lists
+present where they should be, the full-size workload against both the
+oracle's sampled blocks and the plan's own FP64 result, and the integrals-out
+entry with HGP_MIXED against the oracle per class."""
 import numpy as np
 import pytest
 
@@ -98,3 +99,60 @@ def test_mixed_full_size(hgp, torch_cuda):
           f"max |dK| {max(r[3] for r in rows):.2e}, RMS {rms:.2e}")
     for pr, ls, ej, ek, eo in rows:
         assert ej <= JK_TOL and ek <= JK_TOL, (pr, ls, ej, ek)
+
+
+def test_mixed_plans_keep_row_form_classes_fp64(hgp, torch_cuda):
+    """A d-rich basis has (dd|dd)-type lists in the staged row form, which has
+    an FP32 Phase 1 for the integrals-out entry; a mixed J/K plan still runs
+    them in FP64 (their HRR cancellation lifts the FP32 error past what the
+    Schwarz bound controls) and stays within the bar."""
+    bw = workloads.random_small_basis(seed=66, natom=3, lmax=2, maxprim=3, box=4.0, exp_range=(0.2, 20.0))
+    D = workloads.psd_density(bw.nbf, 66)
+    Jr, Kr = oracle.jk(bw, D, tau=0.0)
+    J, K, cls = _jk(hgp, torch_cuda, bw, D, 0.0, 1e-6)
+    assert any(c["tier"] == 1 and hgp.class_has_fp32(c["ls"]) for c in cls)
+    assert all(c["tier"] == 0 for c in cls if c["bits"] == 32) and any(c["bits"] == 32 for c in cls)
+    ej, ek = np.abs(J - Jr).max(), np.abs(K - Kr).max()
+    print(f"|dJ| {ej:.2e} |dK| {ek:.2e}")
+    assert ej <= JK_TOL and ek <= JK_TOL
+
+
+# HGP_MIXED runs the same recurrences as the FP64 path with the VRR values
+# rounded to FP32: its error is the FP64 path's own rounding error scaled by
+# the ratio of the unit roundoffs, 2^-24 / 2^-53 = 2^29, whatever the
+# cancellation the class's HRR brings.  Both errors are taken against the
+# long-double oracle; the bar allows a factor 10 over that scaling, and the
+# FP64 error is floored at one FP64 rounding of the largest integral.
+EPS_RATIO = 2.0 ** 29
+
+
+@pytest.mark.parametrize("ls", [(0, 0, 0, 0), (1, 1, 1, 1), (2, 1, 1, 0), (2, 2, 1, 1), (2, 2, 2, 1), (2, 2, 2, 2),
+                                (3, 2, 1, 0), (3, 3, 3, 3), (4, 4, 4, 4)])
+def test_prim_quartets_mixed(hgp, torch_cuda, ls):
+    torch = torch_cuda
+    n = 200
+    cen, ex = workloads.prim_quartets(max(ls), n, seed=77 + sum(ls))
+    ct, et = torch.tensor(cen, device="cuda"), torch.tensor(ex, device="cuda")
+    nsph = int(np.prod([2 * x + 1 for x in ls]))
+    o64 = torch.empty((n, nsph), dtype=torch.float64, device="cuda")
+    o32 = torch.empty_like(o64)
+    hgp.eri_prim_quartets(ls, ct, et, o64, precision=hgp.HGP_FP64)
+    hgp.eri_prim_quartets(ls, ct, et, o32, precision=hgp.HGP_MIXED)
+    torch.cuda.synchronize()
+    g64, g32 = o64.cpu().numpy(), o32.cpu().numpy()
+    ref = oracle.eri_prim_quartets(ls, cen, ex).reshape(n, -1)
+    ref_ld = oracle.eri_prim_quartets(ls, cen, ex, precision="long double").reshape(n, -1)
+    scale = np.abs(ref_ld).max()
+    e_orc = np.abs(ref - ref_ld).max()
+    e64, e32 = np.abs(g64 - ref_ld).max(), np.abs(g32 - ref_ld).max()
+    rms = float(np.sqrt(np.mean((g32 - ref) ** 2)))
+    tier, f32 = hgp.class_form(ls)
+    print(f"{ls} tier {tier} fp32 form {f32}: scale {scale:.2e}, FP64 err {e64:.2e} (oracle {e_orc:.2e}), "
+          f"mixed err {e32:.2e} ({e32 / scale:.2e} of scale, {e32 / max(e64, 2.0 ** -53 * scale):.2e} x FP64), "
+          f"RMS vs oracle {rms:.2e}")
+    assert e64 <= 1e-12 * scale + 8 * e_orc
+    if f32:
+        assert e32 <= 10 * EPS_RATIO * max(e64, 2.0 ** -53 * scale)
+        assert e32 > e64                       # the FP32 form really ran
+    else:
+        assert np.array_equal(g32, g64)        # no FP32 form: the FP64 kernels, bit for bit

@@ -262,3 +262,48 @@ def test_basis_flags_given_coefficients(hgp, torch_cuda):
     de = np.abs(res[0][2] - res[1][2]).max()
     print(f"flags 0 vs HGP_NORMALIZE: |dJ| {dj:.2e} |dK| {dk:.2e} |dERI| {de:.2e}")
     assert dj <= 1e-12 and dk <= 1e-12 and de <= 1e-13
+
+
+def test_shell_quartets_device_arrays_stream_ordered(hgp, torch_cuda):
+    """hgp_eri_shell_quartets with quartets and offsets already on the device,
+    on a side stream, in mixed classes and shell orders (register, staged and
+    op-table classes in one call): every block equals the oracle's, the
+    blocks between the listed ones stay untouched, and a bad shell index is
+    rejected before anything is written."""
+    torch = torch_cuda
+    bw = workloads.random_small_basis(seed=88, natom=3, lmax=4, maxprim=2, box=3.0, exp_range=(0.3, 8.0))
+    rng = np.random.default_rng(88)
+    ns = bw.nshell
+    quartets = [tuple(int(x) for x in rng.integers(0, ns, 4)) for _ in range(300)]
+    quartets += [(0, 0, 0, 0), (ns - 1, 0, ns - 1, 0)]
+    sizes = [int(np.prod([2 * bw.l[s] + 1 for s in q])) for q in quartets]
+    gap = 3                                             # untouched guard entries between blocks
+    offs = np.concatenate([[0], np.cumsum(np.array(sizes) + gap)[:-1]]).astype(np.int64)
+    total = int(offs[-1] + sizes[-1] + gap)
+    b = hgp.Basis.from_workload(bw)
+    qd = torch.tensor(np.array(quartets, np.int32), device="cuda")
+    od = torch.tensor(offs, device="cuda")
+    out = torch.full((total,), -7.0, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    hgp.eri_shell_quartets(b, qd, od, out, stream=side)
+    side.synchronize()
+    o = out.cpu().numpy()
+    err = 0.0
+    mask = np.ones(total, bool)
+    for i, q in enumerate(quartets):
+        ref = oracle.eri_shell_quartet(bw, *q).ravel()
+        err = max(err, float(np.abs(o[offs[i]:offs[i] + sizes[i]] - ref).max()))
+        mask[offs[i]:offs[i] + sizes[i]] = False
+    print(f"{len(quartets)} quartets, lmax {int(bw.l.max())}: max |dERI| {err:.2e}")
+    assert err <= ERI_TOL
+    assert (o[mask] == -7.0).all()
+    # an out-of-range shell: HGP_E_INVALID, out unchanged
+    bad = qd.clone()
+    bad[5, 2] = ns
+    out2 = torch.full((total,), -7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(hgp.HGPError, match="out of range"):
+        hgp.eri_shell_quartets(b, bad, od, out2)
+    torch.cuda.synchronize()
+    assert (out2.cpu().numpy() == -7.0).all()
+    b.close()

@@ -196,9 +196,15 @@ def test_row_emitter_source():
     assert meta.tier == 1 and meta.form == "row" and meta.chunks >= 1
     assert "void eri_2221(EriArgs a)" in src and "void launch_p1_2221(" in src and "launch_eri_2221" in src
     assert "void jk_2221(JKArgs a)" in meta.extra_sources["jk"] and "launch_jk_2221" in meta.extra_sources["jk"]
-    parts = {k: v for k, v in meta.extra_sources.items() if k != "jk"}
+    parts = {k: v for k, v in meta.extra_sources.items() if k.startswith("p")}
     assert len(parts) == meta.parts and all(f"void p1_2221p{k}(P1Args a)" in parts[f"p{k}"] for k in range(meta.parts))
     assert sum(p.count("case ") for p in parts.values()) == meta.chunks
+    # the FP32 Phase 1 of mixed precision: the same chunks, float VRR and accumulators, FP64 ket stage
+    p32 = {k: v for k, v in meta.extra_sources.items() if k.startswith("q")}
+    assert meta.p1_32 and len(p32) == meta.parts
+    assert all(f"void p1f_2221p{k}(P1Args a)" in p32[f"q{k}"] and "float Bf[" in p32[f"q{k}"] and
+               "= (double)h0f" in p32[f"q{k}"] for k in range(meta.parts))
+    assert "void launch_p1f_2221(" in src
     src, meta = emit_row.emit_class_row(3, 3, 3, 3, budget=200)   # many chunks: several Phase-1 parts
     assert meta.parts == -(-meta.chunks // emit_row.P1_PART_CHUNKS) > 1
     assert all(f"launch_p1_3333p{k}(a, s);" in src for k in range(meta.parts))
@@ -206,5 +212,5 @@ def test_row_emitter_source():
     assert meta.eri_wave and not meta.eri_tiles and "if (j < 49)" in src and "__shared__ double zt[" in src
     from paper_2605_10312_amd.gen import emit
     table = emit.emit_table([meta])
-    assert ", 1, nullptr}" in table
+    assert ", 1, nullptr, launch_p1f_3333, nullptr}" in table
     assert all("hgp_store_runs<" in meta.extra_sources[f"p{k}"] for k in range(meta.parts))
