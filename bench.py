@@ -405,6 +405,54 @@ def serving(args):
     print(json.dumps(line), flush=True)
 
 
+def plan_sizes(args):
+    """Plans at the full sizes of the batched and served workloads' largest
+    members: a 60-atom 4s3p2d1f molecule with U{1..8} primitives per shell
+    (N = 1800) and a 120-atom 5s4p3d2f1g molecule with U{1..3} (N = 6600),
+    grown as the 30-atom workload, tau = 1e-12.  One JSON line per system:
+    plan time, quartets kept and streamed, device bytes, and the build's
+    algorithmic FLOPs (per class: primitive quartets x VRR FLOPs + quartets x
+    Phase-2 FLOPs).  With --plan-jk the 60-atom member's J/K build is also
+    run once and timed."""
+    import torch
+    import paper_2605_10312_amd as hgp
+    import workloads
+
+    members = [("batched 60-atom member", 1004, 60, 3, (1, 8)), ("served 120-atom member", 1005, 120, 4, (1, 3))]
+    for name, seed, natom, lmax, nprim in members:
+        bw = workloads.batch_systems(seed=seed, n=1, natom=(natom, natom), lmax=lmax, nprim=nprim,
+                                     with_density=False)[0][0]
+        print(f"plan-sizes: {name}: N = {bw.nbf}, {bw.nshell} shells; planning", file=sys.stderr, flush=True)
+        b = hgp.Basis.from_workload(bw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = hgp.Plan(b, tau=TAU)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        st = plan.stats()
+        cls = plan.classes()
+        flop = sum(c["prim_quartets"] * c["vrr_flops"] + c["quartets"] * c["phase2_flops"] for c in cls)
+        eris = sum(c["quartets"] * int(np.prod([nsph(x) for x in c["ls"]])) for c in cls)
+        line = {"workload": f"plan_{name.split()[0]}_{natom}atoms", "nbf": int(bw.nbf), "shells": int(bw.nshell),
+                "plan_s": round(t_plan, 2), **st, "eris_per_build": int(eris), "build_tflop": round(flop / 1e12, 1),
+                "free_device_bytes": int(torch.cuda.mem_get_info()[0])}
+        if args.plan_jk and lmax == 3:
+            D = torch.tensor(workloads.psd_density(bw.nbf, seed + 1000), device="cuda")
+            J, K = torch.empty_like(D), torch.empty_like(D)
+            print(f"plan-sizes: {name}: one J/K build ({flop / 1e12:.0f} TFLOP)", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.jk(D, J, K)
+            torch.cuda.synchronize()
+            line["jk_s"] = round(time.perf_counter() - t0, 2)
+            line["jk_tflops"] = round(flop / 1e12 / line["jk_s"], 2)
+            del D, J, K
+        print(json.dumps(line), flush=True)
+        plan.close()
+        b.close()
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,9 +465,11 @@ def main():
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: quartets with Q_ab Q_cd < theta use FP32 VRR/HRR (register tier)")
     ap.add_argument("--theta", type=float, default=None, help="mixed-precision threshold (default: the library's)")
-    ap.add_argument("--workload", choices=("mol30", "microbench", "batch", "serve"), default="mol30",
+    ap.add_argument("--workload", choices=("mol30", "microbench", "batch", "serve", "plan-sizes"), default="mol30",
                     help="mol30: the J/K build (one JSON line); microbench: the high-l primitive-quartet classes; "
-                         "batch: many uneven systems in one HIP graph; serve: continuous batching of requests")
+                         "batch: many uneven systems in one HIP graph; serve: continuous batching of requests; "
+                         "plan-sizes: plans of the batched and served workloads' largest members")
+    ap.add_argument("--plan-jk", action="store_true", help="plan-sizes: also run the 60-atom member's J/K once")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-updates", type=int, default=10)
     ap.add_argument("--serve-rate", type=float, default=200.0, help="offered requests per second")
@@ -452,6 +502,9 @@ def main():
         return
     if args.workload == "serve":
         serving(args)
+        return
+    if args.workload == "plan-sizes":
+        plan_sizes(args)
         return
 
     import torch

@@ -111,7 +111,17 @@ hgp_status hgp_basis_destroy(hgp_basis *b);
  * schwarz_tau = 0 nothing is dropped and every integral is the exact sum.
  *   precision         HGP_FP64, or HGP_MIXED (= hgp_plan_create_mixed with
  *                     theta = HGP_MIXED_THETA_DEFAULT)
- *   hbm_budget_bytes  0 = unlimited; otherwise HGP_E_OOM if the plan needs more
+ *   hbm_budget_bytes  device bytes the plan may hold; 0 = half the device
+ *                     memory free at creation for the quartet lists.  The
+ *                     kept (bra pair, ket pair) lists of the classes (8 B a
+ *                     quartet) are stored while they fit; past that the
+ *                     largest lists are streamed: the plan keeps per bra row
+ *                     the offset of its first kept quartet and every build
+ *                     re-screens those rows, chunk by chunk, into one buffer
+ *                     (same quartets, same order, an extra screening pass per
+ *                     build; the streamed lists then run on hip_stream only).
+ *                     HGP_E_OOM if the pair data, accumulators, staged-tier
+ *                     buffer and one chunk holding the longest row exceed it.
  */
 hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t precision, size_t hbm_budget_bytes,
                            void *hip_stream, hgp_plan **out);
@@ -138,6 +148,10 @@ hgp_status hgp_plan_destroy(hgp_plan *p);
 hgp_status hgp_plan_stats(const hgp_plan *p, int64_t *quartets_kept, int64_t *quartets_total, int64_t *device_bytes);
 /* Primitive pairs held by the plan's shell pairs after and before primitive-pair screening. */
 hgp_status hgp_plan_prim_stats(const hgp_plan *p, int64_t *prim_pairs_kept, int64_t *prim_pairs_total);
+/* Streamed class lists (see hgp_plan_create): kept quartets in them, chunks per build over all of
+ * them, and the chunk buffer's capacity in quartets (0 when nothing is streamed). */
+hgp_status hgp_plan_stream_stats(const hgp_plan *p, int64_t *quartets_streamed, int64_t *chunks,
+                                 int64_t *chunk_capacity);
 /* Per class list c (0 .. n-1, n = hgp_plan_num_classes, in launch order; a mixed plan can hold two
  * lists of one class): angular momenta ls[4], quartets kept, primitive quartets they hold, the
  * generator's FLOP counts per primitive quartet (VRR + accumulate, unchunked) and per contracted

@@ -43,6 +43,7 @@ SIGNATURES = {
     "hgp_plan_destroy": (ctypes.c_int, [_vp]),
     "hgp_plan_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "hgp_plan_prim_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "hgp_plan_stream_stats": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "hgp_plan_num_classes": (_i32, [_vp]),
     "hgp_plan_class_info": (ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                            ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i32)]),
@@ -165,8 +166,11 @@ class Plan:
         _check(lib().hgp_plan_stats(self.handle, ctypes.byref(k), ctypes.byref(t), ctypes.byref(b)))
         pk, pt = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().hgp_plan_prim_stats(self.handle, ctypes.byref(pk), ctypes.byref(pt)))
+        qs, ch, cap = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().hgp_plan_stream_stats(self.handle, ctypes.byref(qs), ctypes.byref(ch), ctypes.byref(cap)))
         return {"quartets_kept": k.value, "quartets_total": t.value, "device_bytes": b.value,
-                "prim_pairs_kept": pk.value, "prim_pairs_total": pt.value}
+                "prim_pairs_kept": pk.value, "prim_pairs_total": pt.value, "quartets_streamed": qs.value,
+                "stream_chunks": ch.value, "chunk_capacity": cap.value}
 
     def classes(self):
         out = []

@@ -13,9 +13,11 @@ void launch_prim_quartet_pairs(int64_t n, const double *centers, const double *e
                                const int perm[4], const int strides[4], int64_t block, PairInfo *pairs,
                                PairGeo *geo, PrimPair *prims, EriTask *tasks, hipStream_t s);
 void launch_screen_count(int b0, int nb, int sym, const double *Q, double tau, double hi, const int *psys,
-                         const int *kbeg, const int *kcnt, int64_t *counts, hipStream_t s);
+                         const int *kbeg, const int *kcnt, const int *npr, int64_t *counts, int64_t *pcounts,
+                         hipStream_t s);
 void launch_screen_write(int b0, int nb, int sym, const double *Q, double tau, double hi, const int *psys,
-                         const int *kbeg, const int *kcnt, const int64_t *offsets, int2 *out, hipStream_t s);
+                         const int *kbeg, const int *kcnt, const int64_t *offsets, int64_t shift, int2 *out,
+                         hipStream_t s);
 void launch_scan(int64_t *v, int n, int64_t *total, hipStream_t s);
 // class of each (la, lb, lc, ld) in canonical order, index ((la*5 + lb)*5 + lc)*5 + ld, -1 if not built;
 // passed by value to the classify kernel

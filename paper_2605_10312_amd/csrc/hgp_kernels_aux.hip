@@ -176,31 +176,48 @@ __device__ __forceinline__ void ket_range(int row, int sym, const int *psys, con
     *len = sym ? (row - kbeg[sy] + 1) : kcnt[sy];
 }
 
+// Per bra row: the kets kept (counts) and the sum of their primitive-pair
+// counts (pcounts, the row's primitive quartets divided by its own count).
 __global__ void screen_count_kernel(int b0, int nb, int sym, const double *Q, double tau, double hi,
-                                    const int *psys, const int *kbeg, const int *kcnt, int64_t *counts)
+                                    const int *psys, const int *kbeg, const int *kcnt, const int *npr,
+                                    int64_t *counts, int64_t *pcounts)
 {
     const int row = b0 + blockIdx.x;
     int k0, len;
     ket_range(row, sym, psys, kbeg, kcnt, &k0, &len);
     const double qb = Q[row];
     int c = 0;
+    int64_t pc = 0;
     for (int j = threadIdx.x; j < len; j += blockDim.x) {
         const double qq = qb * Q[k0 + j];
-        c += (qq >= tau && qq < hi) ? 1 : 0;
+        const bool keep = qq >= tau && qq < hi;
+        c += keep ? 1 : 0;
+        pc += keep ? npr[k0 + j] : 0;
     }
     __shared__ int part[1024 / 64];
+    __shared__ int64_t ppart[1024 / 64];
     // wave reduction
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_down(c, off, 64);
+        pc += __shfl_down(pc, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[threadIdx.x >> 6] = c;
+        ppart[threadIdx.x >> 6] = pc;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+        int64_t pt = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            t += part[w];
+            pt += ppart[w];
+        }
         counts[blockIdx.x] = t;
+        pcounts[blockIdx.x] = pt;
     }
 }
 
-// exclusive scan of n counts in place (single block), total into *total
 // ---------------------------------------------------------------------------
 // Shell quartets given on the device (integrals out, any shell order).
 // Classify: one thread per quartet validates its shells and offset, puts the
@@ -293,6 +310,7 @@ __global__ void sq_scatter_kernel(int64_t nq, const int32_t *quartets, const int
     tasks[slot] = t;
 }
 
+// exclusive scan of n counts in place (single block), total into *total
 __global__ void scan_kernel(int64_t *v, int n, int64_t *total)
 {
     __shared__ int64_t buf[1024];
@@ -318,9 +336,12 @@ __global__ void scan_kernel(int64_t *v, int n, int64_t *total)
     if (threadIdx.x == 0) *total = carry;
 }
 
+// Writes the kept (bra, ket) pairs of rows b0 .. b0 + nb - 1, row r's at
+// out[offsets[r - b0] - shift ...] (shift: the first row's offset when out
+// holds only a chunk of the class list).
 __global__ void screen_write_kernel(int b0, int nb, int sym, const double *Q, double tau, double hi,
                                     const int *psys, const int *kbeg, const int *kcnt, const int64_t *offsets,
-                                    int2 *out)
+                                    int64_t shift, int2 *out)
 {
     const int row = b0 + blockIdx.x;
     int k0, len;
@@ -328,7 +349,7 @@ __global__ void screen_write_kernel(int b0, int nb, int sym, const double *Q, do
     const double qb = Q[row];
     __shared__ int wcount[1024 / 64];
     __shared__ int64_t base;
-    if (threadIdx.x == 0) base = offsets[blockIdx.x];
+    if (threadIdx.x == 0) base = offsets[blockIdx.x] - shift;
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int j0 = 0; j0 < len; j0 += blockDim.x) {
@@ -422,18 +443,20 @@ void launch_prim_quartet_pairs(int64_t n, const double *centers, const double *e
                            tasks);
 }
 void launch_screen_count(int b0, int nb, int sym, const double *Q, double tau, double hi, const int *psys,
-                         const int *kbeg, const int *kcnt, int64_t *counts, hipStream_t s)
+                         const int *kbeg, const int *kcnt, const int *npr, int64_t *counts, int64_t *pcounts,
+                         hipStream_t s)
 {
     if (nb > 0)
         hipLaunchKernelGGL(screen_count_kernel, dim3(nb), dim3(256), 0, s, b0, nb, sym, Q, tau, hi, psys, kbeg, kcnt,
-                           counts);
+                           npr, counts, pcounts);
 }
 void launch_screen_write(int b0, int nb, int sym, const double *Q, double tau, double hi, const int *psys,
-                         const int *kbeg, const int *kcnt, const int64_t *offsets, int2 *out, hipStream_t s)
+                         const int *kbeg, const int *kcnt, const int64_t *offsets, int64_t shift, int2 *out,
+                         hipStream_t s)
 {
     if (nb > 0)
         hipLaunchKernelGGL(screen_write_kernel, dim3(nb), dim3(256), 0, s, b0, nb, sym, Q, tau, hi, psys, kbeg, kcnt,
-                           offsets, out);
+                           offsets, shift, out);
 }
 void launch_scan(int64_t *v, int n, int64_t *total, hipStream_t s)
 {

@@ -227,7 +227,17 @@ struct ClassList {
     int bits = 64;    // 64: FP64 kernel; 32: VRR and contraction in FP32 (mixed plans, Q_ab Q_cd below theta)
     int64_t nq = 0;   // unique quartets kept
     int64_t nprimq = 0;
-    int2 *d_q = nullptr;
+    int2 *d_q = nullptr;   // the kept (bra, ket) pairs, or nullptr for a streamed list
+    // screening parameters: bra rows b0 .. b0 + nb - 1 of pair class bc against
+    // the kets of pair class kc, Q_ab Q_cd in [lo, hi)
+    int b0 = 0, nb = 0, sym = 0, kc = 0;
+    double lo = 0.0, hi = 0.0;
+    // streamed list (its pairs re-screened into the plan's chunk buffer on every
+    // build): per-row first-quartet offsets (device, nb) and the row ranges of
+    // the chunks with their first offsets
+    int64_t *d_off = nullptr;
+    std::vector<int> chunk_row;            // chunk k: rows chunk_row[k] .. chunk_row[k + 1] - 1
+    std::vector<int64_t> chunk_off;        // chunk k: quartets chunk_off[k] .. chunk_off[k + 1] - 1
     int64_t launches[2] = {0, 0};   // timed launches: [0] whole / Phase-1 kernel, [1] Phase-2 kernel
     double ms[2] = {0.0, 0.0};      // their summed durations
 };
@@ -251,6 +261,9 @@ struct hgp_plan {
     double *d_Jacc = nullptr, *d_Kacc = nullptr;
     double *d_scratch = nullptr;           // staged classes: slot-major batch buffer
     int64_t scratch_doubles = 0;
+    int *d_npr = nullptr;                  // primitive pairs of each pair
+    int2 *d_chunk = nullptr;               // streamed lists: one chunk of kept pairs at a time
+    int64_t chunk_cap = 0;                 // its capacity in quartets
     std::vector<ClassList> lists;
     int64_t kept = 0, total = 0, bytes = 0;
     int64_t prim_total = 0, prim_kept = 0;   // primitive pairs before / after primitive screening
@@ -405,7 +418,8 @@ hgp_status hgp_plan_destroy(hgp_plan *p)
     hipFree(p->d_pairs); hipFree(p->d_geo); hipFree(p->d_prims); hipFree(p->d_Q);
     hipFree(p->d_Jacc); hipFree(p->d_Kacc); hipFree(p->d_scratch);
     hipFree(p->d_Dunion); hipFree(p->d_psys); hipFree(p->d_cbeg); hipFree(p->d_ccnt);
-    for (auto &c : p->lists) hipFree(c.d_q);
+    for (auto &c : p->lists) { hipFree(c.d_q); hipFree(c.d_off); }
+    hipFree(p->d_npr); hipFree(p->d_chunk);
     if (p->owned) hgp_basis_destroy(p->owned);
     delete p;
     return HGP_OK;
@@ -700,11 +714,25 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
     }
 
     // ---- screened unique-quartet lists per canonical class
-    int64_t *d_counts = nullptr, *d_total = nullptr;
+    // First every list is counted (per bra row: kets kept and their primitive
+    // pairs).  Lists are then materialised as (bra, ket) pairs while they fit
+    // the budget, smallest first; the rest are streamed: each build re-screens
+    // their rows chunk by chunk into one buffer (same pairs, same order).
+    {
+        std::vector<int> npr(std::max<size_t>(pairs.size(), 1), 0);
+        for (size_t k = 0; k < pairs.size(); ++k) npr[k] = pairs[k].nprim;
+        if ((st = upload(&p->d_npr, npr, &p->bytes))) return st;
+    }
+    int64_t *d_counts = nullptr, *d_pcounts = nullptr;
     int maxrows = 1;
     for (int c = 0; c < npc; ++c) maxrows = std::max(maxrows, p->pc_count[c]);
-    if ((st = dalloc(&d_counts, (size_t)maxrows + 1)) || (st = dalloc(&d_total, 2))) { hipFree(d_counts); return st; }
-    std::vector<int64_t> rowprim(maxrows);
+    if ((st = dalloc(&d_counts, (size_t)maxrows + 1)) || (st = dalloc(&d_pcounts, (size_t)maxrows + 1))) {
+        hipFree(d_counts);
+        return st;
+    }
+    auto free_counts = [&]() { hipFree(d_counts); hipFree(d_pcounts); };
+    std::vector<std::vector<int64_t>> row_off;     // per list: nb + 1 exclusive offsets
+    std::vector<int64_t> hc(maxrows), hp(maxrows);
     for (int bc = 0; bc < npc; ++bc) {
         for (int kc = 0; kc <= bc; ++kc) {
             const int nb = p->pc_count[bc], nk = p->pc_count[kc];
@@ -714,8 +742,8 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
             while (pair_class_of(lc + 1, 0) <= kc) ++lc;
             const int lb = bc - pair_class_of(la, 0), ld = kc - pair_class_of(lc, 0);
             const int ci = class_index(la, lb, lc, ld);
-            if (ci < 0) { hipFree(d_counts); hipFree(d_total); return fail(HGP_E_UNSUPPORTED_L, "class kernel not built"); }
-            if ((st = prepare_class(g_class_table[ci]))) { hipFree(d_counts); hipFree(d_total); return st; }
+            if (ci < 0) { free_counts(); return fail(HGP_E_UNSUPPORTED_L, "class kernel not built"); }
+            if ((st = prepare_class(g_class_table[ci]))) { free_counts(); return st; }
             const int sym = (bc == kc);
             const int b0 = p->pc_begin[bc];
             const double t = tau > 0 ? tau : -1.0;
@@ -736,41 +764,32 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
                 bands.push_back({t, inf, 64});
             }
             for (const Band &bd : bands) {
-            launch_screen_count(b0, nb, sym, p->d_Q, bd.lo, bd.hi, p->d_psys, p->d_cbeg + (size_t)kc * nsys,
-                                p->d_ccnt + (size_t)kc * nsys, d_counts, s);
-            launch_scan(d_counts, nb, d_total, s);
-            int64_t total = 0;
-            HGP_HIP(hipMemcpyAsync(&total, d_total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-            HGP_HIP(hipStreamSynchronize(s));
-            ClassList cl;
-            cl.cls = ci;
-            cl.bits = bd.bits;
-            cl.nq = total;
-            if (budget && (size_t)(p->bytes + total * (int64_t)sizeof(int2)) > budget) {
-                hipFree(d_counts); hipFree(d_total);
-                return fail(HGP_E_OOM, "plan exceeds the HBM budget (quartet lists)");
-            }
-            if ((st = dalloc(&cl.d_q, (size_t)total, &p->bytes))) { hipFree(d_counts); hipFree(d_total); return st; }
-            if (total > 0)
-                launch_screen_write(b0, nb, sym, p->d_Q, bd.lo, bd.hi, p->d_psys, p->d_cbeg + (size_t)kc * nsys,
-                                    p->d_ccnt + (size_t)kc * nsys, d_counts, cl.d_q, s);
-            HGP_HIP(hipGetLastError());
-            // primitive-quartet count: sum over kept quartets of nprim(bra) * nprim(ket)
-            if (total > 0) {
-                std::vector<int2> q((size_t)total);
-                HGP_HIP(hipMemcpyAsync(q.data(), cl.d_q, sizeof(int2) * total, hipMemcpyDeviceToHost, s));
+                launch_screen_count(b0, nb, sym, p->d_Q, bd.lo, bd.hi, p->d_psys, p->d_cbeg + (size_t)kc * nsys,
+                                    p->d_ccnt + (size_t)kc * nsys, p->d_npr, d_counts, d_pcounts, s);
+                HGP_HIP(hipGetLastError());
+                HGP_HIP(hipMemcpyAsync(hc.data(), d_counts, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s));
+                HGP_HIP(hipMemcpyAsync(hp.data(), d_pcounts, sizeof(int64_t) * nb, hipMemcpyDeviceToHost, s));
                 HGP_HIP(hipStreamSynchronize(s));
+                ClassList cl;
+                cl.cls = ci;
+                cl.bits = bd.bits;
+                cl.b0 = b0; cl.nb = nb; cl.sym = sym; cl.kc = kc;
+                cl.lo = bd.lo; cl.hi = bd.hi;
+                std::vector<int64_t> off((size_t)nb + 1, 0);
                 int64_t np = 0;
-                for (const int2 &x : q) np += (int64_t)pairs[x.x].nprim * pairs[x.y].nprim;
+                for (int r = 0; r < nb; ++r) {
+                    off[(size_t)r + 1] = off[(size_t)r] + hc[(size_t)r];
+                    np += (int64_t)pairs[(size_t)(b0 + r)].nprim * hp[(size_t)r];
+                }
+                cl.nq = off[(size_t)nb];
                 cl.nprimq = np;
-            }
-            p->kept += total;
-            p->lists.push_back(cl);
+                p->kept += cl.nq;
+                p->lists.push_back(cl);
+                row_off.push_back(std::move(off));
             }
         }
     }
-    hipFree(d_counts);
-    hipFree(d_total);
+    free_counts();
     // staged-tier buffer: one batch per class where it fits under the cap
     int64_t sbuf = 0;
     for (const ClassList &cl : p->lists) sbuf = std::max(sbuf, staged_need(g_class_table[cl.cls], cl.nq));
@@ -778,6 +797,74 @@ static hgp_status plan_build(hgp_plan *p, double tau, size_t budget, hipStream_t
         return fail(HGP_E_OOM, "plan exceeds the HBM budget (staged-tier buffer)");
     if ((st = dalloc(&p->d_scratch, (size_t)sbuf, &p->bytes))) return st;
     p->scratch_doubles = sbuf;
+    // the budget for the lists: the caller's, else half the device memory free now
+    int64_t room = 0;
+    if (budget) {
+        room = (int64_t)budget - p->bytes;
+    } else {
+        size_t fr = 0, tot = 0;
+        HGP_HIP(hipMemGetInfo(&fr, &tot));
+        room = (int64_t)(fr / 2);
+    }
+    std::vector<size_t> order(p->lists.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return p->lists[x].nq < p->lists[y].nq; });
+    int64_t all = 0, longest_row = 0;
+    for (const ClassList &cl : p->lists) all += cl.nq;
+    // what materialising fits; a streamed list needs its row offsets and a chunk
+    // buffer that holds its longest row
+    std::vector<char> stream(p->lists.size(), 0);
+    int64_t used = 0;
+    for (size_t k : order) {
+        const int64_t need = p->lists[k].nq * (int64_t)sizeof(int2);
+        if (all * (int64_t)sizeof(int2) <= room || used + need <= room / 2) {
+            used += need;
+        } else {
+            stream[k] = 1;
+            used += (int64_t)(p->lists[k].nb + 1) * (int64_t)sizeof(int64_t);
+            for (int r = 0; r < p->lists[k].nb; ++r)
+                longest_row = std::max(longest_row, row_off[k][(size_t)r + 1] - row_off[k][(size_t)r]);
+        }
+    }
+    if (longest_row > 0) {
+        p->chunk_cap = std::max<int64_t>(longest_row, (room - used) / (int64_t)sizeof(int2));
+        p->chunk_cap = std::min<int64_t>(p->chunk_cap, (int64_t)1 << 27);      // 1 GiB of pairs per chunk
+        if (p->chunk_cap < longest_row || (room - used) < longest_row * (int64_t)sizeof(int2))
+            return fail(HGP_E_OOM, "plan exceeds the HBM budget (a streamed row does not fit)");
+        if ((st = dalloc(&p->d_chunk, (size_t)p->chunk_cap, &p->bytes))) return st;
+    }
+    for (size_t k = 0; k < p->lists.size(); ++k) {
+        ClassList &cl = p->lists[k];
+        if (cl.nq == 0) continue;
+        int64_t *d_off = nullptr;
+        if ((st = upload(&d_off, std::vector<int64_t>(row_off[k].begin(), row_off[k].end() - 1),
+                         stream[k] ? &p->bytes : nullptr)))
+            return st;
+        if (stream[k]) {
+            cl.d_off = d_off;
+            // rows into chunks of at most chunk_cap quartets
+            cl.chunk_row.push_back(0);
+            cl.chunk_off.push_back(0);
+            for (int r = 0; r < cl.nb; ++r)
+                if (row_off[k][(size_t)r + 1] - cl.chunk_off.back() > p->chunk_cap) {
+                    cl.chunk_row.push_back(r);
+                    cl.chunk_off.push_back(row_off[k][(size_t)r]);
+                }
+            cl.chunk_row.push_back(cl.nb);
+            cl.chunk_off.push_back(cl.nq);
+            continue;
+        }
+        st = dalloc(&cl.d_q, (size_t)cl.nq, &p->bytes);
+        if (!st) {
+            launch_screen_write(cl.b0, cl.nb, cl.sym, p->d_Q, cl.lo, cl.hi, p->d_psys,
+                                p->d_cbeg + (size_t)cl.kc * nsys, p->d_ccnt + (size_t)cl.kc * nsys, d_off, 0, cl.d_q,
+                                s);
+            const hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = fail(HGP_E_DEVICE, std::string("writing a quartet list: ") + hipGetErrorString(e));
+        }
+        hipFree(d_off);
+        if (st) return st;
+    }
     // side streams for concurrent class lists (default priority, non-blocking)
     for (int k = 0; k < HGP_SIDE_STREAMS; ++k) {
         hipStream_t ss = nullptr;
@@ -903,6 +990,22 @@ hgp_status hgp_plan_prim_stats(const hgp_plan *p, int64_t *prim_pairs_kept, int6
     return HGP_OK;
 }
 
+hgp_status hgp_plan_stream_stats(const hgp_plan *p, int64_t *quartets_streamed, int64_t *chunks,
+                                 int64_t *chunk_capacity)
+{
+    if (!p) return fail(HGP_E_INVALID, "plan is NULL");
+    int64_t q = 0, c = 0;
+    for (const ClassList &cl : p->lists)
+        if (!cl.d_q && cl.nq > 0) {
+            q += cl.nq;
+            c += (int64_t)cl.chunk_row.size() - 1;
+        }
+    if (quartets_streamed) *quartets_streamed = q;
+    if (chunks) *chunks = c;
+    if (chunk_capacity) *chunk_capacity = p->chunk_cap;
+    return HGP_OK;
+}
+
 int32_t hgp_plan_num_classes(const hgp_plan *p) { return p ? (int32_t)p->lists.size() : 0; }
 
 hgp_status hgp_plan_class_precision(const hgp_plan *p, int32_t c, int32_t *bits)
@@ -989,7 +1092,7 @@ static hgp_status jk_classes(hgp_plan *p, const double *D, bool want_j, bool wan
         const ClassKernels &k = g_class_table[cl.cls];
         const double c = cl.nprimq * k.vrr_flops + cl.nq * k.p2_flops;
         int w = 0;
-        if (cl.nq > 0 && (k.tier == 0 || k.tier == 3))
+        if (cl.nq > 0 && cl.d_q && (k.tier == 0 || k.tier == 3))      // streamed lists share the chunk buffer
             w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[(size_t)w] += c;
         where[li] = w;
@@ -1021,41 +1124,56 @@ static hgp_status jk_classes(hgp_plan *p, const double *D, bool want_j, bool wan
         a.D = D; a.J = p->d_Jacc; a.K = p->d_Kacc; a.nbf = (int32_t)p->stride;
         a.want_j = want_j; a.want_k = want_k;
         hipEvent_t e0, e1, e2, e3;
-        if (k.tier == 0 || k.tier == 3) {                // register or wave-cooperative LDS tier
-            if ((st = mark(&e0))) return st;
-            const int64_t chunk = (int64_t)k.block << 20;
-            const launch_jk_fn run = cl.bits == 32 ? k.jk32 : k.jk;
-            for (int64_t q0 = 0; q0 < cl.nq; q0 += chunk) {
-                a.quartets = cl.d_q + q0;
-                a.nq = std::min(chunk, cl.nq - q0);
-                run(a, s);
+        // a streamed list runs chunk by chunk: its rows re-screened into the chunk buffer
+        const int nchunk = cl.d_q ? 1 : (int)cl.chunk_row.size() - 1;
+        for (int ch = 0; ch < nchunk; ++ch) {
+            const int2 *qbase = cl.d_q;
+            int64_t nq = cl.nq;
+            if (!cl.d_q) {
+                const int r0 = cl.chunk_row[(size_t)ch], r1 = cl.chunk_row[(size_t)ch + 1];
+                nq = cl.chunk_off[(size_t)ch + 1] - cl.chunk_off[(size_t)ch];
+                if (nq == 0) continue;
+                launch_screen_write(cl.b0 + r0, r1 - r0, cl.sym, p->d_Q, cl.lo, cl.hi, p->d_psys,
+                                    p->d_cbeg + (size_t)cl.kc * p->nsys, p->d_ccnt + (size_t)cl.kc * p->nsys, cl.d_off + r0,
+                                    cl.chunk_off[(size_t)ch], p->d_chunk, s);
+                qbase = p->d_chunk;
             }
-            if ((st = mark(&e1))) return st;
-            done((int)li, 0, e0, e1);
-        } else {
-            const int64_t B = staged_batch(k, p->scratch_doubles);
-            for (int64_t q0 = 0; q0 < cl.nq; q0 += B) {
-                const int64_t nb = std::min(B, cl.nq - q0);
-                a.quartets = cl.d_q + q0;
-                a.nq = nb;
-                a.scratch = p->d_scratch;
-                a.stride = B;
-                if (k.tier == 2) {                     // HBM-scratch tier: one kernel per batch
-                    if ((st = mark(&e0))) return st;
-                    k.jk(a, s);
-                    if ((st = mark(&e1))) return st;
-                    done((int)li, 0, e0, e1);
-                    continue;
-                }
-                P1Args pa{(const int32_t *)(cl.d_q + q0), 2, nb, p->d_pairs, p->d_geo, p->d_prims, boys,
-                          p->d_scratch, B, 0};
+            if (k.tier == 0 || k.tier == 3) {                // register or wave-cooperative LDS tier
                 if ((st = mark(&e0))) return st;
-                k.p1(pa, s);
-                if ((st = mark(&e1)) || (st = mark(&e2))) return st;
-                k.jk(a, s);
-                if ((st = mark(&e3))) return st;
+                const int64_t chunk = (int64_t)k.block << 20;
+                const launch_jk_fn run = cl.bits == 32 ? k.jk32 : k.jk;
+                for (int64_t q0 = 0; q0 < nq; q0 += chunk) {
+                    a.quartets = qbase + q0;
+                    a.nq = std::min(chunk, nq - q0);
+                    run(a, s);
+                }
+                if ((st = mark(&e1))) return st;
                 done((int)li, 0, e0, e1);
-                done((int)li, 1, e2, e3);
+            } else {
+                const int64_t B = staged_batch(k, p->scratch_doubles);
+                for (int64_t q0 = 0; q0 < nq; q0 += B) {
+                    const int64_t nb = std::min(B, nq - q0);
+                    a.quartets = qbase + q0;
+                    a.nq = nb;
+                    a.scratch = p->d_scratch;
+                    a.stride = B;
+                    if (k.tier == 2) {                     // HBM-scratch tier: one kernel per batch
+                        if ((st = mark(&e0))) return st;
+                        k.jk(a, s);
+                        if ((st = mark(&e1))) return st;
+                        done((int)li, 0, e0, e1);
+                        continue;
+                    }
+                    P1Args pa{(const int32_t *)(qbase + q0), 2, nb, p->d_pairs, p->d_geo, p->d_prims, boys,
+                              p->d_scratch, B, 0};
+                    if ((st = mark(&e0))) return st;
+                    k.p1(pa, s);
+                    if ((st = mark(&e1)) || (st = mark(&e2))) return st;
+                    k.jk(a, s);
+                    if ((st = mark(&e3))) return st;
+                    done((int)li, 0, e0, e1);
+                    done((int)li, 1, e2, e3);
+                }
             }
         }
     }

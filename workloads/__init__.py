@@ -166,11 +166,12 @@ CONFIGS = {
 }
 
 
-def batch_systems(seed: int = 1004, n: int = 64, natom=(5, 60), lmax: int = 3, nprim=(1, 8)):
+def batch_systems(seed: int = 1004, n: int = 64, natom=(5, 60), lmax: int = 3, nprim=(1, 8), with_density=True):
     """n molecules of U{natom} atoms each, grown like molecule_3s2p1d, with
     the shell set of the given l_max per atom (l_max 3: 4s3p2d1f) and U{nprim}
     primitives per shell; exponents log-uniform [0.05, 5e3].  Returns a list
-    of (basis, density), each density from its own stream."""
+    of (basis, density), each density from its own stream (None without
+    with_density)."""
     rng = np.random.default_rng(seed)
     shells = {2: [0, 0, 0, 1, 1, 2], 3: [0, 0, 0, 0, 1, 1, 1, 2, 2, 3],
               4: [0] * 5 + [1] * 4 + [2] * 3 + [3] * 2 + [4]}[lmax]
@@ -179,5 +180,5 @@ def batch_systems(seed: int = 1004, n: int = 64, natom=(5, 60), lmax: int = 3, n
         na = int(rng.integers(natom[0], natom[1] + 1))
         atoms = grow_molecule(rng, na) * ANGSTROM_TO_BOHR
         basis = build_basis(atoms, [(l, nprim) for l in shells], rng, (0.05, 5.0e3))
-        out.append((basis, psd_density(basis.nbf, seed + 1000 + k)))
+        out.append((basis, psd_density(basis.nbf, seed + 1000 + k) if with_density else None))
     return out
