@@ -70,7 +70,8 @@ typedef struct hgp_plan hgp_plan;    /* pair data, Schwarz factors and screened 
 #define HGP_MIXED 1               /* FP32 VRR and primitive contraction where a class has that form; Boys, HRR, J/K in FP64 */
 #define HGP_MIXED_THETA_DEFAULT 1e-10
 
-/* Library version and the highest l built into this library's class kernels. */
+/* Library version and the highest l built into this library's class kernels (the per-class
+ * kernel library of Sec. IV: one generated kernel set per canonical (la lb|lc ld), 120 for l <= 4). */
 int32_t hgp_version(void);
 int32_t hgp_max_l(void);
 
@@ -92,16 +93,20 @@ int32_t hgp_max_l(void);
  */
 hgp_status hgp_basis_create(int32_t nshell, const int32_t *l, const int32_t *nprim, const double *centers,
                             const double *exps, const double *coefs, int32_t flags, hgp_basis **out);
-/* Number of spherical functions; shell_offsets[nshell+1] (host, may be NULL) gets each shell's first function. */
+/* Number of spherical functions (2l+1 per shell, Sec. III-B, Eq. cart2sph); shell_offsets[nshell+1]
+ * (host, may be NULL) gets each shell's first function. */
 hgp_status hgp_basis_nbf(const hgp_basis *b, int32_t *nbf, int32_t *shell_offsets);
+/* Frees the basis's device copies (handle plumbing: no passage of the paper). NULL is accepted. */
 hgp_status hgp_basis_destroy(hgp_basis *b);
 
 /*
  * hgp_plan_create -- everything a J/K build reuses across density updates:
  * shell-pair and primitive-pair data (the Gaussian-product quantities of
  * Alg. 2's GaussianPairs), Schwarz factors Q_ab = sqrt(max |(mn|mn)|), and per
- * canonical class (la lb|lc ld) the list of unique quartets with
- * Q_ab Q_cd >= schwarz_tau (0: keep all).  All of it is computed by device
+ * canonical class (la lb|lc ld) (the l-configurations of Sec. IV) the list of
+ * unique quartets with Q_ab Q_cd >= schwarz_tau (0: keep all).  The screen
+ * is not part of the paper's text: it is the Cauchy-Schwarz bound
+ * |(ab|cd)| <= Q_ab Q_cd applied to the unique quartets of Eq. eri-def.  All of it is computed by device
  * kernels on hip_stream; the call waits for the stream before returning.
  * With schwarz_tau > 0 the plan also drops primitive pairs: with q_r the
  * Schwarz factor of primitive pair r (contraction coefficients included),
@@ -128,8 +133,8 @@ hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t preci
 /*
  * hgp_plan_create_mixed -- a plan whose register-tier classes evaluate the
  * quartets with schwarz_tau <= Q_ab Q_cd < theta with the VRR and the
- * contraction over primitives in FP32 (the reduced-precision option of
- * Sec. III, applied below a Schwarz threshold).  The pair quantities, the
+ * contraction over primitives in FP32 (an extension: the paper's method is
+ * FP64 throughout; here Eq. vrr and the accumulation of Alg. 2 run in FP32).  The pair quantities, the
  * Boys function, the horizontal recurrence and transforms (which cancel
  * between large intermediates) and the J/K digestion stay FP64.
  * Larger-bound quartets and the staged, wave-LDS and HBM-scratch classes run
@@ -143,10 +148,13 @@ hgp_status hgp_plan_create(const hgp_basis *b, double schwarz_tau, int32_t preci
  */
 hgp_status hgp_plan_create_mixed(const hgp_basis *b, double schwarz_tau, double theta, size_t hbm_budget_bytes,
                                  void *hip_stream, hgp_plan **out);
+/* Frees the plan's device data and streams after its pending work (handle plumbing). NULL is accepted. */
 hgp_status hgp_plan_destroy(hgp_plan *p);
-/* Plan statistics: unique quartets kept after screening, candidate quartets, device bytes held. */
+/* Plan statistics: unique quartets kept after screening, candidate quartets, device bytes held
+ * (the quartet counts are those of Eq. eri-def's unique quartets before and after the screen). */
 hgp_status hgp_plan_stats(const hgp_plan *p, int64_t *quartets_kept, int64_t *quartets_total, int64_t *device_bytes);
-/* Primitive pairs held by the plan's shell pairs after and before primitive-pair screening. */
+/* Primitive pairs (Alg. 2's GaussianPairs records) held by the plan's shell pairs after and before
+ * primitive-pair screening. */
 hgp_status hgp_plan_prim_stats(const hgp_plan *p, int64_t *prim_pairs_kept, int64_t *prim_pairs_total);
 /* Streamed class lists (see hgp_plan_create): kept quartets in them, chunks per build over all of
  * them, and the chunk buffer's capacity in quartets (0 when nothing is streamed). */
@@ -155,14 +163,15 @@ hgp_status hgp_plan_stream_stats(const hgp_plan *p, int64_t *quartets_streamed, 
 /* Per class list c (0 .. n-1, n = hgp_plan_num_classes, in launch order; a mixed plan can hold two
  * lists of one class): angular momenta ls[4], quartets kept, primitive quartets they hold, the
  * generator's FLOP counts per primitive quartet (VRR + accumulate, unchunked) and per contracted
- * quartet (Phase 2), and the tier (0 register, 1 staged, 2 HBM scratch, 3 wave-cooperative LDS). */
+ * quartet (Phase 2), and the tier (0 register, 1 staged, 2 HBM scratch, 3 wave-cooperative LDS; the
+ * register-only and buffered tiers of Sec. III-C, the last two this library's forms past them). */
 int32_t hgp_plan_num_classes(const hgp_plan *p);
 hgp_status hgp_plan_class_info(const hgp_plan *p, int32_t c, int32_t *ls, int64_t *nquartets, int64_t *nprim_quartets,
                                double *vrr_flops, double *phase2_flops, int32_t *tier);
 /* Arithmetic width of class list c's VRR/HRR: 64, or 32 for the FP32 part of a mixed plan. */
 hgp_status hgp_plan_class_precision(const hgp_plan *p, int32_t c, int32_t *bits);
 
-/* The plan's Schwarz factors by shell: Q[i*nshell + j] = Q[j*nshell + i] =
+/* The plan's Schwarz factors by shell (the Cauchy-Schwarz screen above): Q[i*nshell + j] = Q[j*nshell + i] =
  * sqrt(max |(mn|mn)|) over m in shell i, n in shell j (host array, nshell^2),
  * from the primitive pairs the plan kept; 0 for a shell pair with none kept
  * (and for shells of different systems of a multi-system plan, whose shells
@@ -170,7 +179,8 @@ hgp_status hgp_plan_class_precision(const hgp_plan *p, int32_t c, int32_t *bits)
 hgp_status hgp_plan_schwarz(const hgp_plan *p, double *Q);
 
 /*
- * Kernel timing for profiling: with timing enabled, hgp_jk records a pair of
+ * Kernel timing for profiling (the per-kernel times of Sec. V's measurements): with timing enabled,
+ * hgp_jk records a pair of
  * HIP events on its stream around each class kernel (the work enqueued is
  * unchanged).  hgp_plan_set_timing(p, 1) also resets the counters.
  * hgp_plan_class_timing waits for the recorded events and returns, for class
@@ -183,7 +193,8 @@ hgp_status hgp_plan_set_timing(hgp_plan *p, int32_t enable);
 hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int32_t kernel, int64_t *launches, double *total_ms);
 
 /*
- * hgp_jk -- J and K for density D (Alg. 2's Scatter step, 8-fold symmetry).
+ * hgp_jk -- J and K for density D (Alg. 2's Scatter step, 8-fold symmetry;
+ * for buffered classes the separate contraction kernel of Sec. III-C.2).
  *   D   N x N symmetric density (device; symmetry is assumed, not checked)
  *   J   N x N output (device, overwritten) or NULL to skip J
  *   K   N x N output (device, overwritten) or NULL to skip K
@@ -193,7 +204,9 @@ hgp_status hgp_plan_class_timing(hgp_plan *p, int32_t c, int32_t kernel, int64_t
 hgp_status hgp_jk(hgp_plan *p, const double *D, double *J, double *K, void *hip_stream);
 
 /*
- * Several systems in one plan (the batched-systems growth of the method):
+ * Several systems in one plan (the batched-systems growth of the method, not
+ * in the paper, which evaluates one molecule at a time; the integrals and J/K
+ * of each system are those of Eq. eri-def and Alg. 2):
  * the n bases are independent systems; the plan keeps only shell pairs
  * within a system and quartets whose two pairs are in the same system, so
  * each class is one launch over the quartets of every system at once
@@ -220,7 +233,8 @@ hgp_status hgp_plan_create_multi(const hgp_basis *const *bases, int32_t n, doubl
 hgp_status hgp_jk_multi(hgp_plan *p, const double *const *D, double *const *J, double *const *K, void *hip_stream);
 
 /*
- * Batched J/K over many systems (the batched-systems growth of the method):
+ * Batched J/K over many systems (the batched-systems growth of the method, not
+ * in the paper; each system's J/K as hgp_jk computes it, Alg. 2):
  * the J/K builds of n plans, each with its own D, J and K, captured once as
  * one HIP graph in which every system is an independent branch, so the
  * device overlaps the classes of small and large systems instead of running
@@ -272,7 +286,9 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
 
 /*
  * hgp_eri_prim_quartets -- n independent primitive quartets of class
- * (la lb|lc ld), each primitive normalised (coefficient N(a,l)).
+ * (la lb|lc ld), each primitive normalised (coefficient N(a,l)): Eq. eri-def
+ * for one-primitive shells, evaluated as Alg. 2 does (Boys, Eq. vrr, Eq. hrr
+ * with the stepwise spherical transform, Eq. stepwise-sph).
  *   centers[12*n]  A, B, C, D per quartet, bohr                      (device)
  *   exps[4*n]      a, b, c, d per quartet                            (device)
  *   out[n * nsph(la) nsph(lb) nsph(lc) nsph(ld)]  spherical blocks   (device)
@@ -296,7 +312,8 @@ hgp_status hgp_eri_prim_quartets(int32_t la, int32_t lb, int32_t lc, int32_t ld,
 
 /*
  * hgp_class_form -- how this library evaluates class (la lb|lc ld) (any
- * order of the four): *tier 0 register, 1 staged, 2 HBM-scratch op tables,
+ * order of the four; the tier routing of Sec. III-C, decided per class at
+ * build time): *tier 0 register, 1 staged, 2 HBM-scratch op tables,
  * 3 wave-LDS op tables; *has_fp32 1 if the class has the FP32
  * VRR-and-contraction form that HGP_MIXED uses.  Either pointer may be NULL.
  * Errors: HGP_E_INVALID for negative l, HGP_E_UNSUPPORTED_L beyond l = 4.
@@ -324,7 +341,7 @@ hgp_status hgp_eri_prim_quartets_noalloc(int32_t la, int32_t lb, int32_t lc, int
 /* Largest n hgp_eri_prim_quartets_noalloc accepts for class (la lb|lc ld); -1 if it cannot run the class. */
 int64_t hgp_eri_prim_quartets_noalloc_max(int32_t la, int32_t lb, int32_t lc, int32_t ld);
 
-/* Thread-local description of the last non-OK status (never NULL). */
+/* Thread-local description of the last non-OK status (never NULL; error plumbing, no passage). */
 const char *hgp_last_error(void);
 
 #ifdef __cplusplus
