@@ -463,7 +463,7 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-high-l", action="store_true", help="skip the high-l class microbench in the default run")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
-                    help="mixed: quartets with Q_ab Q_cd < theta use FP32 VRR/HRR (register tier)")
+                    help="mixed: quartets with Q_ab Q_cd < theta use FP32 VRR and contraction (register tier; HRR, Boys, J/K FP64)")
     ap.add_argument("--theta", type=float, default=None, help="mixed-precision threshold (default: the library's)")
     ap.add_argument("--workload", choices=("mol30", "microbench", "batch", "serve", "plan-sizes"), default="mol30",
                     help="mol30: the J/K build (one JSON line); microbench: the high-l primitive-quartet classes; "
@@ -631,7 +631,7 @@ def main():
         "config": {"workload": "mol30_3s2p1d: 30-atom synthetic molecule, 3s2p1d per atom (1-6 primitives), "
                                "N=420, Schwarz tau=1e-12, J+K " +
                                ("in FP64" if args.precision == "fp64" else
-                                f"mixed (FP32 VRR/HRR below Schwarz bound {theta:g}, FP64 Boys and J/K)"),
+                                f"mixed (FP32 VRR and contraction below Schwarz bound {theta:g}, register tier; FP64 Boys, HRR and J/K)"),
                    "nbf": int(bw.nbf), "shells": int(bw.nshell), "tau": TAU,
                    "quartets_kept": stats["quartets_kept"], "quartets_total": stats["quartets_total"],
                    "prim_pairs_kept": stats["prim_pairs_kept"], "prim_pairs_total": stats["prim_pairs_total"],

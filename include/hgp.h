@@ -168,7 +168,8 @@ hgp_status hgp_plan_stream_stats(const hgp_plan *p, int64_t *quartets_streamed, 
 int32_t hgp_plan_num_classes(const hgp_plan *p);
 hgp_status hgp_plan_class_info(const hgp_plan *p, int32_t c, int32_t *ls, int64_t *nquartets, int64_t *nprim_quartets,
                                double *vrr_flops, double *phase2_flops, int32_t *tier);
-/* Arithmetic width of class list c's VRR/HRR: 64, or 32 for the FP32 part of a mixed plan. */
+/* Arithmetic width of class list c's VRR and primitive contraction: 64, or 32 for the FP32 part of a
+ * mixed plan (HRR, transforms, Boys and digestion are FP64 in both). */
 hgp_status hgp_plan_class_precision(const hgp_plan *p, int32_t c, int32_t *bits);
 
 /* The plan's Schwarz factors by shell (the Cauchy-Schwarz screen above): Q[i*nshell + j] = Q[j*nshell + i] =

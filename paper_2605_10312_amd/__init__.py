@@ -154,7 +154,8 @@ class Plan:
 
     def __init__(self, basis: Basis, tau: float = 1e-12, hbm_budget: int = 0, stream=None, theta: float = 0.0):
         """theta > tau: mixed precision, quartets with tau <= Q_ab Q_cd < theta
-        of register-tier classes use FP32 VRR/HRR (hgp_plan_create_mixed)."""
+        of register-tier classes use FP32 VRR and primitive contraction; HRR, Boys
+        and J/K stay FP64 (hgp_plan_create_mixed)."""
         self.basis = basis
         h = ctypes.c_void_p()
         _check(lib().hgp_plan_create_mixed(basis.handle, float(tau), float(theta), int(hbm_budget),

@@ -267,7 +267,7 @@ struct hgp_plan {
     std::vector<ClassList> lists;
     int64_t kept = 0, total = 0, bytes = 0;
     int64_t prim_total = 0, prim_kept = 0;   // primitive pairs before / after primitive screening
-    double theta = 0.0;                      // mixed plans: quartets with Q_ab Q_cd < theta use FP32 VRR/HRR
+    double theta = 0.0;                      // mixed plans: quartets with Q_ab Q_cd < theta use FP32 VRR and contraction
     bool timing = false;
     std::vector<PendingTiming> pending;
     std::vector<hipEvent_t> event_pool;
