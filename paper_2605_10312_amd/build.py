@@ -33,8 +33,8 @@ REMARKS = ["-Rpass-analysis=kernel-resource-usage"]
 
 
 REGISTER_OPTS = ("waves", "digest", "reduce", "loop", "block")
-STAGED_OPTS = ("cap", "waves", "reduce", "loop")
-ROW_OPTS = ("budget", "waves", "reduce", "loop", "eri_layout")
+STAGED_OPTS = ("cap", "waves", "reduce", "loop", "jk_digest")
+ROW_OPTS = ("budget", "waves", "reduce", "loop", "eri_layout", "jk_digest")
 
 
 _EMITTED: dict = {}     # (class, routing inputs) -> (source, meta): a rerouting pass regenerates only what changed

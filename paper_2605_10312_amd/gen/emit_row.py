@@ -40,7 +40,7 @@ from . import phase2 as p2mod
 from . import vrr as vrrmod
 from .cart import levels
 from .emit import ClassMeta, XYZ, loop_close, loop_prelude, tag_of, waves_attr
-from .emit_staged import _names_in, _op_line, node_flops, slot_digestion, subgraph
+from .emit_staged import FusedDigest, _names_in, _op_line, node_flops, slot_digestion, subgraph
 
 REGISTER_DOUBLES = 240
 ROW_SCHEDULERS = ("dfs_su_e", "dfs_su_f", "dfs")
@@ -358,12 +358,15 @@ def _f32_prelude(L, ind):
 
 
 def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", block=64, waves=0, reduce="segmented",
-                   loop="late", plan=None, eri_layout="quartet"):
+                   loop="late", plan=None, eri_layout="quartet", jk_digest="fused"):
     """eri_layout: how Phase 1 hands the (e|lam sig) values to the
     integrals-out kernel: 'quartet' (each quartet's values contiguous: the
     one-wave-per-quartet kernel reads them with coalesced loads, Phase 1
     stores them a row per lane) or 'slot' (slot-major as for J/K: Phase 1
-    stores coalesced, the integrals-out kernel gathers)."""
+    stores coalesced, the integrals-out kernel gathers).  jk_digest: 'fused'
+    (the J/K kernel digests each ket function's integrals while they are in
+    registers) or 'slots' (stores them, then six contractions stream them
+    back)."""
     ls = (la, lb, lc, ld)
     tag = tag_of(ls)
     assert block == 64, "Phase 1 stages its quartet-major stores per wave"
@@ -560,12 +563,14 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
         lines.append(f"{ind}HGP_STAGE(li);")
         return lines
 
-    def phase2_lines(sink, ind="    "):
+    def phase2_lines(sink, ind="    ", digest=None):
         """Kernel 2's work for one quartet up to the integrals: the ket stage of
         the tiled rows (from their H slots), then per ket function (lam, sig)
         the bra HRR + T(la) T(lb) from the (e|lam sig) slots; sink(mu, nu, lam,
         sig, expr, ind) emits each integral's use.  A stage with many inputs
-        runs in groups of second-index functions, each reloading its inputs."""
+        runs in groups of second-index functions, each reloading its inputs.
+        digest: a FusedDigest over slices (lam, sig); each stage's integrals
+        then go to registers c<mu>_<nu> and are digested after the stage."""
         lines = []
         if plan.tile_rows:
             lines.append(f"{ind}const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
@@ -580,12 +585,29 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
         lines.append(f"{ind}const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz;")
         lines.append(f"{ind}(void)ABx; (void)ABy; (void)ABz;")
         for lam in range(nc):
+            if digest is not None:
+                lines.extend(digest.outer_begin(lam, ind))
             for sig in range(nd):
                 lines.append(f"{ind}// bra HRR + T(la) T(lb) for ket functions ({lam}, {sig})")
+                si = ind
+                if digest is not None:
+                    lines.append(f"{ind}{{")
+                    si = ind + "    "
+                    cs = [f"c{mu}_{nu}" for mu in range(na) for nu in range(nb)]
+                    for k in range(0, len(cs), 8):
+                        lines.append(f"{si}double " + ", ".join(cs[k:k + 8]) + ";")
+                    snk = lambda mu, nu, lam_, sig_, x, i2: [f"{i2}c{mu}_{nu} = {x};"]
+                else:
+                    snk = sink
                 for ops, ins, outs in plan.k2_bra(lam, sig):
                     lines.extend(group_lines(
                         ops, ins, outs, lambda e, lam=lam, sig=sig: f"sb[{plan.zslot(eidx[e], lam, sig)}u * S32 + li]",
-                        lambda key, x, i2, lam=lam, sig=sig: sink(key[0], key[1], lam, sig, x, i2), ind))
+                        lambda key, x, i2, lam=lam, sig=sig, snk=snk: snk(key[0], key[1], lam, sig, x, i2), si))
+                if digest is not None:
+                    lines.extend(digest.slice(lam, sig, lambda r, s_: f"c{r}_{s_}", si))
+                    lines.append(f"{ind}}}")
+            if digest is not None:
+                lines.extend(digest.outer_end(lam, ind))
         return lines
 
     # ---------------------------------------------------------------- kernel 2: integrals out, one wave per quartet
@@ -699,9 +721,16 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
     jw("    const int fa = pb.fa, fb = pb.fb, fc = pk.fa, fd = pk.fb;")
     jw("    const double s = (pb.same ? 0.5 : 1.0) * (pk.same ? 0.5 : 1.0) * (pq.x == pq.y ? 0.5 : 1.0);")
     jw("    const double sj = a.want_j ? 2.0 * s : 0.0, sk = a.want_k ? s : 0.0;")
-    jo.extend(phase2_lines(lambda mu, nu, lam, sig, x, ind: [f"{ind}sb[{plan.islot(mu, nu, lam, sig)}u * S32 + li] = {x};"]))
-    jo.extend(slot_digestion(na, nb, nc, nd, lambda mu, nu, lam, sig: f"sb[{plan.islot(mu, nu, lam, sig)}u * S32 + li]",
-                             reduce))
+    if jk_digest == "fused":
+        # each ket function's integrals digested as the bra stage makes them
+        fdg = FusedDigest((na, nb, nc, nd), 2, 3, reduce)
+        jo.extend(fdg.prologue())
+        jo.extend(phase2_lines(None, digest=fdg))
+        jo.extend(fdg.epilogue())
+    else:
+        jo.extend(phase2_lines(lambda mu, nu, lam, sig, x, ind: [f"{ind}sb[{plan.islot(mu, nu, lam, sig)}u * S32 + li] = {x};"]))
+        jo.extend(slot_digestion(na, nb, nc, nd, lambda mu, nu, lam, sig: f"sb[{plan.islot(mu, nu, lam, sig)}u * S32 + li]",
+                                 reduce))
     jw("}")
     jw("")
     jw("}  // namespace")
@@ -741,5 +770,6 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
     meta.eri_wave = eri_layout == "quartet"        # Phase 1 writes quartet-major for integrals out
     meta.eri_tiles = False          # the tiled rows' ket stage runs inside the integrals-out kernel
     meta.parts = len(parts)
+    meta.jk_digest = jk_digest
     meta.extra_sources = part_src
     return "\n".join(out) + "\n", meta

@@ -119,7 +119,7 @@ def _names_in(op):
 
 
 def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedulers=None, waves=0,
-                      reduce="segmented", loop="late"):
+                      reduce="segmented", loop="late", jk_digest="fused"):
     ls = (la, lb, lc, ld)
     tag = tag_of(ls)
     g = vrrmod.VRRGraph(la, lb, lc, ld, rule=rule)
@@ -135,7 +135,8 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
     tindex = {t: k for k, t in enumerate(g.targets)}
     n_h = len(g.targets)
     islot = lambda mu, nu, lam, sig: n_h + ((mu * nb + nu) * nc + lam) * nd + sig
-    nslots = n_h + nout
+    # H slots, then (for the six-pass digestion only) the integrals
+    nslots = n_h + (nout if jk_digest == "slots" else 0)
     chunks = chunk_targets(g, cap)
     full = g.flops()
     recompute = sum(node_flops(g, subgraph(g, c), len(c)) for c in chunks) / full
@@ -223,9 +224,11 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
     w("")
     F = list(levels(lc, lc + ld))
 
-    def ket_stage(mu, nu, a0, a1, sink, ind="    "):
+    def ket_stage(mu, nu, a0, a1, sink, ind="    ", after=None):
         """Ket HRR + T(lc) T(ld) for bra functions (mu, nu); sink(lam, sig, name)
-        emits the use of each integral while it is still in a register."""
+        emits the use of each integral while it is still in a register;
+        after(names, ind) -> lines that use the stage's integrals together
+        (names[(lam, sig)]) before its scope closes."""
         ops = p2.ops[a0:a1]
         w(f"{ind}{{   // ket HRR + T(lc) T(ld) for bra functions ({mu}, {nu})")
         ren = {}
@@ -235,10 +238,16 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
             w(f"{ind}    const double y{k} = sb[{s2slot[(mu, nu, f)]}u * S32 + li];")
         for op in ops:
             w(f"{ind}    " + _op_line(op, ren))
+        names = {}
         for lam in range(nc):
             for sig in range(nd):
                 nm = p2.out[(mu, nu, lam, sig)]
-                sink(mu, nu, lam, sig, ren.get(nm, nm), ind + "    ")
+                names[(lam, sig)] = ren.get(nm, nm)
+                if sink is not None:
+                    sink(mu, nu, lam, sig, names[(lam, sig)], ind + "    ")
+        if after is not None:
+            for line in after(names, ind + "    "):
+                w(line)
         w(f"{ind}}}")
         w(f"{ind}HGP_STAGE(li);")
 
@@ -270,11 +279,23 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
     def store_sink(mu, nu, lam, sig, name, ind):
         w(f"{ind}sb[{islot(mu, nu, lam, sig)}u * S32 + li] = {name};")
 
-    for (mu, nu, a0, a1) in p2.ket_stages:
-        ket_stage(mu, nu, a0, a1, store_sink)
-
-    out.extend(slot_digestion(na, nb, nc, nd, lambda mu, nu, lam, sig: f"sb[{islot(mu, nu, lam, sig)}u * S32 + li]",
-                              reduce))
+    if jk_digest == "fused":
+        # each bra function pair's integrals digested as the ket stage makes them
+        fdg = FusedDigest((na, nb, nc, nd), 0, 1, reduce)
+        out.extend(fdg.prologue())
+        for (mu, nu, a0, a1) in p2.ket_stages:
+            if nu == 0:
+                out.extend(fdg.outer_begin(mu))
+            ket_stage(mu, nu, a0, a1, None,
+                      after=lambda names, ind, mu=mu, nu=nu: fdg.slice(mu, nu, lambda r, s_: names[(r, s_)], ind))
+            if nu == nb - 1:
+                out.extend(fdg.outer_end(mu))
+        out.extend(fdg.epilogue())
+    else:
+        for (mu, nu, a0, a1) in p2.ket_stages:
+            ket_stage(mu, nu, a0, a1, store_sink)
+        out.extend(slot_digestion(na, nb, nc, nd, lambda mu, nu, lam, sig: f"sb[{islot(mu, nu, lam, sig)}u * S32 + li]",
+                                  reduce))
     w("}")
     w("")
     # ---------------------------------------------------------------- Phase 2 + integrals-out kernel
@@ -325,6 +346,7 @@ def emit_class_staged(la, lb, lc, ld, cap=96, rule="ket_zyx", block=64, schedule
     meta = ClassMeta(ls, tag, 1, block, len(g.nodes), full, n_h, pl, sched, p2.flops, nout, rule,
                      scratch_slots=nslots, chunks=len(chunks), recompute=recompute, cap=cap, waves=waves,
                      digest="", reduce=reduce, loop=loop)
+    meta.jk_digest = jk_digest
     return "\n".join(out) + "\n", meta
 
 
@@ -402,3 +424,169 @@ def slot_digestion(na, nb, nc, nd, I, reduce="segmented"):
                 lambda nu, sig: f"a.K + (int64_t)(fb + {nu}) * N + fd + {sig}", "sk")
     w("    }")
     return out
+
+
+# The six contractions of the 8-fold symmetric Scatter (Alg. 2): target index
+# pair, density index pair, scale, matrix, segmented-reduction key.  Index 0..3
+# = mu, nu, lam, sig of (mu nu|lam sig); their first functions fa, fb, fc, fd.
+_CONTRACTIONS = (
+    ("jab", (0, 1), (2, 3), "sj", "J", "ab"),
+    ("jcd", (2, 3), (0, 1), "sj", "J", None),
+    ("kac", (0, 2), (1, 3), "sk", "K", "ac"),
+    ("kbc", (1, 2), (0, 3), "sk", "K", "ac"),
+    ("kad", (0, 3), (1, 2), "sk", "K", None),
+    ("kbd", (1, 3), (0, 2), "sk", "K", None),
+)
+_FOFF = ("fa", "fb", "fc", "fd")
+
+
+class FusedDigest:
+    """J/K digestion that takes each integral once, while it is still in a
+    register, instead of storing the integrals and streaming them back six
+    times.  Phase 2 produces the integrals in slices: slice (p, q) over an
+    outer index P and an inner index Q holds the values for every (r, s) of
+    the other two indices.  Per contraction, an output element that lies in
+    {P, Q} is complete within one slice (one dot product, one atomic); one that
+    lies in {R, S}, or pairs Q with R or S, collects over every slice (its
+    accumulators live across the whole loop); one that pairs P with R or S
+    collects over the inner loop (accumulators reset per outer index).  The
+    J'[ab], K'[ac] and K'[bc] outputs keep the wave's segmented reductions.
+    sizes = (na, nb, nc, nd); outer, inner = P, Q."""
+
+    def __init__(self, sizes, outer, inner, reduce="segmented"):
+        self.n = sizes
+        self.P, self.Q = outer, inner
+        self.R, self.S = [k for k in range(4) if k not in (outer, inner)]
+        self.seg = reduce == "segmented"
+        self.kind = {}
+        for name, tgt, dd, sc, mat, key in _CONTRACTIONS:
+            st = set(tgt)
+            if st == {self.P, self.Q}:
+                self.kind[name] = "slice"
+            elif self.P in st:
+                self.kind[name] = "outer"
+            else:
+                self.kind[name] = "all"
+
+    def _elems(self, tgt):
+        return [(i, j) for i in range(self.n[tgt[0]]) for j in range(self.n[tgt[1]])]
+
+    def _acc(self, name, i, j):
+        return f"{name}_{i}_{j}"
+
+    def _guard(self, mat):
+        return "a.want_j" if mat == "J" else "a.want_k"
+
+    def _emit(self, name, tgt, sc, mat, key, elems, expr, ind):
+        """Add scale * expr(i, j) to the matrix at each element."""
+        lines = []
+        ptr = lambda i, j: f"a.{mat} + (int64_t)({_FOFF[tgt[0]]} + {i}) * N + {_FOFF[tgt[1]]} + {j}"
+        if key is not None and self.seg:
+            vals = []
+            for k, (i, j) in enumerate(elems):
+                lines.append(f"{ind}const double {name}r{k} = hgp_seg_sum({sc} * ({expr(i, j)}), seg_{key});")
+                vals.append((f"{name}r{k}", ptr(i, j)))
+            lines.append(f"{ind}if (tail_{key}) {{")
+            for v, p in vals:
+                lines.append(f"{ind}    atomicAdd({p}, {v});")
+            lines.append(f"{ind}}}")
+        else:
+            for (i, j) in elems:
+                lines.append(f"{ind}atomicAdd({ptr(i, j)}, {sc} * ({expr(i, j)}));")
+        return lines
+
+    def prologue(self, ind="    "):
+        """Segment keys and the accumulators that live across the whole loop."""
+        lines = []
+        if self.seg:
+            lines.append(f"{ind}const int seg_ab = hgp_seg_start(pq.x);")
+            lines.append(f"{ind}const bool tail_ab = hgp_seg_tail(pq.x);")
+            lines.append(f"{ind}const long long key_ac = ((long long)pq.x << 32) | (unsigned)pk.sh_a;")
+            lines.append(f"{ind}const int seg_ac = hgp_seg_start(key_ac);")
+            lines.append(f"{ind}const bool tail_ac = hgp_seg_tail(key_ac);")
+            lines.append(f"{ind}(void)seg_ab; (void)tail_ab; (void)seg_ac; (void)tail_ac;")
+        for name, tgt, dd, sc, mat, key in _CONTRACTIONS:
+            if self.kind[name] == "all":
+                accs = [self._acc(name, i, j) for (i, j) in self._elems(tgt)]
+                for k in range(0, len(accs), 8):
+                    lines.append(f"{ind}double " + ", ".join(f"{x} = 0.0" for x in accs[k:k + 8]) + ";")
+        return lines
+
+    def outer_begin(self, p, ind="    "):
+        """Opens the outer iteration's scope (closed by outer_end)."""
+        lines = [f"{ind}{{   // outer index {p}"]
+        for name, tgt, dd, sc, mat, key in _CONTRACTIONS:
+            if self.kind[name] == "outer":
+                other = tgt[1] if tgt[0] == self.P else tgt[0]
+                accs = [f"{name}_o{r}" for r in range(self.n[other])]
+                lines.append(f"{ind}double " + ", ".join(f"{x} = 0.0" for x in accs) + ";")
+        return lines
+
+    def slice(self, p, q, val, ind="    "):
+        """One slice: val(r, s) names the integral with index P = p, Q = q,
+        R = r, S = s."""
+        lines = []
+        n = self.n
+        for name, tgt, dd, sc, mat, key in _CONTRACTIONS:
+            kind = self.kind[name]
+            # the terms of every output element this slice touches
+            terms = {}
+            for r in range(n[self.R]):
+                for s_ in range(n[self.S]):
+                    idx = [0] * 4
+                    idx[self.P], idx[self.Q], idx[self.R], idx[self.S] = p, q, r, s_
+                    el = (idx[tgt[0]], idx[tgt[1]])
+                    d = f"D[(int64_t)({_FOFF[dd[0]]} + {idx[dd[0]]}) * N + {_FOFF[dd[1]]} + {idx[dd[1]]}]"
+                    terms.setdefault(el, []).append((val(r, s_), d))
+            body = []
+            if kind == "slice":
+                (el, tl), = terms.items()
+                expr = f"{tl[0][0]} * {tl[0][1]}"
+                for x, y in tl[1:]:
+                    expr = f"fma({x}, {y}, {expr})"
+                body.extend(self._emit(name, tgt, sc, mat, key, [el], lambda i, j, e=expr: e, ind + "    "))
+            else:
+                for el, tl in terms.items():
+                    if kind == "outer":
+                        other = el[1] if tgt[0] == self.P else el[0]
+                        acc = f"{name}_o{other}"
+                    else:
+                        acc = self._acc(name, *el)
+                    expr = acc
+                    for x, y in tl:
+                        expr = f"fma({x}, {y}, {expr})"
+                    body.append(f"{ind}    {acc} = {expr};")
+            lines.append(f"{ind}if ({self._guard(mat)}) {{")
+            lines.extend(body)
+            lines.append(f"{ind}}}")
+        lines.append(f"{ind}HGP_STAGE(li);")
+        return lines
+
+    def outer_end(self, p, ind="    "):
+        lines = []
+        for name, tgt, dd, sc, mat, key in _CONTRACTIONS:
+            if self.kind[name] != "outer":
+                continue
+            if tgt[0] == self.P:
+                elems = [(p, r) for r in range(self.n[tgt[1]])]
+                expr = lambda i, j, nm=name: f"{nm}_o{j}"
+            else:
+                elems = [(r, p) for r in range(self.n[tgt[0]])]
+                expr = lambda i, j, nm=name: f"{nm}_o{i}"
+            lines.append(f"{ind}if ({self._guard(mat)}) {{")
+            lines.extend(self._emit(name, tgt, sc, mat, key, elems, expr, ind + "    "))
+            lines.append(f"{ind}}}")
+        lines.append(f"{ind}}}")
+        lines.append(f"{ind}HGP_STAGE(li);")
+        return lines
+
+    def epilogue(self, ind="    "):
+        lines = []
+        for name, tgt, dd, sc, mat, key in _CONTRACTIONS:
+            if self.kind[name] != "all":
+                continue
+            lines.append(f"{ind}if ({self._guard(mat)}) {{")
+            lines.extend(self._emit(name, tgt, sc, mat, key, self._elems(tgt),
+                                    lambda i, j, nm=name: self._acc(nm, i, j), ind + "    "))
+            lines.append(f"{ind}}}")
+        return lines

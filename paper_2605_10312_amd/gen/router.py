@@ -175,16 +175,21 @@ def fallback(route, spilled):
     tier = route.get("tier", 0)
     if tier == 0:
         return {"tier": 1}
+    if tier == 1:
+        keep = {k: route[k] for k in ("form", "budget", "cap", "jk_digest") if k in route}
+        # a J/K kernel whose one-pass digestion does not fit: the six-pass form first
+        if any(k.startswith("jk_") for k in spilled) and route.get("jk_digest", "fused") == "fused":
+            return {"tier": 1, **keep, "jk_digest": "slots"}
     if tier == 1 and route.get("form") == "row":
         budget = route.get("budget", ROW_BUDGET)
         if all(k.startswith("p1_") for k in spilled) and budget > 160:
-            return {"tier": 1, "form": "row", "budget": budget - 20}
+            return {"tier": 1, **keep, "budget": budget - 20}
         return {"tier": 2}
     if tier == 1:
         if all(k.startswith("p1_") for k in spilled):
             cap = route.get("cap", DEFAULT_CAP)
             smaller = [c for c in CAPS if c < cap]
             if smaller:
-                return {"tier": 1, "cap": smaller[0]}
+                return {"tier": 1, **keep, "cap": smaller[0]}
         return {"tier": 2}
     return None

@@ -115,14 +115,22 @@ def test_router_fallback_ladder():
     assert router.fallback({"tier": 0}, ["jk_2120"]) == {"tier": 1}
     assert router.fallback({"tier": 1, "cap": 96}, ["p1_2222"]) == {"tier": 1, "cap": 64}
     assert router.fallback({"tier": 1, "cap": 16}, ["p1_2222"]) == {"tier": 2}
-    assert router.fallback({"tier": 1, "cap": 96}, ["jk_4410", "p1_4410"]) == {"tier": 2}
+    # a J/K kernel that spills with the one-pass digestion goes back to the six-pass form first
+    assert router.fallback({"tier": 1, "cap": 96}, ["jk_4410", "p1_4410"]) == \
+        {"tier": 1, "cap": 96, "jk_digest": "slots"}
+    assert router.fallback({"tier": 1, "cap": 96, "jk_digest": "slots"}, ["jk_4410", "p1_4410"]) == {"tier": 2}
+    assert router.fallback({"tier": 1, "cap": 96, "jk_digest": "slots"}, ["p1_4410"]) == \
+        {"tier": 1, "cap": 64, "jk_digest": "slots"}
     assert router.fallback({"tier": 2}, ["t3_jk_kernel"]) is None
     assert router.fallback({"tier": 1, "form": "row", "budget": 240}, ["p1_3333"]) == \
         {"tier": 1, "form": "row", "budget": 220}
     assert router.fallback({"tier": 1, "form": "row", "budget": 220}, ["p1_3333p3"]) == \
         {"tier": 1, "form": "row", "budget": 200}
     assert router.fallback({"tier": 1, "form": "row", "budget": 160}, ["p1_3333"]) == {"tier": 2}
-    assert router.fallback({"tier": 1, "form": "row", "budget": 240}, ["jk_4444"]) == {"tier": 2}
+    assert router.fallback({"tier": 1, "form": "row", "budget": 240}, ["jk_4444"]) == \
+        {"tier": 1, "form": "row", "budget": 240, "jk_digest": "slots"}
+    assert router.fallback({"tier": 1, "form": "row", "budget": 240, "jk_digest": "slots"}, ["jk_4444"]) == \
+        {"tier": 2}
     assert router.route((3, 3, 3, 3), {})["form"] == "row" and router.route((2, 2, 2, 1), {})["form"] == "chunk"
     assert router.route((4, 3, 2, 1), {})["form"] == "row"
     assert router.route((4, 4, 2, 1), {})["tier"] == 2             # a (gg| bra stays on the op tables
