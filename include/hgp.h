@@ -286,6 +286,31 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
                                   double *out, void *hip_stream);
 
 /*
+ * hgp_eri_deriv_shell_quartets -- first derivatives of the contracted
+ * spherical integrals with respect to the shell centres, the adjacent step
+ * for nuclear gradients (the paper counts first-derivative kernel variants
+ * in Sec. IV and names derivative integrals as the next step in Sec. VII):
+ * d(ij|kl)/dR_p,x for each position p = 0..3 (the centre of the shell at that
+ * position) and axis x.  Per primitive, the derivative of a Gaussian in its
+ * centre is 2 alpha times the function with that Cartesian index raised
+ * minus the index times the function with it lowered; the contraction,
+ * Eq. hrr and Eq. cart2sph then apply as for the integrals, and the fourth
+ * position follows from translational invariance.
+ *   quartets[4*nq], offsets[nq]  as hgp_eri_shell_quartets       (device)
+ *   out   per quartet 12 blocks [position 0..3][axis x, y, z][n_i][n_j][n_k][n_l],
+ *         row-major, 12 n_i n_j n_k n_l doubles at out + offsets[q] (device)
+ * A shell given at two positions gets a block per position (their sum is
+ * the derivative in its centre).  Shells up to l = hgp_deriv_max_l() (the
+ * derivative tables run on the wave-cooperative interpreter);
+ * HGP_E_UNSUPPORTED_L beyond.  Stream behaviour and other errors as
+ * hgp_eri_shell_quartets.
+ */
+hgp_status hgp_eri_deriv_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartets,
+                                        const int64_t *offsets, double *out, void *hip_stream);
+/* Highest shell l for which hgp_eri_deriv_shell_quartets is built (-1: none). */
+int32_t hgp_deriv_max_l(void);
+
+/*
  * hgp_eri_prim_quartets -- n independent primitive quartets of class
  * (la lb|lc ld), each primitive normalised (coefficient N(a,l)): Eq. eri-def
  * for one-primitive shells, evaluated as Alg. 2 does (Boys, Eq. vrr, Eq. hrr

@@ -52,6 +52,8 @@ SIGNATURES = {
     "hgp_plan_class_timing": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_d)]),
     "hgp_jk": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "hgp_eri_shell_quartets": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
+    "hgp_eri_deriv_shell_quartets": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
+    "hgp_deriv_max_l": (_i32, []),
     "hgp_eri_prim_quartets": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i64, _vp, _vp, _vp, _i32, _vp]),
     "hgp_eri_prim_quartets_noalloc": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i64, _vp, _vp, _vp, _i32, _vp]),
     "hgp_eri_prim_quartets_noalloc_max": (_i64, [_i32, _i32, _i32, _i32]),
@@ -253,10 +255,12 @@ class Plan:
             pass
 
 
-def eri_shell_quartets(basis: Basis, quartets, offsets, out, stream=None):
+def eri_shell_quartets(basis: Basis, quartets, offsets, out, stream=None, deriv=False):
     """Spherical blocks of the listed shell quartets into device tensor `out`.
     quartets [nq, 4] (int32) and offsets [nq] (int64, elements) are device
-    tensors, or host arrays that are copied to the device first."""
+    tensors, or host arrays that are copied to the device first.  deriv: the
+    first derivatives instead, 12 blocks [position][axis] a quartet
+    (hgp_eri_deriv_shell_quartets)."""
     import torch
     made = []
 
@@ -273,8 +277,8 @@ def eri_shell_quartets(basis: Basis, quartets, offsets, out, stream=None):
     if off.shape[0] != q.shape[0]:
         raise ValueError("one offset per quartet")
     sp = _stream_ptr(stream)
-    _check(lib().hgp_eri_shell_quartets(basis.handle, int(q.shape[0]), _dptr(q), _dptr(off), _dptr(out, torch.float64),
-                                        ctypes.c_void_p(sp)))
+    fn = lib().hgp_eri_deriv_shell_quartets if deriv else lib().hgp_eri_shell_quartets
+    _check(fn(basis.handle, int(q.shape[0]), _dptr(q), _dptr(off), _dptr(out, torch.float64), ctypes.c_void_p(sp)))
     if made and sp != torch.cuda.current_stream().cuda_stream:
         torch.cuda.synchronize()     # the copies are freed on return: let the other stream finish reading them
 
@@ -349,3 +353,7 @@ def eri_prim_quartets_noalloc_max(ls) -> int:
 
 def max_l() -> int:
     return int(lib().hgp_max_l())
+
+
+def deriv_max_l() -> int:
+    return int(lib().hgp_deriv_max_l())

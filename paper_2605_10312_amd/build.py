@@ -124,6 +124,19 @@ def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overri
     table_path = os.path.join(GEN, "class_table.hip")
     _write_if_changed(table_path, emit.emit_table(metas))
     files.append(table_path)
+    # first-derivative tables (wave form) for the classes with l <= DERIV_LMAX
+    from .gen import emit_deriv
+    dclasses = [ls for ls in classes if max(ls) <= emit_deriv.DERIV_LMAX]
+    for ls in dclasses:
+        key = ("deriv", tuple(ls))
+        if key not in _EMITTED:
+            _EMITTED[key] = emit_deriv.emit_deriv_class(*ls)
+        path = os.path.join(GEN, f"deriv_{''.join(str(x) for x in ls)}.hip")
+        _write_if_changed(path, _EMITTED[key][0])
+        files.append(path)
+    dtable = os.path.join(GEN, "deriv_table.hip")
+    _write_if_changed(dtable, emit_deriv.emit_deriv_table(dclasses))
+    files.append(dtable)
     _write_if_changed(os.path.join(GEN, "classes.json"),
                       json.dumps([{k: v for k, v in m.__dict__.items() if k != "extra_sources"} for m in metas],
                                  indent=1, default=list))

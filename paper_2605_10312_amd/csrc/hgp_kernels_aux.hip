@@ -94,7 +94,7 @@ __global__ void pair_kernel(int npair, const PairInfo *pairs, const double *cen,
         pp.py = (a * Ay + b * By) * iz;
         pp.pz = (a * Az + b * Bz) * iz;
         pp.k = ncoef[oa + ka] * ncoef[ob + kb] * exp(-a * b * iz * ab2) * pref * iz;
-        pp.pad0 = 0.0; pp.pad1 = 0.0;
+        pp.ea = a; pp.eb = b;
         prims[pi.prim_off + r] = pp;
     }
 }
@@ -147,7 +147,7 @@ __global__ void prim_quartet_pair_kernel(int64_t n, const double *centers, const
         pp.pz = (a * A[2] + b * B[2]) * iz;
         pp.k = nrm[0] * nrm[1] * exp(-a * b * iz * (abx * abx + aby * aby + abz * abz)) * sqrt(2.0) *
                pow(3.14159265358979323846, 1.25) * iz;
-        pp.pad0 = 0.0; pp.pad1 = 0.0;
+        pp.ea = a; pp.eb = b;
         prims[p] = pp;
     }
     EriTask t;

@@ -12,6 +12,7 @@
 
 #include "hgp.h"
 #include "hgp_aux.h"
+#include "hgp_t3.h"
 
 using namespace hgp;
 
@@ -97,6 +98,15 @@ hgp_status keep_pool(int dev)
         g_pool_kept[dev] = true;
     }
     return HGP_OK;
+}
+
+// Highest l of the derivative classes built into the library (-1: none).
+int max_deriv_l()
+{
+    int m = -1;
+    for (int c = 0; c < g_num_deriv; ++c)
+        m = std::max({m, g_deriv_table[c].la, g_deriv_table[c].lb, g_deriv_table[c].lc, g_deriv_table[c].ld});
+    return m;
 }
 
 int class_index(int la, int lb, int lc, int ld)
@@ -1259,8 +1269,14 @@ hgp_status hgp_jk_multi(hgp_plan *p, const double *const *D, double *const *J, d
     return launch_status(p);
 }
 
-hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartets, const int64_t *offsets,
-                                  double *out, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+// Shell quartets given on the device, integrals (deriv = false) or their
+// first derivatives (deriv = true: the derivative tables, 12 blocks a quartet).
+hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartets, const int64_t *offsets,
+                          double *out, void *hip_stream, bool deriv)
 {
     if (!b) return fail(HGP_E_INVALID, "basis is NULL");
     if (nq < 0) return fail(HGP_E_INVALID, "nq < 0");
@@ -1274,11 +1290,12 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
     if ((st = keep_pool(b->device))) return st;
     ClassOf cof;
     for (int k = 0; k < 625; ++k) cof.c[k] = -1;
-    for (int c = 0; c < g_num_classes; ++c) {
-        const ClassKernels &k = g_class_table[c];
-        cof.c[((k.la * 5 + k.lb) * 5 + k.lc) * 5 + k.ld] = (int16_t)c;
+    const int ncls = deriv ? g_num_deriv : g_num_classes;
+    for (int c = 0; c < ncls; ++c) {
+        const int la = deriv ? g_deriv_table[c].la : g_class_table[c].la, lb = deriv ? g_deriv_table[c].lb : g_class_table[c].lb;
+        const int lc = deriv ? g_deriv_table[c].lc : g_class_table[c].lc, ld = deriv ? g_deriv_table[c].ld : g_class_table[c].ld;
+        cof.c[((la * 5 + lb) * 5 + lc) * 5 + ld] = (int16_t)c;
     }
-    const int ncls = g_num_classes;
     // stream-ordered temporaries; every exit below frees them on the stream
     int32_t *d_code = nullptr;
     int64_t *d_poff = nullptr, *d_ptotal = nullptr, *d_base = nullptr, *d_btotal = nullptr;
@@ -1329,11 +1346,25 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
         return fail(HGP_E_DEVICE, std::string("classifying the quartets: ") + hipGetErrorString(e));
     }
     if (h[nc8] & 1ull) { release(); return fail(HGP_E_INVALID, "shell index out of range or negative offset"); }
-    if (h[nc8] & 2ull) { release(); return fail(HGP_E_UNSUPPORTED_L, "class kernel not built"); }
+    if (h[nc8] & 2ull) {
+        release();
+        return fail(HGP_E_UNSUPPORTED_L, deriv ? "derivative integrals are built for shells up to l = " +
+                                                     std::to_string(max_deriv_l())
+                                               : std::string("class kernel not built"));
+    }
     if (ptotal > INT32_MAX) { release(); return fail(HGP_E_INVALID, "too many primitive pairs in one call"); }
     int64_t sneed = 0;
     for (int c = 0; c < ncls; ++c)
         if (h[(size_t)c]) {
+            if (deriv) {
+                const int pe = t3_prepare(*g_deriv_table[c].t);
+                if (pe != 0) {
+                    release();
+                    return fail(HGP_E_DEVICE, std::string("preparing derivative tables: ") +
+                                                  hipGetErrorString((hipError_t)pe));
+                }
+                continue;
+            }
             if ((st = prepare_class(g_class_table[c]))) { release(); return st; }
             sneed = std::max(sneed, staged_need(g_class_table[c], (int64_t)h[(size_t)c]));
         }
@@ -1360,7 +1391,17 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
         a.out = out;
         a.mode = 0;
         a.scratch = d_scr;
-        run_eri_class(g_class_table[c], a, sneed, s);
+        if (deriv) {
+            // launches of at most 2^20 quartets (one workgroup each)
+            for (int64_t q0 = 0; q0 < cnt; q0 += (int64_t)1 << 20) {
+                EriArgs x = a;
+                x.tasks = a.tasks + q0;
+                x.ntask = std::min<int64_t>((int64_t)1 << 20, cnt - q0);
+                t3w_launch_deriv(*g_deriv_table[c].t, x, d_code, s);
+            }
+        } else {
+            run_eri_class(g_class_table[c], a, sneed, s);
+        }
         begin += cnt;
     }
     e = hipGetLastError();
@@ -1368,6 +1409,24 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
     if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("integral kernels: ") + hipGetErrorString(e));
     return HGP_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartets, const int64_t *offsets,
+                                  double *out, void *hip_stream)
+{
+    return shell_quartets(b, nq, quartets, offsets, out, hip_stream, false);
+}
+
+hgp_status hgp_eri_deriv_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartets,
+                                        const int64_t *offsets, double *out, void *hip_stream)
+{
+    return shell_quartets(b, nq, quartets, offsets, out, hip_stream, true);
+}
+
+int32_t hgp_deriv_max_l(void) { return max_deriv_l(); }
 
 }  // extern "C"
 

@@ -9,7 +9,10 @@
 namespace hgp {
 
 // Op codes of the tables (eight uint16 words per op; see gen/emit_t3.py).
-enum : int { T3_VRR_BRA = 1, T3_VRR_KET = 2, T3_ACC = 3, T3_HRR_BRA = 4, T3_HRR_KET = 5, T3_LIN = 6, T3_LIN_ACC = 7 };
+enum : int {
+    T3_VRR_BRA = 1, T3_VRR_KET = 2, T3_ACC = 3, T3_HRR_BRA = 4, T3_HRR_KET = 5, T3_LIN = 6, T3_LIN_ACC = 7,
+    T3_ACC_W = 8    // weighted accumulation (derivative tables, wave form only)
+};
 constexpr uint16_t T3_NONE = 0xFFFF;
 // Ops come in groups of T3_GROUP (padded with op code 0): no op of a group
 // reads a slot another op of the group writes, so a group issues all its
@@ -32,6 +35,7 @@ struct T3Class {
     int lds_bytes;               // LDS per workgroup (slots, zero and sink slots, coefficients, D blocks, outslots)
     int gslots;                  // 1: the slots (nslots + 2 per quartet) live in the scratch buffer, not in LDS
     const T3Class *lane;         // gslots: the lane-per-quartet tables, run for batches of T3G_LANE_MIN or more
+    int out_blocks;              // output blocks per quartet: 0 or 1 for integrals, 12 for first derivatives
 };
 
 // Wave-cooperative variant (tier 3): the same tables regrouped T3W_OPS ops a
@@ -52,5 +56,20 @@ void t3_launch_jk(const T3Class &c, const JKArgs &a, hipStream_t s);
 void t3_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s);
 void t3w_launch_jk(const T3Class &c, const JKArgs &a, hipStream_t s);
 void t3w_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s);
+
+// First-derivative integrals (tables of gen/emit_deriv.py, wave form with the
+// slots in LDS): per task the 12 blocks [centre][axis] of n_a n_b n_c n_d
+// values at a.out + t.off + (3 * centre + axis) * n_a n_b n_c n_d, elements
+// placed by the task's strides, where centre is the requested position of
+// the canonical shell: bits 2r, 2r + 1 of code[t.bra / 2] for canonical shell r.
+void t3w_launch_deriv(const T3Class &c, const EriArgs &a, const int32_t *code, hipStream_t s);
+
+// The derivative tables built into the library, per canonical class.
+struct DerivClass {
+    int la, lb, lc, ld;
+    const T3Class *t;
+};
+extern const DerivClass g_deriv_table[];
+extern const int g_num_deriv;
 
 }  // namespace hgp

@@ -310,6 +310,7 @@ __global__ __launch_bounds__(64) void t3_eri_kernel(T3Params c, const uint4 *__r
 
 struct T3WParams {
     int L, na, nb, nc, nd, n_hrr, acc0, n_vrr, n_p2, nslots, ncoef, maxblk, nint;
+    int deriv;      // 1: derivative tables, whose ACC_W ops read 2a, 2b, 2c from slots L + 1 .. L + 3
 };
 
 // G = false: slots in LDS; a compiler-level barrier suffices.  G = true: slots
@@ -406,16 +407,18 @@ __device__ __forceinline__ void t3w_vrr_group(const uint4 *o, const double *__re
     for (int k = 0; k < T3W_K; ++k) S[o[k].x >> 16] = r[k];
 }
 
+// ACC: dst += src; ACC_W: dst += S[w] * src (w: a per-primitive weight slot).
 __device__ __forceinline__ void t3w_acc_group(const uint4 *o, double *__restrict__ S)
 {
-    double x[T3W_K], y[T3W_K];
+    double x[T3W_K], y[T3W_K], w[T3W_K];
 #pragma unroll
     for (int k = 0; k < T3W_K; ++k) {
         x[k] = S[o[k].x >> 16];
         y[k] = S[o[k].y & 0xFFFFu];
+        w[k] = (o[k].x & 15u) == (uint32_t)T3_ACC_W ? S[o[k].y >> 16] : 1.0;
     }
 #pragma unroll
-    for (int k = 0; k < T3W_K; ++k) S[o[k].x >> 16] = x[k] + y[k];
+    for (int k = 0; k < T3W_K; ++k) S[o[k].x >> 16] = fma(w[k], y[k], x[k]);
 }
 
 struct T3WHrr {
@@ -491,6 +494,10 @@ __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__r
             q.WQx = q.re * PQx; q.WQy = q.re * PQy; q.WQz = q.re * PQz;
             const double T = b.zeta * q.rz * (PQx * PQx + PQy * PQy + PQz * PQz);
             t3w_boys(T, c.L, boys, b.k * e.k * hgp_rsqrt(ze), S, lane);
+            if (c.deriv && lane >= 61) {                    // derivative weights 2a, 2b, 2c (slots past the Boys values)
+                const double wv = lane == 61 ? b.ea : (lane == 62 ? b.eb : e.ea);
+                S[c.L + lane - 60] = 2.0 * wv;
+            }
             if (lane < 16) {                                // the constants record, one value a lane
                 const double rv[16] = {q.PAx, q.WPx, q.PAy, q.WPy, q.PAz, q.WPz, q.QCx, q.WQx,
                                        q.QCy, q.WQy, q.QCz, q.WQz, q.o2z, q.rz,  q.o2e, q.re};
@@ -513,7 +520,8 @@ __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__r
                     o[k] = nx[k];
                     nx[k] = myops[(size_t)(g + 1) * T3W_OPS + k * T3W_GROUP];
                 }
-                if ((__builtin_amdgcn_readfirstlane(o[0].x) & 15u) == (uint32_t)T3_ACC)
+                const uint32_t kind = __builtin_amdgcn_readfirstlane(o[0].x) & 15u;
+                if (kind == (uint32_t)T3_ACC || kind == (uint32_t)T3_ACC_W)
                     t3w_acc_group(o, S);
                 else
                     t3w_vrr_group(o, R, q.o2ze, S);
@@ -692,6 +700,38 @@ __global__ __launch_bounds__(64) void t3w_eri_kernel(T3WParams c, const uint4 *_
             }
 }
 
+// First-derivative integrals of quartet i (tables from gen/emit_deriv.py):
+// the 12 blocks [centre][axis] of the canonical class, canonical centre r's
+// written to the requested centre (code[t.bra / 2] >> 2r) & 3 of the
+// shell-quartet classifier.
+template <bool G>
+__global__ __launch_bounds__(64) void t3w_deriv_kernel(T3WParams c, const uint4 *__restrict__ ops,
+                                                       const double *__restrict__ coefs,
+                                                       const uint16_t *__restrict__ outslots, EriArgs a,
+                                                       const int32_t *__restrict__ code)
+{
+    const int64_t i = blockIdx.x;
+    if (i >= a.ntask) return;
+    const int lane = threadIdx.x;
+    const T3WLds l = t3w_lds<G>(c, t3w_smem, G ? a.scratch + (size_t)i * (size_t)(c.nslots + 2) : nullptr, coefs,
+                                outslots, lane);
+    const EriTask t = a.tasks[i];
+    const PairInfo pb = a.pairs[t.bra], pk = a.pairs[t.ket];
+    const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];
+    t3w_quartet<G>(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, l.R, lane);
+    const int na = c.na, nb = c.nb, nc = c.nc, nd = c.nd;
+    const int nint = na * nb * nc * nd;
+    const int32_t pos = code[t.bra >> 1];
+    double *__restrict__ o = a.out + t.off;
+    for (int k = lane; k < 12 * nint; k += T3W_GROUP) {
+        const int blk = k / nint, r = k - blk * nint;          // blk = 3 * centre + axis
+        const int centre = blk / 3, axis = blk - 3 * centre;
+        const int req = (pos >> (2 * centre)) & 3;
+        const int sig = r % nd, lam = (r / nd) % nc, nu = (r / (nd * nc)) % nb, mu = r / (nd * nc * nb);
+        o[(int64_t)(3 * req + axis) * nint + mu * t.s0 + nu * t.s1 + lam * t.s2 + sig * t.s3] = l.S[l.O[k]];
+    }
+}
+
 // Device copies of a class's tables, uploaded on first use on each device
 // and kept until the process ends.
 std::mutex g_t3_mutex;
@@ -709,7 +749,8 @@ hipError_t t3_device_tables(const T3Class &c, T3Dev *out)
         return hipSuccess;
     }
     // zero groups past the end: the wave variant loads group g + 1 while it runs group g
-    const size_t nops = (size_t)(c.n_vrr + c.n_p2), nout = (size_t)c.na * c.nb * c.nc * c.nd;
+    const size_t nops = (size_t)(c.n_vrr + c.n_p2),
+                 nout = (size_t)c.na * c.nb * c.nc * c.nd * (size_t)(c.out_blocks > 1 ? c.out_blocks : 1);
     const size_t npad = (size_t)T3W_PREFETCH * T3W_OPS;
     void *ops = nullptr, *coefs = nullptr, *outs = nullptr;
     if ((e = hipMalloc(&ops, (nops + npad) * 16)) != hipSuccess ||
@@ -761,6 +802,8 @@ int t3_prepare(const T3Class &c)
                 if ((e = hipFuncSetAttribute((const void *)t3w_jk_kernel<false>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, maxlds)) != hipSuccess ||
                     (e = hipFuncSetAttribute((const void *)t3w_eri_kernel<false>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, maxlds)) != hipSuccess ||
+                    (e = hipFuncSetAttribute((const void *)t3w_deriv_kernel<false>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, maxlds)) != hipSuccess)
                     return (int)e;
                 raised[dev] = true;
@@ -833,6 +876,18 @@ void t3w_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s)
     } else
         hipLaunchKernelGGL(t3w_eri_kernel<false>, dim3((unsigned)a.ntask), dim3(T3W_GROUP), (unsigned)c.lds_bytes, s,
                            wparams(c), d.ops, d.coefs, d.outslots, a);
+}
+
+void t3w_launch_deriv(const T3Class &c, const EriArgs &a, const int32_t *code, hipStream_t s)
+{
+    T3Dev d;
+    if (a.ntask <= 0 || c.lds_bytes <= 0 || c.gslots || c.out_blocks != 12 || t3_device_tables(c, &d) != hipSuccess)
+        return;
+    T3WParams p = wparams(c);
+    p.nint *= 12;
+    p.deriv = 1;
+    hipLaunchKernelGGL(t3w_deriv_kernel<false>, dim3((unsigned)a.ntask), dim3(T3W_GROUP), (unsigned)c.lds_bytes, s, p,
+                       d.ops, d.coefs, d.outslots, a, code);
 }
 
 void t3_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s)

@@ -28,12 +28,13 @@ struct PairGeo {
 // Per primitive pair, 64 bytes (one half cache line):
 // zeta = a + b, 1/(2 zeta), P = (a A + b B)/zeta and
 // K = c_a c_b exp(-a b |AB|^2 / zeta) * sqrt(2) pi^(5/4) / zeta, so that the
-// base integral of a primitive quartet is K_ab K_cd / sqrt(zeta + eta) * F_m(T).
+// base integral of a primitive quartet is K_ab K_cd / sqrt(zeta + eta) * F_m(T);
+// the exponents a and b themselves (the weights of derivative integrals).
 struct PrimPair {
     double zeta, o2z;
     double px, py, pz;
     double k;
-    double pad0, pad1;
+    double ea, eb;
 };
 
 // Integrals-out work item: canonical (bra, ket) pair indices and where each
@@ -129,7 +130,7 @@ struct ClassKernels {
     launch_eri_fn eri;
     launch_p1_fn p1;        // staged tier only (nullptr otherwise)
     prepare_fn prepare;     // HBM-scratch tier: uploads the class tables to the current device (0 on success)
-    launch_jk_fn jk32;      // register tier: VRR/HRR in FP32, digestion in FP64 (mixed plans), or nullptr
+    launch_jk_fn jk32;      // register tier: VRR and contraction in FP32, HRR and digestion in FP64 (mixed plans), or nullptr
     int block;              // threads per block
     double vrr_flops;       // per primitive quartet (generator count)
     double p2_flops;        // per contracted quartet: HRR + transform

@@ -21,6 +21,8 @@ temporaries.  An op is eight uint16 words:
       with (X, Y, o2, r) = (P-A, W-P, 1/(2 zeta), rho/zeta) on the bra side
       and (Q-C, W-Q, 1/(2 eta), rho/eta) on the ket side (Eq. vrr);
   ACC                dst += p1 (a target into its accumulator);
+  ACC_W              dst += w2 * p1, w2 a slot the kernel fills per primitive
+                     quartet (the exponent weights of derivative integrals);
   HRR_BRA / HRR_KET  dst = p1 + (A-B or C-D)[axis] p2 (Eq. hrr);
   LIN / LIN_ACC      dst (+)= c[w5] p1 + c[w6] p2 + c[w7] p3 (a row of the
                      T^(l) transforms, three terms per op, coefficients from
@@ -35,7 +37,7 @@ from . import vrr as vrrmod
 from .cart import nsph
 from .emit import ClassMeta, tag_of
 
-OP_VRR_BRA, OP_VRR_KET, OP_ACC, OP_HRR_BRA, OP_HRR_KET, OP_LIN, OP_LIN_ACC = 1, 2, 3, 4, 5, 6, 7
+OP_VRR_BRA, OP_VRR_KET, OP_ACC, OP_HRR_BRA, OP_HRR_KET, OP_LIN, OP_LIN_ACC, OP_ACC_W = 1, 2, 3, 4, 5, 6, 7, 8
 NONE = 0xFFFF
 XYZ_AXIS = {"x": 0, "y": 1, "z": 2}
 
@@ -134,24 +136,37 @@ def build_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None, bundle=BUNDLE)
     g = vrrmod.VRRGraph(*ls, rule=rule)
     sched, pl, order = vrrmod.best_order(g) if schedulers is None else vrrmod.best_order(g, schedulers)
     n_hrr = len(g.targets)
-    acc0 = L + 1
-    tpos = {tid: k for k, tid in enumerate(g.target_ids)}
+    accs = {tid: [(k, None)] for k, tid in enumerate(g.target_ids)}
+    hname = {t: f"h{k}" for k, t in enumerate(g.targets)}
+    p2 = p2mod.Phase2(la, lb, lc, ld, hname=lambda e, f: hname[(e, f)])
+    na, nb, nc, nd = (nsph(x) for x in ls)
+    out_names = [p2.out[(mu, nu, lam, sig)] for mu in range(na) for nu in range(nb)
+                 for lam in range(nc) for sig in range(nd)]
+    return assemble_tables(g, order, sched, pl, L, L + 1, n_hrr, accs, p2.ops, out_names, g.flops(), p2.flops,
+                           bundle, tag_of(ls))
 
+
+def assemble_tables(g, order, sched, pl, L, acc0, n_acc, accs, p2ops, out_names, vrr_flops, p2_flops, bundle,
+                    tag) -> T3Tables:
+    """Slot-packed op tables from a VRR graph run in `order`, accumulations
+    accs[node] = [(accumulator k, weight slot or None), ...] (a weighted
+    accumulation adds slot * value), and a Phase-2 op list (SSA, see
+    gen/phase2.py) over the accumulators named h<k>, whose results
+    out_names are the outputs, in order.  Slots 0..L hold base * F_m(T);
+    slots L + 1 .. acc0 - 1 are left to the kernel (per-primitive weights)."""
     # ---- abstract ops of the per-primitive part: VRR nodes in schedule
-    # order, each target followed by its accumulation
+    # order, each target followed by its accumulations
     aops = []
     for v in order:
         nd = g.nodes[v]
         if nd.kind != "base":
             aops.append({"kind": "vrr", "out": ("n", v), "ins": [("n", x) for x in nd.parents if x is not None],
                          "node": v})
-        if v in tpos:
-            aops.append({"kind": "acc", "out": None, "ins": [("n", v)], "acc": acc0 + tpos[v]})
-    # ---- Phase 2: HRR + stepwise transforms over the accumulators
-    hname = {t: f"h{k}" for k, t in enumerate(g.targets)}
-    p2 = p2mod.Phase2(la, lb, lc, ld, hname=lambda e, f: hname[(e, f)])
+        for k, ws in accs.get(v, ()):
+            aops.append({"kind": "acc", "out": None, "ins": [("n", v)], "acc": acc0 + k, "w": ws})
+    # ---- Phase 2: the given ops over the accumulators
     pops = []
-    for o in p2.ops:
+    for o in p2ops:
         if o[1] == "hrr":
             pops.append({"kind": "hrr", "out": ("p", o[0]), "ins": [("p", o[2]), ("p", o[3])], "op": o})
         else:
@@ -185,7 +200,7 @@ def build_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None, bundle=BUNDLE)
         for k in grp:
             for x in aops[k]["ins"]:
                 last[x] = gi
-    alloc = _Slots(acc0 + n_hrr)
+    alloc = _Slots(acc0 + n_acc)
     for gi, grp in enumerate(vgroups):
         for k in grp:
             o = aops[k]
@@ -196,30 +211,32 @@ def build_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None, bundle=BUNDLE)
                 p = [slot[("n", x)] if x is not None else NONE for x in nd.parents]
                 code = OP_VRR_BRA if nd.kind == "bra" else OP_VRR_KET
                 emit((code | (nd.axis << 4) | (nd.k_same << 6) | (nd.k_cross << 11), s, *p, NONE))
-            else:
+            elif o.get("w") is None:
                 emit((OP_ACC, o["acc"], slot[o["ins"][0]], NONE, NONE, NONE, NONE, NONE))
+            else:
+                emit((OP_ACC_W, o["acc"], slot[o["ins"][0]], o["w"], NONE, NONE, NONE, NONE))
             n_real += 1
         pad(len(grp))
         for k in grp:
             o = aops[k]
             if o["kind"] == "vrr" and last.get(o["out"], -1) <= gi and g.nodes[o["node"]].kind != "base":
                 alloc.put(slot[o["out"]])        # never read again (a target, accumulated in this group)
-        for x in {x for k in grp for x in aops[k]["ins"]}:
+        for x in sorted({x for k in grp for x in aops[k]["ins"]}):      # sorted: the same tables every run
             if last.get(x) == gi and x in slot and slot[x] > L:
                 alloc.put(slot[x])
     n_vrr = len(words) // 8
     vrr_top = alloc.next
 
     # ---- slots, Phase 2: inputs are the accumulators; VRR temporaries are free
-    name_slot = {("p", f"h{k}"): acc0 + k for k in range(n_hrr)}
-    outputs = {("p", v) for v in p2.out.values()}
+    name_slot = {("p", f"h{k}"): acc0 + k for k in range(n_acc)}
+    outputs = {("p", v) for v in out_names}
     last = {}
     for gi, grp in enumerate(pgroups):
         for k in grp:
             for x in pops[k]["ins"]:
                 last[x] = gi
     alloc2 = _Slots(vrr_top)
-    alloc2.free = sorted(range(acc0 + n_hrr, vrr_top), reverse=True)
+    alloc2.free = sorted(range(acc0 + n_acc, vrr_top), reverse=True)
     coefs, cidx = [], {}
 
     def coef(c):
@@ -248,17 +265,15 @@ def build_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None, bundle=BUNDLE)
                 emit((OP_LIN if o["kind"] == "lin" else OP_LIN_ACC, s, *srcs, *cs))
             n_real += 1
         pad(len(grp))
-        for x in {x for k in grp for x in pops[k]["ins"]}:
+        for x in sorted({x for k in grp for x in pops[k]["ins"]}):
             if last.get(x) == gi and x not in outputs:
                 alloc2.put(name_slot[x])
     n_p2 = len(words) // 8 - n_vrr
     nslots = max(alloc2.next, vrr_top)
     if nslots > 0xFFFE or len(coefs) > 0xFFFF:
-        raise ValueError(f"class {tag_of(ls)}: {nslots} slots do not fit 16-bit slot indices")
-    na, nb, nc, nd = (nsph(x) for x in ls)
-    outslots = [name_slot[("p", p2.out[(mu, nu, lam, sig)])] for mu in range(na) for nu in range(nb)
-                for lam in range(nc) for sig in range(nd)]
-    return T3Tables(words, n_vrr, n_p2, coefs, outslots, nslots, n_hrr, acc0, L, pl, sched, g.flops(), p2.flops,
+        raise ValueError(f"class {tag}: {nslots} slots do not fit 16-bit slot indices")
+    outslots = [name_slot[("p", v)] for v in out_names]
+    return T3Tables(words, n_vrr, n_p2, coefs, outslots, nslots, n_acc, acc0, L, pl, sched, vrr_flops, p2_flops,
                     n_real)
 
 
@@ -288,15 +303,20 @@ def wave_layout(ls, t, gslots=False):
     """(maxblk, LDS doubles, LDS bytes); gslots: the slots are not in LDS."""
     na, nb, nc, nd = (nsph(x) for x in ls)
     maxblk = max(na * nb, nc * nd, na * nc, nb * nc, na * nd, nb * nd)
-    nint = na * nb * nc * nd
+    nint = len(t.outslots)            # the integrals (12 blocks of them for derivative tables)
     doubles = (0 if gslots else t.nslots + 2) + max(len(t.coefs), 1) + 6 * maxblk
     # then the uint16 output-slot map (padded to 16 bytes) and the 16-double VRR constants record
     return maxblk, doubles, doubles * 8 + ((2 * nint + 15) // 16) * 16 + 16 * 8
 
 
 def build_wave_tables(la, lb, lc, ld, rule="ket_zyx", schedulers=None) -> WaveTables:
-    ls = (la, lb, lc, ld)
-    t = build_tables(la, lb, lc, ld, rule, schedulers, bundle=WAVE)
+    return build_wave_tables_from(build_tables(la, lb, lc, ld, rule, schedulers, bundle=WAVE), (la, lb, lc, ld))
+
+
+def build_wave_tables_from(t, ls) -> WaveTables:
+    """The wave form of tables t built with bundle = WAVE (class ls: the D
+    and output blocks of the layout)."""
+    assert (t.n_vrr + t.n_p2) % WAVE == 0, "tables grouped for the lane form"
     Z, SINK = t.nslots, t.nslots + 1
     ops = []
     words = t.ops

@@ -119,3 +119,13 @@ def test_class_form_query():
     assert h.hgp_class_form(5, 0, 0, 0, ctypes.byref(t), None) == -2
     assert h.hgp_class_form(-1, 0, 0, 0, None, None) == -1
     assert h.hgp_class_form(1, 1, 0, 0, None, None) == 0
+
+
+def test_deriv_entry_host_checks():
+    """The derivative integrals entry: built for l <= 2, argument errors
+    before any device work."""
+    import paper_2605_10312_amd as hgp
+    h = hgp.lib()
+    assert hgp.deriv_max_l() == 2
+    assert h.hgp_eri_deriv_shell_quartets(None, 1, None, None, None, None) == -1
+    assert h.hgp_eri_deriv_shell_quartets(None, -1, None, None, None, None) == -1

@@ -23,9 +23,11 @@ def _norm(a, l):
     return (2 * a / np.pi) ** 0.75 * (4 * a) ** (0.5 * l) / np.sqrt(df)
 
 
-def run_tables(t, ls, centers, exps, ops=None, K=None, zero=None):
+def run_tables(t, ls, centers, exps, ops=None, K=None, zero=None, weights=False, shape=None):
     """Run tables t on the quartets; ops/K/zero: the wave-cooperative form
-    (its own words, groups of K ops, absent operands naming slot zero)."""
+    (its own words, groups of K ops, absent operands naming slot zero).
+    weights: fill slots L+1..L+3 with 2a, 2b, 2c of each primitive quartet
+    (the derivative tables' ACC_W weights).  shape: of one quartet's outputs."""
     n = centers.shape[0]
     A, B, C, D = (centers[:, k, :].T for k in range(4))          # [3, n]
     a, b, c, d = (exps[:, k] for k in range(4))
@@ -42,6 +44,8 @@ def run_tables(t, ls, centers, exps, ops=None, K=None, zero=None):
     sb = np.zeros((t.nslots + 2, n))
     for m in range(t.L + 1):
         sb[m] = base * hyp1f1(m + 0.5, m + 1.5, -T) / (2 * m + 1)
+    if weights:
+        sb[t.L + 1], sb[t.L + 2], sb[t.L + 3] = 2 * a, 2 * b, 2 * c
     PA, QC, WP, WQ = P - A, Q - C, -rz * PQ, re * PQ
     o2z, o2e = 0.5 / zeta, 0.5 / eta
     AB, CD = A - B, C - D
@@ -59,7 +63,8 @@ def run_tables(t, ls, centers, exps, ops=None, K=None, zero=None):
     for g0 in range(0, len(ops), K):
         grp = [w for w in ops[g0:g0 + K] if w[0] != 0]
         codes = {w[0] & 15 for w in grp}
-        assert len({0 if c in (1, 2) else c if c < 6 else 6 for c in codes} - {4, 5} | ({4} if codes & {4, 5} else set())) == 1
+        kinds = {0 if c in (1, 2) else 3 if c in (3, 8) else c if c < 6 else 6 for c in codes}
+        assert len(kinds - {4, 5} | ({4} if codes & {4, 5} else set())) == 1
         reads = [[val(s) for s in w[2:7]] + [sb[w[1]].copy()] for w in grp]
         for w, r in zip(grp, reads):
             code, axis = w[0] & 15, (w[0] >> 4) & 3
@@ -67,6 +72,8 @@ def run_tables(t, ls, centers, exps, ops=None, K=None, zero=None):
             assert dst < t.nslots
             if code == emit_t3.OP_ACC:
                 sb[dst] = r[5] + r[0]
+            elif code == emit_t3.OP_ACC_W:
+                sb[dst] = r[5] + r[1] * r[0]
             elif code in (emit_t3.OP_VRR_BRA, emit_t3.OP_VRR_KET):
                 ks, kc = (w[0] >> 6) & 31, (w[0] >> 11) & 31
                 X, Y, o2, rr = (PA, WP, o2z, rz) if code == emit_t3.OP_VRR_BRA else (QC, WQ, o2e, re)
@@ -86,7 +93,7 @@ def run_tables(t, ls, centers, exps, ops=None, K=None, zero=None):
                         v = v + coefs[ci] * x
                 sb[dst] = v
     out = sb[np.array(t.outslots)].T
-    return out.reshape([n] + [2 * l + 1 for l in ls])
+    return out.reshape([n] + (list(shape) if shape else [2 * l + 1 for l in ls]))
 
 
 @pytest.mark.parametrize("ls,n", [((0, 0, 0, 0), 4), ((1, 0, 1, 0), 4), ((2, 1, 1, 0), 4), ((2, 2, 2, 2), 4),
