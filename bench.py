@@ -453,6 +453,95 @@ def plan_sizes(args):
         torch.cuda.empty_cache()
 
 
+def deriv_bench(args):
+    """First-derivative integrals (hgp_eri_deriv_shell_quartets) of a uniform
+    sample of the 30-atom 3s2p1d workload's screened unique shell quartets,
+    quartet and offset arrays on the device.  One JSON line: derivative
+    integrals per second (12 n_sph^4 per quartet), the algorithmic FLOP rate
+    of the derivative tables (per class: primitive quartets x per-primitive
+    ops + quartets x Phase-2 ops of gen/emit_deriv.py) against the FP64
+    peak, the error of sampled quartets against the long-double oracle, and
+    the oracle timed on the host cores."""
+    import torch
+    import oracle
+    import paper_2605_10312_amd as hgp
+    import workloads
+
+    bw, _ = workloads.molecule_3s2p1d()
+    Q = oracle.schwarz(bw)
+    ns = bw.nshell
+    rng = np.random.default_rng(2005)
+    want = args.deriv_quartets
+    picked = []
+    while len(picked) < want:
+        q = rng.integers(0, ns, (4 * want, 4))
+        i, j, k, l = q.T
+        keep = (i >= j) & (k >= l) & (i * (i + 1) // 2 + j >= k * (k + 1) // 2 + l) & (Q[i, j] * Q[k, l] >= TAU)
+        picked.extend(map(tuple, q[keep][: want - len(picked)]))
+    quartets = np.array(picked, np.int32)
+    sizes = np.array([12 * int(np.prod([2 * bw.l[s] + 1 for s in q])) for q in quartets], np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    b = hgp.Basis.from_workload(bw)
+    qd = torch.tensor(quartets, device="cuda")
+    od = torch.tensor(offs, device="cuda")
+    out = torch.empty(int(sizes.sum()), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        hgp.eri_shell_quartets(b, qd, od, out, deriv=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hgp.eri_shell_quartets(b, qd, od, out, deriv=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    # algorithmic FLOPs of the tables
+    info = {d["tag"]: d for d in json.load(open(os.path.join(os.path.dirname(os.path.abspath(hgp.__file__)),
+                                                               "_gen", "deriv.json")))}
+    nprim = np.asarray(bw.nprim)
+    flop = 0.0
+    for q in quartets:
+        ls = [int(bw.l[s]) for s in q]
+        a_, b_ = sorted(ls[:2], reverse=True)
+        c_, d_ = sorted(ls[2:], reverse=True)
+        if (a_ * (a_ + 1) // 2 + b_) < (c_ * (c_ + 1) // 2 + d_):
+            a_, b_, c_, d_ = c_, d_, a_, b_
+        t = info[f"{a_}{b_}{c_}{d_}"]
+        flop += float(np.prod(nprim[list(q)])) * t["vrr_flops"] + t["p2_flops"]
+    got = out.cpu().numpy()
+    chk = rng.choice(len(quartets), 8, replace=False)
+    errs = []
+    for i in chk:
+        ref = oracle.eri_deriv_shell_quartet(bw, *quartets[i], precision="long double")
+        g = got[offs[i]:offs[i] + sizes[i]].reshape(ref.shape)
+        errs.append((np.abs(g - ref).max(), np.abs(ref).max()))
+    # the oracle on the host cores: the same derivative blocks of a bounded sample
+    t0 = time.perf_counter()
+    n_cpu = 0
+    ints_cpu = 0
+    while time.perf_counter() - t0 < args.cpu_seconds / 3 and n_cpu < len(quartets):
+        oracle.eri_deriv_shell_quartet(bw, *quartets[n_cpu])
+        ints_cpu += int(sizes[n_cpu])
+        n_cpu += 1
+    cpu_rate = ints_cpu / (time.perf_counter() - t0)
+    value = float(sizes.sum()) / dt
+    line = {"metric": "first-derivative contracted integrals/s", "value": value, "unit": "derivative integrals/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"deriv_mol30_3s2p1d: {len(quartets)} uniformly drawn screened unique shell "
+                                   "quartets of the 30-atom 3s2p1d molecule (tau 1e-12), d/dR of all four centres, "
+                                   "12 blocks each, FP64",
+                       "quartets": int(len(quartets))},
+            "roofline": {"bound": "alu", "kernel": "t3w_deriv_kernel", "achieved": round(flop / dt / 1e12, 3),
+                         "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(flop / dt / 1e12 / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None},
+            "cpu_baseline": {"value": cpu_rate, "unit": "derivative integrals/s", "cores": oracle.num_threads(),
+                             "kind": "oracle", "sample": f"the first {n_cpu} quartets of the same sample, one at a "
+                                                         "time (oracle_eri_deriv_shell_quartet)"},
+            "err": {"quartets_checked": len(chk), "max_abs_vs_long_double": float(max(e for e, _ in errs)),
+                    "max_abs_derivative": float(max(m for _, m in errs))}}
+    print(json.dumps(line), flush=True)
+    b.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -465,10 +554,13 @@ def main():
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: quartets with Q_ab Q_cd < theta use FP32 VRR and contraction (register tier; HRR, Boys, J/K FP64)")
     ap.add_argument("--theta", type=float, default=None, help="mixed-precision threshold (default: the library's)")
-    ap.add_argument("--workload", choices=("mol30", "microbench", "batch", "serve", "plan-sizes"), default="mol30",
+    ap.add_argument("--workload", choices=("mol30", "microbench", "batch", "serve", "plan-sizes", "deriv"),
+                    default="mol30",
                     help="mol30: the J/K build (one JSON line); microbench: the high-l primitive-quartet classes; "
                          "batch: many uneven systems in one HIP graph; serve: continuous batching of requests; "
-                         "plan-sizes: plans of the batched and served workloads' largest members")
+                         "plan-sizes: plans of the batched and served workloads' largest members; "
+                         "deriv: first-derivative integrals of sampled quartets of the 30-atom workload")
+    ap.add_argument("--deriv-quartets", type=int, default=20000, help="deriv: quartets in the sample")
     ap.add_argument("--plan-jk", action="store_true", help="plan-sizes: also run the 60-atom member's J/K once")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-updates", type=int, default=10)
@@ -505,6 +597,9 @@ def main():
         return
     if args.workload == "plan-sizes":
         plan_sizes(args)
+        return
+    if args.workload == "deriv":
+        deriv_bench(args)
         return
 
     import torch

@@ -137,6 +137,8 @@ def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overri
     dtable = os.path.join(GEN, "deriv_table.hip")
     _write_if_changed(dtable, emit_deriv.emit_deriv_table(dclasses))
     files.append(dtable)
+    _write_if_changed(os.path.join(GEN, "deriv.json"),
+                      json.dumps([_EMITTED[("deriv", tuple(ls))][1] for ls in dclasses], indent=1))
     _write_if_changed(os.path.join(GEN, "classes.json"),
                       json.dumps([{k: v for k, v in m.__dict__.items() if k != "extra_sources"} for m in metas],
                                  indent=1, default=list))
