@@ -619,62 +619,72 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
     # doubles), runs the bra HRR + T(la) T(lb), and writes the (mu nu|lam sig)
     # values, which for a fixed (mu, nu) lie next to each other in the
     # caller's block, so the stores are coalesced too.
+    # A wave takes P = 64 // ncd quartets at once when several fit (lanes
+    # sub * ncd .. sub * ncd + ncd - 1 for quartet sub); the Schwarz mode
+    # (one value per quartet, a reduction over the quartet's lanes) runs P = 1.
     diag_class = (la, lb) == (lc, ld)
     ncd = plan.ncd
     assert ncd <= 64, "one ket function per lane"
     NS = plan.nslots
+    P = max(1, 64 // ncd)
     wops, wins, wouts = plan.wave_bra()
     nt = len(plan.tile_rows)
+
+    def zbase(q):
+        return f"a.scratch + (uint64_t)({q}) * {NS}u" if eri_layout == "quartet" else f"a.scratch + ({q})"
+
+    w("template <int P>")
     w(f"__global__ __launch_bounds__(64) void eri_{tag}(EriArgs a)")
     w("{")
     if nt:
-        w(f"    __shared__ double zt[{nt * ncd}];")
-    w("    const int64_t i = blockIdx.x;                 // quartet of the batch")
-    w("    if (i >= a.ntask) return;")
+        w(f"    __shared__ double zt[P * {nt * ncd}];")
     w("    const int j = threadIdx.x;")
+    w("    const int64_t q0 = (int64_t)blockIdx.x * P;      // first quartet of this wave")
+    w("    if (q0 >= a.ntask) return;")
+    w(f"    const int sub = P == 1 ? 0 : j / {ncd};")
+    w(f"    const int jj = j - sub * {ncd};                  // ket function of this lane")
+    w(f"    const bool act = sub < P && jj < {ncd} && q0 + sub < a.ntask;")
+    w("    const int64_t i = act ? q0 + sub : q0;")
     w("    const EriTask t = a.tasks[i];")
-    if eri_layout == "quartet":
-        w(f"    const double *__restrict__ zq = a.scratch + (uint64_t)i * {NS}u;")
-        w("    const uint32_t ZS = 1u;")
-    else:
-        w("    const double *__restrict__ zq = a.scratch + i;")
-        w("    const uint32_t ZS = (uint32_t)a.stride;")
+    w(f"    const double *__restrict__ zq = {zbase('i')};")
+    w(f"    const uint32_t ZS = {'1u' if eri_layout == 'quartet' else '(uint32_t)a.stride'};")
     if nt:
         tops, tins, touts = plan.wave_ket()
-        w("    {")
-        w("        const PairGeo gk = a.geo[t.ket];")
+        w(f"    for (int job = j; job < P * {nt}; job += 64) {{   // tiled row tr of quartet qs")
+        w(f"        const int qs = job / {nt}, tr = job - qs * {nt};")
+        w("        if (q0 + qs >= a.ntask) continue;")
+        w("        const EriTask etask = a.tasks[q0 + qs];")
+        w("        const PairGeo gk = a.geo[etask.ket];")
         w("        const double CDx = gk.abx, CDy = gk.aby, CDz = gk.abz;")
         w("        (void)CDx; (void)CDy; (void)CDz;")
-        w(f"        for (int tr = j; tr < {nt}; tr += 64) {{   // tiled row tr")
-        w(f"            const double *__restrict__ hrow = zq + ({plan.hslot(0, 0)}u + tr * {len(F)}u) * ZS;")
+        w(f"        const double *__restrict__ hrow = {zbase('q0 + qs')} + ({plan.hslot(0, 0)}u + tr * {len(F)}u) * ZS;")
         tused = {n for op in tops for n in _names_in(op)} | set(touts.values())
         for k, f in enumerate(F):
             nm = tins[f]
             if nm in tused:
-                w(f"            const double {nm} = hrow[{k}u * ZS];")
+                w(f"        const double {nm} = hrow[{k}u * ZS];")
         for op in tops:
-            w("            " + _op_line(op, {}))
+            w("        " + _op_line(op, {}))
         for lam in range(nc):
             for sig in range(nd):
-                w(f"            zt[tr * {ncd} + {lam * nd + sig}] = {touts[(lam, sig)]};")
-        w("        }")
+                w(f"        zt[(qs * {nt} + tr) * {ncd} + {lam * nd + sig}] = {touts[(lam, sig)]};")
         w("    }")
         w("    __syncthreads();")
     w("    const PairGeo gb = a.geo[t.bra];")
     w("    const double ABx = gb.abx, ABy = gb.aby, ABz = gb.abz;")
     w("    (void)ABx; (void)ABy; (void)ABz;")
     w("    double dg = 0.0;")
-    w(f"    if (j < {ncd}) {{")
-    w(f"        const int lam = j / {nd}, sig = j - lam * {nd};")
+    w("    if (act) {")
+    w(f"        const int lam = jj / {nd}, sig = jj - lam * {nd};")
     used = {n for op in wops for n in _names_in(op)} | set(wouts.values())
     for k, e in enumerate(E):
         nm = wins[e]
         if nm not in used:
             continue
         if e in tile_index:
-            w(f"        const double {nm} = zt[{tile_index[e] * ncd} + j];")
+            w(f"        const double {nm} = zt[(sub * {nt} + {tile_index[e]}) * {ncd} + jj];")
         else:
-            w(f"        const double {nm} = zq[({plan.zslot(k, 0, 0)}u + j) * ZS];")
+            w(f"        const double {nm} = zq[({plan.zslot(k, 0, 0)}u + jj) * ZS];")
     for op in wops:
         w("        " + _op_line(op, {}))
     w("        if (a.mode == 0) {")
@@ -689,7 +699,7 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
                 w(f"        if (lam == {mu} && sig == {nu}) dg = fabs({wouts[(mu, nu)]});")
     w("    }")
     if diag_class:
-        w("    if (a.mode == 1) {                             // Schwarz factor: largest diagonal element")
+        w("    if (P == 1 && a.mode == 1) {                  // Schwarz factor: largest diagonal element")
         w("#pragma unroll")
         w("        for (int o = 32; o > 0; o >>= 1) dg = fmax(dg, __shfl_xor(dg, o, 64));")
         w("        if (j == 0) a.out[i] = sqrt(dg);")
@@ -756,7 +766,13 @@ def emit_class_row(la, lb, lc, ld, budget=REGISTER_DOUBLES, rule="ket_zyx", bloc
         w("}")
     w(f"void launch_eri_{tag}(const EriArgs &a, hipStream_t s)")
     w("{")
-    w(f"    if (a.ntask > 0) hipLaunchKernelGGL(eri_{tag}, dim3((unsigned)a.ntask), dim3(64), 0, s, a);")
+    w("    if (a.ntask <= 0) return;")
+    if P > 1:
+        w("    if (a.mode == 0) {")
+        w(f"        hipLaunchKernelGGL(eri_{tag}<{P}>, dim3((unsigned)((a.ntask + {P - 1}) / {P})), dim3(64), 0, s, a);")
+        w("        return;")
+        w("    }")
+    w(f"    hipLaunchKernelGGL(eri_{tag}<1>, dim3((unsigned)a.ntask), dim3(64), 0, s, a);")
     w("}")
 
     w("")

@@ -209,7 +209,10 @@ def test_row_emitter_source():
     assert meta.parts == -(-meta.chunks // emit_row.P1_PART_CHUNKS) > 1
     assert all(f"launch_p1_3333p{k}(a, s);" in src for k in range(meta.parts))
     # integrals out: one wave per quartet; the tiled rows' ket stage runs in it, into LDS
-    assert meta.eri_wave and not meta.eri_tiles and "if (j < 49)" in src and "__shared__ double zt[" in src
+    assert meta.eri_wave and not meta.eri_tiles and "jj < 49 &&" in src and "__shared__ double zt[P * " in src
+    assert "eri_3333<1>" in src and "eri_3333<2>" not in src           # 49 ket functions: one quartet a wave
+    src21, _ = emit_row.emit_class_row(2, 2, 2, 1)
+    assert "eri_2221<4>" in src21 and "eri_2221<1>" in src21           # 15: four quartets a wave (Schwarz mode: one)
     from paper_2605_10312_amd.gen import emit
     table = emit.emit_table([meta])
     assert ", 1, nullptr, launch_p1f_3333, nullptr}" in table
