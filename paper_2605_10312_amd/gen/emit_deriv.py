@@ -186,10 +186,11 @@ def build_deriv_tables(la, lb, lc, ld, rule="ket_zyx", bundle=BUNDLE):
     for o in ops:
         flops += 2 if o[1] == "hrr" else 2 * len(o[2]) - 1
     n_acc = len(acc_index)
-    t = assemble_tables(g, order, sched, pl, L, acc0, n_acc, accs, ops, out_names, g.flops() + n_acc, flops,
-                        bundle, f"d{la}{lb}{lc}{ld}")
-    return t
-
+    # per primitive quartet: the VRR nodes, one add per unweighted and one FMA
+    # (2 FLOP) per weighted accumulation
+    vrr_flops = g.flops() - len(g.targets) + sum(1 if w == "0" else 2 for (w, _) in acc_index)
+    return assemble_tables(g, order, sched, pl, L, acc0, n_acc, accs, ops, out_names, vrr_flops, flops, bundle,
+                           f"d{la}{lb}{lc}{ld}")
 
 
 DERIV_LMAX = 2          # derivative tables are built for the classes with l <= 2
