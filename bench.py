@@ -458,10 +458,11 @@ def deriv_bench(args):
     sample of the 30-atom 3s2p1d workload's screened unique shell quartets,
     quartet and offset arrays on the device.  One JSON line: derivative
     integrals per second (12 n_sph^4 per quartet), the algorithmic FLOP rate
-    of the derivative tables (per class: primitive quartets x per-primitive
-    ops + quartets x Phase-2 ops of gen/emit_deriv.py) against the FP64
-    peak, the error of sampled quartets against the long-double oracle, and
-    the oracle timed on the host cores."""
+    of the derivative program (per class: primitive quartets x per-primitive
+    FLOPs + quartets x Phase-2 FLOPs of gen/emit_deriv.py; the staged form's
+    recomputation is not counted) against the FP64 peak, the error of
+    sampled quartets against the long-double oracle, and the oracle timed on
+    the host cores."""
     import torch
     import oracle
     import paper_2605_10312_amd as hgp
@@ -531,7 +532,8 @@ def deriv_bench(args):
                                    "quartets of the 30-atom 3s2p1d molecule (tau 1e-12), d/dR of all four centres, "
                                    "12 blocks each, FP64",
                        "quartets": int(len(quartets))},
-            "roofline": {"bound": "alu", "kernel": "t3w_deriv_kernel", "achieved": round(flop / dt / 1e12, 3),
+            "roofline": {"bound": "alu", "kernel": "all derivative kernels (dreg_*, dp1_*, t3w_deriv_kernel)",
+                         "achieved": round(flop / dt / 1e12, 3),
                          "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(flop / dt / 1e12 / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None},
             "cpu_baseline": {"value": cpu_rate, "unit": "derivative integrals/s", "cores": oracle.num_threads(),

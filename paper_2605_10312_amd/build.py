@@ -72,7 +72,7 @@ def _route_and_emit(ls, table, defaults, override, reroute):
 
 
 def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overrides=None, gen_dir: str = GEN,
-             defaults=None, reroute=None, jobs: int | None = None):
+             defaults=None, reroute=None, jobs: int | None = None, dreg_off=frozenset(), dstage=None):
     """Write one .hip per canonical class plus the class table into gen_dir.
     Each class is routed to a tier (gen/router.py): defaults (generator
     options for every class) are applied first, then the router's choice
@@ -81,7 +81,11 @@ def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overri
     digest, reduce, loop, block; staged: cap, waves, reduce, loop; row form:
     budget, waves, reduce, loop.  reroute (class tag -> options) is applied
     last: the build's answer to a compiler resource report that showed
-    spills.  Classes are generated in parallel processes."""
+    spills.  Classes are generated in parallel processes.  Derivative
+    classes small enough for registers also get the register form, except
+    those in dreg_off (their register kernel spilled); the others get the
+    staged form's Phase 1 at the chunk cap dstage[tag] (default: the
+    largest of emit_deriv.STAGE_CAPS; None: tables only)."""
     from .gen import emit, router
     from .gen.cart import canonical_classes
 
@@ -134,8 +138,38 @@ def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overri
         path = os.path.join(GEN, f"deriv_{''.join(str(x) for x in ls)}.hip")
         _write_if_changed(path, _EMITTED[key][0])
         files.append(path)
+    reg = []
+    for ls in dclasses:
+        tag = "".join(str(x) for x in ls)
+        if tag in dreg_off or not emit_deriv.reg_eligible(ls):
+            continue
+        key = ("dreg", tuple(ls))
+        if key not in _EMITTED:
+            _EMITTED[key] = emit_deriv.emit_deriv_reg(*ls)
+        path = os.path.join(GEN, f"deriv_reg_{tag}.hip")
+        _write_if_changed(path, _EMITTED[key])
+        files.append(path)
+        reg.append(tag)
+    staged, sinfo = [], []
+    for ls in dclasses:
+        tag = "".join(str(x) for x in ls)
+        cap = (dstage or {}).get(tag, emit_deriv.STAGE_CAPS[0])
+        if tag in reg or cap is None:
+            continue
+        key = ("dstage", tuple(ls), cap)
+        if key not in _EMITTED:
+            _EMITTED[key] = emit_deriv.emit_deriv_staged(*ls, cap=cap)
+        srcs, info = _EMITTED[key]
+        for p, text in sorted(srcs.items()):
+            path = os.path.join(GEN, f"deriv_p1_{tag}p{p}.hip")
+            _write_if_changed(path, text)
+            files.append(path)
+        staged.append(tag)
+        sinfo.append(info)
     dtable = os.path.join(GEN, "deriv_table.hip")
-    _write_if_changed(dtable, emit_deriv.emit_deriv_table(dclasses))
+    _write_if_changed(dtable, emit_deriv.emit_deriv_table(dclasses, reg, staged))
+    _write_if_changed(os.path.join(GEN, "deriv_forms.json"),
+                      json.dumps({"register": reg, "staged": sinfo}, indent=1))
     files.append(dtable)
     _write_if_changed(os.path.join(GEN, "deriv.json"),
                       json.dumps([_EMITTED[("deriv", tuple(ls))][1] for ls in dclasses], indent=1))
@@ -279,10 +313,20 @@ def _spilled_classes(res: dict) -> dict:
     out: dict = {}
     for k in check_resources(res):
         name = k.split("#")[0]
+        if name.startswith(("dreg_", "dp1_")):             # derivative forms: _spilled_dreg
+            continue
         m = re.search(r"_(\d{4})(?:p\d+)?$", name)        # class kernels, Phase-1 parts included
         if m:
             out.setdefault(m.group(1), []).append(name)
     return out
+
+
+def _spilled_dreg(res: dict, prefix: str = "dreg") -> set:
+    """Tags of the derivative register kernels (prefix dreg) or staged
+    Phase-1 parts (prefix dp1) that use private scratch."""
+    import re
+    return {m.group(1) for k in check_resources(res)
+            for m in [re.match(prefix + r"_(\d{4})(?:p\d+)?$", k.split("#")[0])] if m}
 
 
 def build(lmax: int = DEFAULT_LMAX, jobs: int | None = None, force: bool = False, verbose: bool = True,
@@ -302,9 +346,11 @@ def build(lmax: int = DEFAULT_LMAX, jobs: int | None = None, force: bool = False
     main_table = table is None and defaults is None and overrides is None
     reroute: dict = dict(router.load_reroutes()) if main_table else {}
     compiled: set = set()
+    dreg_off: set = set()
+    dstage: dict = {}
     for attempt in range(8):
         gen_files, metas = generate(lmax, verbose=False, overrides=overrides, gen_dir=gen_dir, defaults=defaults,
-                                    table=table, reroute=reroute)
+                                    table=table, reroute=reroute, dreg_off=frozenset(dreg_off), dstage=dstage)
         srcs = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".hip")] + gen_files
         objs = []
         with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
@@ -324,7 +370,23 @@ def build(lmax: int = DEFAULT_LMAX, jobs: int | None = None, force: bool = False
         # the compiler's resource report has the last word on the register
         # model: a class whose kernels spill moves down the router's ladder
         spilled = _spilled_classes(res)
-        if not spilled or allow_scratch:
+        dspill = _spilled_dreg(res)
+        sspill = _spilled_dreg(res, "dp1")
+        if (dspill or sspill) and not allow_scratch:
+            # a derivative class whose register kernel spills takes the staged
+            # form; a staged one steps down the chunk caps, then keeps only its tables
+            from .gen import emit_deriv
+            if verbose and dspill:
+                print(f"  derivative register forms {' '.join(sorted(dspill))} use private scratch; staged", flush=True)
+            dreg_off |= dspill
+            caps = list(emit_deriv.STAGE_CAPS)
+            for tag in sorted(sspill):
+                cur = dstage.get(tag, caps[0])
+                dstage[tag] = caps[caps.index(cur) + 1] if cur in caps[:-1] else None
+                if verbose:
+                    print(f"  derivative staged form {tag} at cap {cur} uses private scratch; "
+                          f"{'cap ' + str(dstage[tag]) if dstage[tag] else 'tables only'}", flush=True)
+        if (not spilled and not dspill and not sspill) or allow_scratch:
             break
         by_tag = {m.tag: m for m in metas}
         for tag, kernels in sorted(spilled.items()):

@@ -100,6 +100,14 @@ hgp_status keep_pool(int dev)
     return HGP_OK;
 }
 
+// Quartets per batch of a staged derivative class of cnt quartets: its
+// accumulators (n_hrr per quartet) within DERIV_STAGE_DOUBLES, at most 2^20.
+int64_t deriv_batch(const DerivClass &dc, int64_t cnt)
+{
+    const int64_t per = std::max<int64_t>(1, DERIV_STAGE_DOUBLES / std::max(1, dc.t->n_hrr));
+    return std::max<int64_t>(1, std::min({cnt, per, (int64_t)1 << 20}));
+}
+
 // Highest l of the derivative classes built into the library (-1: none).
 int max_deriv_l()
 {
@@ -1274,7 +1282,8 @@ hgp_status hgp_jk_multi(hgp_plan *p, const double *const *D, double *const *J, d
 namespace {
 
 // Shell quartets given on the device, integrals (deriv = false) or their
-// first derivatives (deriv = true: the derivative tables, 12 blocks a quartet).
+// first derivatives (deriv = true: 12 blocks a quartet, from the register form
+// of the class where it has one, else from its wave-form tables).
 hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartets, const int64_t *offsets,
                           double *out, void *hip_stream, bool deriv)
 {
@@ -1357,12 +1366,15 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
     for (int c = 0; c < ncls; ++c)
         if (h[(size_t)c]) {
             if (deriv) {
-                const int pe = t3_prepare(*g_deriv_table[c].t);
+                const DerivClass &dc = g_deriv_table[c];
+                if (dc.reg) continue;
+                const int pe = t3_prepare(*dc.t);
                 if (pe != 0) {
                     release();
                     return fail(HGP_E_DEVICE, std::string("preparing derivative tables: ") +
                                                   hipGetErrorString((hipError_t)pe));
                 }
+                if (dc.p1) sneed = std::max(sneed, deriv_batch(dc, (int64_t)h[(size_t)c]) * (int64_t)dc.t->n_hrr);
                 continue;
             }
             if ((st = prepare_class(g_class_table[c]))) { release(); return st; }
@@ -1392,12 +1404,23 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
         a.mode = 0;
         a.scratch = d_scr;
         if (deriv) {
-            // launches of at most 2^20 quartets (one workgroup each)
-            for (int64_t q0 = 0; q0 < cnt; q0 += (int64_t)1 << 20) {
+            // launches of at most 2^20 quartets (a workgroup each in the table form); the
+            // staged form in batches whose accumulators fit the buffer, slot stride = batch
+            const DerivClass &dc = g_deriv_table[c];
+            const int64_t step = dc.reg || !dc.p1 ? (int64_t)1 << 20 : deriv_batch(dc, cnt);
+            for (int64_t q0 = 0; q0 < cnt; q0 += step) {
                 EriArgs x = a;
                 x.tasks = a.tasks + q0;
-                x.ntask = std::min<int64_t>((int64_t)1 << 20, cnt - q0);
-                t3w_launch_deriv(*g_deriv_table[c].t, x, d_code, s);
+                x.ntask = std::min<int64_t>(step, cnt - q0);
+                if (dc.reg) {
+                    dc.reg(x, d_code, s);
+                } else if (dc.p1) {
+                    x.stride = x.ntask;
+                    dc.p1(x, d_code, s);
+                    t3w_launch_deriv_p2(*dc.t, x, d_code, s);
+                } else {
+                    t3w_launch_deriv(*dc.t, x, d_code, s);
+                }
             }
         } else {
             run_eri_class(g_class_table[c], a, sneed, s);

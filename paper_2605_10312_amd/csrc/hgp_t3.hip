@@ -464,19 +464,26 @@ __device__ __forceinline__ void t3w_lin_group(const uint4 *o, const double *__re
 }
 
 // The quartet's integrals into their output slots (LDS), as t3_quartet.
-template <bool G>
+// P2: the accumulators come in from acc_in[k * acc_stride] (a staged form's
+// Phase 1) and only Phase 2 runs.
+template <bool G, bool P2 = false>
 __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__restrict__ ops, const PairInfo &pb,
                             const PairGeo &gb, const PairInfo &pk, const PairGeo &gk,
                             const PrimPair *__restrict__ prims, const double *__restrict__ boys, double *__restrict__ S,
-                            const double *__restrict__ C, double *__restrict__ R, int lane)
+                            const double *__restrict__ C, double *__restrict__ R, int lane,
+                            const double *__restrict__ acc_in = nullptr, int64_t acc_stride = 0)
 {
-    for (int k = lane; k < c.n_hrr; k += T3W_GROUP) S[c.acc0 + k] = 0.0;
+    if (P2) {
+        for (int k = lane; k < c.n_hrr; k += T3W_GROUP) S[c.acc0 + k] = acc_in[(int64_t)k * acc_stride];
+    } else {
+        for (int k = lane; k < c.n_hrr; k += T3W_GROUP) S[c.acc0 + k] = 0.0;
+    }
     if (lane == 0) S[c.nslots] = 0.0;                       // the zero slot
     t3w_sync<G>();
     const uint4 *__restrict__ myops = ops + lane;
     const PrimPair *__restrict__ pbp = prims + pb.prim_off;
     const PrimPair *__restrict__ pkp = prims + pk.prim_off;
-    for (int ip = 0; ip < pb.nprim; ++ip) {
+    for (int ip = 0; ip < (P2 ? 0 : pb.nprim); ++ip) {
         const PrimPair b = pbp[ip];
         for (int jp = 0; jp < pk.nprim; ++jp) {
             const PrimPair e = pkp[jp];
@@ -704,7 +711,8 @@ __global__ __launch_bounds__(64) void t3w_eri_kernel(T3WParams c, const uint4 *_
 // the 12 blocks [centre][axis] of the canonical class, canonical centre r's
 // written to the requested centre (code[t.bra / 2] >> 2r) & 3 of the
 // shell-quartet classifier.
-template <bool G>
+// P2: Phase 2 only, from the accumulators a.scratch[k * a.stride + i].
+template <bool G, bool P2 = false>
 __global__ __launch_bounds__(64) void t3w_deriv_kernel(T3WParams c, const uint4 *__restrict__ ops,
                                                        const double *__restrict__ coefs,
                                                        const uint16_t *__restrict__ outslots, EriArgs a,
@@ -718,7 +726,8 @@ __global__ __launch_bounds__(64) void t3w_deriv_kernel(T3WParams c, const uint4 
     const EriTask t = a.tasks[i];
     const PairInfo pb = a.pairs[t.bra], pk = a.pairs[t.ket];
     const PairGeo gb = a.geo[t.bra], gk = a.geo[t.ket];
-    t3w_quartet<G>(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, l.R, lane);
+    t3w_quartet<G, P2>(c, ops, pb, gb, pk, gk, a.prims, a.boys, l.S, l.C, l.R, lane, P2 ? a.scratch + i : nullptr,
+                       a.stride);
     const int na = c.na, nb = c.nb, nc = c.nc, nd = c.nd;
     const int nint = na * nb * nc * nd;
     const int32_t pos = code[t.bra >> 1];
@@ -804,6 +813,8 @@ int t3_prepare(const T3Class &c)
                     (e = hipFuncSetAttribute((const void *)t3w_eri_kernel<false>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, maxlds)) != hipSuccess ||
                     (e = hipFuncSetAttribute((const void *)t3w_deriv_kernel<false>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, maxlds)) != hipSuccess ||
+                    (e = hipFuncSetAttribute((const void *)t3w_deriv_kernel<false, true>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, maxlds)) != hipSuccess)
                     return (int)e;
                 raised[dev] = true;
@@ -888,6 +899,19 @@ void t3w_launch_deriv(const T3Class &c, const EriArgs &a, const int32_t *code, h
     p.deriv = 1;
     hipLaunchKernelGGL(t3w_deriv_kernel<false>, dim3((unsigned)a.ntask), dim3(T3W_GROUP), (unsigned)c.lds_bytes, s, p,
                        d.ops, d.coefs, d.outslots, a, code);
+}
+
+void t3w_launch_deriv_p2(const T3Class &c, const EriArgs &a, const int32_t *code, hipStream_t s)
+{
+    T3Dev d;
+    if (a.ntask <= 0 || c.lds_bytes <= 0 || c.gslots || c.out_blocks != 12 || !a.scratch ||
+        t3_device_tables(c, &d) != hipSuccess)
+        return;
+    T3WParams p = wparams(c);
+    p.nint *= 12;
+    p.deriv = 1;
+    hipLaunchKernelGGL((t3w_deriv_kernel<false, true>), dim3((unsigned)a.ntask), dim3(T3W_GROUP),
+                       (unsigned)c.lds_bytes, s, p, d.ops, d.coefs, d.outslots, a, code);
 }
 
 void t3_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s)

@@ -111,7 +111,7 @@ def _p2_lines(p2, indent, f32=False):
     return lines
 
 
-def loop_prelude(L, ind, style="late"):
+def loop_prelude(L, ind, style="late", weights=False, seg=False):
     """The primitive-quartet loop up to the VRR (Alg. 2's GaussianPairs and
     Boys steps), flattened over bra x ket primitive pairs.
     style 'prefetch': the next iteration's pair records are loaded at the top
@@ -119,7 +119,12 @@ def loop_prelude(L, ind, style="late"):
     style 'late': they are loaded into the same registers as soon as the
     current records have been turned into the derived quantities, so no
     second set and no copies are needed; the loads still have the Boys step
-    and the whole VRR to arrive."""
+    and the whole VRR to arrive.
+    weights ('late' only): the current primitive quartet's 2 alpha, 2 beta
+    (bra pair's exponents) and 2 gamma (ket pair's first exponent) as wa, wb,
+    wg, the weights of first-derivative integrals.
+    seg ('late' only): the loop runs segment s of nseg (both in scope) of the
+    flattened primitive quartets, t in [ntot s / nseg, ntot (s + 1) / nseg)."""
     i2 = ind + "    "
     head = [
         f"{ind}const double Ax = gb.ax, Ay = gb.ay, Az = gb.az;",
@@ -163,21 +168,33 @@ def loop_prelude(L, ind, style="late"):
         ] + derived + tail
     if style != "late":
         raise ValueError(f"unknown loop style {style!r}")
+    r0b, r0k, t0 = ("pbp[0]", "pkp[0]", "0")
+    seg_lines = []
+    if seg:
+        seg_lines = [f"{ind}const int t_lo = (int)(((int64_t)ntot * s) / nseg), t_hi = (int)(((int64_t)ntot * (s + 1)) / nseg);",
+                     f"{ind}const int ip0 = t_lo / nkp, jp0 = t_lo - ip0 * nkp;      // t_lo < ntot: both in range"]
+        r0b, r0k, t0 = ("pbp[ip0]", "pkp[jp0]", "t_lo")
+    w_init = [f"{ind}double rea = {r0b}.ea, reb = {r0b}.eb, rga = {r0k}.ea;"] if weights else []
+    w_cur = [f"{i2}const double wa = 2.0 * rea, wb = 2.0 * reb, wg = 2.0 * rga;"] if weights else []
+    w_next = [f"{i2}    rea = b->ea; reb = b->eb; rga = k->ea;"] if weights else []
+    ij = [f"{ind}int ip = ip0, jp = jp0;"] if seg else [f"{ind}int ip = 0, jp = 0;"]
     return head + [
         f"{ind}const int nbm1 = pb.nprim - 1;",
-        f"{ind}double rzeta = pbp[0].zeta, ro2z = pbp[0].o2z, rPx = pbp[0].px, rPy = pbp[0].py, rPz = pbp[0].pz, rKb = pbp[0].k;",
-        f"{ind}double reta = pkp[0].zeta, ro2e = pkp[0].o2z, rQx = pkp[0].px, rQy = pkp[0].py, rQz = pkp[0].pz, rKk = pkp[0].k;",
-        f"{ind}int ip = 0, jp = 0;",
-        f"{ind}for (int t = 0; t < ntot; ++t) {{",
+    ] + seg_lines + [
+        f"{ind}double rzeta = {r0b}.zeta, ro2z = {r0b}.o2z, rPx = {r0b}.px, rPy = {r0b}.py, rPz = {r0b}.pz, rKb = {r0b}.k;",
+        f"{ind}double reta = {r0k}.zeta, ro2e = {r0k}.o2z, rQx = {r0k}.px, rQy = {r0k}.py, rQz = {r0k}.pz, rKk = {r0k}.k;",
+    ] + w_init + ij + [
+        f"{ind}for (int t = {t0}; t < {'t_hi' if seg else 'ntot'}; ++t) {{",
         f"{i2}const double zeta = rzeta, o2z = ro2z, Px = rPx, Py = rPy, Pz = rPz, Kb = rKb;",
         f"{i2}const double eta = reta, o2e = ro2e, Qx = rQx, Qy = rQy, Qz = rQz, Kk = rKk;",
-    ] + derived + [
+    ] + w_cur + derived + [
         # the records of iteration t + 1 (clamped in range on the last iteration)
         f"{i2}if (++jp == nkp) {{ jp = 0; ++ip; }}",
         f"{i2}{{",
         f"{i2}    const PrimPair *b = pbp + min(ip, nbm1), *k = pkp + jp;",
         f"{i2}    rzeta = b->zeta; ro2z = b->o2z; rPx = b->px; rPy = b->py; rPz = b->pz; rKb = b->k;",
         f"{i2}    reta = k->zeta; ro2e = k->o2z; rQx = k->px; rQy = k->py; rQz = k->pz; rKk = k->k;",
+    ] + w_next + [
         f"{i2}}}",
     ] + tail
 
