@@ -83,7 +83,7 @@ def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overri
     last: the build's answer to a compiler resource report that showed
     spills.  Classes are generated in parallel processes.  Derivative
     classes small enough for registers also get the register form, except
-    those in dreg_off (their register kernel spilled); the others get the
+    those in dreg_off (their register kernel spilled); every class gets the
     staged form's Phase 1 at the chunk cap dstage[tag] (default: the
     largest of emit_deriv.STAGE_CAPS; None: tables only)."""
     from .gen import emit, router
@@ -154,7 +154,7 @@ def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overri
     for ls in dclasses:
         tag = "".join(str(x) for x in ls)
         cap = (dstage or {}).get(tag, emit_deriv.STAGE_CAPS[0])
-        if tag in reg or cap is None:
+        if cap is None:
             continue
         key = ("dstage", tuple(ls), cap)
         if key not in _EMITTED:
@@ -167,7 +167,8 @@ def generate(lmax: int = DEFAULT_LMAX, verbose: bool = False, table=None, overri
         staged.append(tag)
         sinfo.append(info)
     dtable = os.path.join(GEN, "deriv_table.hip")
-    _write_if_changed(dtable, emit_deriv.emit_deriv_table(dclasses, reg, staged))
+    _write_if_changed(dtable, emit_deriv.emit_deriv_table(
+        dclasses, reg, {i["tag"]: -(-i["chunks"] // i["parts"]) for i in sinfo}))
     _write_if_changed(os.path.join(GEN, "deriv_forms.json"),
                       json.dumps({"register": reg, "staged": sinfo}, indent=1))
     files.append(dtable)
@@ -191,22 +192,36 @@ def _write_if_changed(path, text):
     os.replace(path + ".tmp", path)
 
 
+def _generated_deps(src: str) -> list:
+    """A generated source and the library headers it includes, directly or
+    through another library header (generated files see only csrc/)."""
+    import re
+    deps, todo = [src], [src]
+    while todo:
+        for name in re.findall(r'^#include "([^"]+)"', open(todo.pop()).read(), re.M):
+            h = os.path.join(CSRC, name)
+            if os.path.exists(h) and h not in deps:
+                deps.append(h)
+                todo.append(h)
+    return deps
+
+
 def class_source_hash(tag: str, gen_dir: str = GEN) -> str | None:
     """Hash of everything a generated class kernel is compiled from (its
-    source and the device headers): measurements tied to a kernel, such as
-    hardware byte counters, stay valid only while this is unchanged."""
+    source and the headers it includes): measurements tied to a kernel, such
+    as hardware byte counters, stay valid only while this is unchanged."""
     src = os.path.join(gen_dir, f"class_{tag}.hip")
     if not os.path.exists(src):
         return None
     h = hashlib.sha256()
-    for d in [src] + [os.path.join(CSRC, x) for x in ("hgp_device.h", "hgp_types.h", "hgp_t3.h")]:
+    for d in _generated_deps(src):
         h.update(open(d, "rb").read())
     return h.hexdigest()[:16]
 
 
 def _compile(src: str, force: bool):
-    if not src.startswith(CSRC + os.sep):  # generated class files see only these headers
-        deps = [src] + [os.path.join(CSRC, h) for h in ("hgp_device.h", "hgp_types.h", "hgp_t3.h")]
+    if not src.startswith(CSRC + os.sep):
+        deps = _generated_deps(src)
     else:
         deps = [src] + [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".h")] + \
                [os.path.join(INCLUDE, f) for f in sorted(os.listdir(INCLUDE))]

@@ -18,7 +18,9 @@ void launch_screen_count(int b0, int nb, int sym, const double *Q, double tau, d
 void launch_screen_write(int b0, int nb, int sym, const double *Q, double tau, double hi, const int *psys,
                          const int *kbeg, const int *kcnt, const int64_t *offsets, int64_t shift, int2 *out,
                          hipStream_t s);
-void launch_scan(int64_t *v, int n, int64_t *total, hipStream_t s);
+// Exclusive scan of v[0 .. n) in place, the sum into *total; tmp (at least
+// (n + 1023) / 1024 values, or nullptr for one workgroup) holds block sums.
+void launch_scan(int64_t *v, int n, int64_t *total, int64_t *tmp, hipStream_t s);
 // class of each (la, lb, lc, ld) in canonical order, index ((la*5 + lb)*5 + lc)*5 + ld, -1 if not built;
 // passed by value to the classify kernel
 struct ClassOf {

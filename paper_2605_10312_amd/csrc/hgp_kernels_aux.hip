@@ -228,86 +228,135 @@ __global__ void screen_count_kernel(int b0, int nb, int sym, const double *Q, do
 // ---------------------------------------------------------------------------
 __device__ inline int dev_pair_class(int la, int lb) { return la * (la + 1) / 2 + lb; }
 
-__global__ void sq_classify_kernel(int64_t nq, const int32_t *quartets, const int64_t *offsets, int nshell,
-                                   const int *l, const int *nprim, ClassOf class_of, int32_t *code,
-                                   int64_t *primcnt, unsigned long long *counts, unsigned long long *err)
+__global__ __launch_bounds__(256) void sq_classify_kernel(int64_t nq, const int32_t *quartets,
+                                                           const int64_t *offsets, int nshell, const int *l,
+                                                           const int *nprim, ClassOf class_of, int32_t *code,
+                                                           int64_t *primcnt, unsigned long long *counts,
+                                                           unsigned long long *err)
 {
+    // per-class counts of the block in LDS, then one global atomic per class present
+    __shared__ unsigned hist[625];
+    for (int j = threadIdx.x; j < 625; j += blockDim.x) hist[j] = 0u;
+    __syncthreads();
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
-    int sh[4];
-    bool bad = offsets[q] < 0;
-    for (int r = 0; r < 4; ++r) {
-        sh[r] = quartets[4 * q + r];
-        bad = bad || sh[r] < 0 || sh[r] >= nshell;
+    if (q < nq) {
+        int sh[4];
+        bool bad = offsets[q] < 0;
+        for (int r = 0; r < 4; ++r) {
+            sh[r] = quartets[4 * q + r];
+            bad = bad || sh[r] < 0 || sh[r] >= nshell;
+        }
+        int ci = -1;
+        if (bad) {
+            atomicOr(err, 1ull);
+        } else {
+            int L[4];
+            for (int r = 0; r < 4; ++r) L[r] = l[sh[r]];
+            int pos[4] = {0, 1, 2, 3};
+            if (L[0] < L[1]) { pos[0] = 1; pos[1] = 0; }
+            if (L[2] < L[3]) { pos[2] = 3; pos[3] = 2; }
+            if (dev_pair_class(L[pos[0]], L[pos[1]]) < dev_pair_class(L[pos[2]], L[pos[3]])) {
+                int t = pos[0]; pos[0] = pos[2]; pos[2] = t;
+                t = pos[1]; pos[1] = pos[3]; pos[3] = t;
+            }
+            ci = class_of.c[((L[pos[0]] * 5 + L[pos[1]]) * 5 + L[pos[2]]) * 5 + L[pos[3]]];
+            if (ci < 0) {
+                atomicOr(err, 2ull);
+            } else {
+                atomicAdd(&hist[ci], 1u);
+                code[q] = ci << 8 | pos[0] | pos[1] << 2 | pos[2] << 4 | pos[3] << 6;
+                primcnt[q] = (int64_t)nprim[sh[0]] * nprim[sh[1]] + (int64_t)nprim[sh[2]] * nprim[sh[3]];
+            }
+        }
+        if (ci < 0) {
+            code[q] = -1;
+            primcnt[q] = 0;
+        }
     }
-    if (bad) {
-        atomicOr(err, 1ull);
-        code[q] = -1;
-        primcnt[q] = 0;
-        return;
-    }
-    int L[4];
-    for (int r = 0; r < 4; ++r) L[r] = l[sh[r]];
-    int pos[4] = {0, 1, 2, 3};
-    if (L[0] < L[1]) { pos[0] = 1; pos[1] = 0; }
-    if (L[2] < L[3]) { pos[2] = 3; pos[3] = 2; }
-    if (dev_pair_class(L[pos[0]], L[pos[1]]) < dev_pair_class(L[pos[2]], L[pos[3]])) {
-        int t = pos[0]; pos[0] = pos[2]; pos[2] = t;
-        t = pos[1]; pos[1] = pos[3]; pos[3] = t;
-    }
-    const int ci = class_of.c[((L[pos[0]] * 5 + L[pos[1]]) * 5 + L[pos[2]]) * 5 + L[pos[3]]];
-    if (ci < 0) {
-        atomicOr(err, 2ull);
-        code[q] = -1;
-        primcnt[q] = 0;
-        return;
-    }
-    atomicAdd(&counts[ci], 1ull);
-    code[q] = ci << 8 | pos[0] | pos[1] << 2 | pos[2] << 4 | pos[3] << 6;
-    primcnt[q] = (int64_t)nprim[sh[0]] * nprim[sh[1]] + (int64_t)nprim[sh[2]] * nprim[sh[3]];
+    __syncthreads();
+    for (int j = threadIdx.x; j < 625; j += blockDim.x)
+        if (hist[j]) atomicAdd(&counts[j], (unsigned long long)hist[j]);
 }
 
 // Scatter: the two pair records of quartet q (2q bra, 2q + 1 ket, primitive
 // records from prim_off[q], an exclusive scan of the classify counts) and its
 // task, placed in its class's range (class_base, an exclusive scan of the
 // class counts) at a slot taken from that class's cursor.
-__global__ void sq_scatter_kernel(int64_t nq, const int32_t *quartets, const int64_t *offsets, const int *l,
-                                  const int *nprim, const int *foff, const int32_t *code, const int64_t *prim_off,
-                                  const int64_t *class_base, unsigned long long *cursor, PairInfo *pairs,
-                                  EriTask *tasks)
+__global__ __launch_bounds__(256) void sq_scatter_kernel(int64_t nq, const int32_t *quartets, const int64_t *offsets,
+                                                          const int *l, const int *nprim, const int *foff,
+                                                          const int32_t *code, const int64_t *prim_off,
+                                                          const int64_t *class_base, unsigned long long *cursor,
+                                                          PairInfo *pairs, EriTask *tasks)
 {
+    // a quartet's slot: its class's base + the block's share of the class
+    // cursor (one global atomic per class present) + its rank in the block
+    __shared__ unsigned hist[625];
+    __shared__ unsigned long long blk[625];
+    for (int j = threadIdx.x; j < 625; j += blockDim.x) hist[j] = 0u;
+    __syncthreads();
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
-    const int32_t c = code[q];
-    const int ci = c >> 8;
-    int sh[4], pos[4], n[4], stride[4];
-    for (int r = 0; r < 4; ++r) {
-        sh[r] = quartets[4 * q + r];
-        pos[r] = (c >> (2 * r)) & 3;
-        n[r] = 2 * l[sh[r]] + 1;
-    }
-    stride[3] = 1; stride[2] = n[3]; stride[1] = n[2] * n[3]; stride[0] = n[1] * n[2] * n[3];
-    int64_t po = prim_off[q];
-    for (int side = 0; side < 2; ++side) {
-        PairInfo pi;
-        pi.sh_a = sh[pos[2 * side]];
-        pi.sh_b = sh[pos[2 * side + 1]];
-        pi.prim_off = (int32_t)po;
-        pi.nprim = nprim[pi.sh_a] * nprim[pi.sh_b];
-        pi.fa = foff[pi.sh_a];
-        pi.fb = foff[pi.sh_b];
-        pi.same = pi.sh_a == pi.sh_b;
-        pi.cls = dev_pair_class(l[pi.sh_a], l[pi.sh_b]);
-        po += pi.nprim;
-        pairs[2 * q + side] = pi;
-    }
-    const int64_t slot = class_base[ci] + (int64_t)atomicAdd(&cursor[ci], 1ull);
+    const int32_t c = q < nq ? code[q] : -1;
+    const int ci = c >> 8;              // -1 for no quartet (the runtime scatters only valid codes)
+    unsigned rank = 0u;
     EriTask t;
-    t.bra = (int32_t)(2 * q);
-    t.ket = (int32_t)(2 * q + 1);
-    t.off = offsets[q];
-    t.s0 = stride[pos[0]]; t.s1 = stride[pos[1]]; t.s2 = stride[pos[2]]; t.s3 = stride[pos[3]];
-    tasks[slot] = t;
+    if (c >= 0) {
+        rank = atomicAdd(&hist[ci], 1u);
+        int sh[4], pos[4], n[4], stride[4];
+        for (int r = 0; r < 4; ++r) {
+            sh[r] = quartets[4 * q + r];
+            pos[r] = (c >> (2 * r)) & 3;
+            n[r] = 2 * l[sh[r]] + 1;
+        }
+        stride[3] = 1; stride[2] = n[3]; stride[1] = n[2] * n[3]; stride[0] = n[1] * n[2] * n[3];
+        int64_t po = prim_off[q];
+        for (int side = 0; side < 2; ++side) {
+            PairInfo pi;
+            pi.sh_a = sh[pos[2 * side]];
+            pi.sh_b = sh[pos[2 * side + 1]];
+            pi.prim_off = (int32_t)po;
+            pi.nprim = nprim[pi.sh_a] * nprim[pi.sh_b];
+            pi.fa = foff[pi.sh_a];
+            pi.fb = foff[pi.sh_b];
+            pi.same = pi.sh_a == pi.sh_b;
+            pi.cls = dev_pair_class(l[pi.sh_a], l[pi.sh_b]);
+            po += pi.nprim;
+            pairs[2 * q + side] = pi;
+        }
+        t.bra = (int32_t)(2 * q);
+        t.ket = (int32_t)(2 * q + 1);
+        t.off = offsets[q];
+        t.s0 = stride[pos[0]]; t.s1 = stride[pos[1]]; t.s2 = stride[pos[2]]; t.s3 = stride[pos[3]];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < 625; j += blockDim.x)
+        if (hist[j]) blk[j] = atomicAdd(&cursor[j], (unsigned long long)hist[j]);
+    __syncthreads();
+    if (c >= 0) tasks[class_base[ci] + (int64_t)blk[ci] + rank] = t;
+}
+
+// Exclusive scan of the 1024-element block b of v in place (LDS), its sum into bsum[b].
+__global__ __launch_bounds__(1024) void scan_block_kernel(int64_t *v, int64_t n, int64_t *bsum)
+{
+    __shared__ int64_t buf[1024];
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int64_t x = i < n ? v[i] : 0;
+    buf[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t y = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0;
+        __syncthreads();
+        buf[threadIdx.x] += y;
+        __syncthreads();
+    }
+    if (i < n) v[i] = buf[threadIdx.x] - x;
+    if (threadIdx.x == 1023) bsum[blockIdx.x] = buf[1023];
+}
+
+// Adds boff[b] (the exclusive scan of the block sums) to block b of v.
+__global__ __launch_bounds__(1024) void scan_add_kernel(int64_t *v, int64_t n, const int64_t *boff)
+{
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    if (i < n) v[i] += boff[blockIdx.x];
 }
 
 // exclusive scan of n counts in place (single block), total into *total
@@ -458,9 +507,16 @@ void launch_screen_write(int b0, int nb, int sym, const double *Q, double tau, d
         hipLaunchKernelGGL(screen_write_kernel, dim3(nb), dim3(256), 0, s, b0, nb, sym, Q, tau, hi, psys, kbeg, kcnt,
                            offsets, shift, out);
 }
-void launch_scan(int64_t *v, int n, int64_t *total, hipStream_t s)
+void launch_scan(int64_t *v, int n, int64_t *total, int64_t *tmp, hipStream_t s)
 {
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, v, n, total);
+    const int nb = (n + 1023) / 1024;
+    if (nb <= 1 || !tmp) {
+        hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, v, n, total);
+        return;
+    }
+    hipLaunchKernelGGL(scan_block_kernel, dim3((unsigned)nb), dim3(1024), 0, s, v, (int64_t)n, tmp);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, tmp, nb, total);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)nb), dim3(1024), 0, s, v, (int64_t)n, (const int64_t *)tmp);
 }
 void launch_sq_classify(int64_t nq, const int32_t *quartets, const int64_t *offsets, int nshell, const int *l,
                         const int *nprim, const ClassOf &class_of, int32_t *code, int64_t *primcnt,

@@ -100,11 +100,27 @@ hgp_status keep_pool(int dev)
     return HGP_OK;
 }
 
-// Quartets per batch of a staged derivative class of cnt quartets: its
-// accumulators (n_hrr per quartet) within DERIV_STAGE_DOUBLES, at most 2^20.
-int64_t deriv_batch(const DerivClass &dc, int64_t cnt)
+// Staged derivative class of cnt quartets: segments of each quartet's
+// primitive loop, enough for about 2^17 lanes per Phase-1 launch (two waves
+// a SIMD), at most 16; then quartets per batch, whose partial accumulators
+// (nseg n_hrr per quartet) stay within DERIV_STAGE_DOUBLES, at most 2^20.
+int deriv_nseg(const DerivClass &dc, int64_t cnt)
 {
-    const int64_t per = std::max<int64_t>(1, DERIV_STAGE_DOUBLES / std::max(1, dc.t->n_hrr));
+    const int64_t lanes = (int64_t)std::max(1, dc.p1_chunks) * std::max<int64_t>(1, cnt);
+    return (int)std::min<int64_t>(16, std::max<int64_t>(1, (((int64_t)1 << 17) + lanes - 1) / lanes));
+}
+
+// The register form (one lane per quartet, no Phase-1 buffer) where the class
+// has one and its quartets alone fill the device; else the staged form, whose
+// segments fill it.
+bool deriv_use_reg(const DerivClass &dc, int64_t cnt)
+{
+    return dc.reg && (!dc.p1 || cnt >= DERIV_REG_MIN);
+}
+
+int64_t deriv_batch(const DerivClass &dc, int64_t cnt, int nseg)
+{
+    const int64_t per = std::max<int64_t>(1, DERIV_STAGE_DOUBLES / ((int64_t)nseg * std::max(1, dc.t->n_hrr)));
     return std::max<int64_t>(1, std::min({cnt, per, (int64_t)1 << 20}));
 }
 
@@ -1307,7 +1323,7 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
     }
     // stream-ordered temporaries; every exit below frees them on the stream
     int32_t *d_code = nullptr;
-    int64_t *d_poff = nullptr, *d_ptotal = nullptr, *d_base = nullptr, *d_btotal = nullptr;
+    int64_t *d_poff = nullptr, *d_ptotal = nullptr, *d_base = nullptr, *d_btotal = nullptr, *d_stmp = nullptr;
     unsigned long long *d_counts = nullptr, *d_cursor = nullptr, *d_err = nullptr;
     PairInfo *d_pairs = nullptr;
     PairGeo *d_geo = nullptr;
@@ -1330,6 +1346,7 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
     if (e == hipSuccess) e = get((void **)&d_ptotal, sizeof(int64_t));
     if (e == hipSuccess) e = get((void **)&d_base, sizeof(int64_t) * nc8);
     if (e == hipSuccess) e = get((void **)&d_btotal, sizeof(int64_t));
+    if (e == hipSuccess) e = get((void **)&d_stmp, sizeof(int64_t) * (size_t)((nq + 1023) / 1024));
     // counts, cursors and the error word in one zeroed block
     if (e == hipSuccess) e = get((void **)&d_counts, sizeof(unsigned long long) * (2 * nc8 + 1));
     if (e != hipSuccess) {
@@ -1340,9 +1357,13 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
     d_err = d_counts + 2 * nc8;
     launch_fill_zero((double *)d_counts, (int64_t)(2 * nc8 + 1), s);      // all-zero bits
     launch_sq_classify(nq, quartets, offsets, b->nshell, b->d_l, b->d_nprim, cof, d_code, d_poff, d_counts, d_err, s);
-    launch_scan(d_poff, (int)nq, d_ptotal, s);
-    HGP_HIP(hipMemcpyAsync(d_base, d_counts, sizeof(int64_t) * nc8, hipMemcpyDeviceToDevice, s));
-    launch_scan(d_base, ncls, d_btotal, s);
+    launch_scan(d_poff, (int)nq, d_ptotal, d_stmp, s);
+    e = hipMemcpyAsync(d_base, d_counts, sizeof(int64_t) * nc8, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+        release();
+        return fail(HGP_E_DEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    }
+    launch_scan(d_base, ncls, d_btotal, nullptr, s);
     // the one wait: per-class counts, the error word and the primitive total size the launches
     std::vector<unsigned long long> h((size_t)(nc8 + 1));
     int64_t ptotal = 0;
@@ -1367,14 +1388,18 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
         if (h[(size_t)c]) {
             if (deriv) {
                 const DerivClass &dc = g_deriv_table[c];
-                if (dc.reg) continue;
+                if (deriv_use_reg(dc, (int64_t)h[(size_t)c])) continue;
                 const int pe = t3_prepare(*dc.t);
                 if (pe != 0) {
                     release();
                     return fail(HGP_E_DEVICE, std::string("preparing derivative tables: ") +
                                                   hipGetErrorString((hipError_t)pe));
                 }
-                if (dc.p1) sneed = std::max(sneed, deriv_batch(dc, (int64_t)h[(size_t)c]) * (int64_t)dc.t->n_hrr);
+                if (dc.p1) {
+                    const int64_t n = (int64_t)h[(size_t)c];
+                    const int ns = deriv_nseg(dc, n);
+                    sneed = std::max(sneed, deriv_batch(dc, n, ns) * ns * (int64_t)dc.t->n_hrr);
+                }
                 continue;
             }
             if ((st = prepare_class(g_class_table[c]))) { release(); return st; }
@@ -1407,17 +1432,19 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
             // launches of at most 2^20 quartets (a workgroup each in the table form); the
             // staged form in batches whose accumulators fit the buffer, slot stride = batch
             const DerivClass &dc = g_deriv_table[c];
-            const int64_t step = dc.reg || !dc.p1 ? (int64_t)1 << 20 : deriv_batch(dc, cnt);
+            const bool reg = deriv_use_reg(dc, cnt);
+            const int nseg = dc.p1 && !reg ? deriv_nseg(dc, cnt) : 1;
+            const int64_t step = reg || !dc.p1 ? (int64_t)1 << 20 : deriv_batch(dc, cnt, nseg);
             for (int64_t q0 = 0; q0 < cnt; q0 += step) {
                 EriArgs x = a;
                 x.tasks = a.tasks + q0;
                 x.ntask = std::min<int64_t>(step, cnt - q0);
-                if (dc.reg) {
-                    dc.reg(x, d_code, s);
+                if (reg) {
+                    dc.reg(x, d_code, 1, s);
                 } else if (dc.p1) {
                     x.stride = x.ntask;
-                    dc.p1(x, d_code, s);
-                    t3w_launch_deriv_p2(*dc.t, x, d_code, s);
+                    dc.p1(x, d_code, nseg, s);
+                    t3w_launch_deriv_p2(*dc.t, x, d_code, nseg, s);
                 } else {
                     t3w_launch_deriv(*dc.t, x, d_code, s);
                 }

@@ -64,24 +64,30 @@ void t3w_launch_eri(const T3Class &c, const EriArgs &a, hipStream_t s);
 // the canonical shell: bits 2r, 2r + 1 of code[t.bra / 2] for canonical shell r.
 void t3w_launch_deriv(const T3Class &c, const EriArgs &a, const int32_t *code, hipStream_t s);
 
-// The same from the weighted accumulators of Phase 1 (the staged form):
-// accumulator k of task i at a.scratch[k * a.stride + i], Phase 2 only.
-void t3w_launch_deriv_p2(const T3Class &c, const EriArgs &a, const int32_t *code, hipStream_t s);
+// The same from the weighted accumulators of Phase 1 (the staged form), Phase
+// 2 only: accumulator k of task i is the sum over segments s < nseg, in that
+// order, of a.scratch[(s * n_acc + k) * a.stride + i] (n_acc = c.n_hrr).
+void t3w_launch_deriv_p2(const T3Class &c, const EriArgs &a, const int32_t *code, int nseg, hipStream_t s);
 
 // The derivative classes built into the library: per canonical class its
-// tables and, for classes whose values fit in registers, the register form
-// (one lane per quartet; same task layout and centre code), else for the
-// others the staged form's Phase 1 (accumulators into a.scratch, slot
-// stride a.stride, then t3w_launch_deriv_p2), or nullptr.
-typedef void (*launch_deriv_fn)(const EriArgs &, const int32_t *code, hipStream_t);
+// tables; for classes whose values fit in registers, the register form (one
+// lane per quartet; same task layout and centre code; nseg unused), or
+// nullptr; and the staged form's Phase 1 (partial accumulators of nseg
+// segments of each quartet's primitive quartets into a.scratch as above,
+// then t3w_launch_deriv_p2), or nullptr.
+typedef void (*launch_deriv_fn)(const EriArgs &, const int32_t *code, int nseg, hipStream_t);
 struct DerivClass {
     int la, lb, lc, ld;
     const T3Class *t;
     launch_deriv_fn reg;
     launch_deriv_fn p1;
+    int p1_chunks;      // chunks per Phase-1 launch (the largest part)
 };
 // Staged derivative classes: doubles of accumulator buffer at most (1 GiB).
 constexpr int64_t DERIV_STAGE_DOUBLES = (int64_t)1 << 27;
+// A class with both forms takes the register form from this many quartets on
+// (a wave a SIMD at one wave per SIMD), the staged form below.
+constexpr int64_t DERIV_REG_MIN = 65536;
 extern const DerivClass g_deriv_table[];
 extern const int g_num_deriv;
 

@@ -311,6 +311,7 @@ __global__ __launch_bounds__(64) void t3_eri_kernel(T3Params c, const uint4 *__r
 struct T3WParams {
     int L, na, nb, nc, nd, n_hrr, acc0, n_vrr, n_p2, nslots, ncoef, maxblk, nint;
     int deriv;      // 1: derivative tables, whose ACC_W ops read 2a, 2b, 2c from slots L + 1 .. L + 3
+    int nseg;       // Phase 2 only: partial accumulators per accumulator (segments of the primitive loop)
 };
 
 // G = false: slots in LDS; a compiler-level barrier suffices.  G = true: slots
@@ -474,7 +475,11 @@ __device__ __forceinline__ void t3w_quartet(const T3WParams &c, const uint4 *__r
                             const double *__restrict__ acc_in = nullptr, int64_t acc_stride = 0)
 {
     if (P2) {
-        for (int k = lane; k < c.n_hrr; k += T3W_GROUP) S[c.acc0 + k] = acc_in[(int64_t)k * acc_stride];
+        for (int k = lane; k < c.n_hrr; k += T3W_GROUP) {
+            double x = acc_in[(int64_t)k * acc_stride];
+            for (int sg = 1; sg < c.nseg; ++sg) x += acc_in[((int64_t)sg * c.n_hrr + k) * acc_stride];
+            S[c.acc0 + k] = x;
+        }
     } else {
         for (int k = lane; k < c.n_hrr; k += T3W_GROUP) S[c.acc0 + k] = 0.0;
     }
@@ -901,15 +906,16 @@ void t3w_launch_deriv(const T3Class &c, const EriArgs &a, const int32_t *code, h
                        d.ops, d.coefs, d.outslots, a, code);
 }
 
-void t3w_launch_deriv_p2(const T3Class &c, const EriArgs &a, const int32_t *code, hipStream_t s)
+void t3w_launch_deriv_p2(const T3Class &c, const EriArgs &a, const int32_t *code, int nseg, hipStream_t s)
 {
     T3Dev d;
-    if (a.ntask <= 0 || c.lds_bytes <= 0 || c.gslots || c.out_blocks != 12 || !a.scratch ||
+    if (a.ntask <= 0 || nseg < 1 || c.lds_bytes <= 0 || c.gslots || c.out_blocks != 12 || !a.scratch ||
         t3_device_tables(c, &d) != hipSuccess)
         return;
     T3WParams p = wparams(c);
     p.nint *= 12;
     p.deriv = 1;
+    p.nseg = nseg;
     hipLaunchKernelGGL((t3w_deriv_kernel<false, true>), dim3((unsigned)a.ntask), dim3(T3W_GROUP),
                        (unsigned)c.lds_bytes, s, p, d.ops, d.coefs, d.outslots, a, code);
 }

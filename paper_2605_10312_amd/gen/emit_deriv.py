@@ -266,25 +266,27 @@ def emit_deriv_class(la, lb, lc, ld, rule="ket_zyx"):
 
 def emit_deriv_table(classes, reg=(), staged=()):
     """The descriptor table of the derivative classes built into the library;
-    reg, staged: the tags of the classes that also have the register form,
-    or the staged form's Phase-1 kernels."""
+    reg: the tags of the classes that also have the register form; staged:
+    {tag: chunks per Phase-1 launch} of those with the staged form's Phase-1
+    kernels."""
     out = ["// Generated: the first-derivative classes of the library.", '#include "hgp_t3.h"', "",
            "#if !defined(__HIP_DEVICE_COMPILE__)", "namespace hgp {"]
     for ls in classes:
         tag = "".join(str(x) for x in ls)
         out.append(f"extern const T3Class t3_d{tag};")
         if tag in reg:
-            out.append(f"void launch_dreg_{tag}(const EriArgs &, const int32_t *, hipStream_t);")
+            out.append(f"void launch_dreg_{tag}(const EriArgs &, const int32_t *, int, hipStream_t);")
         if tag in staged:
-            out.append(f"void launch_dp1_{tag}(const EriArgs &, const int32_t *, hipStream_t);")
+            out.append(f"void launch_dp1_{tag}(const EriArgs &, const int32_t *, int, hipStream_t);")
     out.append("extern const DerivClass g_deriv_table[] = {")
     for ls in classes:
         tag = "".join(str(x) for x in ls)
         fn = f"launch_dreg_{tag}" if tag in reg else "nullptr"
         p1 = f"launch_dp1_{tag}" if tag in staged else "nullptr"
-        out.append(f"    {{{ls[0]}, {ls[1]}, {ls[2]}, {ls[3]}, &t3_d{tag}, {fn}, {p1}}},")
+        cpl = (staged or {}).get(tag, 0) if isinstance(staged, dict) else 0
+        out.append(f"    {{{ls[0]}, {ls[1]}, {ls[2]}, {ls[3]}, &t3_d{tag}, {fn}, {p1}, {cpl}}},")
     if not classes:
-        out.append("    {0, 0, 0, 0, nullptr, nullptr, nullptr},")
+        out.append("    {0, 0, 0, 0, nullptr, nullptr, nullptr, 0},")
     out.append("};")
     out.append(f"extern const int g_num_deriv = {len(classes)};")
     out.append("}  // namespace hgp")
@@ -405,7 +407,7 @@ def emit_deriv_reg(la, lb, lc, ld, rule="ket_zyx", block=REG_BLOCK):
     w("")
     w("}  // namespace")
     w("")
-    w(f"void launch_dreg_{tag}(const EriArgs &a, const int32_t *code, hipStream_t s)")
+    w(f"void launch_dreg_{tag}(const EriArgs &a, const int32_t *code, int, hipStream_t s)")
     w("{")
     w(f"    hipLaunchKernelGGL(dreg_{tag}, dim3((unsigned)((a.ntask + {block - 1}) / {block})), dim3({block}), 0, s, "
       "a, code);")
@@ -417,14 +419,16 @@ def emit_deriv_reg(la, lb, lc, ld, rule="ket_zyx", block=REG_BLOCK):
 
 # ---------------------------------------------------------------------------
 # Staged form, for the classes whose accumulators do not fit in registers:
-# Phase 1 runs one lane per (quartet, chunk), a chunk being a run of the
-# targets (e, f) in (|e|, e, |f|, f) order carrying at most `cap`
+# Phase 1 runs one lane per (quartet, chunk, segment), a chunk being a run of
+# the targets (e, f) in (|e|, e, |f|, f) order carrying at most `cap`
 # accumulators of all banks, with the VRR subgraph of its targets scheduled
-# on its own (nodes that chunks share are recomputed); after the primitive
-# loop it stores its weighted accumulators to the slot-major buffer,
-# accumulator k of batch quartet i at scratch[k * stride + i].  Phase 2 is
-# the wave-form tables' Phase 2, which reads the accumulators from there
-# (t3w_launch_deriv_p2).
+# on its own (nodes that chunks share are recomputed), and segment s of nseg
+# a proportional share of the quartet's primitive quartets (so that classes
+# with few quartets still fill the device).  After its primitive loop a lane
+# stores its partial weighted accumulators to the slot-major buffer,
+# accumulator k of batch quartet i at scratch[(s * n_acc + k) * stride + i].
+# Phase 2 is the wave-form tables' Phase 2, which sums the nseg partials of
+# each accumulator in segment order (t3w_launch_deriv_p2).
 
 STAGE_CAPS = (96, 64, 40)     # accumulators per chunk: the build steps down this list while a part spills
 STAGE_PART = 16               # chunks per Phase-1 kernel (one translation unit each)
@@ -470,14 +474,14 @@ def chunk_vrr(P, targets, ind=""):
 
 
 def _chunk_lines(P, targets, ind):
-    """Accumulator declarations, the primitive loop with the chunk's VRR and
-    weighted accumulation, and the stores, for one chunk."""
+    """Accumulator declarations, the primitive loop (segment s of nseg) with
+    the chunk's VRR and weighted accumulation, and the stores, for one chunk."""
     from .emit import loop_close, loop_prelude
     vrr, ks, nn, pl = chunk_vrr(P, targets, ind + "    ")
     out = []
     for k0 in range(0, len(ks), 8):
         out.append(f"{ind}double " + ", ".join(f"h{k} = 0.0" for k in ks[k0:k0 + 8]) + ";")
-    out.extend(loop_prelude(P.L, ind, "late", weights=True))
+    out.extend(loop_prelude(P.L, ind, "late", weights=True, seg=True))
     out.extend(vrr)
     out.extend(loop_close(ind))
     for k in ks:
@@ -503,19 +507,20 @@ def emit_deriv_staged(la, lb, lc, ld, cap=STAGE_CAPS[0], rule="ket_zyx", block=R
                f"// chunks {p * STAGE_PART} .. {p * STAGE_PART + len(part) - 1} of {len(chunks)} "
                f"(at most {cap} weighted accumulators each).",
                '#include "hgp_device.h"', "", "namespace hgp {", "namespace {", "",
-               f"__global__ __launch_bounds__({block}) void dp1_{tag}p{p}(EriArgs a)", "{"]
+               f"__global__ __launch_bounds__({block}) void dp1_{tag}p{p}(EriArgs a, int nseg)", "{"]
         w = out.append
         w(f"    const int64_t item = (int64_t)blockIdx.x * {block} + threadIdx.x;")
-        w("    const int64_t n = a.ntask;")
-        w(f"    if (item >= {len(part)} * n) return;")
-        w("    const int c = (int)(item / n);                // chunk-major: a wave's lanes share the chunk")
-        w("    const int64_t i = item - c * n;")
+        w("    const int64_t n = a.ntask, per = (int64_t)nseg * n;")
+        w(f"    if (item >= {len(part)} * per) return;")
+        w("    const int c = (int)(item / per);              // chunk- then segment-major: a wave's lanes share both")
+        w("    const int s = (int)((item - c * per) / n);")
+        w("    const int64_t i = item - c * per - s * n;")
         w("    const EriTask tk = a.tasks[i];")
         w("    const PairInfo pb = a.pairs[tk.bra], pk = a.pairs[tk.ket];")
         w("    const PairGeo gb = a.geo[tk.bra], gk = a.geo[tk.ket];")
         w("    const PrimPair *__restrict__ prims = a.prims;")
         w("    const double *__restrict__ boys = a.boys;")
-        w("    double *__restrict__ S = a.scratch + i;")
+        w(f"    double *__restrict__ S = a.scratch + (int64_t)s * {len(P.acc_index)} * a.stride + i;")
         w("    switch (c) {")
         for j, targets in enumerate(part):
             w(f"    case {j}: {{")
@@ -532,20 +537,20 @@ def emit_deriv_staged(la, lb, lc, ld, cap=STAGE_CAPS[0], rule="ket_zyx", block=R
         w("")
         w("}  // namespace")
         w("")
-        w(f"void launch_dp1_{tag}p{p}(const EriArgs &a, hipStream_t s)")
+        w(f"void launch_dp1_{tag}p{p}(const EriArgs &a, int nseg, hipStream_t s)")
         w("{")
-        w(f"    const int64_t items = {len(part)} * a.ntask;")
+        w(f"    const int64_t items = {len(part)} * (int64_t)nseg * a.ntask;")
         w(f"    hipLaunchKernelGGL(dp1_{tag}p{p}, dim3((unsigned)((items + {block - 1}) / {block})), dim3({block}), 0, "
-          "s, a);")
+          "s, a, nseg);")
         w("}")
         if p == 0:
             w("")
             for q in range(1, nparts):
-                w(f"void launch_dp1_{tag}p{q}(const EriArgs &a, hipStream_t s);")
-            w(f"void launch_dp1_{tag}(const EriArgs &a, const int32_t *, hipStream_t s)")
+                w(f"void launch_dp1_{tag}p{q}(const EriArgs &a, int nseg, hipStream_t s);")
+            w(f"void launch_dp1_{tag}(const EriArgs &a, const int32_t *, int nseg, hipStream_t s)")
             w("{")
             for q in range(nparts):
-                w(f"    launch_dp1_{tag}p{q}(a, s);")
+                w(f"    launch_dp1_{tag}p{q}(a, nseg, s);")
             w("}")
         w("")
         w("}  // namespace hgp")

@@ -109,11 +109,11 @@ def test_register_form_matches_oracle(ls):
 
 def test_register_source_declares_what_it_uses():
     src = emit_deriv.emit_deriv_reg(2, 1, 0, 0)
-    assert "void launch_dreg_2100(const EriArgs &a, const int32_t *code, hipStream_t s)" in src
+    assert "void launch_dreg_2100(const EriArgs &a, const int32_t *code, int, hipStream_t s)" in src
     assert "__launch_bounds__(128) void dreg_2100(EriArgs a, const int32_t *__restrict__ code)" in src
     assert src.count("HGP_DSTORE(o3, ") == 3 * 5 * 3      # centre D: 3 axes x 15 elements
     table = emit_deriv.emit_deriv_table([(2, 1, 0, 0), (2, 2, 2, 2)], ["2100"])
-    assert "&t3_d2100, launch_dreg_2100, nullptr}" in table and "&t3_d2222, nullptr, nullptr}" in table
+    assert "&t3_d2100, launch_dreg_2100, nullptr, 0}" in table and "&t3_d2222, nullptr, nullptr, 0}" in table
 
 
 def _prim_env(ls, seed):
@@ -170,9 +170,39 @@ def test_staged_chunks_cover_every_accumulator(ls, cap):
 def test_staged_source_shape():
     srcs, info = emit_deriv.emit_deriv_staged(2, 1, 2, 1, cap=96)
     assert info["parts"] == len(srcs) == (info["chunks"] + emit_deriv.STAGE_PART - 1) // emit_deriv.STAGE_PART
-    assert "void launch_dp1_2121(const EriArgs &a, const int32_t *, hipStream_t s)" in srcs[0]
-    assert all(f"launch_dp1_2121p{p}(a, s);" in srcs[0] for p in srcs)
+    assert "void launch_dp1_2121(const EriArgs &a, const int32_t *, int nseg, hipStream_t s)" in srcs[0]
+    assert all(f"launch_dp1_2121p{p}(a, nseg, s);" in srcs[0] for p in srcs)
     n_store = sum(src.count(" * a.stride] = h") for src in srcs.values())
     assert n_store == info["n_acc"]
-    table = emit_deriv.emit_deriv_table([(2, 1, 2, 1), (1, 0, 0, 0)], ["1000"], ["2121"])
-    assert "&t3_d2121, nullptr, launch_dp1_2121}" in table and "&t3_d1000, launch_dreg_1000, nullptr}" in table
+    assert all("double *__restrict__ S = a.scratch + (int64_t)s * 1548 * a.stride + i;" in src for src in srcs.values())
+    table = emit_deriv.emit_deriv_table([(2, 1, 2, 1), (1, 0, 0, 0)], ["1000"], {"2121": 16})
+    assert "&t3_d2121, nullptr, launch_dp1_2121, 16}" in table and "&t3_d1000, launch_dreg_1000, nullptr, 0}" in table
+
+
+def test_segments_partition_the_primitive_loop():
+    """The loop prelude's segment bounds (segment s of nseg covers t in
+    [ntot s / nseg, ntot (s + 1) / nseg) of the flattened bra x ket
+    primitive quartets) tile [0, ntot) in order, and the first record of
+    every segment is in range; run on the emitted expressions (integer
+    division, non-negative operands)."""
+    from paper_2605_10312_amd.gen import emit
+    lines = emit.loop_prelude(2, "", "late", weights=True, seg=True)
+    seg = [ln.strip() for ln in lines if "t_lo =" in ln or "ip0 =" in ln]
+    assert len(seg) == 2
+    stmts = []
+    for ln in seg:
+        body = ln.split(";")[0].replace("const int ", "").replace("(int64_t)", "").replace("(int)", "")
+        stmts.extend(x.strip().replace("/", "//") for x in body.split(", "))
+    code = compile("\n".join(stmts), "<seg>", "exec")
+    for nb in range(1, 7):
+        for nkp in range(1, 7):
+            ntot = nb * nkp
+            for nseg in range(1, 17):
+                covered = []
+                for s_ in range(nseg):
+                    env = {"ntot": ntot, "s": s_, "nseg": nseg, "nkp": nkp}
+                    exec(code, env)
+                    assert 0 <= env["t_lo"] <= env["t_hi"] <= ntot and env["t_lo"] < ntot
+                    assert env["ip0"] < nb and env["jp0"] < nkp and env["ip0"] * nkp + env["jp0"] == env["t_lo"]
+                    covered.extend(range(env["t_lo"], env["t_hi"]))
+                assert covered == list(range(ntot))

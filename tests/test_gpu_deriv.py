@@ -79,3 +79,30 @@ def test_deriv_rejects_g_and_bad_index(hgp, torch_cuda):
     torch_cuda.cuda.synchronize()
     assert (out.cpu().numpy() == -3.0).all()                # nothing written
     b.close()
+
+
+def test_deriv_register_and_staged_forms_agree_at_scale(hgp, torch_cuda):
+    """A class with both forms runs the register form from 65 536 quartets on
+    and the staged form (segmented primitive loops) below: 40 distinct
+    quartets of four register-form classes, repeated to 68 000 and to 750
+    quartets of each class, give the oracle's blocks in every copy."""
+    bw = workloads.random_small_basis(seed=404, natom=3, lmax=2, maxprim=3, box=3.0, exp_range=(0.2, 8.0))
+    rng = np.random.default_rng(404)
+    L = np.asarray(bw.l)
+    s_sh, p_sh, d_sh = (np.nonzero(L == l)[0] for l in range(3))
+    pick = lambda a: int(rng.choice(a))
+    # (ps|ps), (ds|ps), (dp|ss) and (ps|ss) in shuffled shell orders
+    base = []
+    for _ in range(10):
+        base += [(pick(p_sh), pick(s_sh), pick(p_sh), pick(s_sh)), (pick(s_sh), pick(d_sh), pick(p_sh), pick(s_sh)),
+                 (pick(d_sh), pick(p_sh), pick(s_sh), pick(s_sh)), (pick(s_sh), pick(s_sh), pick(s_sh), pick(p_sh))]
+    refs = [oracle.eri_deriv_shell_quartet(bw, *q, precision="long double") for q in base]
+    scale = max(np.abs(r).max() for r in refs)
+    for copies in (1700, 75):
+        quartets = base * copies
+        got = _run(hgp, torch_cuda, bw, quartets)
+        worst = 0.0
+        for i, g in enumerate(got):
+            worst = max(worst, np.abs(g - refs[i % len(base)]).max())
+        assert worst <= 1e-12 * scale, (copies, worst, scale)
+        print(f"{len(quartets)} quartets: worst |d - oracle| {worst:.2e} (max |d| {scale:.2e})")
