@@ -26,12 +26,19 @@ void launch_scan(int64_t *v, int n, int64_t *total, int64_t *tmp, hipStream_t s)
 struct ClassOf {
     int16_t c[625];
 };
+// Shell quartets are keyed by class and, within a class, by primitive-quartet
+// count: key = class * SQ_BUCKETS + (SQ_BUCKETS - 1 - min(floor(log2(n_bra n_ket)),
+// SQ_BUCKETS - 1)), so a class's quartets are contiguous, the costliest first,
+// and the lanes of a wave loop over similar counts.  code[q] = key << 8 | the
+// four canonical positions (2 bits each); counts[key] per key.
+constexpr int SQ_BUCKETS = 16;
 void launch_sq_classify(int64_t nq, const int32_t *quartets, const int64_t *offsets, int nshell, const int *l,
-                        const int *nprim, const ClassOf &class_of, int32_t *code, int64_t *primcnt,
+                        const int *nprim, const ClassOf &class_of, int nkeys, int32_t *code, int64_t *primcnt,
                         unsigned long long *counts, unsigned long long *err, hipStream_t s);
+// Pair records and tasks: quartet q's task at key_base[key] + its rank in the key.
 void launch_sq_scatter(int64_t nq, const int32_t *quartets, const int64_t *offsets, const int *l, const int *nprim,
-                       const int *foff, const int32_t *code, const int64_t *prim_off, const int64_t *class_base,
-                       unsigned long long *cursor, PairInfo *pairs, EriTask *tasks, hipStream_t s);
+                       const int *foff, const int32_t *code, const int64_t *prim_off, const int64_t *key_base,
+                       int nkeys, unsigned long long *cursor, PairInfo *pairs, EriTask *tasks, hipStream_t s);
 void launch_store_q(int npair, const double *qv, PairGeo *geo, double *Q, hipStream_t s);
 void launch_fill_zero(double *x, int64_t n, hipStream_t s);
 void launch_symmetrize(const double *acc, int64_t astride, double *out, int n, hipStream_t s);

@@ -230,13 +230,13 @@ __device__ inline int dev_pair_class(int la, int lb) { return la * (la + 1) / 2 
 
 __global__ __launch_bounds__(256) void sq_classify_kernel(int64_t nq, const int32_t *quartets,
                                                            const int64_t *offsets, int nshell, const int *l,
-                                                           const int *nprim, ClassOf class_of, int32_t *code,
-                                                           int64_t *primcnt, unsigned long long *counts,
-                                                           unsigned long long *err)
+                                                           const int *nprim, ClassOf class_of, int nkeys,
+                                                           int32_t *code, int64_t *primcnt,
+                                                           unsigned long long *counts, unsigned long long *err)
 {
-    // per-class counts of the block in LDS, then one global atomic per class present
-    __shared__ unsigned hist[625];
-    for (int j = threadIdx.x; j < 625; j += blockDim.x) hist[j] = 0u;
+    // per-key counts of the block in LDS, then one global atomic per key present
+    extern __shared__ unsigned sq_hist[];
+    for (int j = threadIdx.x; j < nkeys; j += blockDim.x) sq_hist[j] = 0u;
     __syncthreads();
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q < nq) {
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void sq_classify_kernel(int64_t nq, const int3
             sh[r] = quartets[4 * q + r];
             bad = bad || sh[r] < 0 || sh[r] >= nshell;
         }
-        int ci = -1;
+        int key = -1;
         if (bad) {
             atomicOr(err, 1ull);
         } else {
@@ -259,23 +259,27 @@ __global__ __launch_bounds__(256) void sq_classify_kernel(int64_t nq, const int3
                 int t = pos[0]; pos[0] = pos[2]; pos[2] = t;
                 t = pos[1]; pos[1] = pos[3]; pos[3] = t;
             }
-            ci = class_of.c[((L[pos[0]] * 5 + L[pos[1]]) * 5 + L[pos[2]]) * 5 + L[pos[3]]];
+            const int ci = class_of.c[((L[pos[0]] * 5 + L[pos[1]]) * 5 + L[pos[2]]) * 5 + L[pos[3]]];
             if (ci < 0) {
                 atomicOr(err, 2ull);
             } else {
-                atomicAdd(&hist[ci], 1u);
-                code[q] = ci << 8 | pos[0] | pos[1] << 2 | pos[2] << 4 | pos[3] << 6;
-                primcnt[q] = (int64_t)nprim[sh[0]] * nprim[sh[1]] + (int64_t)nprim[sh[2]] * nprim[sh[3]];
+                const int64_t nb = (int64_t)nprim[sh[0]] * nprim[sh[1]], nk = (int64_t)nprim[sh[2]] * nprim[sh[3]];
+                // most primitive quartets first: bucket floor(log2(n_bra n_ket)), reversed
+                const int lg = 63 - __builtin_clzll((unsigned long long)(nb * nk));
+                key = ci * SQ_BUCKETS + (SQ_BUCKETS - 1 - min(lg, SQ_BUCKETS - 1));
+                atomicAdd(&sq_hist[key], 1u);
+                code[q] = key << 8 | pos[0] | pos[1] << 2 | pos[2] << 4 | pos[3] << 6;
+                primcnt[q] = nb + nk;
             }
         }
-        if (ci < 0) {
+        if (key < 0) {
             code[q] = -1;
             primcnt[q] = 0;
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < 625; j += blockDim.x)
-        if (hist[j]) atomicAdd(&counts[j], (unsigned long long)hist[j]);
+    for (int j = threadIdx.x; j < nkeys; j += blockDim.x)
+        if (sq_hist[j]) atomicAdd(&counts[j], (unsigned long long)sq_hist[j]);
 }
 
 // Scatter: the two pair records of quartet q (2q bra, 2q + 1 ket, primitive
@@ -285,22 +289,22 @@ __global__ __launch_bounds__(256) void sq_classify_kernel(int64_t nq, const int3
 __global__ __launch_bounds__(256) void sq_scatter_kernel(int64_t nq, const int32_t *quartets, const int64_t *offsets,
                                                           const int *l, const int *nprim, const int *foff,
                                                           const int32_t *code, const int64_t *prim_off,
-                                                          const int64_t *class_base, unsigned long long *cursor,
-                                                          PairInfo *pairs, EriTask *tasks)
+                                                          const int64_t *key_base, int nkeys,
+                                                          unsigned long long *cursor, PairInfo *pairs, EriTask *tasks)
 {
-    // a quartet's slot: its class's base + the block's share of the class
-    // cursor (one global atomic per class present) + its rank in the block
-    __shared__ unsigned hist[625];
-    __shared__ unsigned long long blk[625];
-    for (int j = threadIdx.x; j < 625; j += blockDim.x) hist[j] = 0u;
+    // a quartet's slot: its key's base + the block's share of the key's
+    // cursor (one global atomic per key present) + its rank in the block
+    extern __shared__ unsigned long long sq_blk[];
+    unsigned *hist = (unsigned *)(sq_blk + nkeys);
+    for (int j = threadIdx.x; j < nkeys; j += blockDim.x) hist[j] = 0u;
     __syncthreads();
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t c = q < nq ? code[q] : -1;
-    const int ci = c >> 8;              // -1 for no quartet (the runtime scatters only valid codes)
+    const int key = c >> 8;             // -1 for no quartet (the runtime scatters only valid codes)
     unsigned rank = 0u;
     EriTask t;
     if (c >= 0) {
-        rank = atomicAdd(&hist[ci], 1u);
+        rank = atomicAdd(&hist[key], 1u);
         int sh[4], pos[4], n[4], stride[4];
         for (int r = 0; r < 4; ++r) {
             sh[r] = quartets[4 * q + r];
@@ -328,10 +332,10 @@ __global__ __launch_bounds__(256) void sq_scatter_kernel(int64_t nq, const int32
         t.s0 = stride[pos[0]]; t.s1 = stride[pos[1]]; t.s2 = stride[pos[2]]; t.s3 = stride[pos[3]];
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < 625; j += blockDim.x)
-        if (hist[j]) blk[j] = atomicAdd(&cursor[j], (unsigned long long)hist[j]);
+    for (int j = threadIdx.x; j < nkeys; j += blockDim.x)
+        if (hist[j]) sq_blk[j] = atomicAdd(&cursor[j], (unsigned long long)hist[j]);
     __syncthreads();
-    if (c >= 0) tasks[class_base[ci] + (int64_t)blk[ci] + rank] = t;
+    if (c >= 0) tasks[key_base[key] + (int64_t)sq_blk[key] + rank] = t;
 }
 
 // Exclusive scan of the 1024-element block b of v in place (LDS), its sum into bsum[b].
@@ -519,20 +523,22 @@ void launch_scan(int64_t *v, int n, int64_t *total, int64_t *tmp, hipStream_t s)
     hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)nb), dim3(1024), 0, s, v, (int64_t)n, (const int64_t *)tmp);
 }
 void launch_sq_classify(int64_t nq, const int32_t *quartets, const int64_t *offsets, int nshell, const int *l,
-                        const int *nprim, const ClassOf &class_of, int32_t *code, int64_t *primcnt,
+                        const int *nprim, const ClassOf &class_of, int nkeys, int32_t *code, int64_t *primcnt,
                         unsigned long long *counts, unsigned long long *err, hipStream_t s)
 {
     if (nq > 0)
-        hipLaunchKernelGGL(sq_classify_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, quartets,
-                           offsets, nshell, l, nprim, class_of, code, primcnt, counts, err);
+        hipLaunchKernelGGL(sq_classify_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256),
+                           (unsigned)(sizeof(unsigned) * nkeys), s, nq, quartets, offsets, nshell, l, nprim, class_of,
+                           nkeys, code, primcnt, counts, err);
 }
 void launch_sq_scatter(int64_t nq, const int32_t *quartets, const int64_t *offsets, const int *l, const int *nprim,
-                       const int *foff, const int32_t *code, const int64_t *prim_off, const int64_t *class_base,
-                       unsigned long long *cursor, PairInfo *pairs, EriTask *tasks, hipStream_t s)
+                       const int *foff, const int32_t *code, const int64_t *prim_off, const int64_t *key_base,
+                       int nkeys, unsigned long long *cursor, PairInfo *pairs, EriTask *tasks, hipStream_t s)
 {
     if (nq > 0)
-        hipLaunchKernelGGL(sq_scatter_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nq, quartets,
-                           offsets, l, nprim, foff, code, prim_off, class_base, cursor, pairs, tasks);
+        hipLaunchKernelGGL(sq_scatter_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256),
+                           (unsigned)((sizeof(unsigned long long) + sizeof(unsigned)) * nkeys), s, nq, quartets,
+                           offsets, l, nprim, foff, code, prim_off, key_base, nkeys, cursor, pairs, tasks);
 }
 void launch_store_q(int npair, const double *qv, PairGeo *geo, double *Q, hipStream_t s)
 {

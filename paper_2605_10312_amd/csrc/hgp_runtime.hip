@@ -1340,41 +1340,46 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
         for (void *p : held) hipFreeAsync(p, s);
         held.clear();
     };
-    const size_t nc8 = (size_t)ncls;
+    const size_t nc8 = (size_t)ncls, nk8 = nc8 * SQ_BUCKETS;      // keys: (class, primitive-count bucket)
     hipError_t e = get((void **)&d_code, sizeof(int32_t) * nq);
     if (e == hipSuccess) e = get((void **)&d_poff, sizeof(int64_t) * nq);
     if (e == hipSuccess) e = get((void **)&d_ptotal, sizeof(int64_t));
-    if (e == hipSuccess) e = get((void **)&d_base, sizeof(int64_t) * nc8);
+    if (e == hipSuccess) e = get((void **)&d_base, sizeof(int64_t) * nk8);
     if (e == hipSuccess) e = get((void **)&d_btotal, sizeof(int64_t));
     if (e == hipSuccess) e = get((void **)&d_stmp, sizeof(int64_t) * (size_t)((nq + 1023) / 1024));
     // counts, cursors and the error word in one zeroed block
-    if (e == hipSuccess) e = get((void **)&d_counts, sizeof(unsigned long long) * (2 * nc8 + 1));
+    if (e == hipSuccess) e = get((void **)&d_counts, sizeof(unsigned long long) * (2 * nk8 + 1));
     if (e != hipSuccess) {
         release();
         return fail(HGP_E_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
     }
-    d_cursor = d_counts + nc8;
-    d_err = d_counts + 2 * nc8;
-    launch_fill_zero((double *)d_counts, (int64_t)(2 * nc8 + 1), s);      // all-zero bits
-    launch_sq_classify(nq, quartets, offsets, b->nshell, b->d_l, b->d_nprim, cof, d_code, d_poff, d_counts, d_err, s);
+    d_cursor = d_counts + nk8;
+    d_err = d_counts + 2 * nk8;
+    launch_fill_zero((double *)d_counts, (int64_t)(2 * nk8 + 1), s);      // all-zero bits
+    launch_sq_classify(nq, quartets, offsets, b->nshell, b->d_l, b->d_nprim, cof, (int)nk8, d_code, d_poff, d_counts,
+                       d_err, s);
     launch_scan(d_poff, (int)nq, d_ptotal, d_stmp, s);
-    e = hipMemcpyAsync(d_base, d_counts, sizeof(int64_t) * nc8, hipMemcpyDeviceToDevice, s);
+    e = hipMemcpyAsync(d_base, d_counts, sizeof(int64_t) * nk8, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) {
         release();
         return fail(HGP_E_DEVICE, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
     }
-    launch_scan(d_base, ncls, d_btotal, nullptr, s);
-    // the one wait: per-class counts, the error word and the primitive total size the launches
-    std::vector<unsigned long long> h((size_t)(nc8 + 1));
+    launch_scan(d_base, (int)nk8, d_btotal, nullptr, s);
+    // the one wait: per-key counts, the error word and the primitive total size the launches
+    std::vector<unsigned long long> hk(nk8 + 1);
     int64_t ptotal = 0;
-    e = hipMemcpyAsync(h.data(), d_counts, sizeof(unsigned long long) * nc8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&h[nc8], d_err, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(hk.data(), d_counts, sizeof(unsigned long long) * nk8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hk[nk8], d_err, sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&ptotal, d_ptotal, sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         release();
         return fail(HGP_E_DEVICE, std::string("classifying the quartets: ") + hipGetErrorString(e));
     }
+    // per class (its keys are contiguous), then the error word
+    std::vector<unsigned long long> h(nc8 + 1, 0ull);
+    for (size_t k = 0; k < nk8; ++k) h[k / SQ_BUCKETS] += hk[k];
+    h[nc8] = hk[nk8];
     if (h[nc8] & 1ull) { release(); return fail(HGP_E_INVALID, "shell index out of range or negative offset"); }
     if (h[nc8] & 2ull) {
         release();
@@ -1414,8 +1419,8 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
         release();
         return fail(HGP_E_OOM, std::string("hipMallocAsync: ") + hipGetErrorString(e));
     }
-    launch_sq_scatter(nq, quartets, offsets, b->d_l, b->d_nprim, b->d_foff, d_code, d_poff, d_base, d_cursor, d_pairs,
-                      d_tasks, s);
+    launch_sq_scatter(nq, quartets, offsets, b->d_l, b->d_nprim, b->d_foff, d_code, d_poff, d_base, (int)nk8, d_cursor,
+                      d_pairs, d_tasks, s);
     launch_pairs((int)(2 * nq), d_pairs, b->d_cen, b->d_poff, b->d_exps, b->d_ncoef, d_geo, d_prims, s);
     int64_t begin = 0;
     for (int c = 0; c < ncls; ++c) {
