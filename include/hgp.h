@@ -300,10 +300,10 @@ hgp_status hgp_eri_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t 
  *   out   per quartet 12 blocks [position 0..3][axis x, y, z][n_i][n_j][n_k][n_l],
  *         row-major, 12 n_i n_j n_k n_l doubles at out + offsets[q] (device)
  * A shell given at two positions gets a block per position (their sum is
- * the derivative in its centre).  Shells up to l = hgp_deriv_max_l() (the
- * derivative tables run on the wave-cooperative interpreter);
+ * the derivative in its centre).  Shells up to l = hgp_deriv_max_l();
  * HGP_E_UNSUPPORTED_L beyond.  Stream behaviour and other errors as
- * hgp_eri_shell_quartets.
+ * hgp_eri_shell_quartets; the call also holds, stream-ordered, a buffer of
+ * at most 1 GiB for the partial accumulators of its larger classes.
  */
 hgp_status hgp_eri_deriv_shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartets,
                                         const int64_t *offsets, double *out, void *hip_stream);
