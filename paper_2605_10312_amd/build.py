@@ -399,8 +399,8 @@ def build(lmax: int = DEFAULT_LMAX, jobs: int | None = None, force: bool = False
                 cur = dstage.get(tag, caps[0])
                 dstage[tag] = caps[caps.index(cur) + 1] if cur in caps[:-1] else None
                 if verbose:
-                    print(f"  derivative staged form {tag} at cap {cur} uses private scratch; "
-                          f"{'cap ' + str(dstage[tag]) if dstage[tag] else 'tables only'}", flush=True)
+                    print(f"  derivative staged form {tag} at (cap, waves) {cur} uses private scratch; "
+                          f"{dstage[tag] if dstage[tag] else 'tables only'}", flush=True)
         if (not spilled and not dspill and not sspill) or allow_scratch:
             break
         by_tag = {m.tag: m for m in metas}

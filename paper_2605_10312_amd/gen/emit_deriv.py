@@ -430,7 +430,12 @@ def emit_deriv_reg(la, lb, lc, ld, rule="ket_zyx", block=REG_BLOCK):
 # Phase 2 is the wave-form tables' Phase 2, which sums the nseg partials of
 # each accumulator in segment order (t3w_launch_deriv_p2).
 
-STAGE_CAPS = (96, 64, 40)     # accumulators per chunk: the build steps down this list while a part spills
+# (accumulators per chunk, waves per SIMD asked of the compiler, 0: none): the
+# build steps down this list while a Phase-1 part of the class spills.  Two
+# waves per SIMD at caps 48/32 measured slower on the 400 000-quartet sample
+# for 17 of the 20 staged classes (35.9 against 29.0 ms a call): the extra
+# recomputation (x2-2.9 instead of x1.2-2) costs more than the occupancy gains.
+STAGE_CAPS = ((96, 0), (64, 0), (40, 0))
 STAGE_PART = 16               # chunks per Phase-1 kernel (one translation unit each)
 
 
@@ -491,8 +496,11 @@ def _chunk_lines(P, targets, ind):
 
 def emit_deriv_staged(la, lb, lc, ld, cap=STAGE_CAPS[0], rule="ket_zyx", block=REG_BLOCK):
     """Sources of the staged form's Phase-1 kernels: {part: source}, and its
-    description.  Part 0 also holds the class launcher launch_dp1_<tag>,
-    which runs every part over the batch a.tasks[0 .. a.ntask)."""
+    description; cap = (accumulators per chunk, waves per SIMD or 0).  Part 0
+    also holds the class launcher launch_dp1_<tag>, which runs every part
+    over the batch a.tasks[0 .. a.ntask)."""
+    from .emit import waves_attr
+    cap, waves = cap if isinstance(cap, tuple) else (cap, 0)
     ls = (la, lb, lc, ld)
     tag = "".join(str(x) for x in ls)
     P = deriv_program(*ls, rule=rule)
@@ -507,7 +515,7 @@ def emit_deriv_staged(la, lb, lc, ld, cap=STAGE_CAPS[0], rule="ket_zyx", block=R
                f"// chunks {p * STAGE_PART} .. {p * STAGE_PART + len(part) - 1} of {len(chunks)} "
                f"(at most {cap} weighted accumulators each).",
                '#include "hgp_device.h"', "", "namespace hgp {", "namespace {", "",
-               f"__global__ __launch_bounds__({block}) void dp1_{tag}p{p}(EriArgs a, int nseg)", "{"]
+               f"__global__ __launch_bounds__({block}){waves_attr(waves)} void dp1_{tag}p{p}(EriArgs a, int nseg)", "{"]
         w = out.append
         w(f"    const int64_t item = (int64_t)blockIdx.x * {block} + threadIdx.x;")
         w("    const int64_t n = a.ntask, per = (int64_t)nseg * n;")
@@ -555,6 +563,6 @@ def emit_deriv_staged(la, lb, lc, ld, cap=STAGE_CAPS[0], rule="ket_zyx", block=R
         w("")
         w("}  // namespace hgp")
         srcs[p] = "\n".join(out) + "\n"
-    info = {"tag": tag, "cap": cap, "chunks": len(chunks), "parts": nparts, "nodes": nodes,
+    info = {"tag": tag, "cap": cap, "waves": waves, "chunks": len(chunks), "parts": nparts, "nodes": nodes,
             "recompute": round(nodes / len(P.g.nodes), 3), "max_peak_live": maxpl, "n_acc": len(P.acc_index)}
     return srcs, info
