@@ -454,6 +454,10 @@ def plan_sizes(args):
 
 
 def deriv_bench(args):
+    print(json.dumps(deriv_run(args.deriv_quartets, args.steps, args.warmup, args.cpu_seconds, 8)), flush=True)
+
+
+def deriv_run(want, steps, warmup, cpu_seconds, n_check):
     """First-derivative integrals (hgp_eri_deriv_shell_quartets) of a uniform
     sample of the 30-atom 3s2p1d workload's screened unique shell quartets,
     quartet and offset arrays on the device.  One JSON line: derivative
@@ -472,7 +476,6 @@ def deriv_bench(args):
     Q = oracle.schwarz(bw)
     ns = bw.nshell
     rng = np.random.default_rng(2005)
-    want = args.deriv_quartets
     picked = []
     while len(picked) < want:
         q = rng.integers(0, ns, (4 * want, 4))
@@ -486,14 +489,14 @@ def deriv_bench(args):
     qd = torch.tensor(quartets, device="cuda")
     od = torch.tensor(offs, device="cuda")
     out = torch.empty(int(sizes.sum()), dtype=torch.float64, device="cuda")
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         hgp.eri_shell_quartets(b, qd, od, out, deriv=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         hgp.eri_shell_quartets(b, qd, od, out, deriv=True)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     # algorithmic FLOPs of the tables
     info = {d["tag"]: d for d in json.load(open(os.path.join(os.path.dirname(os.path.abspath(hgp.__file__)),
                                                                "_gen", "deriv.json")))}
@@ -508,7 +511,7 @@ def deriv_bench(args):
         t = info[f"{a_}{b_}{c_}{d_}"]
         flop += float(np.prod(nprim[list(q)])) * t["vrr_flops"] + t["p2_flops"]
     got = out.cpu().numpy()
-    chk = rng.choice(len(quartets), 8, replace=False)
+    chk = rng.choice(len(quartets), n_check, replace=False)
     errs = []
     for i in chk:
         ref = oracle.eri_deriv_shell_quartet(bw, *quartets[i], precision="long double")
@@ -519,14 +522,14 @@ def deriv_bench(args):
     t0 = time.perf_counter()
     n_cpu = 0
     ints_cpu = 0
-    while time.perf_counter() - t0 < args.cpu_seconds / 3 and n_cpu < len(quartets):
+    while time.perf_counter() - t0 < cpu_seconds / 3 and n_cpu < len(quartets):
         oracle.eri_deriv_shell_quartet(bw, *quartets[n_cpu])
         ints_cpu += int(sizes[n_cpu])
         n_cpu += 1
-    cpu_rate = ints_cpu / (time.perf_counter() - t0)
+    cpu_rate = ints_cpu / (time.perf_counter() - t0) if n_cpu else None
     value = float(sizes.sum()) / dt
     line = {"metric": "first-derivative contracted integrals/s", "value": value, "unit": "derivative integrals/s",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+            "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(dt * 1e3, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"deriv_mol30_3s2p1d: {len(quartets)} uniformly drawn screened unique shell "
                                    "quartets of the 30-atom 3s2p1d molecule (tau 1e-12), d/dR of all four centres, "
@@ -536,14 +539,15 @@ def deriv_bench(args):
                          "achieved": round(flop / dt / 1e12, 3),
                          "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(flop / dt / 1e12 / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None},
-            "cpu_baseline": {"value": cpu_rate, "unit": "derivative integrals/s", "cores": oracle.num_threads(),
-                             "kind": "oracle", "sample": f"the first {n_cpu} quartets of the same sample, one at a "
-                                                         "time (oracle_eri_deriv_shell_quartet)"},
-            "err": {"quartets_checked": len(chk), "max_abs_vs_long_double": float(max(e[0] for e in errs)),
-                    "oracle_fp64_vs_long_double_max_abs": float(max(e[2] for e in errs)),
-                    "max_abs_derivative": float(max(e[1] for e in errs))}}
-    print(json.dumps(line), flush=True)
+            "cpu_baseline": None if not n_cpu else {
+                "value": cpu_rate, "unit": "derivative integrals/s", "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"the first {n_cpu} quartets of the same sample, one at a time (oracle_eri_deriv_shell_quartet)"},
+            "err": None if not errs else {
+                "quartets_checked": len(chk), "max_abs_vs_long_double": float(max(e[0] for e in errs)),
+                "oracle_fp64_vs_long_double_max_abs": float(max(e[2] for e in errs)),
+                "max_abs_derivative": float(max(e[1] for e in errs))}}
     b.close()
+    return line
 
 
 def main():
@@ -555,6 +559,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-high-l", action="store_true", help="skip the high-l class microbench in the default run")
+    ap.add_argument("--no-deriv", action="store_true", help="skip the first-derivative run in the default run")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: quartets with Q_ab Q_cd < theta use FP32 VRR and contraction (register tier; HRR, Boys, J/K FP64)")
     ap.add_argument("--theta", type=float, default=None, help="mixed-precision threshold (default: the library's)")
@@ -713,6 +718,11 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(bw, args.cpu_seconds)
     # the high-l classes, which this workload (l <= 2) does not reach
     high_l = None if args.no_high_l else microbench_runs(2, 1, check=0 if args.no_check else 32)
+    # first-derivative integrals of a sample of the same molecule's quartets
+    deriv = None
+    if not args.no_deriv:
+        d = deriv_run(args.deriv_quartets, 3, 1, 0.0, 0 if args.no_check else 4)
+        deriv = {k: d[k] for k in ("metric", "value", "unit", "ms_per_step", "dtype", "config", "roofline", "err")}
 
     line = {
         "metric": METRIC,
@@ -746,6 +756,7 @@ def main():
         "err_vs_fp64": err_fp64,
         "kernels": per_kernel,
         "high_l_microbench": high_l,
+        "first_derivatives": deriv,
     }
     print(json.dumps(line), flush=True)
 
