@@ -81,8 +81,22 @@ def measured_traffic(kernel):
     return None
 
 
+from paper_2605_10312_amd.counts import pair_functions, unique_eris      # noqa: E402  (host counting only)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(bw, target_s, seed=7):
-    """Oracle ERIs/s on random screened unique quartets of the same workload."""
+    """Oracle ERIs/s (unique function quartets, as the GPU line counts them) on
+    random screened unique quartets of the same workload."""
     import oracle
 
     rng = np.random.default_rng(seed)
@@ -109,11 +123,18 @@ def cpu_baseline(bw, target_s, seed=7):
     n = int(max(200, min(2_000_000, 200 * target_s / max(dt, 1e-3))))
     sample = draw(n)
     t = time.perf_counter()
-    cnt, _ = oracle.eri_quartet_list(bw, sample)
+    oracle.eri_quartet_list(bw, sample)
     dt = time.perf_counter() - t
-    return {"value": cnt / dt, "unit": "contracted ERIs/s", "cores": oracle.num_threads(), "kind": "oracle",
+    L = np.asarray(bw.l)
+    a, b_, c, d = (sample[:, k] for k in range(4))
+    Fb = pair_functions(L[a], L[b_], a == b_)
+    Fk = pair_functions(L[c], L[d], c == d)
+    same = (a == c) & (b_ == d)
+    cnt = float(np.sum(np.where(same, Fb * (Fb + 1) // 2, Fb * Fk)))
+    return {"value": cnt / dt, "unit": "contracted ERIs/s", "cores": oracle.num_threads(), "cpu_model": cpu_model(),
+            "kind": "oracle",
             "sample": f"{n} uniformly drawn screened unique shell quartets of the same workload, "
-                      f"integrals only (no J/K digestion), {dt:.1f} s"}
+                      f"integrals only (no J/K digestion), {dt:.1f} s; ERIs counted as unique function quartets"}
 
 
 def kernel_resources():
@@ -266,7 +287,7 @@ def batch(args):
         p = hgp.Plan(b, tau=TAU)
         bases.append(b)
         plans.append(p)
-        eris += sum(c["quartets"] * np.prod([nsph(x) for x in c["ls"]]) for c in p.classes())
+        eris += unique_eris(p.schwarz(), np.asarray(bw.l), TAU)[0]     # unique function quartets, as the J/K line
         Dt = torch.tensor(D, dtype=torch.float64, device="cuda")
         Ds.append(Dt)
         Js.append(torch.empty_like(Dt))
@@ -432,7 +453,7 @@ def plan_sizes(args):
         st = plan.stats()
         cls = plan.classes()
         flop = sum(c["prim_quartets"] * c["vrr_flops"] + c["quartets"] * c["phase2_flops"] for c in cls)
-        eris = sum(c["quartets"] * int(np.prod([nsph(x) for x in c["ls"]])) for c in cls)
+        eris = unique_eris(plan.schwarz(), np.asarray(bw.l), TAU)[0]
         line = {"workload": f"plan_{name.split()[0]}_{natom}atoms", "nbf": int(bw.nbf), "shells": int(bw.nshell),
                 "plan_s": round(t_plan, 2), **st, "eris_per_build": int(eris), "build_tflop": round(flop / 1e12, 1),
                 "free_device_bytes": int(torch.cuda.mem_get_info()[0])}
@@ -634,7 +655,13 @@ def main():
     setup_s = time.perf_counter() - t0
     classes = plan.classes()
     stats = plan.stats()
-    eris = sum(c["quartets"] * np.prod([nsph(x) for x in c["ls"]]) for c in classes)
+    # unique (8-fold) spherical function quartets of the kept shell quartets, from
+    # the plan's own Schwarz factors; the kernels compute whole blocks
+    blocks = sum(c["quartets"] * np.prod([nsph(x) for x in c["ls"]]) for c in classes)
+    eris, nkept = unique_eris(plan.schwarz(), np.asarray(bw.l), TAU)
+    if nkept != stats["quartets_kept"]:
+        print(f"warning: the ERI count's screen keeps {nkept} shell quartets, the plan {stats['quartets_kept']}",
+              file=sys.stderr, flush=True)
 
     Dt = torch.tensor(D, dtype=torch.float64, device="cuda")
     J = torch.empty_like(Dt)
@@ -744,7 +771,9 @@ def main():
                    "nbf": int(bw.nbf), "shells": int(bw.nshell), "tau": TAU,
                    "quartets_kept": stats["quartets_kept"], "quartets_total": stats["quartets_total"],
                    "prim_pairs_kept": stats["prim_pairs_kept"], "prim_pairs_total": stats["prim_pairs_total"],
-                   "eris_per_step": int(eris)},
+                   "eris_per_step": int(eris), "eri_block_elements_per_step": int(blocks),
+                   "eri_count_quartets": int(nkept),
+                   "eris_counted_as": "unique (8-fold) spherical function quartets of the kept shell quartets"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "jk_build_ms": round(ms_per_step, 4),

@@ -19,6 +19,8 @@ import time
 
 import numpy as np
 
+from .counts import unique_eris
+
 
 @dataclasses.dataclass
 class Request:
@@ -378,7 +380,7 @@ class GpuExecutor:
         D = [torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda") for x in r.densities]
         J = torch.empty_like(D[0])
         K = torch.empty_like(D[0])
-        self.eris[r.rid] = sum(c["quartets"] * int(np.prod([2 * x + 1 for x in c["ls"]])) for c in p.classes())
+        self.eris[r.rid] = unique_eris(p.schwarz(), np.asarray(r.basis.l), r.tau)[0]
         return {"basis": b, "plan": p, "D": D, "J": J, "K": K, "bytes": p.stats()["device_bytes"] + dev_bytes}
 
     def plan_bytes(self, h):
@@ -469,7 +471,14 @@ class GpuMultiExecutor:
             if e.status == STATUS_OOM:
                 raise OverBudget() from e
             raise
-        self.plan_eris[id(p)] = sum(c["quartets"] * int(np.prod([2 * x + 1 for x in c["ls"]])) for c in p.classes())
+        # per system: a multi-system plan pairs no shells of different systems
+        Q = p.schwarz()
+        n0, eris = 0, 0
+        for r in reqs:
+            n1 = n0 + len(r.basis.l)
+            eris += unique_eris(Q[n0:n1, n0:n1], np.asarray(r.basis.l), r.tau)[0]
+            n0 = n1
+        self.plan_eris[id(p)] = eris
         return p
 
     def submit(self, p, reqs, ks):
