@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <limits>
@@ -1297,6 +1298,29 @@ hgp_status hgp_jk_multi(hgp_plan *p, const double *const *D, double *const *J, d
 
 namespace {
 
+// Side streams of the derivative path, one set per device, created on first
+// use (default priority) and kept until the process ends.  A call holds its
+// device's set while it enqueues; its classes go to the caller's stream and
+// these, forked and joined with the set's events, each stream with its own
+// region of the accumulator buffer.
+constexpr int SQ_NSIDE = 3;
+struct SqSide {
+    std::mutex m;
+    bool ok = false;
+    hipStream_t st[SQ_NSIDE] = {};
+    hipEvent_t fork = nullptr, join[SQ_NSIDE] = {};
+};
+
+SqSide *sq_side(int dev)
+{
+    static std::mutex mm;
+    static std::map<int, SqSide *> sets;
+    std::lock_guard<std::mutex> lock(mm);
+    SqSide *&x = sets[dev];
+    if (!x) x = new SqSide;
+    return x;
+}
+
 // Shell quartets given on the device, integrals (deriv = false) or their
 // first derivatives (deriv = true: 12 blocks a quartet, from the register form
 // of the class where it has one, else from its wave-form tables).
@@ -1389,6 +1413,27 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
     }
     if (ptotal > INT32_MAX) { release(); return fail(HGP_E_INVALID, "too many primitive pairs in one call"); }
     int64_t sneed = 0;
+    // derivative classes over the caller's stream (0) and the side streams
+    // (1 .. SQ_NSIDE), largest estimated work first, each to the least loaded
+    std::vector<int> lane((size_t)ncls, 0);
+    int64_t need[1 + SQ_NSIDE] = {0}, roff[1 + SQ_NSIDE] = {0};
+    if (deriv) {
+        std::vector<std::pair<double, int>> est;
+        for (int c = 0; c < ncls; ++c)
+            if (h[(size_t)c])
+                est.push_back({(double)h[(size_t)c] * (g_deriv_table[c].t->n_vrr + g_deriv_table[c].t->n_p2), c});
+        std::sort(est.begin(), est.end(), [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
+            return a.first > b.first || (a.first == b.first && a.second < b.second);
+        });
+        double load[1 + SQ_NSIDE] = {0.0};
+        for (const auto &x : est) {
+            int k = 0;
+            for (int j = 1; j <= SQ_NSIDE; ++j)
+                if (load[j] < load[k]) k = j;
+            lane[(size_t)x.second] = k;
+            load[k] += x.first;
+        }
+    }
     for (int c = 0; c < ncls; ++c)
         if (h[(size_t)c]) {
             if (deriv) {
@@ -1403,13 +1448,20 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
                 if (dc.p1) {
                     const int64_t n = (int64_t)h[(size_t)c];
                     const int ns = deriv_nseg(dc, n);
-                    sneed = std::max(sneed, deriv_batch(dc, n, ns) * ns * (int64_t)dc.t->n_hrr);
+                    int64_t &nd = need[lane[(size_t)c]];
+                    nd = std::max(nd, deriv_batch(dc, n, ns) * ns * (int64_t)dc.t->n_hrr);
                 }
                 continue;
             }
             if ((st = prepare_class(g_class_table[c]))) { release(); return st; }
             sneed = std::max(sneed, staged_need(g_class_table[c], (int64_t)h[(size_t)c]));
         }
+    if (deriv) {
+        for (int k = 0; k <= SQ_NSIDE; ++k) {
+            roff[k] = sneed;
+            sneed += need[k];
+        }
+    }
     e = get((void **)&d_pairs, sizeof(PairInfo) * 2 * nq);
     if (e == hipSuccess) e = get((void **)&d_geo, sizeof(PairGeo) * 2 * nq);
     if (e == hipSuccess) e = get((void **)&d_prims, sizeof(PrimPair) * (size_t)std::max<int64_t>(ptotal, 1));
@@ -1422,6 +1474,33 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
     launch_sq_scatter(nq, quartets, offsets, b->d_l, b->d_nprim, b->d_foff, d_code, d_poff, d_base, (int)nk8, d_cursor,
                       d_pairs, d_tasks, s);
     launch_pairs((int)(2 * nq), d_pairs, b->d_cen, b->d_poff, b->d_exps, b->d_ncoef, d_geo, d_prims, s);
+    // fork the side streams (derivatives), which read what the stream has written so far
+    SqSide *sd = nullptr;
+    std::unique_lock<std::mutex> side_lock;
+    bool used[1 + SQ_NSIDE] = {true, false, false, false};
+    if (deriv) {
+        int dev = 0;
+        e = hipGetDevice(&dev);
+        if (e == hipSuccess) {
+            sd = sq_side(dev);
+            side_lock = std::unique_lock<std::mutex>(sd->m);
+            for (int k = 0; k < SQ_NSIDE && !sd->ok && e == hipSuccess; ++k) {
+                e = hipStreamCreateWithFlags(&sd->st[k], hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&sd->join[k], hipEventDisableTiming);
+            }
+            if (!sd->ok && e == hipSuccess) e = hipEventCreateWithFlags(&sd->fork, hipEventDisableTiming);
+            if (e == hipSuccess) sd->ok = true;
+        }
+        for (int c = 0; c < ncls; ++c)
+            if (h[(size_t)c]) used[lane[(size_t)c]] = true;
+        if (e == hipSuccess) e = hipEventRecord(sd->fork, s);
+        for (int k = 0; k < SQ_NSIDE && e == hipSuccess; ++k)
+            if (used[k + 1]) e = hipStreamWaitEvent(sd->st[k], sd->fork, 0);
+        if (e != hipSuccess) {
+            release();
+            return fail(HGP_E_DEVICE, std::string("derivative side streams: ") + hipGetErrorString(e));
+        }
+    }
     int64_t begin = 0;
     for (int c = 0; c < ncls; ++c) {
         const int64_t cnt = (int64_t)h[(size_t)c];
@@ -1437,6 +1516,8 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
             // launches of at most 2^20 quartets (a workgroup each in the table form); the
             // staged form in batches whose accumulators fit the buffer, slot stride = batch
             const DerivClass &dc = g_deriv_table[c];
+            const int k = lane[(size_t)c];
+            hipStream_t ss = k ? sd->st[k - 1] : s;
             const bool reg = deriv_use_reg(dc, cnt);
             const int nseg = dc.p1 && !reg ? deriv_nseg(dc, cnt) : 1;
             const int64_t step = reg || !dc.p1 ? (int64_t)1 << 20 : deriv_batch(dc, cnt, nseg);
@@ -1445,13 +1526,14 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
                 x.tasks = a.tasks + q0;
                 x.ntask = std::min<int64_t>(step, cnt - q0);
                 if (reg) {
-                    dc.reg(x, d_code, 1, s);
+                    dc.reg(x, d_code, 1, ss);
                 } else if (dc.p1) {
                     x.stride = x.ntask;
-                    dc.p1(x, d_code, nseg, s);
-                    t3w_launch_deriv_p2(*dc.t, x, d_code, nseg, s);
+                    x.scratch = d_scr + roff[k];
+                    dc.p1(x, d_code, nseg, ss);
+                    t3w_launch_deriv_p2(*dc.t, x, d_code, nseg, ss);
                 } else {
-                    t3w_launch_deriv(*dc.t, x, d_code, s);
+                    t3w_launch_deriv(*dc.t, x, d_code, ss);
                 }
             }
         } else {
@@ -1460,6 +1542,13 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
         begin += cnt;
     }
     e = hipGetLastError();
+    // join the side streams before the temporaries are freed on the caller's stream
+    for (int k = 0; sd && k < SQ_NSIDE; ++k)
+        if (used[k + 1]) {
+            hipError_t j = hipEventRecord(sd->join[k], sd->st[k]);
+            if (j == hipSuccess) j = hipStreamWaitEvent(s, sd->join[k], 0);
+            if (j != hipSuccess && e == hipSuccess) e = j;
+        }
     release();
     if (e != hipSuccess) return fail(HGP_E_DEVICE, std::string("integral kernels: ") + hipGetErrorString(e));
     return HGP_OK;
