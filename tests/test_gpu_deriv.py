@@ -106,3 +106,55 @@ def test_deriv_register_and_staged_forms_agree_at_scale(hgp, torch_cuda):
             worst = max(worst, np.abs(g - refs[i % len(base)]).max())
         assert worst <= 1e-12 * scale, (copies, worst, scale)
         print(f"{len(quartets)} quartets: worst |d - oracle| {worst:.2e} (max |d| {scale:.2e})")
+
+
+def test_deriv_full_size_sample(hgp, torch_cuda):
+    """The timed derivative workload at its full size and launch shape: 400 000
+    uniformly drawn screened unique shell quartets of the 30-atom 3s2p1d
+    molecule (tau 1e-12) in one call, device arrays.  64 sampled quartets
+    against the long-double oracle (1e-12 of the sample's largest derivative
+    plus 8 times the FP64 oracle's own error), translational invariance on
+    4 000 sampled blocks, and every value finite."""
+    torch = torch_cuda
+    bw, _ = workloads.molecule_3s2p1d()
+    Q = oracle.schwarz(bw)
+    ns = bw.nshell
+    rng = np.random.default_rng(2005)
+    want, picked = 400000, []
+    while len(picked) < want:
+        q = rng.integers(0, ns, (4 * want, 4))
+        i, j, k, l = q.T
+        keep = (i >= j) & (k >= l) & (i * (i + 1) // 2 + j >= k * (k + 1) // 2 + l) & (Q[i, j] * Q[k, l] >= 1e-12)
+        picked.extend(map(tuple, q[keep][: want - len(picked)]))
+    quartets = np.array(picked, np.int32)
+    L = np.asarray(bw.l)
+    sizes = 12 * np.prod(2 * L[quartets] + 1, axis=1).astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    b = hgp.Basis.from_workload(bw)
+    out = torch.full((int(sizes.sum()),), np.nan, dtype=torch.float64, device="cuda")
+    hgp.eri_shell_quartets(b, torch.tensor(quartets, device="cuda"), torch.tensor(offs, device="cuda"), out,
+                           deriv=True)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(out).all())
+    o = out.cpu().numpy()
+    b.close()
+    chk = rng.choice(len(quartets), 64, replace=False)
+    refs = [oracle.eri_deriv_shell_quartet(bw, *quartets[i], precision="long double") for i in chk]
+    scale = max(np.abs(r).max() for r in refs)
+    worst, at = 0.0, None
+    for i, ref in zip(chk, refs):
+        g = o[offs[i]:offs[i] + sizes[i]].reshape(ref.shape)
+        e_orc = np.abs(oracle.eri_deriv_shell_quartet(bw, *quartets[i]) - ref).max()
+        err = np.abs(g - ref).max()
+        if err > worst:
+            worst, at = err, (tuple(int(x) for x in quartets[i]), [int(L[x]) for x in quartets[i]], e_orc,
+                              float(np.abs(ref).max()))
+        assert err <= 1e-12 * scale + 8 * e_orc, (tuple(quartets[i]), err, scale, e_orc)
+    inv = 0.0
+    for i in rng.choice(len(quartets), 4000, replace=False):
+        g = o[offs[i]:offs[i] + sizes[i]].reshape(4, -1)
+        inv = max(inv, np.abs(g.sum(axis=0)).max())
+    assert inv <= 1e-12 * max(scale, np.abs(o).max())
+    print(f"400 000 quartets: worst |d - oracle| {worst:.2e} over 64 (max |d| {scale:.2e}) at quartet {at[0]} "
+          f"(l {at[1]}, its max |d| {at[3]:.2e}, the FP64 oracle's own error there {at[2]:.2e}), "
+          f"max |sum over centres| {inv:.2e} over 4 000")
