@@ -1298,11 +1298,11 @@ hgp_status hgp_jk_multi(hgp_plan *p, const double *const *D, double *const *J, d
 
 namespace {
 
-// Side streams of the derivative path, one set per device, created on first
-// use (default priority) and kept until the process ends.  A call holds its
-// device's set while it enqueues; its classes go to the caller's stream and
-// these, forked and joined with the set's events, each stream with its own
-// region of the accumulator buffer.
+// Side streams of the shell-quartet calls, one set per device, created on
+// first use (default priority) and kept until the process ends.  A call holds
+// its device's set while it enqueues; its classes go to the caller's stream
+// and these, forked and joined with the set's events (derivative classes with
+// a region of the accumulator buffer per stream).
 constexpr int SQ_NSIDE = 3;
 struct SqSide {
     std::mutex m;
@@ -1413,19 +1413,33 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
     }
     if (ptotal > INT32_MAX) { release(); return fail(HGP_E_INVALID, "too many primitive pairs in one call"); }
     int64_t sneed = 0;
-    // derivative classes over the caller's stream (0) and the side streams
-    // (1 .. SQ_NSIDE), largest estimated work first, each to the least loaded
+    // classes over the caller's stream (0) and the side streams (1 ..
+    // SQ_NSIDE), largest estimated work first, each to the least loaded:
+    // every derivative class (each stream gets its own buffer region), and of
+    // the integral classes those that use no buffer (register and wave-LDS
+    // tiers); staged and HBM-scratch integral classes share the buffer on 0
     std::vector<int> lane((size_t)ncls, 0);
     int64_t need[1 + SQ_NSIDE] = {0}, roff[1 + SQ_NSIDE] = {0};
-    if (deriv) {
+    {
         std::vector<std::pair<double, int>> est;
-        for (int c = 0; c < ncls; ++c)
-            if (h[(size_t)c])
-                est.push_back({(double)h[(size_t)c] * (g_deriv_table[c].t->n_vrr + g_deriv_table[c].t->n_p2), c});
+        double load[1 + SQ_NSIDE] = {0.0};
+        for (int c = 0; c < ncls; ++c) {
+            if (!h[(size_t)c]) continue;
+            const double n = (double)h[(size_t)c];
+            if (deriv) {
+                est.push_back({n * (g_deriv_table[c].t->n_vrr + g_deriv_table[c].t->n_p2), c});
+            } else {
+                const ClassKernels &k = g_class_table[c];
+                const double w = n * (k.vrr_flops + k.p2_flops);
+                if (k.tier == 0 || k.tier == 3)
+                    est.push_back({w, c});
+                else
+                    load[0] += w;
+            }
+        }
         std::sort(est.begin(), est.end(), [](const std::pair<double, int> &a, const std::pair<double, int> &b) {
             return a.first > b.first || (a.first == b.first && a.second < b.second);
         });
-        double load[1 + SQ_NSIDE] = {0.0};
         for (const auto &x : est) {
             int k = 0;
             for (int j = 1; j <= SQ_NSIDE; ++j)
@@ -1474,11 +1488,13 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
     launch_sq_scatter(nq, quartets, offsets, b->d_l, b->d_nprim, b->d_foff, d_code, d_poff, d_base, (int)nk8, d_cursor,
                       d_pairs, d_tasks, s);
     launch_pairs((int)(2 * nq), d_pairs, b->d_cen, b->d_poff, b->d_exps, b->d_ncoef, d_geo, d_prims, s);
-    // fork the side streams (derivatives), which read what the stream has written so far
+    // fork the side streams, which read what the stream has written so far
     SqSide *sd = nullptr;
     std::unique_lock<std::mutex> side_lock;
     bool used[1 + SQ_NSIDE] = {true, false, false, false};
-    if (deriv) {
+    for (int c = 0; c < ncls; ++c)
+        if (h[(size_t)c]) used[lane[(size_t)c]] = true;
+    if (used[1] || used[2] || used[3]) {
         int dev = 0;
         e = hipGetDevice(&dev);
         if (e == hipSuccess) {
@@ -1491,14 +1507,12 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
             if (!sd->ok && e == hipSuccess) e = hipEventCreateWithFlags(&sd->fork, hipEventDisableTiming);
             if (e == hipSuccess) sd->ok = true;
         }
-        for (int c = 0; c < ncls; ++c)
-            if (h[(size_t)c]) used[lane[(size_t)c]] = true;
         if (e == hipSuccess) e = hipEventRecord(sd->fork, s);
         for (int k = 0; k < SQ_NSIDE && e == hipSuccess; ++k)
             if (used[k + 1]) e = hipStreamWaitEvent(sd->st[k], sd->fork, 0);
         if (e != hipSuccess) {
             release();
-            return fail(HGP_E_DEVICE, std::string("derivative side streams: ") + hipGetErrorString(e));
+            return fail(HGP_E_DEVICE, std::string("side streams: ") + hipGetErrorString(e));
         }
     }
     int64_t begin = 0;
@@ -1537,7 +1551,7 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
                 }
             }
         } else {
-            run_eri_class(g_class_table[c], a, sneed, s);
+            run_eri_class(g_class_table[c], a, sneed, lane[(size_t)c] ? sd->st[lane[(size_t)c] - 1] : s);
         }
         begin += cnt;
     }
