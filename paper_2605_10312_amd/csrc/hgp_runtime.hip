@@ -1426,11 +1426,15 @@ hgp_status shell_quartets(const hgp_basis *b, int64_t nq, const int32_t *quartet
         for (int c = 0; c < ncls; ++c) {
             if (!h[(size_t)c]) continue;
             const double n = (double)h[(size_t)c];
+            // primitive quartets from the keys' log2 buckets (bucket b: about 1.5 * 2^(SQ_BUCKETS - 1 - b) each)
+            double np = 0.0;
+            for (int bk = 0; bk < SQ_BUCKETS; ++bk)
+                np += (double)hk[(size_t)c * SQ_BUCKETS + bk] * 1.5 * std::ldexp(1.0, SQ_BUCKETS - 1 - bk);
             if (deriv) {
-                est.push_back({n * (g_deriv_table[c].t->n_vrr + g_deriv_table[c].t->n_p2), c});
+                est.push_back({np * g_deriv_table[c].t->n_vrr + n * g_deriv_table[c].t->n_p2, c});
             } else {
                 const ClassKernels &k = g_class_table[c];
-                const double w = n * (k.vrr_flops + k.p2_flops);
+                const double w = np * k.vrr_flops + n * k.p2_flops;
                 if (k.tier == 0 || k.tier == 3)
                     est.push_back({w, c});
                 else
