@@ -47,7 +47,12 @@ VARIANTS = {
     "cap48": {"digest": "loads_first", "reduce": "segmented", "cap": 48},
     "staged": {"digest": "loads_first", "reduce": "segmented", "tier": 1},
     "plain": {"digest": "interleaved", "reduce": "none"},
+    "row_b180": {"digest": "loads_first", "reduce": "segmented", "budget": 180},
+    "row_b200": {"digest": "loads_first", "reduce": "segmented", "budget": 200},
 }
+# timing workloads: the 30-atom 3s2p1d molecule (l <= 2 classes) and a
+# 15-atom 4s3p2d1f molecule of the batched-systems recipe (l <= 3 classes)
+WORKLOADS = ("mol30", "f15")
 # Measured and dropped: 6 or 8 waves per SIMD forced on every l <= 2 class
 # (block 64, with and without prefetch) spills and ran 1.04-15x slower than
 # the tuned choice on every class.
@@ -64,13 +69,16 @@ def build_variants(names, lmax):
         print(f"built variant {name} -> {out} in {time.time() - t:.1f}s", flush=True)
 
 
-def time_library(steps, warmup):
+def time_library(steps, warmup, workload="mol30"):
     """Child process: per-class milliseconds per J/K build with the library named by HGP_LIB."""
     import torch
     import paper_2605_10312_amd as hgp
     import workloads
 
-    bw, D = workloads.molecule_3s2p1d()
+    if workload == "f15":
+        bw, D = workloads.batch_systems(seed=1006, n=1, natom=(15, 15), lmax=3, nprim=(1, 3))[0]
+    else:
+        bw, D = workloads.molecule_3s2p1d()
     basis = hgp.Basis.from_workload(bw)
     plan = hgp.Plan(basis, tau=1e-12)
     Dt = torch.tensor(D, dtype=torch.float64, device="cuda")
@@ -113,11 +121,11 @@ def measure(names, out, steps, warmup, timeout):
             json.dump(results, fh, indent=1)
 
 
-def refine(names, out, steps, warmup, timeout, margin=0.02, table=TABLE):
+def refine(names, out, steps, warmup, timeout, margin=0.02, table=TABLE, workload="mol30", min_l=0):
     """Time the current library (the package's libhgp.so, built from the
     tuning table) beside the named variants in one session, and adopt a
     variant's options for a class only where it beats the current choice by
-    more than `margin`."""
+    more than `margin` (and only for classes with a shell of l >= min_l)."""
     from . import LIB_PATH
     results = {}
     for name, lib in [("current", LIB_PATH)] + [(n, os.path.join(VARIANTS_DIR, f"libhgp_{n}.so")) for n in names]:
@@ -125,8 +133,8 @@ def refine(names, out, steps, warmup, timeout, margin=0.02, table=TABLE):
             raise FileNotFoundError(lib)
         print(f"== {name}", flush=True)
         r = subprocess.run([sys.executable, "-m", "paper_2605_10312_amd.tune", "_time", "--steps", str(steps),
-                            "--warmup", str(warmup)], env=dict(os.environ, HGP_LIB=lib), capture_output=True,
-                           text=True, timeout=timeout)
+                            "--warmup", str(warmup), "--workload", workload], env=dict(os.environ, HGP_LIB=lib),
+                           capture_output=True, text=True, timeout=timeout)
         if r.returncode != 0:
             print(r.stderr[-3000:], flush=True)
             raise SystemExit(f"{name} failed with status {r.returncode}")
@@ -134,7 +142,7 @@ def refine(names, out, steps, warmup, timeout, margin=0.02, table=TABLE):
         print(f"   {results[name]['ms_per_build']:.2f} ms per J/K build", flush=True)
     with open(out, "w") as fh:
         json.dump(results, fh, indent=1)
-    apply_refine(out, margin, table)
+    apply_refine(out, margin, table, min_l)
 
 
 def spills(name, tag):
@@ -148,11 +156,13 @@ def spills(name, tag):
     return b.class_scratch(json.load(open(path)), tag) > 0
 
 
-def apply_refine(path, margin=0.02, table=TABLE):
+def apply_refine(path, margin=0.02, table=TABLE, min_l=0):
     """The table update of `refine`, from its saved timings."""
     results = json.load(open(path))
     cur = json.load(open(table))
     for tag, c in results["current"]["classes"].items():
+        if max(int(x) for x in tag) < min_l:
+            continue
         best = min(((r["classes"][tag]["ms"], n) for n, r in results.items()
                     if n != "current" and tag in r["classes"] and r["classes"][tag]["tier"] == c["tier"]
                     and not spills(n, tag)),
@@ -161,7 +171,7 @@ def apply_refine(path, margin=0.02, table=TABLE):
             opts = {"tier": c["tier"]}
             opts.update(VARIANTS[best[1]])
             if opts["tier"] == 1:
-                opts = {k: v for k, v in opts.items() if k in ("tier", "cap", "waves", "reduce", "loop")}
+                opts = {k: v for k, v in opts.items() if k in ("tier", "cap", "waves", "reduce", "loop", "budget")}
             opts["variant"] = best[1]
             opts["ms"] = round(best[0], 4)
             print(f"{tag}: {c['ms']:.3f} -> {best[0]:.3f} ms with {best[1]}")
@@ -218,26 +228,30 @@ def main(argv=None):
     pr.add_argument("--steps", type=int, default=3)
     pr.add_argument("--warmup", type=int, default=1)
     pr.add_argument("--timeout", type=float, default=180.0)
+    pr.add_argument("--workload", choices=WORKLOADS, default="mol30")
+    pr.add_argument("--min-l", type=int, default=0, help="adopt only for classes with a shell of l >= this")
     pa = sub.add_parser("apply")
     pa.add_argument("results")
+    pa.add_argument("--min-l", type=int, default=0, help="adopt only for classes with a shell of l >= this")
     ps = sub.add_parser("select")
     ps.add_argument("results")
     pt = sub.add_parser("_time")
     pt.add_argument("--steps", type=int, default=3)
     pt.add_argument("--warmup", type=int, default=1)
+    pt.add_argument("--workload", choices=WORKLOADS, default="mol30")
     a = ap.parse_args(argv)
     if a.cmd == "build":
         build_variants(a.variants, a.lmax)
     elif a.cmd == "measure":
         measure(a.variants, a.out, a.steps, a.warmup, a.timeout)
     elif a.cmd == "refine":
-        refine(a.variants, a.out, a.steps, a.warmup, a.timeout)
+        refine(a.variants, a.out, a.steps, a.warmup, a.timeout, workload=a.workload, min_l=a.min_l)
     elif a.cmd == "apply":
-        apply_refine(a.results)
+        apply_refine(a.results, min_l=a.min_l)
     elif a.cmd == "select":
         select(a.results)
     else:
-        time_library(a.steps, a.warmup)
+        time_library(a.steps, a.warmup, a.workload)
 
 
 if __name__ == "__main__":
