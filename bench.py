@@ -474,6 +474,71 @@ def plan_sizes(args):
         torch.cuda.empty_cache()
 
 
+def sample_quartets(hgp, bw, b, want, seed=2005):
+    """`want` uniformly drawn unique shell quartets (i >= j, k >= l, ij >= kl)
+    of basis bw that the library's own Schwarz screen keeps (factors of a
+    plan at tau 1e-12)."""
+    plan = hgp.Plan(b, tau=TAU)
+    Q = plan.schwarz()
+    plan.close()
+    ns = bw.nshell
+    rng = np.random.default_rng(seed)
+    picked = []
+    while len(picked) < want:
+        q = rng.integers(0, ns, (4 * want, 4))
+        i, j, k, l = q.T
+        keep = (i >= j) & (k >= l) & (i * (i + 1) // 2 + j >= k * (k + 1) // 2 + l) & (Q[i, j] * Q[k, l] >= TAU)
+        picked.extend(map(tuple, q[keep][: want - len(picked)]))
+    return np.array(picked, np.int32)
+
+
+def sq_bench(args):
+    """Contracted integrals (hgp_eri_shell_quartets) of the same 400 000-quartet
+    sample as the derivative run, quartet and offset arrays on the device.
+    One JSON line: contracted ERIs/s (whole n_sph^4 blocks, as the call
+    writes them) and the error of sampled quartets against the long-double
+    oracle."""
+    import torch
+    import oracle
+    import paper_2605_10312_amd as hgp
+    import workloads
+
+    bw, _ = workloads.molecule_3s2p1d()
+    b = hgp.Basis.from_workload(bw)
+    quartets = sample_quartets(hgp, bw, b, args.deriv_quartets)
+    L = np.asarray(bw.l)
+    sizes = np.prod(2 * L[quartets] + 1, axis=1).astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    qd, od = torch.tensor(quartets, device="cuda"), torch.tensor(offs, device="cuda")
+    out = torch.empty(int(sizes.sum()), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        hgp.eri_shell_quartets(b, qd, od, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        hgp.eri_shell_quartets(b, qd, od, out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    o = out.cpu().numpy()
+    rng = np.random.default_rng(7)
+    errs = []
+    for i in rng.choice(len(quartets), 16, replace=False):
+        ref = oracle.eri_shell_quartet(bw, *quartets[i], precision="long double")
+        own = np.abs(oracle.eri_shell_quartet(bw, *quartets[i]) - ref).max()
+        errs.append((np.abs(o[offs[i]:offs[i] + sizes[i]].reshape(ref.shape) - ref).max(), own))
+    b.close()
+    line = {"metric": "contracted ERIs/s (shell quartets given on the device)", "value": float(sizes.sum()) / dt,
+            "unit": "contracted ERIs/s (whole blocks)", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"sq_mol30_3s2p1d: {len(quartets)} uniformly drawn screened unique shell quartets "
+                                   "of the 30-atom 3s2p1d molecule (tau 1e-12), integrals, FP64",
+                       "quartets": int(len(quartets))},
+            "err": {"quartets_checked": len(errs), "max_abs_vs_long_double": float(max(e[0] for e in errs)),
+                    "oracle_fp64_vs_long_double_max_abs": float(max(e[1] for e in errs))}}
+    print(json.dumps(line), flush=True)
+
+
 def deriv_bench(args):
     print(json.dumps(deriv_run(args.deriv_quartets, args.steps, args.warmup, args.cpu_seconds, 8)), flush=True)
 
@@ -494,19 +559,10 @@ def deriv_run(want, steps, warmup, cpu_seconds, n_check):
     import workloads
 
     bw, _ = workloads.molecule_3s2p1d()
-    Q = oracle.schwarz(bw)
-    ns = bw.nshell
-    rng = np.random.default_rng(2005)
-    picked = []
-    while len(picked) < want:
-        q = rng.integers(0, ns, (4 * want, 4))
-        i, j, k, l = q.T
-        keep = (i >= j) & (k >= l) & (i * (i + 1) // 2 + j >= k * (k + 1) // 2 + l) & (Q[i, j] * Q[k, l] >= TAU)
-        picked.extend(map(tuple, q[keep][: want - len(picked)]))
-    quartets = np.array(picked, np.int32)
+    b = hgp.Basis.from_workload(bw)
+    quartets = sample_quartets(hgp, bw, b, want)
     sizes = np.array([12 * int(np.prod([2 * bw.l[s] + 1 for s in q])) for q in quartets], np.int64)
     offs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
-    b = hgp.Basis.from_workload(bw)
     qd = torch.tensor(quartets, device="cuda")
     od = torch.tensor(offs, device="cuda")
     out = torch.empty(int(sizes.sum()), dtype=torch.float64, device="cuda")
@@ -532,6 +588,7 @@ def deriv_run(want, steps, warmup, cpu_seconds, n_check):
         t = info[f"{a_}{b_}{c_}{d_}"]
         flop += float(np.prod(nprim[list(q)])) * t["vrr_flops"] + t["p2_flops"]
     got = out.cpu().numpy()
+    rng = np.random.default_rng(2006)
     chk = rng.choice(len(quartets), n_check, replace=False)
     errs = []
     for i in chk:
@@ -584,7 +641,7 @@ def main():
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: quartets with Q_ab Q_cd < theta use FP32 VRR and contraction (register tier; HRR, Boys, J/K FP64)")
     ap.add_argument("--theta", type=float, default=None, help="mixed-precision threshold (default: the library's)")
-    ap.add_argument("--workload", choices=("mol30", "microbench", "batch", "serve", "plan-sizes", "deriv"),
+    ap.add_argument("--workload", choices=("mol30", "microbench", "batch", "serve", "plan-sizes", "deriv", "sq"),
                     default="mol30",
                     help="mol30: the J/K build (one JSON line); microbench: the high-l primitive-quartet classes; "
                          "batch: many uneven systems in one HIP graph; serve: continuous batching of requests; "
@@ -627,6 +684,9 @@ def main():
         return
     if args.workload == "plan-sizes":
         plan_sizes(args)
+        return
+    if args.workload == "sq":
+        sq_bench(args)
         return
     if args.workload == "deriv":
         deriv_bench(args)
