@@ -274,8 +274,11 @@ hgp_status hgp_batch_destroy(hgp_batch *b);
  * The quartets are classified on the device (class and canonical order per
  * quartet); the call then waits once for hip_stream, to read the per-class
  * counts that size the class launches, enqueues the pair precompute and the
- * class kernels, and returns.  out is complete when hip_stream reaches the
- * end of that work; quartets and offsets must stay valid until then.
+ * class kernels, and returns.  Part of the class kernels runs on side streams
+ * the library keeps per device, forked from and joined back into hip_stream,
+ * so out is complete when hip_stream reaches the end of that work; quartets
+ * and offsets must stay valid until then.  Calls on one device from several
+ * host threads enqueue one at a time.
  * Temporary buffers are taken from and returned to the device's default
  * memory pool on hip_stream.  Blocks must not overlap (each is written, not
  * accumulated).  Errors: HGP_E_INVALID for NULL pointers, nq < 0 or beyond
