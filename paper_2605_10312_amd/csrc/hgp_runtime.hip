@@ -151,10 +151,28 @@ int built_max_l()
 }
 
 // Batch size of a staged class over a buffer of `doubles`: a multiple of 64.
+// Quartets of one round of the lane-per-quartet op-table form on the current
+// device: one wave of 64 lanes per SIMD (its kernel runs at one wave per SIMD).
+int64_t lane_round()
+{
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || cu <= 0)
+        return 0;
+    return (int64_t)cu * 4 * 64;
+}
+
+// A class with both op-table forms (max_batch > 0): a batch holding more than
+// one lane-form round is cut to whole rounds, so that no batch ends in a
+// partly filled round (the remainder then runs as a batch of its own).
 int64_t staged_batch(const ClassKernels &k, int64_t doubles)
 {
     int64_t b = doubles / (k.scratch_slots > 0 ? k.scratch_slots : 1);
     b = (b / 64) * 64;
+    if (k.max_batch > 0) {
+        const int64_t r = lane_round();
+        if (r > 0 && b > r) b = (b / r) * r;
+    }
     return b < 64 ? 64 : b;
 }
 

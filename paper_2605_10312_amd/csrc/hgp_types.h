@@ -111,7 +111,9 @@ constexpr int64_t T3_SCRATCH_MAX_DOUBLES = (int64_t)1 << 31;
 // HBM-scratch classes with both a wave-cooperative (slots in the buffer, at
 // most max_batch quartets per launch) and a lane-per-quartet form: batches of
 // at least this many quartets take the lane form, smaller ones the wave form.
-constexpr int64_t T3G_LANE_MIN = 65536;
+// The lane form runs in rounds of one wave per SIMD (65 536 quartets on 256
+// CUs); from half a round on it beats the wave form.
+constexpr int64_t T3G_LANE_MIN = 32768;
 
 // Launchers run one lane per work item (nq or ntask): the register tier's
 // whole evaluation, or a staged class's Phase 2 + digestion; p1 launchers run
